@@ -1,0 +1,222 @@
+"""Scalar CPU oracle for the vectorized Quicksort (Blacher et al. 2022).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+CPU-baseline leg of bench.py.  The GPU library never imports, links or calls it,
+and it shares no code with the GPU library.
+
+The arithmetic lives in plain C (vqs_oracle.c, one scalar routine per step of
+the paper's method); this module only marshals numpy arrays through ctypes.
+The learned-splitter model oracle is in oracle/mlp.py.
+
+Key types use the interface numbering: 1 u16, 2 u32, 3 u64, 4 u128 (numpy
+uint64 array of shape (n, 2): column 0 the low word, column 1 the high word),
+5 f32, 6 f64.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "vqs_oracle.c")
+_lock = threading.Lock()
+_lib = None
+
+U16, U32, U64, U128, F32, F64 = 1, 2, 3, 4, 5, 6
+_DTYPES = {U16: np.uint16, U32: np.uint32, U64: np.uint64, U128: np.uint64,
+           F32: np.float32, F64: np.float64}
+KEY_SIZE = {U16: 2, U32: 4, U64: 8, U128: 16, F32: 4, F64: 8}
+NB_DEFAULT = 256
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in (
+        "partitions", "keys_partitioned", "degenerate", "all_equal", "basecases",
+        "heapsorts", "heapsort_keys", "max_depth", "depth_limit_used")]
+
+    def as_dict(self):
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
+def build(force: bool = False) -> str:
+    """Compile liboracle.so with gcc (strict IEEE: no FP contraction)."""
+    with _lock:
+        if force or not os.path.exists(_LIB_PATH) or \
+                os.path.getmtime(_LIB_PATH) < max(os.path.getmtime(_SRC),
+                                                  os.path.getmtime(os.path.join(_HERE, "oracle_body.h")),
+                                                  os.path.getmtime(os.path.join(_HERE, "mlp_oracle.c"))):
+            tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+            subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+                                   "-fno-fast-math", "-Wall", "-Wno-unused-function",
+                                   "-o", tmp, _SRC, os.path.join(_HERE, "mlp_oracle.c"), "-lm"])
+            os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB_PATH)
+        u64, i64, vp, i32 = ctypes.c_uint64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int
+        L.vqo_sort_segmented.argtypes = [vp, vp, u64, i32, i32, u64, u64, i64, ctypes.POINTER(Stats)]
+        L.vqo_sort.argtypes = [vp, u64, i32, i32, u64, u64, i64, ctypes.POINTER(Stats)]
+        L.vqo_choose_pivot.argtypes = [vp, u64, u64, i32, i32, u64, vp]
+        L.vqo_partition.argtypes = [vp, u64, u64, i32, i32, vp]
+        L.vqo_partition.restype = i64
+        L.vqo_minmax.argtypes = [vp, u64, u64, i32, i32, vp, vp]
+        L.vqo_basecase.argtypes = [vp, u64, i32, i32]
+        L.vqo_heapsort.argtypes = [vp, u64, i32, i32]
+        L.vqo_sfc64_raw.argtypes = [vp, vp, u64]
+        L.vqo_splitmix64_next.argtypes = [ctypes.POINTER(u64)]
+        L.vqo_splitmix64_next.restype = u64
+        L.vqo_seg_rng_state.argtypes = [u64, u64, u64, vp]
+        L.vqo_multiply_shift.argtypes = [ctypes.c_uint32, u64]
+        L.vqo_multiply_shift.restype = u64
+        L.vqo_pivot_offsets.argtypes = [u64, u64, u64, u64, vp]
+        L.vqo_default_depth_limit.argtypes = [u64]
+        L.vqo_default_depth_limit.restype = u64
+        L.vqo_green16.argtypes = [vp]
+        L.vqo_merge_network.argtypes = [u64, vp]
+        L.vqo_med3_u64.argtypes = [u64, u64, u64, i32]
+        L.vqo_med3_u64.restype = u64
+        L.vqo_key_size.argtypes = [i32]
+        _mlp_signatures(L)
+        _lib = L
+    return _lib
+
+
+def _mlp_signatures(L):
+    vp, u64, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int
+    L.vqo_mlp_forward_f32.argtypes = [vp, vp, u64, vp]
+    L.vqo_mlp_bucket_u64.argtypes = [vp, vp, u64, i32, vp]
+    L.vqo_key_to_x_u64.argtypes = [vp, u64, vp]
+
+
+def _ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+def _check_keys(keys: np.ndarray, kt: int) -> None:
+    if not keys.flags.c_contiguous:
+        raise ValueError("keys must be C-contiguous")
+    if keys.dtype != _DTYPES[kt]:
+        raise TypeError(f"key type {kt} needs dtype {_DTYPES[kt]}, got {keys.dtype}")
+    if kt == U128 and (keys.ndim != 2 or keys.shape[1] != 2):
+        raise ValueError("u128 keys are an (n, 2) uint64 array [lo, hi]")
+
+
+def nkeys(keys: np.ndarray, kt: int) -> int:
+    return keys.shape[0] if kt == U128 else keys.size
+
+
+def sort(keys: np.ndarray, kt: int, ascending: bool = True, seed: int = 0,
+         nb: int = NB_DEFAULT, depth_limit: int = -1, stats: bool = False):
+    """Sort keys in place with the paper's method; returns stats if asked."""
+    _check_keys(keys, kt)
+    st = Stats()
+    rc = lib().vqo_sort(_ptr(keys), nkeys(keys, kt), kt, int(bool(ascending)), seed, nb,
+                        depth_limit, ctypes.byref(st))
+    if rc != 0:
+        raise RuntimeError(f"vqo_sort failed: {rc}")
+    return st.as_dict() if stats else None
+
+
+def sort_segmented(keys: np.ndarray, offsets: np.ndarray, kt: int, ascending: bool = True,
+                   seed: int = 0, nb: int = NB_DEFAULT, depth_limit: int = -1, stats: bool = False):
+    _check_keys(keys, kt)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    st = Stats()
+    rc = lib().vqo_sort_segmented(_ptr(keys), _ptr(offsets), offsets.size - 1, kt,
+                                  int(bool(ascending)), seed, nb, depth_limit, ctypes.byref(st))
+    if rc != 0:
+        raise RuntimeError(f"vqo_sort_segmented failed: {rc}")
+    return st.as_dict() if stats else None
+
+
+def choose_pivot(keys: np.ndarray, b: int, e: int, kt: int, ascending: bool = True, seed: int = 0):
+    _check_keys(keys, kt)
+    out = np.zeros(2 if kt == U128 else 1, dtype=_DTYPES[kt])
+    rc = lib().vqo_choose_pivot(_ptr(keys), b, e, kt, int(bool(ascending)), seed, _ptr(out))
+    if rc != 0:
+        raise RuntimeError(f"vqo_choose_pivot failed: {rc}")
+    return out if kt == U128 else out[0]
+
+
+def partition(keys: np.ndarray, b: int, e: int, pivot, kt: int, ascending: bool = True) -> int:
+    _check_keys(keys, kt)
+    p = np.array(pivot, dtype=_DTYPES[kt]).reshape(-1)
+    return int(lib().vqo_partition(_ptr(keys), b, e, kt, int(bool(ascending)), _ptr(p)))
+
+
+def minmax(keys: np.ndarray, b: int, e: int, kt: int, ascending: bool = True):
+    _check_keys(keys, kt)
+    f = np.zeros(2 if kt == U128 else 1, dtype=_DTYPES[kt])
+    l = np.zeros_like(f)
+    if lib().vqo_minmax(_ptr(keys), b, e, kt, int(bool(ascending)), _ptr(f), _ptr(l)) != 0:
+        raise ValueError("empty range")
+    return (f, l) if kt == U128 else (f[0], l[0])
+
+
+def basecase(keys: np.ndarray, kt: int, ascending: bool = True) -> None:
+    _check_keys(keys, kt)
+    if lib().vqo_basecase(_ptr(keys), nkeys(keys, kt), kt, int(bool(ascending))) != 0:
+        raise ValueError("base case holds at most 1024 keys")
+
+
+def heapsort(keys: np.ndarray, kt: int, ascending: bool = True) -> None:
+    _check_keys(keys, kt)
+    lib().vqo_heapsort(_ptr(keys), nkeys(keys, kt), kt, int(bool(ascending)))
+
+
+def sfc64_raw(state, count: int) -> np.ndarray:
+    st = np.array(state, dtype=np.uint64)
+    out = np.zeros(count, dtype=np.uint64)
+    lib().vqo_sfc64_raw(_ptr(st), _ptr(out), count)
+    return out
+
+
+def splitmix64(x: int, count: int):
+    s = ctypes.c_uint64(x)
+    return [int(lib().vqo_splitmix64_next(ctypes.byref(s))) for _ in range(count)]
+
+
+def seg_rng_state(seed: int, b: int, e: int) -> np.ndarray:
+    out = np.zeros(4, dtype=np.uint64)
+    lib().vqo_seg_rng_state(seed, b, e, _ptr(out))
+    return out
+
+
+def multiply_shift(u: int, rng: int) -> int:
+    return int(lib().vqo_multiply_shift(u, rng))
+
+
+def pivot_offsets(seed: int, b: int, e: int, w: int) -> np.ndarray:
+    out = np.zeros(9, dtype=np.uint64)
+    lib().vqo_pivot_offsets(seed, b, e, w, _ptr(out))
+    return out
+
+
+def default_depth_limit(n: int) -> int:
+    return int(lib().vqo_default_depth_limit(n))
+
+
+def green16():
+    out = np.zeros(120, dtype=np.uint32)
+    n = lib().vqo_green16(_ptr(out))
+    return [tuple(map(int, out[2 * i:2 * i + 2])) for i in range(n)]
+
+
+def merge_network(length: int):
+    out = np.zeros(length * 32, dtype=np.uint32)
+    n = lib().vqo_merge_network(length, _ptr(out))
+    return [tuple(map(int, out[2 * i:2 * i + 2])) for i in range(n)]
+
+
+def med3_u64(a: int, b: int, c: int, ascending: bool = True) -> int:
+    return int(lib().vqo_med3_u64(a, b, c, int(bool(ascending))))

@@ -1,0 +1,229 @@
+/*
+ * oracle_body.h -- type-generic body of the scalar CPU oracle.
+ *
+ * TEST INFRASTRUCTURE: only tests/, the smoke check and the CPU-baseline leg of
+ * bench.py use the oracle.  It shares no code with the GPU library.
+ *
+ * Included once per key type by vqs_oracle.c with these macros defined:
+ *   KT            the C key type
+ *   SFX(name)     pastes a per-type suffix onto a name
+ *   KLESS(a, b)   the natural strict order of KT (ascending)
+ *   KMAXV, KMINV  the last / first value of KT in ascending order (padding)
+ *   KW            keys per 64-byte sampling chunk (64 / sizeof(KT))
+ *
+ * Every routine follows one step of the paper's method:
+ *   Sec. 2 / Alg. 1    Recurse (partition, degenerate handling, base case, tail calls)
+ *   Sec. 2.1           Partition (keys not after the pivot go left)
+ *   Sec. 2.2           ChoosePivot (nine random 64-byte chunks, medians of three),
+ *                      depth limit 2*log2(n)+4 with Heapsort as the fallback
+ *   Sec. 2.3, Sec. 3   BaseCase (16-row matrix, Green's 16-input column network,
+ *                      bitonic merges of adjacent sorted column groups)
+ *   Sec. 2.4           sort order (ascending / descending) via a single "before" relation
+ */
+
+/* "a is before b" in the requested sort order (Sec. 2.4: OrderAscending /
+ * OrderDescending define Compare; descending is the mirrored relation). */
+static inline int SFX(before)(KT a, KT b, int asc) { return asc ? KLESS(a, b) : KLESS(b, a); }
+
+/* Compare-and-exchange module (Sec. 3): afterwards *a is not after *b. */
+static inline void SFX(cex)(KT* a, KT* b, int asc) {
+    if (SFX(before)(*b, *a, asc)) { KT t = *a; *a = *b; *b = t; }
+}
+
+/* Median of three with the network (0,2) (0,1) (1,2) of Sec. 2.2; element 1 is
+ * the median afterwards. */
+static KT SFX(med3)(KT x0, KT x1, KT x2, int asc) {
+    SFX(cex)(&x0, &x2, asc);
+    SFX(cex)(&x0, &x1, asc);
+    SFX(cex)(&x1, &x2, asc);
+    return x1;
+}
+
+/* ChoosePivot (Sec. 2.2).  Nine chunks of KW keys (64 bytes) are taken at random
+ * chunk-aligned offsets relative to the range start; lanewise medians of three over
+ * chunk groups (0,1,2), (3,4,5), (6,7,8) give 3*KW medians.  These are reduced by
+ * medians of three: first whole "vectors" of KW lanes three at a time, then single
+ * consecutive triples, dropping the 0..2 leftovers, until fewer than three remain.
+ * The first remaining median is the pivot. */
+static KT SFX(choose_pivot)(const KT* keys, uint64_t b, uint64_t e, int asc, uint64_t seed) {
+    const uint64_t W = KW;
+    const uint64_t nchunks = (e - b) / W;      /* whole chunks; the tail is never sampled */
+    uint32_t u[10];
+    uint64_t st[4];
+    seg_rng_state(seed, b, e, st);
+    for (int i = 0; i < 5; i++) {             /* five 64-bit draws -> ten 32-bit halves */
+        uint64_t r = sfc64_next(st);
+        u[2 * i] = (uint32_t)r;
+        u[2 * i + 1] = (uint32_t)(r >> 32);
+    }
+    const KT* chunk[9];
+    for (int i = 0; i < 9; i++) {
+        uint64_t off = multiply_shift_offset(u[i], nchunks);
+        chunk[i] = keys + b + off * W;
+    }
+    KT bufA[3 * KW], bufB[3 * KW];
+    KT* cur = bufA;
+    KT* nxt = bufB;
+    for (uint64_t g = 0; g < 3; g++)
+        for (uint64_t j = 0; j < W; j++)
+            cur[g * W + j] = SFX(med3)(chunk[3 * g][j], chunk[3 * g + 1][j], chunk[3 * g + 2][j], asc);
+    uint64_t m = 3 * W;
+    while (m >= 3) {
+        uint64_t i = 0, o = 0;
+        while (i + 3 * W <= m) {              /* whole vectors, lanewise */
+            for (uint64_t j = 0; j < W; j++)
+                nxt[o++] = SFX(med3)(cur[i + j], cur[i + W + j], cur[i + 2 * W + j], asc);
+            i += 3 * W;
+        }
+        while (i + 3 <= m) {                  /* single elements */
+            nxt[o++] = SFX(med3)(cur[i], cur[i + 1], cur[i + 2], asc);
+            i += 3;
+        }
+        KT* t = cur; cur = nxt; nxt = t;
+        m = o;
+    }
+    return cur[0];
+}
+
+/* Partition (Sec. 2.1): keys not after the pivot move before all others; returns
+ * the index of the first key of the right side.  Written as a plain out-of-place
+ * split: a single scan places left keys from the front in input order and right
+ * keys from the back (so in reverse input order); the buffer is copied back. */
+static uint64_t SFX(partition)(KT* keys, KT* tmp, uint64_t b, uint64_t e, KT pivot, int asc) {
+    uint64_t l = b, r = e;
+    for (uint64_t i = b; i < e; i++) {
+        KT k = keys[i];
+        if (!SFX(before)(pivot, k, asc)) tmp[l++] = k;
+        else tmp[--r] = k;
+    }
+    memcpy(keys + b, tmp + b, (e - b) * sizeof(KT));
+    return l;
+}
+
+/* ScanMinMax (Alg. 1): first and last key of the range in sort order. */
+static void SFX(minmax)(const KT* keys, uint64_t b, uint64_t e, int asc, KT* first, KT* last) {
+    KT f = keys[b], l = keys[b];
+    for (uint64_t i = b + 1; i < e; i++) {
+        if (SFX(before)(keys[i], f, asc)) f = keys[i];
+        if (SFX(before)(l, keys[i], asc)) l = keys[i];
+    }
+    *first = f;
+    *last = l;
+}
+
+/* Textbook Heapsort (the depth-limit fallback of Sec. 2.2). */
+static void SFX(sift_down)(KT* a, uint64_t i, uint64_t n, int asc) {
+    for (;;) {
+        uint64_t c = 2 * i + 1;
+        if (c >= n) return;
+        if (c + 1 < n && SFX(before)(a[c], a[c + 1], asc)) c++;
+        if (!SFX(before)(a[i], a[c], asc)) return;
+        KT t = a[i]; a[i] = a[c]; a[c] = t;
+        i = c;
+    }
+}
+
+static void SFX(heapsort)(KT* a, uint64_t n, int asc) {
+    if (n < 2) return;
+    for (uint64_t i = n / 2; i-- > 0;) SFX(sift_down)(a, i, n, asc);
+    for (uint64_t end = n - 1; end > 0; end--) {
+        KT t = a[0]; a[0] = a[end]; a[end] = t;
+        SFX(sift_down)(a, 0, end, asc);
+    }
+}
+
+/* BaseCase (Sec. 2.3 and Sec. 3).  The n <= 16*c keys are copied into a buffer
+ * viewed as a row-major matrix of 16 rows and c columns (c the smallest power of
+ * two with 16*c >= n), padded with the last value in sort order so the padding
+ * stays in place.  Each column is sorted with Green's 60-module network; then
+ * adjacent sorted groups of w columns are merged into groups of 2w columns with
+ * the bitonic merge network (flip stage, then half-cleaners) until one group
+ * remains.  A group's sorted sequence is its elements in row-major order, so the
+ * final group is the whole buffer in order. */
+static void SFX(basecase)(KT* keys, uint64_t n, int asc) {
+    if (n < 2) return;
+    uint64_t c = 1;
+    while (16 * c < n) c *= 2;
+    const uint64_t cells = 16 * c;
+    KT* buf = (KT*)malloc(cells * sizeof(KT));
+    KT* seq = (KT*)malloc(cells * sizeof(KT));
+    memcpy(buf, keys, n * sizeof(KT));
+    const KT last = asc ? KMAXV : KMINV;
+    for (uint64_t i = n; i < cells; i++) buf[i] = last;
+
+    for (uint64_t j = 0; j < c; j++)
+        for (int m = 0; m < GREEN16_MODULES; m++)
+            SFX(cex)(&buf[(uint64_t)GREEN16[m][0] * c + j], &buf[(uint64_t)GREEN16[m][1] * c + j], asc);
+
+    for (uint64_t w = 1; w < c; w *= 2) {
+        const uint64_t L = 16 * w;                 /* keys per input group */
+        int npairs = 0;
+        const uint32_t(*net)[2] = merge_network(2 * L, &npairs);
+        for (uint64_t g0 = 0; g0 < c; g0 += 2 * w) {
+            for (uint64_t k = 0; k < L; k++) {
+                seq[k] = buf[(k / w) * c + g0 + k % w];
+                seq[L + k] = buf[(k / w) * c + g0 + w + k % w];
+            }
+            for (int m = 0; m < npairs; m++) SFX(cex)(&seq[net[m][0]], &seq[net[m][1]], asc);
+            for (uint64_t k = 0; k < 2 * L; k++) buf[(k / (2 * w)) * c + g0 + k % (2 * w)] = seq[k];
+        }
+    }
+    memcpy(keys, buf, n * sizeof(KT));
+    free(buf);
+    free(seq);
+}
+
+/* Recurse (Alg. 1).  depth counts nested Recurse calls (the first call is 1); a
+ * call deeper than the limit Heapsorts its range instead. */
+static void SFX(recurse)(KT* keys, KT* tmp, uint64_t b, uint64_t e, KT pivot, uint64_t depth,
+                         const vqo_params* p, vqo_stats* st) {
+    if (depth > st->depth_limit_used) {
+        SFX(heapsort)(keys + b, e - b, p->ascending);
+        st->heapsorts++;
+        st->heapsort_keys += e - b;
+        return;
+    }
+    if (depth > st->max_depth) st->max_depth = depth;
+    const uint64_t bound = SFX(partition)(keys, tmp, b, e, pivot, p->ascending);
+    st->partitions++;
+    st->keys_partitioned += e - b;
+    if (bound == e) {                               /* degenerate: right side empty */
+        KT first, last;
+        st->degenerate++;
+        SFX(minmax)(keys, b, e, p->ascending, &first, &last);
+        if (!SFX(before)(first, last, p->ascending)) {  /* all keys equal */
+            st->all_equal++;
+            return;
+        }
+        SFX(recurse)(keys, tmp, b, e, first, depth + 1, p, st);
+        return;
+    }
+    if (bound - b <= p->nb) {
+        SFX(basecase)(keys + b, bound - b, p->ascending);
+        st->basecases++;
+    } else {
+        KT next = SFX(choose_pivot)(keys, b, bound, p->ascending, p->seed);
+        SFX(recurse)(keys, tmp, b, bound, next, depth + 1, p, st);
+    }
+    if (e - bound <= p->nb) {
+        SFX(basecase)(keys + bound, e - bound, p->ascending);
+        st->basecases++;
+    } else {
+        KT next = SFX(choose_pivot)(keys, bound, e, p->ascending, p->seed);
+        SFX(recurse)(keys, tmp, bound, e, next, depth + 1, p, st);
+    }
+}
+
+/* Sort the range [b, e) of keys (positions are absolute, they seed the sampler). */
+static void SFX(sort_range)(KT* keys, KT* tmp, uint64_t b, uint64_t e, const vqo_params* p,
+                            vqo_stats* st) {
+    const uint64_t n = e - b;
+    if (n <= p->nb) {
+        SFX(basecase)(keys + b, n, p->ascending);
+        if (n > 0) st->basecases++;
+        return;
+    }
+    st->depth_limit_used = p->depth_limit >= 0 ? (uint64_t)p->depth_limit : default_depth_limit(n);
+    KT pivot = SFX(choose_pivot)(keys, b, e, p->ascending, p->seed);
+    SFX(recurse)(keys, tmp, b, e, pivot, 1, p, st);
+}

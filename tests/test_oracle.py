@@ -1,0 +1,459 @@
+"""Pins of the CPU oracle against facts the paper and mathematics fix.
+
+Each test checks the oracle against something other than itself: library sorts
+(np.sort, Python's sorted on ints), numpy's SFC64, exhaustive 0-1 inputs, closed
+forms, special cases and the paper's worked examples (tests/golden/).
+"""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2205_05982_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+TYPES = [oracle.U16, oracle.U32, oracle.U64, oracle.U128, oracle.F32, oracle.F64]
+
+
+def _read_pairs(name):
+    out = []
+    for line in open(os.path.join(GOLDEN, name)):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            a, b = line.split()
+            out.append((int(a), int(b)))
+    return out
+
+
+def _random_keys(kt, n, seed):
+    rng = np.random.default_rng(seed)
+    if kt == oracle.U16:
+        return rng.integers(0, 2**16, n, dtype=np.uint16)
+    if kt == oracle.U32:
+        return rng.integers(0, 2**32, n, dtype=np.uint32)
+    if kt == oracle.U64:
+        return rng.integers(0, 2**64, n, dtype=np.uint64)
+    if kt == oracle.U128:
+        k = np.empty((n, 2), np.uint64)
+        k[:, 0] = rng.integers(0, 2**64, n, dtype=np.uint64)
+        k[:, 1] = rng.integers(0, 4, n, dtype=np.uint64)   # many equal high words
+        return k
+    if kt == oracle.F32:
+        a = rng.standard_normal(n, dtype=np.float32) * 1e3
+        a[a == 0] = 0.0
+        return a
+    a = rng.standard_normal(n) * 1e-3
+    a[a == 0] = 0.0
+    return a
+
+
+def _expected(keys, kt, asc):
+    if kt == oracle.U128:
+        ints = sorted(((int(h) << 64) | int(l) for l, h in keys), reverse=not asc)
+        return np.array([[v & (2**64 - 1), v >> 64] for v in ints], dtype=np.uint64).reshape(-1, 2)
+    s = np.sort(keys, kind="stable")
+    return s if asc else s[::-1].copy()
+
+
+# ---- final output: the plain definition -------------------------------------------
+
+@pytest.mark.parametrize("kt", TYPES)
+@pytest.mark.parametrize("asc", [True, False])
+@pytest.mark.parametrize("n", [0, 1, 2, 17, 255, 256, 257, 1000, 4096, 50_000])
+def test_sort_equals_library_sort(kt, asc, n):
+    keys = _random_keys(kt, n, seed=1000 + n + kt)
+    got = keys.copy()
+    oracle.sort(got, kt, ascending=asc, seed=7)
+    np.testing.assert_array_equal(got, _expected(keys, kt, asc))
+
+
+@pytest.mark.parametrize("dist", W.C2_DISTRIBUTIONS)
+def test_sort_c2_distributions_small(dist):
+    keys = W.c2(dist, 200_000)
+    got = keys.copy()
+    st = oracle.sort(got, oracle.U64, seed=3, stats=True)
+    np.testing.assert_array_equal(got, np.sort(keys))
+    if dist == "zipf":
+        # A heavy value that is the maximum of its range makes the partition
+        # degenerate; the paper's rule (pivot := first key in sort order) then peels
+        # one distinct value per re-partition, so such ranges reach the depth limit.
+        assert st["heapsorts"] > 0 and st["degenerate"] > 0
+    else:
+        assert st["heapsorts"] == 0      # random sampling is not fooled by these inputs
+
+
+def test_c1_uniform_u32_full_size():
+    keys = W.uniform_u32(1_000_000, 1)
+    got = keys.copy()
+    oracle.sort(got, oracle.U32, seed=0)
+    np.testing.assert_array_equal(got, np.sort(keys))
+
+
+def test_descending_is_reverse_of_ascending():
+    keys = W.zipf_u64(100_000, 3)
+    a, d = keys.copy(), keys.copy()
+    oracle.sort(a, oracle.U64, True)
+    oracle.sort(d, oracle.U64, False)
+    np.testing.assert_array_equal(d, a[::-1])
+
+
+def test_u16_counts_match_counting_sort():
+    keys = W.uniform_u16(300_000, 10)
+    got = keys.copy()
+    oracle.sort(got, oracle.U16)
+    counts = np.bincount(keys, minlength=65536)
+    np.testing.assert_array_equal(got, np.repeat(np.arange(65536, dtype=np.uint16), counts))
+
+
+def test_segmented_sorts_each_segment():
+    off = W.segment_offsets(300, seed=12, lo=16, hi=5000)
+    keys = W.uniform_u32(int(off[-1]), 13)
+    got = keys.copy()
+    oracle.sort_segmented(got, off, oracle.U32)
+    for i in range(off.size - 1):
+        np.testing.assert_array_equal(got[off[i]:off[i + 1]], np.sort(keys[off[i]:off[i + 1]]))
+
+
+# ---- networks: 0-1 principle and the paper's worked examples -------------------------
+
+def _zero_one_sorts(net, n):
+    x = ((np.arange(1 << n, dtype=np.int64)[:, None] >> np.arange(n)[None, :]) & 1).astype(np.uint8)
+    for a, b in net:
+        lo = np.minimum(x[:, a], x[:, b])
+        x[:, b] = np.maximum(x[:, a], x[:, b])
+        x[:, a] = lo
+    return bool((np.diff(x.astype(np.int8), axis=1) >= 0).all())
+
+
+def test_green16_is_a_60_module_sorting_network():
+    net = oracle.green16()
+    assert len(net) == 60                       # Sec. 3: Green's network, 60 modules
+    assert all(0 <= a < b < 16 for a, b in net)
+    assert _zero_one_sorts(net, 16)             # all 2^16 0-1 inputs
+    # ten layers: greedy layering of the listed order
+    layers, used = 1, set()
+    for a, b in net:
+        if a in used or b in used:
+            layers, used = layers + 1, set()
+        used |= {a, b}
+    assert layers == 10
+
+
+def test_green16_is_minimal_sized_against_a_dropped_module():
+    net = oracle.green16()
+    for drop in range(len(net)):
+        assert not _zero_one_sorts(net[:drop] + net[drop + 1:], 16)
+
+
+def test_merge8_equals_fig2():
+    fig2 = [(a - 1, b - 1) for a, b in _read_pairs("fig2_merge8.txt")]
+    assert oracle.merge_network(8) == fig2
+
+
+@pytest.mark.parametrize("length", [8, 16, 32, 64, 128, 256])
+def test_merge_network_merges_all_sorted_zero_one_pairs(length):
+    net = np.array(oracle.merge_network(length), dtype=np.int64)
+    half = length // 2
+    # 0-1 principle for merging networks: every pair of sorted 0-1 halves
+    rows = []
+    for z1 in range(half + 1):
+        for z2 in range(half + 1):
+            rows.append(np.r_[np.zeros(z1), np.ones(half - z1), np.zeros(z2), np.ones(half - z2)])
+    x = np.array(rows, dtype=np.uint8)
+    for a, b in net:
+        lo = np.minimum(x[:, a], x[:, b])
+        x[:, b] = np.maximum(x[:, a], x[:, b])
+        x[:, a] = lo
+    assert (np.diff(x.astype(np.int8), axis=1) >= 0).all()
+    assert len(net) == half * int(math.log2(length))
+
+
+def test_med3_network_fixture_and_exhaustive():
+    assert _read_pairs("med3_network.txt") == [(0, 2), (0, 1), (1, 2)]
+    for a, b, c in itertools.product(range(3), repeat=3):
+        assert oracle.med3_u64(a, b, c, True) == sorted((a, b, c))[1]
+        assert oracle.med3_u64(a, b, c, False) == sorted((a, b, c))[1]
+
+
+@pytest.mark.parametrize("n", list(range(1, 21)))
+def test_basecase_all_zero_one_inputs(n):
+    # every 0-1 input of length n, each sorted by BaseCase (segments of n <= nb keys)
+    m = 1 << n
+    keys = ((np.arange(m, dtype=np.uint64)[:, None] >> np.arange(n, dtype=np.uint64)[None, :]) & 1)
+    keys = np.ascontiguousarray(keys.astype(np.uint32).reshape(-1))
+    off = np.arange(m + 1, dtype=np.int64) * n
+    st = oracle.sort_segmented(keys, off, oracle.U32, nb=256, stats=True)
+    rows = keys.reshape(m, n)
+    assert (np.diff(rows.astype(np.int64), axis=1) >= 0).all()
+    assert (rows.sum(axis=1) == np.array([bin(i).count("1") for i in range(m)])).all()
+    assert st["partitions"] == 0 and st["basecases"] == m
+
+
+@pytest.mark.parametrize("n", [2, 3, 5, 8, 9])
+def test_basecase_all_permutations(n):
+    perms = np.array(list(itertools.permutations(range(n))), dtype=np.uint64)
+    keys = np.ascontiguousarray(perms.reshape(-1))
+    off = np.arange(perms.shape[0] + 1, dtype=np.int64) * n
+    oracle.sort_segmented(keys, off, oracle.U64, nb=256)
+    assert (keys.reshape(-1, n) == np.arange(n, dtype=np.uint64)).all()
+
+
+@pytest.mark.parametrize("kt", TYPES)
+@pytest.mark.parametrize("asc", [True, False])
+def test_basecase_every_size_with_padding(kt, asc):
+    for n in range(0, 257):
+        keys = _random_keys(kt, n, seed=n)
+        got = keys.copy()
+        oracle.basecase(got, kt, asc)
+        np.testing.assert_array_equal(got, _expected(keys, kt, asc))
+
+
+def test_basecase_with_extreme_keys_keeps_padding_out():
+    # keys equal to the padding value must not be confused with padding
+    keys = np.array([2**64 - 1, 0, 2**64 - 1, 5, 7] * 20, dtype=np.uint64)
+    got = keys.copy()
+    oracle.basecase(got, oracle.U64, True)
+    np.testing.assert_array_equal(got, np.sort(keys))
+    got = keys.copy()
+    oracle.basecase(got, oracle.U64, False)
+    np.testing.assert_array_equal(got, np.sort(keys)[::-1])
+
+
+# ---- random numbers and sampling -----------------------------------------------------
+
+def test_sfc64_matches_numpy():
+    for state in ([1, 2, 3, 4], [0xDEADBEEF, 2**63 + 5, 12345678901234567, 1],
+                  [2**64 - 1, 2**64 - 1, 2**64 - 1, 2**64 - 1]):
+        bg = np.random.SFC64()
+        bg.state = {"bit_generator": "SFC64",
+                    "state": {"state": np.array(state, dtype=np.uint64)},
+                    "has_uint32": 0, "uinteger": 0}
+        np.testing.assert_array_equal(oracle.sfc64_raw(state, 1000), bg.random_raw(1000))
+
+
+def test_splitmix64_known_answers():
+    # Published reference outputs of SplitMix64 started from state 0.
+    assert oracle.splitmix64(0, 3) == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+def test_multiply_shift_offsets_closed_form():
+    for rng_ in (1, 3, 7, 1000, 2**24, 2**31 + 11, 2**32 - 1):
+        for v in sorted({0, 1, rng_ // 2, rng_ - 1} & set(range(rng_)) if rng_ < 8 else {0, 1, rng_ // 2, rng_ - 1}):
+            lo = -((-v << 32) // rng_)               # ceil(v * 2^32 / range): first draw giving v
+            assert oracle.multiply_shift(lo, rng_) == v
+            if lo > 0:
+                assert oracle.multiply_shift(lo - 1, rng_) == v - 1
+        assert oracle.multiply_shift(2**32 - 1, rng_) == rng_ - 1
+    # bias: each value is hit floor or ceil of 2^32/range times; relative spread < range/2^32
+    r = 2**24
+    counts = {}
+    for v in (0, 5, r - 1):
+        first = -((-v << 32) // r)
+        nxt = -((-(v + 1) << 32) // r)
+        counts[v] = nxt - first
+    assert set(counts.values()) <= {2**32 // r, 2**32 // r + 1}
+
+
+def _pivot_independent(keys, b, e, w, seed, asc=True):
+    """ChoosePivot recomputed from the description of Sec. 2.2 with numpy's SFC64
+    for the draws and numpy sorts for the medians."""
+    bg = np.random.SFC64()
+    bg.state = {"bit_generator": "SFC64", "state": {"state": oracle.seg_rng_state(seed, b, e)},
+                "has_uint32": 0, "uinteger": 0}
+    draws = bg.random_raw(5)
+    halves = []
+    for d in draws.tolist():
+        halves += [d & 0xFFFFFFFF, d >> 32]
+    nch = (e - b) // w
+    offs = [(u * nch) >> 32 for u in halves[:9]]
+    chunks = np.array([keys[b + o * w: b + o * w + w] for o in offs])
+    med = lambda x, y, z: np.sort(np.stack([x, y, z]), axis=0)[1]
+    cur = np.concatenate([med(chunks[3 * g], chunks[3 * g + 1], chunks[3 * g + 2]) for g in range(3)])
+    while cur.size >= 3:
+        out, i = [], 0
+        while i + 3 * w <= cur.size:
+            out.append(med(cur[i:i + w], cur[i + w:i + 2 * w], cur[i + 2 * w:i + 3 * w]))
+            i += 3 * w
+        while i + 3 <= cur.size:
+            out.append(med(cur[i:i + 1], cur[i + 1:i + 2], cur[i + 2:i + 3]))
+            i += 3
+        cur = np.concatenate(out)
+    return cur[0]
+
+
+@pytest.mark.parametrize("kt,w", [(oracle.U16, 32), (oracle.U32, 16), (oracle.U64, 8), (oracle.F64, 8)])
+def test_choose_pivot_matches_independent_recomputation(kt, w):
+    keys = _random_keys(kt, 20_000, seed=kt)
+    for b, e in [(0, 20_000), (100, 5_000), (3, 3 + 9 * w), (777, 20_000)]:
+        for seed in (0, 1, 2**40 + 3):
+            p = oracle.choose_pivot(keys, b, e, kt, True, seed)
+            assert p == _pivot_independent(keys, b, e, w, seed)
+            assert p in keys[b:e]
+
+
+def test_pivot_median_counts_per_type():
+    # 3W medians, then W, then scalar triples: u64 24 -> 8 -> 2, u32 48 -> 16 -> 5 -> 1,
+    # u16 96 -> 32 -> 10 -> 3 -> 1, u128 12 -> 4 -> 1 (reduction rule of Sec. 2.2).
+    def rounds(w):
+        m, seq = 3 * w, [3 * w]
+        while m >= 3:
+            nv = m // (3 * w)
+            m = nv * w + (m - nv * 3 * w) // 3
+            seq.append(m)
+        return seq
+    assert rounds(8) == [24, 8, 2]
+    assert rounds(16) == [48, 16, 5, 1]
+    assert rounds(32) == [96, 32, 10, 3, 1]
+    assert rounds(4) == [12, 4, 1]
+
+
+def test_pivot_is_central_on_uniform_data():
+    keys = W.uniform_u64(1_000_000, 2)
+    ranks = []
+    srt = np.sort(keys)
+    for s in range(200):
+        p = oracle.choose_pivot(keys, 0, keys.size, oracle.U64, True, s)
+        ranks.append(np.searchsorted(srt, p) / keys.size)
+    ranks = np.array(ranks)
+    assert abs(np.median(ranks) - 0.5) < 0.05
+    assert ranks.min() > 0.15 and ranks.max() < 0.85
+
+
+def test_pivot_of_constant_range_is_the_constant():
+    keys = np.full(1000, 42, dtype=np.uint32)
+    assert oracle.choose_pivot(keys, 0, 1000, oracle.U32, True, 5) == 42
+
+
+def test_pivot_sorted_range_descending_order():
+    keys = np.arange(10_000, dtype=np.uint64)
+    pa = oracle.choose_pivot(keys, 0, 10_000, oracle.U64, True, 9)
+    pd = oracle.choose_pivot(keys, 0, 10_000, oracle.U64, False, 9)
+    assert pa == pd            # the median of three does not depend on the direction
+
+
+# ---- partition, degenerate path, depth limit -------------------------------------------
+
+@pytest.mark.parametrize("kt", TYPES)
+def test_partition_bound_and_sides(kt):
+    keys = _random_keys(kt, 5000, seed=3 + kt)
+    for asc in (True, False):
+        k = keys.copy()
+        b, e = 123, 4321
+        piv = keys[2000]
+        bound = oracle.partition(k, b, e, piv, kt, asc)
+        seg = keys[b:e]
+        if kt == oracle.U128:
+            ints = [(int(h) << 64) | int(l) for l, h in seg]
+            pv = (int(piv[1]) << 64) | int(piv[0])
+            isleft = np.array([(v <= pv) if asc else (v >= pv) for v in ints])
+        else:
+            isleft = (seg <= piv) if asc else (seg >= piv)
+        assert bound == b + int(isleft.sum())
+        np.testing.assert_array_equal(k[b:bound], seg[isleft])          # left: input order
+        np.testing.assert_array_equal(k[bound:e], seg[~isleft][::-1])   # right: reverse order
+        np.testing.assert_array_equal(k[:b], keys[:b])
+        np.testing.assert_array_equal(k[e:], keys[e:])
+
+
+def test_all_equal_input_takes_degenerate_path_once():
+    keys = np.full(100_000, 7, dtype=np.uint64)
+    st = oracle.sort(keys, oracle.U64, stats=True)
+    assert st == {**st, "partitions": 1, "degenerate": 1, "all_equal": 1, "basecases": 0}
+    assert (keys == 7).all()
+
+
+def test_two_value_input_repartitions_with_first_key():
+    keys = np.array([5] * 30_000 + [9] * 70_000, dtype=np.uint32)
+    np.random.default_rng(0).shuffle(keys)
+    for asc in (True, False):
+        k = keys.copy()
+        st = oracle.sort(k, oracle.U32, ascending=asc, stats=True)
+        np.testing.assert_array_equal(k, np.sort(keys) if asc else np.sort(keys)[::-1])
+        assert st["all_equal"] == 2            # each value ends in one all-equal range
+        assert st["degenerate"] >= 2
+
+
+def test_minmax_first_last():
+    keys = W.normal_f32(10_000, 7)
+    f, l = oracle.minmax(keys, 10, 9000, oracle.F32, True)
+    assert f == keys[10:9000].min() and l == keys[10:9000].max()
+    f, l = oracle.minmax(keys, 10, 9000, oracle.F32, False)
+    assert f == keys[10:9000].max() and l == keys[10:9000].min()
+
+
+def test_depth_limit_formula():
+    for n in (257, 1000, 2**20, 10**8, 2**33 + 1):
+        assert oracle.default_depth_limit(n) == 2 * int(math.floor(math.log2(n))) + 4
+    assert oracle.default_depth_limit(2**20) == 44
+
+
+@pytest.mark.parametrize("limit", [0, 1, 3])
+def test_forced_depth_limit_falls_back_to_heapsort(limit):
+    keys = W.uniform_u64(50_000, 2)
+    got = keys.copy()
+    st = oracle.sort(got, oracle.U64, depth_limit=limit, stats=True)
+    np.testing.assert_array_equal(got, np.sort(keys))
+    assert st["heapsorts"] >= 1
+    assert st["max_depth"] <= limit
+
+
+def test_heapsort_matches_library_sort():
+    for kt in TYPES:
+        keys = _random_keys(kt, 3000, seed=kt)
+        got = keys.copy()
+        oracle.heapsort(got, kt, True)
+        np.testing.assert_array_equal(got, _expected(keys, kt, True))
+
+
+def test_planted_partition_mistake_is_caught():
+    # A plausible mistake (strict '<' instead of 'not after') changes the bound on
+    # a range with keys equal to the pivot; the closed form above catches it.
+    keys = np.array([3, 1, 3, 2, 3], dtype=np.uint32)
+    k = keys.copy()
+    assert oracle.partition(k, 0, 5, 3, oracle.U32, True) == 5
+    assert int((keys < 3).sum()) != 5
+
+
+# ---- adversarial generator self-check ---------------------------------------------------
+
+def _textbook_m3_quicksort_depth(a):
+    a = list(a)
+    maxd = 0
+    stack = [(0, len(a), 1)]
+    while stack:
+        lo, hi, d = stack.pop()
+        while hi - lo > 16:
+            maxd = max(maxd, d)
+            mid = lo + (hi - lo) // 2
+            p = sorted((a[lo], a[mid], a[hi - 1]))[1]
+            i, j = lo, hi
+            while True:
+                while a[i] < p:
+                    i += 1
+                j -= 1
+                while p < a[j]:
+                    j -= 1
+                if not i < j:
+                    break
+                a[i], a[j] = a[j], a[i]
+                i += 1
+            stack.append((i, hi, d + 1))
+            hi, d = i, d + 1
+    return maxd
+
+
+def test_median3_killer_drives_textbook_quicksort_linear():
+    n = 4000
+    k = W.median3_killer_u64(n)
+    assert sorted(k.tolist()) == list(range(1, n + 1))
+    assert _textbook_m3_quicksort_depth(k.tolist()) > n // 8
+    rnd = np.random.default_rng(0).permutation(n) + 1
+    assert _textbook_m3_quicksort_depth(rnd.tolist()) < 40
+    # the paper's random chunk sampling is not fooled: no Heapsort fallback
+    got = W.median3_killer_u64(200_000)
+    st = oracle.sort(got, oracle.U64, stats=True)
+    assert st["heapsorts"] == 0 and st["max_depth"] < 40
+    assert (got == np.arange(1, 200_001, dtype=np.uint64)).all()
