@@ -1,0 +1,193 @@
+"""Benchmark: the vectorized Quicksort on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--n N]
+
+A step is one complete sort (every level of partitions, the per-workgroup finish
+and the in-LDS base cases) of one array of synthetic keys.  Every timed step sorts
+its own pre-staged copy of the input, so all inputs are resident in HBM when the
+timed region starts and nothing but sorting is timed.  Prints one JSON line.
+
+Roofline: the dominant kernel is the device-wide partition (level kernel).  Its
+algorithmic traffic per launch is 2 * keys * key_size bytes (each key of the level
+read once and written once); HIP events around every launch on the library's
+stream give the durations.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "Gkeys/s & % of HBM roofline, 1e8 u64 sort; learned-splitter vs plain"
+
+WORKLOADS = {
+    # name: (key type, default n, generator, description)
+    "c2_uniform": (3, 100_000_000, "uniform", "1e8 u64 uniform over [0, 2^64), seed 2, ascending"),
+    "c2_zipf": (3, 100_000_000, "zipf", "1e8 u64 Zipf(1.0) over 2^20 values, seed 3"),
+    "c2_8distinct": (3, 100_000_000, "8distinct", "1e8 u64, 8 distinct values, seed 4"),
+    "c2_sorted": (3, 100_000_000, "sorted", "1e8 u64 uniform, sorted"),
+    "c2_reverse": (3, 100_000_000, "reverse", "1e8 u64 uniform, reverse sorted"),
+    "c2_almost": (3, 100_000_000, "almost", "1e8 u64 sorted + 1% random pair swaps"),
+    "c2_m3killer": (3, 100_000_000, "m3killer", "1e8 u64 median-of-3 killer permutation"),
+    "c1_u32": (2, 1_000_000, None, "1e6 u32 uniform, seed 1"),
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2_uniform", choices=sorted(WORKLOADS))
+    ap.add_argument("--n", type=int, default=0, help="override the key count")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=20_000_000)
+    ap.add_argument("--profile-json", default="", help="write per-launch kernel times here")
+    return ap.parse_args()
+
+
+def make_input(name: str, n: int) -> np.ndarray:
+    from paper_2205_05982_amd import workloads as W
+    kt, _, dist, _ = WORKLOADS[name]
+    if name == "c1_u32":
+        return W.uniform_u32(n, 1)
+    return W.c2(dist, n)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2205_05982_amd import vqs
+
+    kt, n_default, _, desc = WORKLOADS[args.workload]
+    n = args.n or n_default
+    ks = vqs.KEY_SIZE[kt]
+    dev = torch.device("cuda", 0)
+    t0 = time.time()
+    host = make_input(args.workload, n)
+    print(f"# input {args.workload} n={n} generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    src = torch.from_numpy(host).to(dev)
+    nbuf = args.steps + args.warmup
+    bufs = [torch.empty_like(src) for _ in range(nbuf)]
+    for b in bufs:
+        b.copy_(src)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+
+    # warmup (also allocates the library workspace)
+    for i in range(args.warmup):
+        vqs.sort(bufs[i], key_type=kt)
+    torch.cuda.synchronize()
+    err = vqs.last_error_bits()
+    if err:
+        raise RuntimeError(f"device error bits {err:#x}")
+    print(f"# warmup done", file=sys.stderr, flush=True)
+
+    vqs.profile(True)
+    vqs.profile_read()            # drop records of the warmup
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for i in range(args.steps):
+        vqs.sort(bufs[args.warmup + i], key_type=kt)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(stop)
+    recs = vqs.profile_read()
+    vqs.profile(False)
+    stats = vqs.get_stats()
+    err = vqs.last_error_bits()
+    if err:
+        raise RuntimeError(f"device error bits {err:#x}")
+    ms_step = total_ms / args.steps
+    gkeys = n / (ms_step * 1e-3) / 1e9
+    print(f"# timed {args.steps} steps: {ms_step:.3f} ms/step", file=sys.stderr, flush=True)
+
+    # correctness of the last output: sorted, same multiset as the input
+    out = bufs[-1]
+    sgn = torch.tensor(-(2**63), dtype=torch.int64, device=dev) if ks == 8 else None
+    o64 = out.view(torch.int64) if ks == 8 else out.to(torch.int64)
+    i64 = src.view(torch.int64) if ks == 8 else src.to(torch.int64)
+    if ks == 8:
+        o_s = o64 ^ sgn
+    else:
+        o_s = o64
+    sorted_ok = bool((o_s[1:] >= o_s[:-1]).all().item())
+    sum_ok = bool((o64.sum() == i64.sum()).item()) and bool(((o64 * o64).sum() == (i64 * i64).sum()).item())
+    if not (sorted_ok and sum_ok):
+        raise RuntimeError(f"bench output check failed: sorted={sorted_ok} multiset={sum_ok}")
+
+    # roofline of the dominant kernel: the level (device-wide partition) kernel
+    lv = [r for r in recs if r["kind"] == "level_partition" and r["keys"] > 0]
+    solo = [r for r in recs if r["kind"] == "solo"]
+    lv_bytes = sum(2 * r["keys"] * ks for r in lv)
+    lv_ms = sum(r["ms"] for r in lv)
+    achieved = lv_bytes / (lv_ms * 1e-3) / 1e9 if lv_ms > 0 else 0.0
+    levels_per_step = len(lv) / args.steps
+    solo_ms = sum(r["ms"] for r in solo) / max(args.steps, 1)
+    all_ms = sum(r["ms"] for r in recs) / max(args.steps, 1)
+    passes = stats["keys_partitioned"] / n + 1.0     # partitions + the final local-sort pass
+    e2e_frac = (passes * 2 * n * ks / (ms_step * 1e-3) / 1e9) / HBM_PEAK_GBS
+    if args.profile_json:
+        with open(args.profile_json, "w") as f:
+            json.dump({"records": recs, "stats": stats}, f, indent=1)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        m = min(args.cpu_sample, n)
+        sample = host[:m].copy()
+        t0 = time.perf_counter()
+        oracle.sort(sample, kt)
+        dt = time.perf_counter() - t0
+        cpu = {"value": m / dt / 1e9, "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {m} keys of the same input, scalar C oracle, one thread, {dt:.1f} s"}
+
+    line = {
+        "metric": METRIC,
+        "value": round(gkeys, 4),
+        "unit": "Gkeys/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {2: "u32", 3: "u64"}.get(kt, str(kt)),
+        "data": "synthetic",
+        "config": {"workload": desc, "n": n, "method": "plain", "key_bytes": ks},
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "level_kernel (device-wide partition)",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "launches_per_step": round(levels_per_step, 2),
+            "level_ms_per_step": round(lv_ms / args.steps, 4),
+            "solo_ms_per_step": round(solo_ms, 4),
+            "kernels_ms_per_step": round(all_ms, 4),
+            "passes": round(passes, 3),
+            "end_to_end_frac": round(e2e_frac, 4),
+        },
+        "stats": {k: stats[k] for k in ("partitions", "degenerate", "basecases", "fallbacks", "max_depth",
+                                       "levels", "solo_items")},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

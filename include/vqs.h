@@ -1,0 +1,170 @@
+/*
+ * vqs.h -- C interface of the MI355X (gfx950) vectorized Quicksort library.
+ *
+ * The method is the Quicksort of Blacher, Giesen, Sanders and Wassenberg,
+ * "Vectorized and performance-portable Quicksort" (2022): Alg. 1 (recursion with
+ * degenerate-partition handling), Sec. 2.1 (Partition: keys not after the pivot
+ * move before the others), Sec. 2.2 (ChoosePivot from nine random 64-byte chunks by
+ * medians of three; recursion depth limit 2*log2(n)+4 with a bounded-time fallback),
+ * Sec. 2.3 and Sec. 3 (BaseCase: 16-row sorting network, Green's column network and
+ * transposition-free bitonic merges) and Sec. 2.4 (ascending / descending order,
+ * 128-bit keys as pairs of 64-bit halves).
+ *
+ * Conventions for every entry point:
+ *  - keys and offsets are DEVICE pointers owned by the caller (e.g. a torch
+ *    tensor's data_ptr()).  Sorting is in place: on return keys holds the result.
+ *  - n counts keys, not bytes or words.  keys must be aligned to the key size
+ *    (16 bytes for VQS_U128).
+ *  - VQS_U128 keys are 16 bytes each, little-endian: the low 64-bit word at byte 0,
+ *    the high word at byte 8; they compare as (high, low) lexicographically (Alg. 2).
+ *  - Floating-point keys are ordered by the total order of their bit patterns:
+ *    -NaN < -inf < ... < -0.0 < +0.0 < ... < +inf < +NaN.  For inputs without NaN
+ *    and without -0.0 this is the IEEE order, and the result is unique.
+ *  - Calls are asynchronous on `stream` (a hipStream_t; NULL is the default
+ *    stream).  Argument errors return at once without launching anything.  The
+ *    library keeps a scratch workspace of n keys plus bookkeeping per stream,
+ *    allocated on first use and reused; calls on distinct streams are thread safe.
+ *    If the workspace cannot be allocated, VQS_ENOMEM is returned and keys is
+ *    untouched.
+ *  - Sorting is not stable (Sec. 5): equal keys are bit-identical here, so the
+ *    output is the unique sorted rearrangement of the input.
+ */
+#ifndef VQS_H
+#define VQS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Key types. */
+enum vqs_key_type {
+    VQS_U16 = 1,
+    VQS_U32 = 2,
+    VQS_U64 = 3,
+    VQS_U128 = 4,
+    VQS_F32 = 5,
+    VQS_F64 = 6
+};
+
+/* Return codes: 0 on success, negative on failure. */
+enum vqs_status {
+    VQS_OK = 0,
+    VQS_EINVAL = -1,     /* bad argument (null pointer, misaligned keys, bad option) */
+    VQS_ETYPE = -2,      /* unknown key type */
+    VQS_ENOMEM = -3,     /* workspace allocation failed */
+    VQS_EHIP = -4,       /* a HIP runtime call failed */
+    VQS_EOFFSETS = -5,   /* offsets decrease (checked only with options.validate) */
+    VQS_EINTERNAL = -6   /* a device-side capacity check failed (see vqs_last_error_bits) */
+};
+
+/* Method selector of vqs_options.method. */
+enum vqs_method {
+    VQS_METHOD_PLAIN = 0,    /* the paper's Quicksort */
+    VQS_METHOD_LEARNED = 1   /* learned 256-bucket splitter first, then the plain method */
+};
+
+/* Options of the extended entry points.  Zero-initialise and set struct_size;
+ * every zero field selects the default. */
+typedef struct vqs_options {
+    uint32_t struct_size;       /* sizeof(vqs_options) */
+    uint32_t method;            /* enum vqs_method */
+    uint64_t seed;              /* seed of the pivot sampler (Sec. 2.2); default 0 */
+    int64_t depth_limit;        /* 0: 2*floor(log2 n)+4 per range; > 0: that limit;
+                                   < 0: limit 0 (every range above the base case
+                                   takes the bounded-time fallback) */
+    uint32_t base_case;         /* NBaseCase in keys, 32..256; default 256 */
+    uint32_t local_keys;        /* LDS local-sort capacity in keys; default: tuned */
+    uint64_t solo_max;          /* ranges up to this many keys are finished by one
+                                   workgroup; default: tuned */
+    uint32_t use_graph;         /* segmented sort: capture the launch sequence once in a
+                                   hipGraph and replay it on later calls with the same
+                                   arguments */
+    uint32_t validate;          /* check offsets for monotonicity (synchronises) */
+    /* learned splitter (method VQS_METHOD_LEARNED, u64 keys) */
+    uint32_t train_steps;       /* optimiser steps; default 300 */
+    uint32_t batch;             /* training minibatch; default 8192 */
+    float sample_fraction;      /* fraction of keys sampled; default 0.01 */
+    float overflow_factor;      /* a bucket above overflow_factor * n/256 keys is left
+                                   to the plain method; default 2.0 */
+    float learning_rate;        /* Adam step size; default 0.01 */
+    uint32_t reserved[7];
+} vqs_options;
+
+/* Counters of the last call on a stream (copied with synchronisation).  The first
+ * eight count the recursion exactly like the CPU oracle does. */
+typedef struct vqs_stats {
+    uint64_t partitions;        /* Partition calls (all ranges, all levels) */
+    uint64_t keys_partitioned;  /* sum of partitioned range lengths */
+    uint64_t degenerate;        /* partitions with an empty right side */
+    uint64_t all_equal;         /* degenerate ranges holding one value */
+    uint64_t basecases;         /* BaseCase calls */
+    uint64_t fallbacks;         /* ranges past the depth limit */
+    uint64_t fallback_keys;     /* keys in those ranges */
+    uint64_t max_depth;         /* deepest partitioning recursion */
+    uint64_t levels;            /* device-wide partition levels launched with work */
+    uint64_t level_tiles;       /* tiles processed by the level kernels */
+    uint64_t solo_items;        /* ranges finished by single workgroups */
+    uint64_t lds_partitions;    /* partitions done inside LDS */
+    /* learned splitter */
+    uint64_t learned_buckets;   /* buckets produced (0 if the plain method ran) */
+    uint64_t overflow_buckets;  /* buckets above the overflow bound */
+    uint64_t max_bucket;        /* largest bucket */
+    double train_loss;          /* final minibatch loss */
+} vqs_stats;
+
+/* Sort keys[0, n) in place on the default stream with default options. */
+int vqs_sort(void* keys, uint64_t n, int key_type, int ascending);
+
+/* Sort each segment [offsets[i], offsets[i+1]) of keys independently, for
+ * i < nseg.  offsets is a device array of nseg + 1 non-decreasing int64 values;
+ * empty segments are allowed. */
+int vqs_sort_segmented(void* keys, const int64_t* offsets, uint64_t nseg, int key_type, int ascending);
+
+/* Extended forms: options may be NULL (defaults); stream is a hipStream_t or NULL. */
+int vqs_sort_ex(void* keys, uint64_t n, int key_type, int ascending, const vqs_options* options,
+                void* stream);
+int vqs_sort_segmented_ex(void* keys, const int64_t* offsets, uint64_t nseg, int key_type,
+                          int ascending, const vqs_options* options, void* stream);
+
+/* Device bytes of the workspace a sort of n keys (in nseg segments) needs. */
+uint64_t vqs_workspace_bytes(uint64_t n, uint64_t nseg, int key_type, const vqs_options* options);
+
+/* Statistics of the last call issued on `stream`; waits for that call to finish. */
+int vqs_get_stats(void* stream, vqs_stats* out);
+
+/* Device error bits of the last call on `stream` (0 if none); waits for it. */
+int vqs_last_error_bits(void* stream, uint32_t* out);
+
+/* Kernel timing records (profiling): one per kernel launch on a stream since the
+ * records were last read, measured with HIP events recorded on that stream around
+ * the launch. */
+typedef struct vqs_kernel_time {
+    int32_t kind;               /* 0 clear, 1 seed, 2 level partition, 3 solo, 4.. learned */
+    int32_t level;              /* recursion level of a level launch, else -1 */
+    uint64_t keys;              /* keys the launch partitions (level launches), else 0 */
+    double ms;                  /* event-measured duration */
+} vqs_kernel_time;
+
+/* Enable (1) or disable (0) event recording around every launch of later calls. */
+int vqs_profile(int enable);
+
+/* Copy up to max records of the calls on `stream` since the last read to out and
+ * clear them; *count receives the number copied.  Waits for the stream. */
+int vqs_profile_read(void* stream, vqs_kernel_time* out, int max, int* count);
+
+/* Free every workspace held by the library (waits for pending work). */
+int vqs_release(void);
+
+/* Human-readable text of a return code. */
+const char* vqs_strerror(int code);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int vqs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VQS_H */

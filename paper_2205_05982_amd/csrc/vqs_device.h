@@ -1,0 +1,305 @@
+// vqs_device.h -- device-side building blocks for gfx950 (CDNA4, wave64).
+//
+// Key traits: every key type is sorted internally as an unsigned integer in
+// ascending order.  Floats are mapped to unsigned integers by the order-preserving
+// bit transform (flip all bits of negatives, set the sign bit of non-negatives), and
+// descending order is the bitwise complement, so one comparison serves the six key
+// types and both orders of Sec. 2.4.  The transform is applied when keys are first
+// read from the caller's array and inverted when results are written back.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "vqs_types.h"
+
+namespace vqs {
+
+constexpr int WAVE = 64;
+
+template <int BITS>
+struct Key;
+
+template <>
+struct Key<16> {
+  using S = uint16_t;  // storage in memory / LDS
+  using R = uint32_t;  // register form (zero-extended)
+  static constexpr int SIZE = 2;
+  static constexpr int V = 8;  // keys per 16-byte chunk
+  __device__ static R load_t(S s, int mode) {
+    R r = s;
+    if (mode & MODE_DESC) r = (~r) & 0xFFFFu;
+    return r;
+  }
+  __device__ static S store_t(R r, int mode) {
+    if (mode & MODE_DESC) r = (~r) & 0xFFFFu;
+    return (S)r;
+  }
+  __device__ static bool lt(R a, R b) { return a < b; }
+  __device__ static bool eq(R a, R b) { return a == b; }
+  __device__ static R maxv() { return 0xFFFFu; }
+  __device__ static R kmin(R a, R b) { return a < b ? a : b; }
+  __device__ static R kmax(R a, R b) { return a < b ? b : a; }
+  __device__ static R shfl(R v, int lane) { return (R)__shfl((int)v, lane); }
+  __device__ static R shfl_xor(R v, int m) { return (R)__shfl_xor((int)v, m); }
+  __device__ static void unpack(const uint4& c, R (&k)[V]) {
+    const uint32_t w[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      k[2 * i] = w[i] & 0xFFFFu;
+      k[2 * i + 1] = w[i] >> 16;
+    }
+  }
+  __device__ static void to_u64x2(R r, uint64_t& lo, uint64_t& hi) { lo = r; hi = 0; }
+  __device__ static R from_u64x2(uint64_t lo, uint64_t) { return (R)lo; }
+};
+
+template <>
+struct Key<32> {
+  using S = uint32_t;
+  using R = uint32_t;
+  static constexpr int SIZE = 4;
+  static constexpr int V = 4;
+  __device__ static R load_t(S s, int mode) {
+    R r = s;
+    if (mode & MODE_FLOAT) r = (r & 0x80000000u) ? ~r : (r | 0x80000000u);
+    if (mode & MODE_DESC) r = ~r;
+    return r;
+  }
+  __device__ static S store_t(R r, int mode) {
+    if (mode & MODE_DESC) r = ~r;
+    if (mode & MODE_FLOAT) r = (r & 0x80000000u) ? (r & 0x7FFFFFFFu) : ~r;
+    return r;
+  }
+  __device__ static bool lt(R a, R b) { return a < b; }
+  __device__ static bool eq(R a, R b) { return a == b; }
+  __device__ static R maxv() { return 0xFFFFFFFFu; }
+  __device__ static R kmin(R a, R b) { return a < b ? a : b; }
+  __device__ static R kmax(R a, R b) { return a < b ? b : a; }
+  __device__ static R shfl(R v, int lane) { return (R)__shfl((int)v, lane); }
+  __device__ static R shfl_xor(R v, int m) { return (R)__shfl_xor((int)v, m); }
+  __device__ static void unpack(const uint4& c, R (&k)[V]) {
+    k[0] = c.x;
+    k[1] = c.y;
+    k[2] = c.z;
+    k[3] = c.w;
+  }
+  __device__ static void to_u64x2(R r, uint64_t& lo, uint64_t& hi) { lo = r; hi = 0; }
+  __device__ static R from_u64x2(uint64_t lo, uint64_t) { return (R)lo; }
+};
+
+template <>
+struct Key<64> {
+  using S = uint64_t;
+  using R = uint64_t;
+  static constexpr int SIZE = 8;
+  static constexpr int V = 2;
+  __device__ static R load_t(S s, int mode) {
+    R r = s;
+    if (mode & MODE_FLOAT) r = (r >> 63) ? ~r : (r | 0x8000000000000000ull);
+    if (mode & MODE_DESC) r = ~r;
+    return r;
+  }
+  __device__ static S store_t(R r, int mode) {
+    if (mode & MODE_DESC) r = ~r;
+    if (mode & MODE_FLOAT) r = (r >> 63) ? (r & 0x7FFFFFFFFFFFFFFFull) : ~r;
+    return r;
+  }
+  __device__ static bool lt(R a, R b) { return a < b; }
+  __device__ static bool eq(R a, R b) { return a == b; }
+  __device__ static R maxv() { return ~0ull; }
+  __device__ static R kmin(R a, R b) { return a < b ? a : b; }
+  __device__ static R kmax(R a, R b) { return a < b ? b : a; }
+  __device__ static R shfl(R v, int lane) {
+    return ((R)(uint32_t)__shfl((int)(uint32_t)(v >> 32), lane) << 32) |
+           (uint32_t)__shfl((int)(uint32_t)v, lane);
+  }
+  __device__ static R shfl_xor(R v, int m) {
+    return ((R)(uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m) << 32) |
+           (uint32_t)__shfl_xor((int)(uint32_t)v, m);
+  }
+  __device__ static void unpack(const uint4& c, R (&k)[V]) {
+    k[0] = ((uint64_t)c.y << 32) | c.x;
+    k[1] = ((uint64_t)c.w << 32) | c.z;
+  }
+  __device__ static void to_u64x2(R r, uint64_t& lo, uint64_t& hi) { lo = r; hi = 0; }
+  __device__ static R from_u64x2(uint64_t lo, uint64_t) { return lo; }
+};
+
+// 128-bit keys: two 64-bit words, low word first in memory; compared as (hi, lo)
+// lexicographically (Sec. 2.4, Alg. 2).
+template <>
+struct Key<128> {
+  using S = u128k;
+  using R = u128k;
+  static constexpr int SIZE = 16;
+  static constexpr int V = 1;
+  __device__ static R load_t(S s, int mode) {
+    if (mode & MODE_DESC) {
+      s.lo = ~s.lo;
+      s.hi = ~s.hi;
+    }
+    return s;
+  }
+  __device__ static S store_t(R r, int mode) { return load_t(r, mode); }
+  __device__ static bool lt(R a, R b) { return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo); }
+  __device__ static bool eq(R a, R b) { return a.hi == b.hi && a.lo == b.lo; }
+  __device__ static R maxv() { return R{~0ull, ~0ull}; }
+  __device__ static R kmin(R a, R b) { return lt(b, a) ? b : a; }
+  __device__ static R kmax(R a, R b) { return lt(b, a) ? a : b; }
+  __device__ static R shfl(R v, int lane) { return R{Key<64>::shfl(v.lo, lane), Key<64>::shfl(v.hi, lane)}; }
+  __device__ static R shfl_xor(R v, int m) {
+    return R{Key<64>::shfl_xor(v.lo, m), Key<64>::shfl_xor(v.hi, m)};
+  }
+  __device__ static void unpack(const uint4& c, R (&k)[V]) {
+    k[0].lo = ((uint64_t)c.y << 32) | c.x;
+    k[0].hi = ((uint64_t)c.w << 32) | c.z;
+  }
+  __device__ static void to_u64x2(R r, uint64_t& lo, uint64_t& hi) {
+    lo = r.lo;
+    hi = r.hi;
+  }
+  __device__ static R from_u64x2(uint64_t lo, uint64_t hi) { return R{lo, hi}; }
+};
+
+// ---- wave utilities ---------------------------------------------------------------
+
+__device__ inline int lane_id() { return __lane_id(); }
+
+// number of set bits of mask below this lane
+__device__ inline uint32_t mbcnt(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ inline uint64_t ballot(bool p) { return __ballot(p); }
+
+// ---- random numbers for the pivot sampler (Sec. 2.2) ---------------------------------
+
+// SplitMix64 (Steele, Lea, Flood): golden-ratio increment, variant-13 finalizer.
+__device__ inline uint64_t splitmix64(uint64_t& x) {
+  uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// SFC64 (Doty-Humphrey), state a, b, c, counter.
+struct Sfc64 {
+  uint64_t a, b, c, w;
+  __device__ uint64_t next() {
+    const uint64_t out = a + b + w;
+    w += 1;
+    a = b ^ (b >> 11);
+    b = c + (c << 3);
+    c = ((c << 24) | (c >> 40)) + out;
+    return out;
+  }
+};
+
+// Sampler state of the range [b, e): SplitMix64 from the seed with b, then e, mixed
+// in before the draws giving a, b, c; counter 1; twelve outputs discarded.
+__device__ inline Sfc64 range_rng(uint64_t seed, uint64_t b, uint64_t e) {
+  uint64_t x = seed;
+  Sfc64 s;
+  x ^= b;
+  s.a = splitmix64(x);
+  x ^= e;
+  s.b = splitmix64(x);
+  s.c = splitmix64(x);
+  s.w = 1;
+  for (int i = 0; i < 12; i++) (void)s.next();
+  return s;
+}
+
+template <class K>
+__device__ inline typename K::R med3(typename K::R x0, typename K::R x1, typename K::R x2) {
+  // network (0,2) (0,1) (1,2): element 1 ends as the median
+  typename K::R lo = K::kmin(x0, x2), hi = K::kmax(x0, x2);
+  typename K::R m = K::kmax(lo, x1);
+  return K::kmin(m, hi);
+}
+
+// ChoosePivot by one wave.  `load(i)` returns the key at position i relative to the
+// range start (internal form).  b, e are the absolute range bounds (they seed the
+// sampler).  Nine 64-byte chunks at random chunk offsets, lanewise medians of three of
+// chunk groups, then reduction by medians of three (whole groups of W lanes while 3W
+// remain, then consecutive triples, 0..2 leftovers dropped) until fewer than three
+// remain; the first is the pivot.  All lanes return the pivot.
+template <class K, class Load>
+__device__ typename K::R choose_pivot_wave(Load load, uint64_t b, uint64_t e, uint64_t seed) {
+  using R = typename K::R;
+  constexpr int W = 64 / K::SIZE;
+  constexpr int M0 = 3 * W;               // 96, 48, 24 or 12 medians
+  constexpr int NR = (M0 + WAVE - 1) / WAVE;
+  const int lane = lane_id();
+  const uint64_t nch = (e - b) / W;
+  Sfc64 rng = range_rng(seed, b, e);
+  uint32_t u[10];
+#pragma unroll
+  for (int i = 0; i < 5; i++) {
+    uint64_t r = rng.next();
+    u[2 * i] = (uint32_t)r;
+    u[2 * i + 1] = (uint32_t)(r >> 32);
+  }
+  uint64_t off[9];
+#pragma unroll
+  for (int i = 0; i < 9; i++) off[i] = (((uint64_t)u[i] * nch) >> 32) * W;
+  // chunk start of chunk c, selected without dynamic register indexing
+  auto chunk_at = [&](int c) -> uint64_t {
+    uint64_t r = off[0];
+#pragma unroll
+    for (int i = 1; i < 9; i++) r = (c == i) ? off[i] : r;
+    return r;
+  };
+
+  // slot m lives in lane m % 64, register m / 64
+  R v[NR];
+#pragma unroll
+  for (int r = 0; r < NR; r++) {
+    const int m = r * WAVE + lane;
+    v[r] = K::maxv();
+    if (m < M0) {
+      const int g = m / W, j = m % W;
+      R x0 = load(chunk_at(3 * g) + j), x1 = load(chunk_at(3 * g + 1) + j), x2 = load(chunk_at(3 * g + 2) + j);
+      v[r] = med3<K>(x0, x1, x2);
+    }
+  }
+  int cnt = M0;
+  while (cnt >= 3) {
+    const int nv = cnt / (3 * W);               // whole vector groups
+    const int ns = (cnt - nv * 3 * W) / 3;      // then single triples
+    const int outc = nv * W + ns;
+    R nvv[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+      const int o = r * WAVE + lane;
+      int i0, d;
+      if (o < nv * W) {
+        i0 = (o / W) * 3 * W + (o % W);
+        d = W;
+      } else {
+        i0 = nv * 3 * W + 3 * (o - nv * W);
+        d = 1;
+      }
+      R x[3];
+#pragma unroll
+      for (int t = 0; t < 3; t++) {
+        int idx = i0 + t * d;
+        if (idx >= cnt) idx = 0;   // lanes beyond the outputs: any in-range slot
+        R got = K::shfl(v[0], idx & (WAVE - 1));
+#pragma unroll
+        for (int rr = 1; rr < NR; rr++) {
+          R g2 = K::shfl(v[rr], idx & (WAVE - 1));
+          if ((idx >> 6) == rr) got = g2;
+        }
+        x[t] = got;
+      }
+      nvv[r] = med3<K>(x[0], x[1], x[2]);
+    }
+#pragma unroll
+    for (int r = 0; r < NR; r++) v[r] = nvv[r];
+    cnt = outc;
+  }
+  return K::shfl(v[0], 0);
+}
+
+}  // namespace vqs

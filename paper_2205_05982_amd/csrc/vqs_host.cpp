@@ -1,0 +1,624 @@
+// vqs_host.cpp -- host runtime of the library: argument checks, per-stream workspaces,
+// the level loop of the breadth-first recursion, hipGraph capture for segmented
+// sorts, statistics, and the C interface declared in include/vqs.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "../../include/vqs.h"
+#include "vqs_launch.h"
+#include "vqs_learned.h"
+
+namespace vqs {
+
+namespace {
+
+constexpr int VERSION = 10000;  // 1.0.0
+
+struct Geometry {
+  int num_cu = 256;
+  int level_grid = 2048;
+  int solo_grid = 512;
+};
+
+struct GraphKey {
+  void* keys;
+  const int64_t* offsets;
+  uint64_t nseg, n;
+  int kt, asc;
+  uint64_t seed;
+  int64_t depth_limit;
+  uint32_t nb, local;
+  uint64_t solo;
+  bool operator<(const GraphKey& o) const {
+    return std::tie(keys, offsets, nseg, n, kt, asc, seed, depth_limit, nb, local, solo) <
+           std::tie(o.keys, o.offsets, o.nseg, o.n, o.kt, o.asc, o.seed, o.depth_limit, o.nb, o.local, o.solo);
+  }
+};
+
+struct ProfRec {
+  int kind, level;
+  hipEvent_t a, b;
+};
+
+bool g_profile = false;
+
+struct Workspace {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  char* mem = nullptr;
+  size_t bytes = 0;
+  // capacities the allocation was carved for
+  uint64_t cap_n = 0, cap_lvl = 0, cap_tiles = 0, cap_solo = 0, cap_scratch_bytes = 0;
+  int cap_levels = 0;
+  Params p{};  // carved pointers
+  unsigned long long* host_pinned = nullptr;
+  int last_levels = 0;
+  bool have_result = false;
+  LearnedState learned;
+  hipGraphExec_t graph = nullptr;
+  GraphKey graph_key{};
+  bool graph_valid = false;
+  std::vector<hipEvent_t> event_pool;
+  std::vector<ProfRec> prof;
+  size_t events_used = 0;
+  bool capturing = false;
+  hipEvent_t next_event() {
+    if (events_used == event_pool.size()) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      event_pool.push_back(e);
+    }
+    return event_pool[events_used++];
+  }
+  // record an event pair around a launch when profiling
+  template <class F>
+  hipError_t timed(int kind, int level, F&& launch) {
+    if (!g_profile || capturing) return launch();
+    hipEvent_t a = next_event(), b = next_event();
+    if (a) (void)hipEventRecord(a, stream);
+    hipError_t e = launch();
+    if (b) (void)hipEventRecord(b, stream);
+    if (a && b) prof.push_back(ProfRec{kind, level, a, b});
+    return e;
+  }
+  ~Workspace() {
+    for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
+    if (graph) (void)hipGraphExecDestroy(graph);
+    if (mem) (void)hipFree(mem);
+    if (host_pinned) (void)hipHostFree(host_pinned);
+    learned.release();
+  }
+};
+
+std::mutex g_mu;
+std::map<std::pair<int, hipStream_t>, std::unique_ptr<Workspace>> g_ws;
+std::map<int, Geometry> g_geom;
+
+Geometry geometry(int dev) {
+  auto it = g_geom.find(dev);
+  if (it != g_geom.end()) return it->second;
+  Geometry g;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0) g.num_cu = prop.multiProcessorCount;
+  g.level_grid = g.num_cu * 8;
+  g.solo_grid = g.num_cu * 2;
+  g_geom[dev] = g;
+  return g;
+}
+
+int key_bits(int kt) {
+  switch (kt) {
+    case VQS_U16: return 16;
+    case VQS_U32: case VQS_F32: return 32;
+    case VQS_U64: case VQS_F64: return 64;
+    case VQS_U128: return 128;
+    default: return 0;
+  }
+}
+
+uint64_t level_tile_keys(int bits) {
+  switch (bits) {
+    case 16: return Launch<16>::level_tile_keys();
+    case 32: return Launch<32>::level_tile_keys();
+    case 64: return Launch<64>::level_tile_keys();
+    default: return Launch<128>::level_tile_keys();
+  }
+}
+
+uint64_t local_buffer_keys(int bits) {
+  switch (bits) {
+    case 16: return Launch<16>::local_buffer_keys();
+    case 32: return Launch<32>::local_buffer_keys();
+    case 64: return Launch<64>::local_buffer_keys();
+    default: return Launch<128>::local_buffer_keys();
+  }
+}
+
+uint32_t depth_limit_for(uint64_t n) {
+  uint32_t lg = 0;
+  while ((n >> (lg + 1)) != 0) lg++;
+  return 2 * lg + 4;
+}
+
+struct Plan {
+  int bits, ks, mode;
+  uint64_t n, nseg;
+  uint32_t nb, local;
+  uint64_t solo;
+  int max_levels;
+  uint64_t cap_lvl, cap_tiles, cap_solo;
+  uint64_t seed;
+  int64_t depth_limit;  // < 0: default per range, else this limit for every range
+};
+
+int make_plan(uint64_t n, uint64_t nseg, int kt, int asc, const vqs_options* o, const Geometry& g, Plan* pl) {
+  const int bits = key_bits(kt);
+  if (!bits) return VQS_ETYPE;
+  pl->bits = bits;
+  pl->ks = bits / 8;
+  pl->mode = ((kt == VQS_F32 || kt == VQS_F64) ? MODE_FLOAT : 0) | (asc ? 0 : MODE_DESC);
+  pl->n = n;
+  pl->nseg = nseg;
+  pl->seed = o ? o->seed : 0;
+  pl->nb = (o && o->base_case) ? o->base_case : 256;
+  if (pl->nb < 32 || pl->nb > 256) return VQS_EINVAL;
+  const uint64_t lbk = local_buffer_keys(bits);
+  pl->local = (o && o->local_keys) ? o->local_keys : (uint32_t)lbk;
+  if (pl->local > lbk || pl->local < pl->nb) return VQS_EINVAL;
+  // every LDS recursion level holds fewer than LOCAL_LIST_CAP ranges longer than nb
+  if (pl->local / (pl->nb + 1) >= (uint32_t)LOCAL_LIST_CAP) {
+    if (o && o->local_keys) return VQS_EINVAL;
+    pl->local = (uint32_t)((LOCAL_LIST_CAP - 1) * (pl->nb + 1));
+  }
+  if (o && o->solo_max) {
+    pl->solo = o->solo_max;
+    if (pl->solo < pl->local) return VQS_EINVAL;
+  } else {
+    // enough ranges for every solo workgroup, each at most 2^20 keys
+    uint64_t s = n / ((uint64_t)g.solo_grid * 4);
+    s = std::max<uint64_t>(s, std::max<uint64_t>(pl->local, 1u << 14));
+    s = std::min<uint64_t>(s, 1ull << 20);
+    pl->solo = std::max<uint64_t>(s, pl->local);
+  }
+  pl->depth_limit = -1;
+  uint32_t lim = depth_limit_for(std::max<uint64_t>(n, 2));
+  if (o && o->depth_limit != 0) {
+    pl->depth_limit = o->depth_limit > 0 ? o->depth_limit : 0;
+    if (pl->depth_limit > 200) return VQS_EINVAL;
+    lim = (uint32_t)pl->depth_limit;
+  }
+  pl->max_levels = (int)lim + 3;
+  const uint64_t T = level_tile_keys(bits);
+  pl->cap_lvl = n / (pl->solo + 1) + 2;
+  pl->cap_tiles = n / T + 2 * pl->cap_lvl + 2;
+  pl->cap_solo = nseg + 2ull * (uint64_t)pl->max_levels * pl->cap_lvl + n / FILL_CHUNK + 64;
+  return VQS_OK;
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Allocate (or reuse) the workspace for a plan.  Caller holds g_mu.
+int ensure_workspace(Workspace* ws, const Plan& pl) {
+  const uint64_t scratch_bytes = (pl.n + 32) * (uint64_t)pl.ks + 64;
+  if (ws->mem && scratch_bytes <= ws->cap_scratch_bytes && pl.cap_lvl <= ws->cap_lvl &&
+      pl.cap_tiles <= ws->cap_tiles && pl.cap_solo <= ws->cap_solo && pl.max_levels <= ws->cap_levels)
+    return VQS_OK;
+  if (ws->mem) {
+    (void)hipStreamSynchronize(ws->stream);
+    if (ws->graph) {
+      (void)hipGraphExecDestroy(ws->graph);
+      ws->graph = nullptr;
+      ws->graph_valid = false;
+    }
+    (void)hipFree(ws->mem);
+    ws->mem = nullptr;
+  }
+  const uint64_t cap_scratch = std::max(scratch_bytes, ws->cap_scratch_bytes);
+  const uint64_t cap_lvl = std::max(pl.cap_lvl, ws->cap_lvl);
+  const uint64_t cap_tiles = std::max(pl.cap_tiles, ws->cap_tiles);
+  const uint64_t cap_solo = std::max(pl.cap_solo, ws->cap_solo);
+  const int cap_levels = std::max(pl.max_levels, ws->cap_levels);
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    size_t o = off;
+    off = align_up(off + b, 256);
+    return o;
+  };
+  const size_t o_scratch = take(cap_scratch);
+  const size_t o_seg0 = take(cap_lvl * sizeof(Seg));
+  const size_t o_seg1 = take(cap_lvl * sizeof(Seg));
+  const size_t o_tb0 = take(cap_lvl * 8);
+  const size_t o_tb1 = take(cap_lvl * 8);
+  const size_t o_ctr = take((size_t)cap_levels * sizeof(LevelCtr));
+  const size_t o_flags = take(cap_tiles * 8);
+  const size_t o_tmin = take(cap_tiles * sizeof(u128k));
+  const size_t o_solo = take(cap_solo * sizeof(Seg));
+  const size_t o_sctr = take(sizeof(SoloCtr));
+  const size_t o_stats = take(sizeof(DevStats));
+  const size_t o_err = take(16);
+  void* mem = nullptr;
+  if (hipMalloc(&mem, off) != hipSuccess || !mem) {
+    (void)hipGetLastError();
+    return VQS_ENOMEM;
+  }
+  ws->mem = (char*)mem;
+  ws->bytes = off;
+  ws->cap_scratch_bytes = cap_scratch;
+  ws->cap_lvl = cap_lvl;
+  ws->cap_tiles = cap_tiles;
+  ws->cap_solo = cap_solo;
+  ws->cap_levels = cap_levels;
+  Params& p = ws->p;
+  p.scratch = ws->mem + o_scratch;  // re-based per call to the keys' alignment
+  p.lvl_segs[0] = (Seg*)(ws->mem + o_seg0);
+  p.lvl_segs[1] = (Seg*)(ws->mem + o_seg1);
+  p.lvl_tbase[0] = (unsigned long long*)(ws->mem + o_tb0);
+  p.lvl_tbase[1] = (unsigned long long*)(ws->mem + o_tb1);
+  p.lvl_ctr = (LevelCtr*)(ws->mem + o_ctr);
+  p.flags = (unsigned long long*)(ws->mem + o_flags);
+  p.tilemin = (u128k*)(ws->mem + o_tmin);
+  p.solo = (Seg*)(ws->mem + o_solo);
+  p.solo_ctr = (SoloCtr*)(ws->mem + o_sctr);
+  p.stats = (DevStats*)(ws->mem + o_stats);
+  p.err = (unsigned int*)(ws->mem + o_err);
+  p.cap_lvl = cap_lvl;
+  p.cap_tiles = cap_tiles;
+  p.cap_solo = cap_solo;
+  if (!ws->host_pinned && hipHostMalloc((void**)&ws->host_pinned, 4096, hipHostMallocDefault) != hipSuccess) {
+    ws->host_pinned = nullptr;
+    return VQS_ENOMEM;
+  }
+  if (hipMemsetAsync(ws->mem + o_stats, 0, sizeof(DevStats), ws->stream) != hipSuccess) return VQS_EHIP;
+  return VQS_OK;
+}
+
+Workspace* workspace_for(hipStream_t s) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  auto key = std::make_pair(dev, s);
+  auto it = g_ws.find(key);
+  if (it != g_ws.end()) return it->second.get();
+  auto ws = std::make_unique<Workspace>();
+  ws->device = dev;
+  ws->stream = s;
+  Workspace* r = ws.get();
+  g_ws[key] = std::move(ws);
+  return r;
+}
+
+template <int B>
+hipError_t launch_all(Workspace* ws, const Params& base, const Plan& pl, const Geometry& g,
+                      const int64_t* offsets, uint64_t nseg, bool capture, int* levels_out) {
+  hipStream_t s = ws->stream;
+  hipError_t e = ws->timed(0, -1, [&] { return Launch<B>::clear(base, s); });
+  if (e != hipSuccess) return e;
+  e = ws->timed(1, -1, [&] { return Launch<B>::seed(base, offsets, nseg, s); });
+  if (e != hipSuccess) return e;
+  // the level loop: launch levels in batches, then read the next level's counter
+  int L = 0;
+  if (pl.n > pl.solo) {
+    if (capture) {
+      for (; L < pl.max_levels - 1; L++) {
+        Params p = base;
+        p.level = L;
+        e = ws->timed(2, L, [&] { return Launch<B>::level(p, g.level_grid, s); });
+        if (e != hipSuccess) return e;
+      }
+    } else {
+      int batch = 2;
+      {
+        uint64_t x = pl.n / std::max<uint64_t>(pl.solo, 1);
+        while (x > 1) {
+          batch++;
+          x >>= 1;
+        }
+      }
+      for (;;) {
+        const int upto = std::min(L + batch, pl.max_levels - 1);
+        for (; L < upto; L++) {
+          Params p = base;
+          p.level = L;
+          e = ws->timed(2, L, [&] { return Launch<B>::level(p, g.level_grid, s); });
+          if (e != hipSuccess) return e;
+        }
+        if (L >= pl.max_levels - 1) break;
+        e = hipMemcpyAsync(ws->host_pinned, &base.lvl_ctr[L].packed, 8, hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return e;
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return e;
+        if (ws->host_pinned[0] == 0) break;
+        batch = 2;
+      }
+    }
+  }
+  *levels_out = L;
+  return ws->timed(3, -1, [&] { return Launch<B>::solo(base, g.solo_grid, s); });
+}
+
+hipError_t dispatch_launch(Workspace* ws, const Params& base, const Plan& pl, const Geometry& g,
+                           const int64_t* offsets, uint64_t nseg, bool capture, int* levels) {
+  switch (pl.bits) {
+    case 16: return launch_all<16>(ws, base, pl, g, offsets, nseg, capture, levels);
+    case 32: return launch_all<32>(ws, base, pl, g, offsets, nseg, capture, levels);
+    case 64: return launch_all<64>(ws, base, pl, g, offsets, nseg, capture, levels);
+    default: return launch_all<128>(ws, base, pl, g, offsets, nseg, capture, levels);
+  }
+}
+
+int check_offsets_host(const int64_t* offsets, uint64_t nseg, uint64_t* total, hipStream_t s) {
+  int64_t* h = (int64_t*)malloc((nseg + 1) * sizeof(int64_t));
+  if (!h) return VQS_ENOMEM;
+  if (hipMemcpyAsync(h, offsets, (nseg + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    free(h);
+    return VQS_EHIP;
+  }
+  int rc = VQS_OK;
+  if (h[0] < 0) rc = VQS_EOFFSETS;
+  for (uint64_t i = 0; i < nseg && rc == VQS_OK; i++)
+    if (h[i + 1] < h[i]) rc = VQS_EOFFSETS;
+  *total = rc == VQS_OK ? (uint64_t)h[nseg] : 0;
+  free(h);
+  return rc;
+}
+
+int sort_impl(void* keys, const int64_t* offsets, uint64_t nseg, uint64_t n, int kt, int asc,
+              const vqs_options* o, hipStream_t stream) {
+  if (o && o->struct_size != 0 && o->struct_size < offsetof(vqs_options, train_steps)) return VQS_EINVAL;
+  const int bits = key_bits(kt);
+  if (!bits) return VQS_ETYPE;
+  if (asc != 0 && asc != 1) return VQS_EINVAL;
+  if (n == 0) return VQS_OK;
+  if (!keys) return VQS_EINVAL;
+  const int ks = bits / 8;
+  const uintptr_t addr = (uintptr_t)keys;
+  if (addr % (uintptr_t)std::min(ks, 16)) return VQS_EINVAL;
+  std::lock_guard<std::mutex> lock(g_mu);
+  Workspace* ws = workspace_for(stream);
+  const Geometry g = geometry(ws->device);
+  Plan pl;
+  int rc = make_plan(n, nseg, kt, asc, o, g, &pl);
+  if (rc != VQS_OK) return rc;
+  const bool learned = o && o->method == VQS_METHOD_LEARNED;
+  if (o && o->method > VQS_METHOD_LEARNED) return VQS_EINVAL;
+  if (learned && (bits != 64 || (kt == VQS_F64) || offsets)) return VQS_EINVAL;
+  rc = ensure_workspace(ws, pl);
+  if (rc != VQS_OK) return rc;
+  Params base = ws->p;
+  base.keys = keys;
+  base.off = (int)((addr % 16) / (uintptr_t)ks);
+  // scratch shares the keys' offset from a 16-byte boundary
+  base.scratch = (void*)(((uintptr_t)ws->p.scratch + 15) / 16 * 16 + (addr % 16));
+  base.n_total = n;
+  base.mode = pl.mode;
+  base.seed = pl.seed;
+  base.nb = pl.nb;
+  base.local_cap = pl.local;
+  base.solo_max = pl.solo;
+  base.max_levels = pl.max_levels;
+  base.level = 0;
+  ws->have_result = false;
+  base.fixed_limit = pl.depth_limit;
+  int levels = 0;
+  hipError_t e;
+  if (learned) {
+    rc = learned_sort(ws->learned, base, pl.n, o, stream, &levels);
+    if (rc != VQS_OK) return rc;
+    ws->last_levels = levels;
+    ws->have_result = true;
+    return VQS_OK;
+  }
+  const bool use_graph = o && o->use_graph && offsets;
+  if (use_graph) {
+    GraphKey gk{keys, offsets, nseg, n, kt, asc, pl.seed, pl.depth_limit, pl.nb, pl.local, pl.solo};
+    if (!(ws->graph_valid && !(gk < ws->graph_key) && !(ws->graph_key < gk))) {
+      if (ws->graph) {
+        (void)hipGraphExecDestroy(ws->graph);
+        ws->graph = nullptr;
+      }
+      ws->graph_valid = false;
+      hipStream_t cap;
+      if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) return VQS_EHIP;
+      hipStream_t saved = ws->stream;
+      ws->stream = cap;
+      ws->capturing = true;
+      e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) e = dispatch_launch(ws, base, pl, g, offsets, nseg, true, &levels);
+      hipGraph_t graph = nullptr;
+      hipError_t e2 = hipStreamEndCapture(cap, &graph);
+      ws->stream = saved;
+      ws->capturing = false;
+      if (e == hipSuccess) e = e2;
+      if (e == hipSuccess) e = hipGraphInstantiate(&ws->graph, graph, nullptr, nullptr, 0);
+      if (graph) (void)hipGraphDestroy(graph);
+      (void)hipStreamDestroy(cap);
+      if (e != hipSuccess) return VQS_EHIP;
+      ws->graph_key = gk;
+      ws->graph_valid = true;
+    }
+    e = hipGraphLaunch(ws->graph, stream);
+    if (e != hipSuccess) return VQS_EHIP;
+    ws->last_levels = pl.max_levels - 1;
+    ws->have_result = true;
+    return VQS_OK;
+  }
+  e = dispatch_launch(ws, base, pl, g, offsets, nseg, false, &levels);
+  if (e != hipSuccess) return VQS_EHIP;
+  ws->last_levels = levels;
+  ws->have_result = true;
+  return VQS_OK;
+}
+
+}  // namespace
+
+}  // namespace vqs
+
+using namespace vqs;
+
+extern "C" {
+
+int vqs_sort_ex(void* keys, uint64_t n, int key_type, int ascending, const vqs_options* options, void* stream) {
+  return sort_impl(keys, nullptr, 1, n, key_type, ascending, options, (hipStream_t)stream);
+}
+
+int vqs_sort(void* keys, uint64_t n, int key_type, int ascending) {
+  return vqs_sort_ex(keys, n, key_type, ascending, nullptr, nullptr);
+}
+
+int vqs_sort_segmented_ex(void* keys, const int64_t* offsets, uint64_t nseg, int key_type, int ascending,
+                          const vqs_options* options, void* stream) {
+  if (!key_bits(key_type)) return VQS_ETYPE;
+  if (nseg == 0) return VQS_OK;
+  if (!offsets) return VQS_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  // total key count = offsets[nseg] (and the scratch size): read it once
+  uint64_t total = 0;
+  if (options && options->validate) {
+    int rc = check_offsets_host(offsets, nseg, &total, s);
+    if (rc != VQS_OK) return rc;
+  } else {
+    int64_t last = 0;
+    if (hipMemcpyAsync(&last, offsets + nseg, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return VQS_EHIP;
+    if (last < 0) return VQS_EOFFSETS;
+    total = (uint64_t)last;
+  }
+  return sort_impl(keys, offsets, nseg, total, key_type, ascending, options, s);
+}
+
+int vqs_sort_segmented(void* keys, const int64_t* offsets, uint64_t nseg, int key_type, int ascending) {
+  return vqs_sort_segmented_ex(keys, offsets, nseg, key_type, ascending, nullptr, nullptr);
+}
+
+uint64_t vqs_workspace_bytes(uint64_t n, uint64_t nseg, int key_type, const vqs_options* options) {
+  if (!key_bits(key_type)) return 0;
+  Geometry g;
+  Plan pl;
+  if (make_plan(n, nseg ? nseg : 1, key_type, 1, options, g, &pl) != VQS_OK) return 0;
+  uint64_t b = (n + 32) * (uint64_t)pl.ks + 64;
+  b += 2 * pl.cap_lvl * (sizeof(Seg) + 8) + (uint64_t)pl.max_levels * sizeof(LevelCtr);
+  b += pl.cap_tiles * (8 + sizeof(u128k)) + pl.cap_solo * sizeof(Seg) + 4096;
+  return b;
+}
+
+int vqs_get_stats(void* stream, vqs_stats* out) {
+  if (!out) return VQS_EINVAL;
+  std::lock_guard<std::mutex> lock(g_mu);
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  auto it = g_ws.find(std::make_pair(dev, (hipStream_t)stream));
+  memset(out, 0, sizeof(*out));
+  if (it == g_ws.end() || !it->second->have_result) return VQS_OK;
+  Workspace* ws = it->second.get();
+  DevStats d;
+  if (hipMemcpyAsync(&d, ws->p.stats, sizeof(d), hipMemcpyDeviceToHost, ws->stream) != hipSuccess ||
+      hipStreamSynchronize(ws->stream) != hipSuccess)
+    return VQS_EHIP;
+  out->partitions = d.partitions;
+  out->keys_partitioned = d.keys_partitioned;
+  out->degenerate = d.degenerate;
+  out->all_equal = d.all_equal;
+  out->basecases = d.basecases;
+  out->fallbacks = d.fallbacks;
+  out->fallback_keys = d.fallback_keys;
+  out->max_depth = d.max_depth;
+  out->level_tiles = d.level_tiles;
+  out->solo_items = d.solo_items;
+  out->lds_partitions = d.lds_partitions;
+  // levels that had work
+  const int nl = std::min(ws->last_levels + 1, ws->cap_levels);
+  LevelCtr* h = (LevelCtr*)malloc(sizeof(LevelCtr) * (size_t)std::max(nl, 1));
+  if (h && nl > 0 && hipMemcpy(h, ws->p.lvl_ctr, sizeof(LevelCtr) * nl, hipMemcpyDeviceToHost) == hipSuccess) {
+    for (int i = 0; i < nl; i++)
+      if (h[i].packed) out->levels++;
+  }
+  free(h);
+  ws->learned.fill_stats(out);
+  return VQS_OK;
+}
+
+int vqs_last_error_bits(void* stream, uint32_t* out) {
+  if (!out) return VQS_EINVAL;
+  std::lock_guard<std::mutex> lock(g_mu);
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  *out = 0;
+  auto it = g_ws.find(std::make_pair(dev, (hipStream_t)stream));
+  if (it == g_ws.end() || !it->second->mem) return VQS_OK;
+  Workspace* ws = it->second.get();
+  unsigned int e = 0;
+  if (hipMemcpyAsync(&e, ws->p.err, 4, hipMemcpyDeviceToHost, ws->stream) != hipSuccess ||
+      hipStreamSynchronize(ws->stream) != hipSuccess)
+    return VQS_EHIP;
+  *out = e;
+  return VQS_OK;
+}
+
+int vqs_profile(int enable) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_profile = enable != 0;
+  return VQS_OK;
+}
+
+int vqs_profile_read(void* stream, vqs_kernel_time* out, int max, int* count) {
+  if (!count || (max > 0 && !out)) return VQS_EINVAL;
+  std::lock_guard<std::mutex> lock(g_mu);
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  *count = 0;
+  auto it = g_ws.find(std::make_pair(dev, (hipStream_t)stream));
+  if (it == g_ws.end() || !it->second->mem) return VQS_OK;
+  Workspace* ws = it->second.get();
+  if (hipStreamSynchronize(ws->stream) != hipSuccess) return VQS_EHIP;
+  std::vector<LevelCtr> ctr((size_t)ws->cap_levels);
+  if (hipMemcpy(ctr.data(), ws->p.lvl_ctr, sizeof(LevelCtr) * ctr.size(), hipMemcpyDeviceToHost) != hipSuccess)
+    return VQS_EHIP;
+  int n = 0;
+  for (const ProfRec& r : ws->prof) {
+    if (n >= max) break;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return VQS_EHIP;
+    out[n].kind = r.kind;
+    out[n].level = r.level;
+    out[n].keys = (r.kind == 2 && r.level >= 0 && r.level < (int)ctr.size()) ? ctr[r.level].keys : 0;
+    out[n].ms = ms;
+    n++;
+  }
+  *count = n;
+  ws->prof.clear();
+  ws->events_used = 0;
+  return VQS_OK;
+}
+
+int vqs_release(void) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  for (auto& kv : g_ws) (void)hipStreamSynchronize(kv.second->stream);
+  g_ws.clear();
+  return VQS_OK;
+}
+
+const char* vqs_strerror(int code) {
+  switch (code) {
+    case VQS_OK: return "success";
+    case VQS_EINVAL: return "invalid argument";
+    case VQS_ETYPE: return "unknown key type";
+    case VQS_ENOMEM: return "device workspace allocation failed";
+    case VQS_EHIP: return "HIP runtime error";
+    case VQS_EOFFSETS: return "segment offsets decrease";
+    case VQS_EINTERNAL: return "device-side capacity check failed";
+    default: return "unknown error";
+  }
+}
+
+int vqs_version(void) { return VERSION; }
+
+}  // extern "C"

@@ -1,0 +1,1086 @@
+// vqs_kernels.h -- HIP kernels of the vectorized Quicksort for gfx950.
+//
+// The paper's recursion (Alg. 1) is run breadth-first across the whole GPU:
+//
+//  * level_kernel: one launch per recursion level.  Every range longer than the
+//    "solo" threshold is cut into 16-byte-aligned tiles; all tiles of all ranges of
+//    the level are partitioned in one persistent launch (atomic tile tickets).  Each
+//    tile recomputes its range's pivot (ChoosePivot, Sec. 2.2), classifies its keys
+//    against it, ranks them with wave ballots and prefix counts, stages them in LDS
+//    in compacted order (the compress-store of Sec. 2.1) and writes two coalesced
+//    runs.  A tile's offset inside its range comes from a decoupled look-back over
+//    the left counts of the preceding tiles.  The last tile of a range plans the
+//    children: small ones go to the solo list, large ones to the next level.
+//  * solo_kernel: one persistent launch; each workgroup takes whole ranges from the
+//    solo list and finishes them alone: partition passes through global memory while
+//    the range is larger than the LDS capacity, then the local sort in LDS
+//    (partitions by single waves down to NBaseCase keys, then the 16x16 sorting
+//    network of Sec. 3 in registers: Green's 60-module column network in every lane,
+//    then transposition-free bitonic merges across lanes).
+//
+// Partition layout (both kernels, global and LDS): keys not after the pivot are
+// written from the range start in input order, the others from the range end
+// backwards (reverse input order).  This is the layout of the oracle's scalar
+// out-of-place split, so pivots, ranges and recursion depths agree at every level.
+#pragma once
+#include "vqs_device.h"
+#include "vqs_types.h"
+
+namespace vqs {
+
+__device__ inline void set_err(const Params& p, uint32_t e) { atomicOr(p.err, e); }
+
+template <class K>
+__device__ inline void to_words(typename K::R r, uint64_t& lo, uint64_t& hi) {
+  K::to_u64x2(r, lo, hi);
+}
+
+template <class K>
+__device__ inline typename K::R wave_min(typename K::R v) {
+#pragma unroll
+  for (int m = 1; m < WAVE; m <<= 1) v = K::kmin(v, K::shfl_xor(v, m));
+  return v;
+}
+
+// number of 16-byte-aligned tiles of T keys that intersect [b, e)
+__device__ inline uint64_t tiles_of(uint64_t b, uint64_t e, int off, uint64_t T) {
+  return (e - 1 + off) / T - (b + off) / T + 1;
+}
+
+__device__ inline uint32_t depth_limit_of(uint64_t n) {
+  uint32_t lg = 63 - __clzll(n | 1);
+  return 2 * lg + 4;
+}
+
+// ---- tile partition (workgroup) -------------------------------------------------------
+
+template <class K, int P, int I>
+struct Tile {
+  using R = typename K::R;
+  using S = typename K::S;
+  static constexpr int V = K::V;
+  static constexpr int NW = P / WAVE;
+  static constexpr int TC = P * I;      // chunks per tile
+  static constexpr int T = TC * V;      // keys per tile
+
+  struct Aux {
+    uint32_t cnt[I][NW];
+    R wmin[NW];
+    R pivot;
+  };
+
+  // Load the tile's chunks; key (j, q) of this thread sits at v-index
+  // (k*TC + j*P + tid)*V + q.  Only chunks holding a key of [vs, ve) are read: a
+  // 16-byte aligned load touching a valid key never leaves its page.
+  __device__ static void load(const S* base_aligned, uint64_t k, uint64_t vs, uint64_t ve, int tmode,
+                              R (&key)[I][V]) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < I; j++) {
+      const uint64_t c = k * TC + (uint64_t)j * P + tid;
+      const uint64_t v0 = c * V;
+      if (v0 + V > vs && v0 < ve) {
+        const uint4 raw = *reinterpret_cast<const uint4*>(reinterpret_cast<const char*>(base_aligned) + c * 16);
+        R tmp[V];
+        K::unpack(raw, tmp);
+#pragma unroll
+        for (int q = 0; q < V; q++) key[j][q] = tmp[q];
+        if (tmode) {
+#pragma unroll
+          for (int q = 0; q < V; q++) {
+            S s;
+            if constexpr (sizeof(S) == sizeof(R)) {
+              s = tmp[q];
+            } else {
+              s = (S)tmp[q];
+            }
+            key[j][q] = K::load_t(s, tmode);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < V; q++) key[j][q] = K::maxv();
+      }
+    }
+  }
+
+  // Classify against the pivot, rank stably, stage in LDS (left keys from 0 upward,
+  // right keys from nvalid-1 downward).  Returns the tile's left count; *tmin gets
+  // the tile minimum (thread 0).  Ends with a barrier.
+  __device__ static uint32_t rank_and_stage(S* stage, Aux& sh, const R (&key)[I][V], uint64_t k,
+                                            uint64_t vs, uint64_t ve, R pivot, R* tmin) {
+    const int tid = threadIdx.x;
+    const int w = tid / WAVE;
+    uint32_t pre[I];
+    uint32_t flag[I];  // bit q: key (j, q) goes left
+    R mn = K::maxv();
+#pragma unroll
+    for (int j = 0; j < I; j++) {
+      const uint64_t v0 = (k * TC + (uint64_t)j * P + tid) * V;
+      uint32_t f = 0, lanepre = 0, tot = 0;
+#pragma unroll
+      for (int q = 0; q < V; q++) {
+        const bool valid = (v0 + q >= vs) && (v0 + q < ve);
+        const bool left = valid && !K::lt(pivot, key[j][q]);
+        if (valid) mn = K::kmin(mn, key[j][q]);
+        const uint64_t m = ballot(left);
+        lanepre += mbcnt(m);
+        tot += __popcll(m);
+        f |= (left ? 1u : 0u) << q;
+      }
+      pre[j] = lanepre;
+      flag[j] = f;
+      if ((tid & (WAVE - 1)) == 0) sh.cnt[j][w] = tot;
+    }
+    mn = wave_min<K>(mn);
+    if ((tid & (WAVE - 1)) == 0) sh.wmin[w] = mn;
+    __syncthreads();
+    uint32_t total = 0, mybase[I];
+#pragma unroll
+    for (int j = 0; j < I; j++) {
+      uint32_t before = 0;
+#pragma unroll
+      for (int ww = 0; ww < NW; ww++) before += (ww < w) ? sh.cnt[j][ww] : 0u;
+      mybase[j] = total + before;
+#pragma unroll
+      for (int ww = 0; ww < NW; ww++) total += sh.cnt[j][ww];
+    }
+    const uint32_t nvalid = (uint32_t)(ve - vs);
+#pragma unroll
+    for (int j = 0; j < I; j++) {
+      const uint64_t v0 = (k * TC + (uint64_t)j * P + tid) * V;
+      uint32_t lb = mybase[j] + pre[j];
+#pragma unroll
+      for (int q = 0; q < V; q++) {
+        const uint64_t v = v0 + q;
+        if (v >= vs && v < ve) {
+          const uint32_t pos_in_tile = (uint32_t)(v - vs);
+          uint32_t dst;
+          if ((flag[j] >> q) & 1u) {
+            dst = lb;
+            lb++;
+          } else {
+            const uint32_t rrank = pos_in_tile - lb;   // right keys before this one
+            dst = nvalid - 1 - rrank;
+          }
+          if constexpr (sizeof(S) == sizeof(R)) {
+            stage[dst] = key[j][q];
+          } else {
+            stage[dst] = (S)key[j][q];
+          }
+        }
+      }
+    }
+    if (tid == 0) {
+      R m2 = sh.wmin[0];
+#pragma unroll
+      for (int ww = 1; ww < NW; ww++) m2 = K::kmin(m2, sh.wmin[ww]);
+      *tmin = m2;
+    }
+    __syncthreads();
+    return total;
+  }
+
+  // Write the staged tile: left run to dst[left_base ...], right run to
+  // dst[right_base ...].  tmode != 0 applies the output transform.
+  __device__ static void write_out(const S* stage, S* dst, uint32_t nleft, uint32_t nvalid,
+                                   uint64_t left_base, uint64_t right_base, int tmode, uint64_t n_total) {
+    for (uint32_t s = threadIdx.x; s < nvalid; s += P) {
+      S val = stage[s];
+      if (tmode) {
+        R r;
+        if constexpr (sizeof(S) == sizeof(R)) {
+          r = val;
+        } else {
+          r = (R)val;
+        }
+        val = K::store_t(r, tmode);
+      }
+      const uint64_t idx = s < nleft ? left_base + s : right_base + (s - nleft);
+      if (idx < n_total) dst[idx] = val;
+    }
+  }
+};
+
+// ---- segment bookkeeping --------------------------------------------------------------
+
+__device__ inline void push_solo(const Params& p, const Seg& s) {
+  const unsigned long long i = atomicAdd(&p.solo_ctr->count, 1ull);
+  if (i >= p.cap_solo) {
+    set_err(p, ERR_SOLO_OVERFLOW);
+    return;
+  }
+  p.solo[i] = s;
+  atomicAdd(&p.stats->solo_items, 1ull);
+}
+
+template <class K, int T>
+__device__ inline void push_level(const Params& p, int next_level, const Seg& s) {
+  if (next_level >= p.max_levels) {
+    set_err(p, ERR_LEVEL_OVERFLOW);
+    return;
+  }
+  const unsigned long long nt = tiles_of(s.b, s.e, p.off, (uint64_t)T);
+  const unsigned long long old = atomicAdd(&p.lvl_ctr[next_level].packed, (1ull << 40) | nt);
+  const unsigned long long idx = old >> 40, tb = old & TILE_MASK40;
+  if (idx >= p.cap_lvl || tb + nt > p.cap_tiles) {
+    set_err(p, ERR_LEVEL_OVERFLOW);
+    return;
+  }
+  p.lvl_segs[next_level & 1][idx] = s;
+  p.lvl_tbase[next_level & 1][idx] = tb;
+  atomicAdd(&p.lvl_ctr[next_level].keys, (unsigned long long)(s.e - s.b));
+}
+
+// Route a child range [b, e) (data in the buffer `scratch_side`) after a partition.
+template <class K, int T>
+__device__ inline void route_child(const Params& p, uint64_t b, uint64_t e, uint32_t depth, uint32_t limit,
+                                   bool scratch_side, int next_level) {
+  Seg s{};
+  s.b = b;
+  s.e = e;
+  s.depth = depth;
+  s.limit = limit;
+  s.flags = scratch_side ? SEG_SCRATCH : 0u;
+  const uint64_t len = e - b;
+  if (len == 0) return;
+  if (len <= p.solo_max) {
+    push_solo(p, s);
+  } else if (depth > limit) {
+    s.flags |= SEG_FALLBACK;
+    push_solo(p, s);
+  } else {
+    push_level<K, T>(p, next_level, s);
+  }
+}
+
+// ---- level kernel ------------------------------------------------------------------------
+
+
+template <class K>
+__global__ void __launch_bounds__(LEVEL_P) level_kernel(Params p) {
+  using R = typename K::R;
+  using S = typename K::S;
+  constexpr int I = LEVEL_I;
+  using TL = Tile<K, LEVEL_P, I>;
+  constexpr int T = TL::T;
+  __shared__ S stage[T];
+  __shared__ typename TL::Aux sh;
+  __shared__ unsigned long long sh_ticket;
+  __shared__ unsigned long long sh_excl;
+  __shared__ R sh_segmin;
+  __shared__ int sh_seg;
+
+  const int L = p.level;
+  const unsigned long long packed = p.lvl_ctr[L].packed;
+  const uint32_t nseg = (uint32_t)(packed >> 40);
+  const unsigned long long ntiles = packed & TILE_MASK40;
+  if (ntiles == 0) return;
+  const Seg* segs = p.lvl_segs[L & 1];
+  const unsigned long long* tbase = p.lvl_tbase[L & 1];
+  const bool src_scratch = (L & 1) != 0;
+  const S* src = (const S*)(src_scratch ? p.scratch : p.keys);
+  S* dst = (S*)(src_scratch ? p.keys : p.scratch);
+  const S* src_aligned = src - p.off;
+  const int tmode = (L == 0) ? p.mode : 0;   // only the first level reads untransformed keys
+  const unsigned long long epoch = (unsigned long long)(L + 1) << 48;
+  constexpr unsigned long long ST_AGG = 1ull << 46, ST_INC = 2ull << 46;
+  constexpr unsigned long long VAL_MASK = (1ull << 46) - 1;
+  const int tid = threadIdx.x;
+
+  for (;;) {
+    if (tid == 0) sh_ticket = atomicAdd(&p.lvl_ctr[L].ticket, 1u);
+    __syncthreads();
+    const unsigned long long g = sh_ticket;
+    if (g >= ntiles) break;
+    // segment of tile g: last s with tbase[s] <= g
+    if (tid == 0) {
+      uint32_t lo = 0, hi = nseg;  // invariant: tbase[lo] <= g < tbase[hi] (hi may be nseg)
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (tbase[mid] <= g) lo = mid; else hi = mid;
+      }
+      sh_seg = (int)lo;
+    }
+    __syncthreads();
+    const int si = sh_seg;
+    const Seg sg = segs[si];
+    const unsigned long long g0 = tbase[si];
+    const uint64_t ntile_seg = tiles_of(sg.b, sg.e, p.off, T);
+    const uint64_t k = (sg.b + p.off) / T + (g - g0);
+    const uint64_t vs = (k * T > sg.b + p.off) ? k * T : sg.b + p.off;
+    const uint64_t ve = ((k + 1) * T < sg.e + p.off) ? (k + 1) * T : sg.e + p.off;
+
+    R key[I][K::V];
+    TL::load(src_aligned, k, vs, ve, tmode, key);
+    if (sg.flags & SEG_OVERRIDE) {
+      if (tid == 0) sh.pivot = K::from_u64x2(sg.pv_lo, sg.pv_hi);
+    } else if (tid < WAVE) {
+      const S* sb = src + sg.b;
+      R pv = choose_pivot_wave<K>(
+          [&](uint64_t i) -> R {
+            S s = sb[i];
+            R r;
+            if constexpr (sizeof(S) == sizeof(R)) r = s; else r = (R)s;
+            return tmode ? K::load_t(s, tmode) : r;
+          },
+          sg.b, sg.e, p.seed);
+      if (tid == 0) sh.pivot = pv;
+    }
+    __syncthreads();
+    const R pivot = sh.pivot;
+    R tmin;
+    const uint32_t nl = TL::rank_and_stage(stage, sh, key, k, vs, ve, pivot, &tmin);
+
+    // decoupled look-back on the left counts of the range's earlier tiles
+    if (tid == 0) {
+      uint64_t lo, hi;
+      to_words<K>(tmin, lo, hi);
+      p.tilemin[g] = u128k{lo, hi};
+      unsigned long long excl = 0;
+      if (g != g0) {
+        __hip_atomic_store(&p.flags[g], epoch | ST_AGG | nl, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned long long j = g - 1;
+        uint32_t spins = 0;
+        for (;;) {
+          const unsigned long long f = __hip_atomic_load(&p.flags[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if ((f & ~((1ull << 48) - 1)) != epoch || (f & (3ull << 46)) == 0) {
+            ++spins;
+            if ((spins & 1023u) == 0 &&
+                (spins > (1u << 22) || __hip_atomic_load(p.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+              set_err(p, ERR_SPIN);
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+          }
+          excl += f & VAL_MASK;
+          if (f & ST_INC) break;
+          j--;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      }
+      __hip_atomic_store(&p.flags[g], epoch | ST_INC | (excl + nl), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      sh_excl = excl;
+    }
+    __syncthreads();
+    const unsigned long long excl_l = sh_excl;
+    const uint32_t nvalid = (uint32_t)(ve - vs);
+    const uint64_t before = vs - (sg.b + p.off);             // keys of the range before this tile
+    const uint64_t excl_r = before - excl_l;
+    const uint32_t nr = nvalid - nl;
+    TL::write_out(stage, dst, nl, nvalid, sg.b + excl_l, sg.e - excl_r - nr, 0, p.n_total);
+
+    if (g == g0 + ntile_seg - 1) {
+      // last tile of the range: the range is partitioned; plan what follows
+      const uint64_t bound = sg.b + excl_l + nl;
+      const bool dst_scratch = !src_scratch;
+      if (bound == sg.e) {
+        // degenerate: the minimum of the range decides (Alg. 1, ScanMinMax)
+        R m = K::maxv();
+        for (unsigned long long t = g0 + tid; t <= g; t += LEVEL_P) {
+          const u128k w = p.tilemin[t];
+          m = K::kmin(m, K::from_u64x2(w.lo, w.hi));
+        }
+        m = wave_min<K>(m);
+        if ((tid & (WAVE - 1)) == 0) sh.wmin[tid / WAVE] = m;
+        __syncthreads();
+        if (tid == 0) {
+          R mm = sh.wmin[0];
+          for (int ww = 1; ww < LEVEL_P / WAVE; ww++) mm = K::kmin(mm, sh.wmin[ww]);
+          sh_segmin = mm;
+        }
+        __syncthreads();
+        const R mn = sh_segmin;
+        if (tid == 0) {
+          atomicAdd(&p.stats->partitions, 1ull);
+          atomicAdd(&p.stats->keys_partitioned, (unsigned long long)(sg.e - sg.b));
+          atomicMax(&p.stats->max_depth, (unsigned long long)sg.depth);
+          atomicAdd(&p.stats->degenerate, 1ull);
+        }
+        if (K::eq(mn, pivot)) {
+          if (tid == 0) atomicAdd(&p.stats->all_equal, 1ull);
+          if (p.mode != 0 && L > 0) {
+            // the caller's array holds the value in transformed form: write it back
+            const uint64_t nch = (sg.e - sg.b + FILL_CHUNK - 1) / FILL_CHUNK;
+            __shared__ unsigned long long sh_fill0;
+            if (tid == 0) {
+              sh_fill0 = atomicAdd(&p.solo_ctr->count, (unsigned long long)nch);
+              atomicAdd(&p.stats->solo_items, (unsigned long long)nch);
+            }
+            __syncthreads();
+            uint64_t lo, hi;
+            to_words<K>(pivot, lo, hi);
+            for (uint64_t c = tid; c < nch; c += LEVEL_P) {
+              const unsigned long long i = sh_fill0 + c;
+              if (i >= p.cap_solo) {
+                set_err(p, ERR_SOLO_OVERFLOW);
+                continue;
+              }
+              Seg f{};
+              f.b = sg.b + c * FILL_CHUNK;
+              f.e = (f.b + FILL_CHUNK < sg.e) ? f.b + FILL_CHUNK : sg.e;
+              f.flags = SEG_FILL;
+              f.pv_lo = lo;
+              f.pv_hi = hi;
+              p.solo[i] = f;
+            }
+          }
+        } else if (tid == 0) {
+          Seg s{};
+          s.b = sg.b;
+          s.e = sg.e;
+          s.depth = sg.depth + 1;
+          s.limit = sg.limit;
+          s.flags = SEG_OVERRIDE | (dst_scratch ? SEG_SCRATCH : 0u);
+          to_words<K>(mn, s.pv_lo, s.pv_hi);
+          if (s.depth > s.limit) {
+            s.flags = SEG_FALLBACK | (dst_scratch ? SEG_SCRATCH : 0u);
+            push_solo(p, s);
+          } else {
+            push_level<K, T>(p, L + 1, s);
+          }
+        }
+      } else if (tid == 0) {
+        atomicAdd(&p.stats->partitions, 1ull);
+        atomicAdd(&p.stats->keys_partitioned, (unsigned long long)(sg.e - sg.b));
+        atomicMax(&p.stats->max_depth, (unsigned long long)sg.depth);
+        route_child<K, T>(p, sg.b, bound, sg.depth + 1, sg.limit, dst_scratch, L + 1);
+        route_child<K, T>(p, bound, sg.e, sg.depth + 1, sg.limit, dst_scratch, L + 1);
+      }
+    }
+    if (tid == 0) atomicAdd(&p.stats->level_tiles, 1ull);
+    __syncthreads();
+  }
+}
+
+// ---- base case: 16x16 sorting network in registers (Sec. 2.3, Sec. 3) ------------------
+
+// Green's 16-input network: four hypercube layers, then 28 modules.
+#define VQS_GREEN16(CE)                                                                            \
+  CE(0, 1) CE(2, 3) CE(4, 5) CE(6, 7) CE(8, 9) CE(10, 11) CE(12, 13) CE(14, 15)                  \
+  CE(0, 2) CE(1, 3) CE(4, 6) CE(5, 7) CE(8, 10) CE(9, 11) CE(12, 14) CE(13, 15)                  \
+  CE(0, 4) CE(1, 5) CE(2, 6) CE(3, 7) CE(8, 12) CE(9, 13) CE(10, 14) CE(11, 15)                  \
+  CE(0, 8) CE(1, 9) CE(2, 10) CE(3, 11) CE(4, 12) CE(5, 13) CE(6, 14) CE(7, 15)                  \
+  CE(5, 10) CE(6, 9) CE(3, 12) CE(13, 14) CE(7, 11) CE(1, 2) CE(4, 8)                            \
+  CE(1, 4) CE(7, 13) CE(2, 8) CE(11, 14) CE(5, 6) CE(9, 10)                                      \
+  CE(2, 4) CE(11, 13) CE(3, 8) CE(7, 12)                                                          \
+  CE(6, 8) CE(10, 12) CE(3, 5) CE(7, 9)                                                           \
+  CE(3, 4) CE(5, 6) CE(7, 8) CE(9, 10) CE(11, 12)                                                 \
+  CE(6, 7) CE(8, 9)
+
+// Sorts 16 registers x 16 lanes of each 16-lane group: the group's 256 keys end in
+// sequence order s = 16 * (lane % 16) + register.  Column sort: Green's network in
+// every lane (no lane traffic).  Merges of adjacent groups of w lanes: the flip stage
+// pairs lane l, register r with lane l ^ (2w-1), register 15-r, bringing the two nodes
+// of every module to the same register of two lanes; half-cleaners at lane distances
+// w/2..1 exchange the same register; the last four stages are inside each lane.
+template <class K>
+__device__ inline void network16x16(typename K::R (&x)[16]) {
+  using R = typename K::R;
+  const int gl = lane_id() & 15;
+#define VQS_CE(a, b)                 \
+  {                                  \
+    R lo_ = K::kmin(x[a], x[b]);     \
+    R hi_ = K::kmax(x[a], x[b]);     \
+    x[a] = lo_;                      \
+    x[b] = hi_;                      \
+  }
+  VQS_GREEN16(VQS_CE)
+#pragma unroll
+  for (int w = 1; w < 16; w *= 2) {
+    {
+      const bool up = (gl & w) != 0;
+      R y[16];
+#pragma unroll
+      for (int r = 0; r < 16; r++) y[r] = K::shfl_xor(x[15 - r], 2 * w - 1);
+#pragma unroll
+      for (int r = 0; r < 16; r++) x[r] = up ? K::kmax(x[r], y[r]) : K::kmin(x[r], y[r]);
+    }
+#pragma unroll
+    for (int d = w / 2; d >= 1; d /= 2) {
+      const bool up = (gl & d) != 0;
+#pragma unroll
+      for (int r = 0; r < 16; r++) {
+        R y = K::shfl_xor(x[r], d);
+        x[r] = up ? K::kmax(x[r], y) : K::kmin(x[r], y);
+      }
+    }
+#pragma unroll
+    for (int d = 8; d >= 1; d /= 2) {
+#pragma unroll
+      for (int r = 0; r < 16; r++)
+        if ((r & d) == 0) VQS_CE(r, r + d)
+    }
+  }
+#undef VQS_CE
+}
+
+// ---- local sort in LDS (workgroup) --------------------------------------------------------
+
+constexpr int SOLO_NW = SOLO_P / WAVE;
+constexpr int LIST_CAP = LOCAL_LIST_CAP;
+constexpr int BC_CAP = 256;     // base cases per LDS recursion level
+
+template <class K>
+struct LocalItem {
+  uint32_t lb, le;
+  uint32_t depth;
+  uint32_t flags;  // bit0: in buffer B, bit1: override pivot
+  typename K::R pv;
+};
+
+template <class K>
+struct LocalShared {
+  LocalItem<K> list[2][LIST_CAP];
+  uint32_t bc[BC_CAP];      // (lb << 9 | len-1) << 1 | buffer   (len <= 256)
+  LocalItem<K> fb[LIST_CAP];  // fallbacks of this level
+  uint32_t nlist[2];
+  uint32_t nbc, nfb;
+  uint32_t stat_part, stat_bc, stat_deg, stat_eq, stat_fb, stat_fbkeys, stat_maxd, stat_pkeys;
+};
+
+// Bitonic sort (flip form: every module puts the smaller key at the lower index) of
+// a[0, n) in LDS by the whole workgroup; virtual positions >= n act as +inf and never
+// move, so no padding is stored.  Bounded time: the fallback when the recursion gets
+// deeper than the limit (Sec. 2.2 uses Heapsort there).
+template <class K, class S>
+__device__ void wg_bitonic_lds(S* a, uint32_t n) {
+  using R = typename K::R;
+  uint32_t p2 = 1;
+  while (p2 < n) p2 <<= 1;
+  for (uint32_t kk = 2; kk <= p2; kk <<= 1) {
+    for (uint32_t d = kk; d >= 2; d >>= 1) {
+      const uint32_t half = d >> 1;
+      for (uint32_t idx = threadIdx.x; idx < p2 / 2; idx += blockDim.x) {
+        const uint32_t i = (idx / half) * d + (idx % half);
+        const uint32_t j = (d == kk) ? (i ^ (d - 1)) : (i + half);
+        if (j < n) {
+          R x = (R)a[i], y = (R)a[j];
+          if (K::lt(y, x)) {
+            a[i] = (S)y;
+            a[j] = (S)x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Sort keys [b, e) of `src` (n <= local_cap) in LDS and write them to `out` (the
+// caller's array, output transform applied) or, if out_internal, to `out` in internal
+// form.  bufA/bufB hold local_cap keys each.
+template <class K>
+__device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* bufA, typename K::S* bufB,
+                           const typename K::S* src, bool raw, uint64_t b, uint64_t e, uint32_t depth,
+                           uint32_t limit, bool override_pv, typename K::R pv, typename K::S* out,
+                           bool out_internal) {
+  using R = typename K::R;
+  using S = typename K::S;
+  constexpr int V = K::V;
+  const int tid = threadIdx.x;
+  const int lane = lane_id();
+  const int wave = tid / WAVE;
+  const uint32_t n = (uint32_t)(e - b);
+  const int tmode = raw ? p.mode : 0;
+
+  // 1. load into bufA[0, n) (16-byte aligned chunks in v-space)
+  {
+    const S* src_aligned = src - p.off;
+    const uint64_t vb = b + p.off, ve = e + p.off;
+    const uint64_t c0 = vb / V, c1 = (ve + V - 1) / V;
+    for (uint64_t c = c0 + tid; c < c1; c += SOLO_P) {
+      const uint4 rawc = *reinterpret_cast<const uint4*>(reinterpret_cast<const char*>(src_aligned) + c * 16);
+      R tmp[V];
+      K::unpack(rawc, tmp);
+#pragma unroll
+      for (int q = 0; q < V; q++) {
+        const uint64_t v = c * V + q;
+        if (v >= vb && v < ve) {
+          R r = tmp[q];
+          if (tmode) r = K::load_t((S)r, tmode);
+          bufA[v - vb] = (S)r;
+        }
+      }
+    }
+  }
+  if (tid == 0) {
+    ls.nlist[0] = 0;
+    ls.nlist[1] = 0;
+    ls.nbc = 0;
+    ls.nfb = 0;
+    ls.stat_part = ls.stat_bc = ls.stat_deg = ls.stat_eq = ls.stat_fb = ls.stat_fbkeys = ls.stat_maxd = 0;
+    ls.stat_pkeys = 0;
+    if (n > 0) {
+      if (n <= p.nb) {
+        ls.bc[0] = ((0u << 9) | (n - 1)) << 1;
+        ls.nbc = 1;
+      } else {
+        LocalItem<K> it;
+        it.lb = 0;
+        it.le = n;
+        it.depth = depth;
+        it.flags = override_pv ? 2u : 0u;
+        it.pv = pv;
+        ls.list[0][0] = it;
+        ls.nlist[0] = 1;
+      }
+    }
+  }
+  __syncthreads();
+
+  int cur = 0;
+  for (;;) {
+    const uint32_t nitems = ls.nlist[cur];
+    // 2. partition this level's ranges, one wave per range
+    for (uint32_t it_i = wave; it_i < nitems; it_i += SOLO_NW) {
+      LocalItem<K> it = ls.list[cur][it_i];
+      S* s_buf = (it.flags & 1u) ? bufB : bufA;
+      S* d_buf = (it.flags & 1u) ? bufA : bufB;
+      const uint32_t lb = it.lb, le = it.le;
+      if (it.depth > limit) {
+        if (lane == 0) {
+          const uint32_t f = atomicAdd(&ls.nfb, 1u);
+          if (f < LIST_CAP) ls.fb[f] = it;
+          else set_err(p, ERR_LOCAL_OVERFLOW);
+        }
+        continue;
+      }
+      R pivot;
+      if (it.flags & 2u) {
+        pivot = it.pv;
+      } else {
+        const S* sb = s_buf + lb;
+        pivot = choose_pivot_wave<K>([&](uint64_t i) -> R { return (R)sb[i]; }, b + lb, b + le, p.seed);
+      }
+      uint32_t l = lb, r = le;
+      R mn = K::maxv();
+      for (uint32_t base = lb; base < le; base += WAVE) {
+        const uint32_t i = base + lane;
+        const bool valid = i < le;
+        R kx = valid ? (R)s_buf[i] : K::maxv();
+        const bool isl = valid && !K::lt(pivot, kx);
+        const bool isr = valid && !isl;
+        if (valid) mn = K::kmin(mn, kx);
+        const uint64_t ml = ballot(isl), mr = ballot(isr);
+        if (isl) d_buf[l + mbcnt(ml)] = (S)kx;
+        if (isr) d_buf[r - 1 - mbcnt(mr)] = (S)kx;
+        l += __popcll(ml);
+        r -= __popcll(mr);
+      }
+      mn = wave_min<K>(mn);
+      const uint32_t bound = l;
+      const uint32_t nbuf = (it.flags & 1u) ? 0u : 1u;   // children live in d_buf
+      if (lane == 0) {
+        atomicAdd(&ls.stat_part, 1u);
+        atomicAdd(&ls.stat_pkeys, le - lb);
+        atomicMax(&ls.stat_maxd, it.depth);
+      }
+      if (bound == le) {
+        if (lane == 0) atomicAdd(&ls.stat_deg, 1u);
+        if (K::eq(mn, pivot)) {
+          // all equal: done; make sure the keys sit in bufA
+          if (lane == 0) atomicAdd(&ls.stat_eq, 1u);
+          if (nbuf == 1) {
+            for (uint32_t i = lb + lane; i < le; i += WAVE) bufA[i] = bufB[i];
+          }
+        } else if (lane == 0) {
+          LocalItem<K> c;
+          c.lb = lb;
+          c.le = le;
+          c.depth = it.depth + 1;
+          c.flags = nbuf | 2u;
+          c.pv = mn;
+          const uint32_t s = atomicAdd(&ls.nlist[cur ^ 1], 1u);
+          if (s < LIST_CAP) ls.list[cur ^ 1][s] = c;
+          else set_err(p, ERR_LOCAL_OVERFLOW);
+        }
+      } else if (lane == 0) {
+        const uint32_t cb[2] = {lb, bound}, ce[2] = {bound, le};
+        for (int c = 0; c < 2; c++) {
+          const uint32_t len = ce[c] - cb[c];
+          if (len == 0) continue;
+          if (len <= p.nb) {
+            const uint32_t s = atomicAdd(&ls.nbc, 1u);
+            if (s < BC_CAP) ls.bc[s] = ((cb[c] << 9) | (len - 1)) << 1 | nbuf;
+            else set_err(p, ERR_LOCAL_OVERFLOW);
+          } else {
+            LocalItem<K> ci;
+            ci.lb = cb[c];
+            ci.le = ce[c];
+            ci.depth = it.depth + 1;
+            ci.flags = nbuf;
+            ci.pv = pivot;
+            const uint32_t s = atomicAdd(&ls.nlist[cur ^ 1], 1u);
+            if (s < LIST_CAP) ls.list[cur ^ 1][s] = ci;
+            else set_err(p, ERR_LOCAL_OVERFLOW);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // 3. base cases of this level: four per wave, one per 16-lane group
+    const uint32_t nbc = ls.nbc < BC_CAP ? ls.nbc : BC_CAP;
+    for (uint32_t q0 = wave * 4; q0 < nbc; q0 += SOLO_NW * 4) {
+      const uint32_t qi = q0 + (lane >> 4);
+      const int gl = lane & 15;
+      uint32_t lb = 0, len = 0, inb = 0;
+      if (qi < nbc) {
+        const uint32_t w = ls.bc[qi];
+        inb = w & 1u;
+        len = ((w >> 1) & 511u) + 1;
+        lb = w >> 10;
+      }
+      const S* s_buf = inb ? bufB : bufA;
+      R x[16];
+#pragma unroll
+      for (int r = 0; r < 16; r++) {
+        const uint32_t pos = (uint32_t)(16 * r + gl);
+        x[r] = pos < len ? (R)s_buf[lb + pos] : K::maxv();
+      }
+      network16x16<K>(x);
+#pragma unroll
+      for (int r = 0; r < 16; r++) {
+        const uint32_t pos = (uint32_t)(16 * gl + r);
+        if (pos < len) bufA[lb + pos] = (S)x[r];
+      }
+    }
+    // 4. fallbacks of this level (whole workgroup, one range at a time)
+    __syncthreads();
+    const uint32_t nfb = ls.nfb < LIST_CAP ? ls.nfb : LIST_CAP;
+    for (uint32_t f = 0; f < nfb; f++) {
+      const LocalItem<K> it = ls.fb[f];
+      S* a = (it.flags & 1u) ? bufB : bufA;
+      wg_bitonic_lds<K, S>(a + it.lb, it.le - it.lb);
+      if (it.flags & 1u) {
+        for (uint32_t i = it.lb + tid; i < it.le; i += SOLO_P) bufA[i] = bufB[i];
+      }
+      if (tid == 0) {
+        ls.stat_fb++;
+        ls.stat_fbkeys += it.le - it.lb;
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      ls.stat_bc += ls.nbc;
+      ls.nbc = 0;
+      ls.nfb = 0;
+      ls.nlist[cur] = 0;
+    }
+    __syncthreads();
+    cur ^= 1;
+    if (ls.nlist[cur] == 0) break;
+  }
+  __syncthreads();
+  // 5. write out
+  for (uint32_t i = tid; i < n; i += SOLO_P) {
+    S val = bufA[i];
+    if (!out_internal && p.mode) val = K::store_t((R)val, p.mode);
+    out[b + i] = val;
+  }
+  if (tid == 0) {
+    if (ls.stat_part) {
+      atomicAdd(&p.stats->partitions, (unsigned long long)ls.stat_part);
+      atomicAdd(&p.stats->lds_partitions, (unsigned long long)ls.stat_part);
+      atomicAdd(&p.stats->keys_partitioned, (unsigned long long)ls.stat_pkeys);
+      atomicMax(&p.stats->max_depth, (unsigned long long)ls.stat_maxd);
+    }
+    if (ls.stat_bc) atomicAdd(&p.stats->basecases, (unsigned long long)ls.stat_bc);
+    if (ls.stat_deg) atomicAdd(&p.stats->degenerate, (unsigned long long)ls.stat_deg);
+    if (ls.stat_eq) atomicAdd(&p.stats->all_equal, (unsigned long long)ls.stat_eq);
+    if (ls.stat_fb) {
+      atomicAdd(&p.stats->fallbacks, (unsigned long long)ls.stat_fb);
+      atomicAdd(&p.stats->fallback_keys, (unsigned long long)ls.stat_fbkeys);
+    }
+  }
+  __syncthreads();
+}
+
+
+// ---- solo kernel: whole ranges per workgroup ------------------------------------------
+
+constexpr int STACK_CAP = 48;
+
+// Fill keys[b, e) of the caller's array with one value (output transform applied).
+template <class K>
+__device__ void fill_range(const Params& p, uint64_t b, uint64_t e, typename K::R v) {
+  using S = typename K::S;
+  S* out = (S*)p.keys;
+  const S val = K::store_t(v, p.mode);
+  for (uint64_t i = b + threadIdx.x; i < e; i += blockDim.x) out[i] = val;
+}
+
+// Merge-path merge of sorted runs a[0, na) and c[0, nc) into o[0, na + nc) by the
+// workgroup (ties take a first).
+template <class K>
+__device__ void wg_merge(const typename K::S* a, uint64_t na, const typename K::S* c, uint64_t nc,
+                         typename K::S* out) {
+  using R = typename K::R;
+  const uint64_t total = na + nc;
+  const uint64_t per = (total + blockDim.x - 1) / blockDim.x;
+  const uint64_t o0 = per * threadIdx.x;
+  if (o0 >= total) return;
+  const uint64_t o1 = (o0 + per < total) ? o0 + per : total;
+  uint64_t lo = o0 > nc ? o0 - nc : 0, hi = o0 < na ? o0 : na;
+  while (lo < hi) {
+    const uint64_t mid = (lo + hi) / 2;
+    if (!K::lt((R)c[o0 - mid - 1], (R)a[mid])) lo = mid + 1;
+    else hi = mid;
+  }
+  uint64_t i = lo, j = o0 - lo;
+  for (uint64_t o = o0; o < o1; o++) {
+    bool take_a;
+    if (i >= na) take_a = false;
+    else if (j >= nc) take_a = true;
+    else take_a = !K::lt((R)c[j], (R)a[i]);
+    if (take_a) out[o] = a[i++];
+    else out[o] = c[j++];
+  }
+}
+
+// Bounded-time fallback for a range past the depth limit (Sec. 2.2 uses Heapsort):
+// sort LDS-sized chunks with the bitonic network, then merge runs pairwise through the
+// two global buffers; the result goes to the caller's array.  O(n log n) work.
+template <class K>
+__device__ void fallback_global(const Params& p, typename K::S* bufA, const Seg& it) {
+  using R = typename K::R;
+  using S = typename K::S;
+  const uint64_t b = it.b, e = it.e, n = e - b;
+  S* X = (S*)((it.flags & SEG_SCRATCH) ? p.scratch : p.keys);
+  S* Y = (S*)((it.flags & SEG_SCRATCH) ? p.keys : p.scratch);
+  const int tmode = (it.flags & SEG_RAW) ? p.mode : 0;
+  const uint64_t C = p.local_cap;
+  // 1. chunks: X -> LDS -> sorted -> X (internal form)
+  for (uint64_t c0 = b; c0 < e; c0 += C) {
+    const uint32_t m = (uint32_t)((c0 + C < e) ? C : e - c0);
+    for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) {
+      S s = X[c0 + i];
+      bufA[i] = tmode ? (S)K::load_t(s, tmode) : s;
+    }
+    __syncthreads();
+    wg_bitonic_lds<K, S>(bufA, m);
+    for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) X[c0 + i] = bufA[i];
+    __syncthreads();
+  }
+  // 2. merge passes
+  S* from = X;
+  S* to = Y;
+  for (uint64_t w = C; w < n; w *= 2) {
+    for (uint64_t s = 0; s < n; s += 2 * w) {
+      const uint64_t na = (s + w < n) ? w : n - s;
+      const uint64_t nc = (s + 2 * w < n) ? w : (s + w < n ? n - s - w : 0);
+      wg_merge<K>(from + b + s, na, from + b + s + na, nc, to + b + s);
+    }
+    __syncthreads();
+    S* t = from;
+    from = to;
+    to = t;
+  }
+  // 3. output transform into the caller's array
+  S* out = (S*)p.keys;
+  if (from != out || p.mode != 0) {
+    for (uint64_t i = b + threadIdx.x; i < e; i += blockDim.x) {
+      S v = from[i];
+      out[i] = p.mode ? K::store_t((R)v, p.mode) : v;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicAdd(&p.stats->fallbacks, 1ull);
+    atomicAdd(&p.stats->fallback_keys, (unsigned long long)n);
+  }
+}
+
+template <class K>
+__global__ void __launch_bounds__(SOLO_P) solo_kernel(Params p) {
+  using R = typename K::R;
+  using S = typename K::S;
+  using TL = Tile<K, SOLO_P, SOLO_I>;
+  constexpr int T = TL::T;
+  static_assert(T * sizeof(S) <= LOCAL_BYTES, "tile staging must fit one LDS buffer");
+  __shared__ __attribute__((aligned(16))) char lds_raw[2 * LOCAL_BYTES];
+  __shared__ LocalShared<K> ls;
+  __shared__ typename TL::Aux aux;
+  __shared__ Seg stack[STACK_CAP];
+  __shared__ int sp;
+  __shared__ unsigned long long sh_item;
+  __shared__ R sh_min;
+  S* bufA = (S*)lds_raw;
+  S* bufB = (S*)(lds_raw + LOCAL_BYTES);
+  const int tid = threadIdx.x;
+  const unsigned long long count = p.solo_ctr->count;
+  const unsigned long long nitems = count < p.cap_solo ? count : p.cap_solo;
+
+  for (;;) {
+    if (tid == 0) sh_item = atomicAdd(&p.solo_ctr->ticket, 1ull);
+    __syncthreads();
+    const unsigned long long ii = sh_item;
+    if (ii >= nitems) break;
+    const Seg item = p.solo[ii];
+    if (item.flags & SEG_FILL) {
+      fill_range<K>(p, item.b, item.e, K::from_u64x2(item.pv_lo, item.pv_hi));
+      __syncthreads();
+      continue;
+    }
+    if (tid == 0) {
+      stack[0] = item;
+      sp = 1;
+    }
+    __syncthreads();
+    while (sp > 0) {
+      const Seg cur = stack[sp - 1];
+      __syncthreads();
+      if (tid == 0) sp--;
+      const uint64_t n = cur.e - cur.b;
+      const bool in_scratch = (cur.flags & SEG_SCRATCH) != 0;
+      const S* src = (const S*)(in_scratch ? p.scratch : p.keys);
+      S* dst = (S*)(in_scratch ? p.keys : p.scratch);
+      const bool raw = (cur.flags & SEG_RAW) != 0;
+      if (cur.flags & SEG_FALLBACK) {
+        fallback_global<K>(p, bufA, cur);
+        __syncthreads();
+        continue;
+      }
+      if (n <= p.local_cap) {
+        local_sort<K>(p, ls, bufA, bufB, src, raw, cur.b, cur.e, cur.depth, cur.limit,
+                      (cur.flags & SEG_OVERRIDE) != 0, K::from_u64x2(cur.pv_lo, cur.pv_hi), (S*)p.keys, false);
+        continue;
+      }
+      if (cur.depth > cur.limit) {
+        fallback_global<K>(p, bufA, cur);
+        __syncthreads();
+        continue;
+      }
+      // pivot
+      if (cur.flags & SEG_OVERRIDE) {
+        if (tid == 0) aux.pivot = K::from_u64x2(cur.pv_lo, cur.pv_hi);
+      } else if (tid < WAVE) {
+        const S* sb = src + cur.b;
+        const int tm = raw ? p.mode : 0;
+        R pv = choose_pivot_wave<K>(
+            [&](uint64_t i) -> R {
+              S s = sb[i];
+              R r;
+              if constexpr (sizeof(S) == sizeof(R)) r = s; else r = (R)s;
+              return tm ? K::load_t(s, tm) : r;
+            },
+            cur.b, cur.e, p.seed);
+        if (tid == 0) aux.pivot = pv;
+      }
+      __syncthreads();
+      const R pivot = aux.pivot;
+      // partition tile by tile: src -> dst
+      const S* src_aligned = src - p.off;
+      const uint64_t k0 = (cur.b + p.off) / T, k1 = (cur.e - 1 + p.off) / T;
+      uint64_t excl_l = 0, excl_r = 0;
+      R mn = K::maxv();
+      for (uint64_t k = k0; k <= k1; k++) {
+        const uint64_t vs = (k * T > cur.b + p.off) ? k * T : cur.b + p.off;
+        const uint64_t ve = ((k + 1) * T < cur.e + p.off) ? (k + 1) * T : cur.e + p.off;
+        R key[SOLO_I][K::V];
+        TL::load(src_aligned, k, vs, ve, raw ? p.mode : 0, key);
+        R tmin;
+        const uint32_t nl = TL::rank_and_stage(bufA, aux, key, k, vs, ve, pivot, &tmin);
+        const uint32_t nvalid = (uint32_t)(ve - vs);
+        const uint32_t nr = nvalid - nl;
+        TL::write_out(bufA, dst, nl, nvalid, cur.b + excl_l, cur.e - excl_r - nr, 0, p.n_total);
+        excl_l += nl;
+        excl_r += nr;
+        if (tid == 0) mn = K::kmin(mn, tmin);
+        __syncthreads();
+      }
+      const uint64_t bound = cur.b + excl_l;
+      if (tid == 0) {
+        sh_min = mn;
+        atomicAdd(&p.stats->partitions, 1ull);
+        atomicAdd(&p.stats->global_solo_partitions, 1ull);
+        atomicAdd(&p.stats->keys_partitioned, (unsigned long long)n);
+        atomicMax(&p.stats->max_depth, (unsigned long long)cur.depth);
+      }
+      __syncthreads();
+      const uint32_t child_flags = in_scratch ? 0u : SEG_SCRATCH;
+      if (bound == cur.e) {
+        const R segmin = sh_min;
+        if (tid == 0) atomicAdd(&p.stats->degenerate, 1ull);
+        if (K::eq(segmin, pivot)) {
+          if (tid == 0) atomicAdd(&p.stats->all_equal, 1ull);
+          // the caller's array holds the value already, transformed unless raw
+          if (p.mode != 0 && !raw) fill_range<K>(p, cur.b, cur.e, pivot);
+          __syncthreads();
+        } else if (tid == 0) {
+          Seg s = cur;
+          s.depth = cur.depth + 1;
+          s.flags = child_flags | SEG_OVERRIDE;
+          to_words<K>(segmin, s.pv_lo, s.pv_hi);
+          if (sp < STACK_CAP) stack[sp++] = s;
+          else set_err(p, ERR_STACK);
+        }
+      } else if (tid == 0) {
+        Seg l = cur, r = cur;
+        l.e = bound;
+        r.b = bound;
+        l.depth = r.depth = cur.depth + 1;
+        l.flags = r.flags = child_flags;
+        // larger first, so the smaller range is taken next (stack depth <= log2 n)
+        const bool left_small = (bound - cur.b) <= (cur.e - bound);
+        const Seg& first = left_small ? r : l;
+        const Seg& second = left_small ? l : r;
+        if (sp + 2 <= STACK_CAP) {
+          stack[sp++] = first;
+          stack[sp++] = second;
+        } else {
+          set_err(p, ERR_STACK);
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ---- setup ----------------------------------------------------------------------------------
+
+// Clear counters, statistics and look-back words.
+template <class K>
+__global__ void clear_kernel(Params p) {
+  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = gid; i < p.cap_tiles; i += stride) p.flags[i] = 0;
+  for (uint64_t i = gid; i < (uint64_t)p.max_levels; i += stride) {
+    p.lvl_ctr[i].packed = 0;
+    p.lvl_ctr[i].keys = 0;
+    p.lvl_ctr[i].ticket = 0;
+    p.lvl_ctr[i].pad = 0;
+    p.lvl_ctr[i].pad2 = 0;
+  }
+  if (gid == 0) {
+    p.solo_ctr->count = 0;
+    p.solo_ctr->ticket = 0;
+    *p.err = 0;
+    unsigned long long* st = (unsigned long long*)p.stats;
+    for (size_t i = 0; i < sizeof(DevStats) / 8; i++) st[i] = 0;
+  }
+}
+
+// Route the input ranges: offsets (nseg + 1 entries), or [0, n) when offsets is null.
+template <class K>
+__global__ void seed_kernel(Params p, const int64_t* offsets, uint64_t nseg) {
+  using TL = Tile<K, LEVEL_P, LEVEL_I>;
+  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = gid; i < nseg; i += stride) {
+    const uint64_t b = offsets ? (uint64_t)offsets[i] : 0;
+    const uint64_t e = offsets ? (uint64_t)offsets[i + 1] : p.n_total;
+    if (e <= b) continue;
+    Seg s{};
+    s.b = b;
+    s.e = e;
+    s.depth = 1;
+    s.limit = p.fixed_limit >= 0 ? (uint32_t)p.fixed_limit : depth_limit_of(e - b);
+    s.flags = SEG_RAW;
+    if (e - b <= p.solo_max) push_solo(p, s);
+    else push_level<K, TL::T>(p, 0, s);
+  }
+}
+
+}  // namespace vqs

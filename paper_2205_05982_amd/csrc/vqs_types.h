@@ -1,0 +1,95 @@
+// vqs_types.h -- structures and launch constants shared by the kernels and the host.
+#pragma once
+#include <stdint.h>
+
+namespace vqs {
+
+struct u128k {
+  uint64_t lo, hi;
+};
+
+// transform mode bits of the caller's keys
+constexpr int MODE_FLOAT = 1;
+constexpr int MODE_DESC = 2;
+
+constexpr int LEVEL_P = 256;        // threads per level-kernel workgroup
+constexpr int LEVEL_I = 4;          // 16-byte chunks per thread: 16 KB tiles
+constexpr int SOLO_P = 256;         // threads per solo-kernel workgroup
+constexpr int SOLO_I = 8;           // 16-byte chunks per thread per solo tile (32 KB)
+constexpr int LOCAL_BYTES = 32768;  // one LDS buffer of the local sort
+constexpr int LOCAL_LIST_CAP = 64;  // ranges per LDS recursion level
+
+// ---- shared structures -------------------------------------------------------------
+
+enum : uint32_t {
+  SEG_OVERRIDE = 1u,   // pivot given (degenerate re-partition with the first key)
+  SEG_SCRATCH = 2u,    // data lives in the scratch buffer (else in the caller's array)
+  SEG_RAW = 4u,        // data not yet transformed (caller's array, never touched)
+  SEG_FALLBACK = 8u,   // depth limit exceeded: bounded-time fallback sort
+  SEG_FILL = 16u,      // all keys equal: write pv to [b, e) of the caller's array
+};
+
+struct Seg {
+  uint64_t b, e;
+  uint32_t depth, limit;
+  uint32_t flags, pad;
+  uint64_t pv_lo, pv_hi;  // override pivot or fill value (internal form)
+};
+
+struct LevelCtr {
+  unsigned long long packed;  // (segments << 40) | tiles
+  unsigned long long keys;    // keys in the level's ranges
+  unsigned int ticket;
+  unsigned int pad;
+  unsigned long long pad2;
+};
+
+struct SoloCtr {
+  unsigned long long count;
+  unsigned long long ticket;
+};
+
+// Counters of the recursion, comparable one to one with the oracle's.
+struct DevStats {
+  unsigned long long partitions, keys_partitioned, degenerate, all_equal, basecases, fallbacks,
+      fallback_keys, max_depth;
+  unsigned long long level_tiles, solo_items, lds_partitions, global_solo_partitions;
+};
+
+enum : uint32_t {
+  ERR_LEVEL_OVERFLOW = 1u,
+  ERR_SOLO_OVERFLOW = 2u,
+  ERR_SPIN = 4u,
+  ERR_LOCAL_OVERFLOW = 8u,
+  ERR_STACK = 16u,
+};
+
+struct Params {
+  void* keys;            // caller's array
+  void* scratch;         // ping-pong buffer, same 16-byte alignment offset as keys
+  uint64_t n_total;
+  int off;               // keys before the first 16-byte boundary: (addr % 16) / size
+  int mode;              // MODE_FLOAT | MODE_DESC transform of the caller's keys
+  uint64_t seed;
+  uint32_t nb;           // NBaseCase (<= 256)
+  uint32_t local_cap;    // keys per LDS local sort (<= LDS buffer capacity)
+  uint64_t solo_max;     // ranges up to this length go to the solo kernel
+  Seg* lvl_segs[2];
+  unsigned long long* lvl_tbase[2];
+  LevelCtr* lvl_ctr;
+  unsigned long long* flags;  // look-back words, one per tile
+  u128k* tilemin;        // per-tile minimum (internal form)
+  Seg* solo;
+  SoloCtr* solo_ctr;
+  DevStats* stats;
+  unsigned int* err;
+  uint64_t cap_lvl, cap_tiles, cap_solo;
+  int level;
+  int max_levels;
+  int64_t fixed_limit;   // < 0: 2*floor(log2 len)+4 per input range; else this limit
+};
+
+constexpr uint64_t FILL_CHUNK = 1ull << 16;
+constexpr uint64_t TILE_MASK40 = (1ull << 40) - 1;
+
+}  // namespace vqs

@@ -1,0 +1,203 @@
+"""Python binding of libvqs.so (argument marshalling only).
+
+Every step of the sort runs in the library's HIP kernels; PyTorch only provides
+device memory and the current stream.  If the shared library is missing the
+import fails loudly: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvqs.so")
+
+U16, U32, U64, U128, F32, F64 = 1, 2, 3, 4, 5, 6
+PLAIN, LEARNED = 0, 1
+KEY_SIZE = {U16: 2, U32: 4, U64: 8, U128: 16, F32: 4, F64: 8}
+
+_DTYPE_TO_KT = {torch.float32: F32, torch.float64: F64}
+for _name, _kt in (("uint16", U16), ("uint32", U32), ("uint64", U64)):
+    if hasattr(torch, _name):
+        _DTYPE_TO_KT[getattr(torch, _name)] = _kt
+_ERRORS = {-1: "invalid argument", -2: "unknown key type", -3: "workspace allocation failed",
+           -4: "HIP runtime error", -5: "segment offsets decrease", -6: "device capacity check failed"}
+
+
+class VqsError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {_ERRORS.get(code, 'error')} ({code})")
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("method", ctypes.c_uint32),
+                ("seed", ctypes.c_uint64), ("depth_limit", ctypes.c_int64),
+                ("base_case", ctypes.c_uint32), ("local_keys", ctypes.c_uint32),
+                ("solo_max", ctypes.c_uint64), ("use_graph", ctypes.c_uint32),
+                ("validate", ctypes.c_uint32), ("train_steps", ctypes.c_uint32),
+                ("batch", ctypes.c_uint32), ("sample_fraction", ctypes.c_float),
+                ("overflow_factor", ctypes.c_float), ("learning_rate", ctypes.c_float),
+                ("reserved", ctypes.c_uint32 * 7)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in (
+        "partitions", "keys_partitioned", "degenerate", "all_equal", "basecases", "fallbacks",
+        "fallback_keys", "max_depth", "levels", "level_tiles", "solo_items", "lds_partitions",
+        "learned_buckets", "overflow_buckets", "max_bucket")] + [("train_loss", ctypes.c_double)]
+
+    def as_dict(self):
+        return {n: (float(getattr(self, n)) if n == "train_loss" else int(getattr(self, n)))
+                for n, _ in self._fields_}
+
+
+class KernelTime(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("level", ctypes.c_int32), ("keys", ctypes.c_uint64),
+                ("ms", ctypes.c_double)]
+
+
+KERNEL_KINDS = {0: "clear", 1: "seed", 2: "level_partition", 3: "solo", 4: "learned_sample",
+                5: "learned_train", 6: "learned_thresholds", 7: "learned_scatter"}
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2205_05982_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, u64, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int
+        L.vqs_sort.argtypes = [vp, u64, i32, i32]
+        L.vqs_sort_ex.argtypes = [vp, u64, i32, i32, ctypes.POINTER(Options), vp]
+        L.vqs_sort_segmented.argtypes = [vp, vp, u64, i32, i32]
+        L.vqs_sort_segmented_ex.argtypes = [vp, vp, u64, i32, i32, ctypes.POINTER(Options), vp]
+        L.vqs_workspace_bytes.argtypes = [u64, u64, i32, ctypes.POINTER(Options)]
+        L.vqs_workspace_bytes.restype = u64
+        L.vqs_get_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+        L.vqs_last_error_bits.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32)]
+        L.vqs_strerror.argtypes = [i32]
+        L.vqs_strerror.restype = ctypes.c_char_p
+        L.vqs_profile.argtypes = [i32]
+        L.vqs_profile_read.argtypes = [vp, ctypes.POINTER(KernelTime), i32, ctypes.POINTER(i32)]
+        for name in ("vqs_profile", "vqs_profile_read", "vqs_sort", "vqs_sort_ex", "vqs_sort_segmented", "vqs_sort_segmented_ex",
+                     "vqs_get_stats", "vqs_last_error_bits", "vqs_release", "vqs_version"):
+            getattr(L, name).restype = i32
+        _lib = L
+    return _lib
+
+
+def make_options(**kw) -> Options:
+    o = Options()
+    o.struct_size = ctypes.sizeof(Options)
+    for k, v in kw.items():
+        if v is None:
+            continue
+        if k == "method" and isinstance(v, str):
+            v = {"plain": PLAIN, "learned": LEARNED}[v]
+        setattr(o, k, v)
+    return o
+
+
+def key_type_of(t: torch.Tensor, key_type: int | None = None) -> int:
+    if key_type is not None:
+        return key_type
+    if t.dim() == 2 and t.shape[1] == 2 and t.element_size() == 8:
+        raise ValueError("pass key_type=U128 (or U64) explicitly for a 2-column tensor")
+    kt = _DTYPE_TO_KT.get(t.dtype)
+    if kt is None:
+        raise TypeError(f"no key type for dtype {t.dtype}; pass key_type")
+    return kt
+
+
+def _nkeys(t: torch.Tensor, kt: int) -> int:
+    return t.numel() * t.element_size() // KEY_SIZE[kt]
+
+
+def _stream_handle(stream) -> int | None:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _check(t: torch.Tensor):
+    if not t.is_cuda:
+        raise ValueError("keys must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError("keys must be contiguous")
+
+
+def sort(t: torch.Tensor, ascending: bool = True, key_type: int | None = None, stream=None, **opts) -> torch.Tensor:
+    """Sort t in place (the whole tensor is one array of keys); returns t."""
+    _check(t)
+    kt = key_type_of(t, key_type)
+    o = make_options(**opts)
+    rc = lib().vqs_sort_ex(ctypes.c_void_p(t.data_ptr()), _nkeys(t, kt), kt, int(bool(ascending)),
+                           ctypes.byref(o), ctypes.c_void_p(_stream_handle(stream)))
+    if rc != 0:
+        raise VqsError(rc, "vqs_sort")
+    return t
+
+
+def sort_segmented(t: torch.Tensor, offsets: torch.Tensor, ascending: bool = True,
+                   key_type: int | None = None, stream=None, **opts) -> torch.Tensor:
+    """Sort every segment [offsets[i], offsets[i+1]) of t in place (offsets: int64 on the GPU)."""
+    _check(t)
+    if offsets.dtype != torch.int64 or not offsets.is_cuda or not offsets.is_contiguous():
+        raise ValueError("offsets must be a contiguous int64 GPU tensor")
+    kt = key_type_of(t, key_type)
+    o = make_options(**opts)
+    rc = lib().vqs_sort_segmented_ex(ctypes.c_void_p(t.data_ptr()), ctypes.c_void_p(offsets.data_ptr()),
+                                     offsets.numel() - 1, kt, int(bool(ascending)), ctypes.byref(o),
+                                     ctypes.c_void_p(_stream_handle(stream)))
+    if rc != 0:
+        raise VqsError(rc, "vqs_sort_segmented")
+    return t
+
+
+def get_stats(stream=None) -> dict:
+    st = Stats()
+    rc = lib().vqs_get_stats(ctypes.c_void_p(_stream_handle(stream)), ctypes.byref(st))
+    if rc != 0:
+        raise VqsError(rc, "vqs_get_stats")
+    return st.as_dict()
+
+
+def last_error_bits(stream=None) -> int:
+    v = ctypes.c_uint32(0)
+    rc = lib().vqs_last_error_bits(ctypes.c_void_p(_stream_handle(stream)), ctypes.byref(v))
+    if rc != 0:
+        raise VqsError(rc, "vqs_last_error_bits")
+    return int(v.value)
+
+
+def workspace_bytes(n: int, key_type: int, nseg: int = 1, **opts) -> int:
+    o = make_options(**opts)
+    return int(lib().vqs_workspace_bytes(n, nseg, key_type, ctypes.byref(o)))
+
+
+def release() -> None:
+    lib().vqs_release()
+
+
+def version() -> int:
+    return int(lib().vqs_version())
+
+
+def profile(enable: bool) -> None:
+    """Record HIP events around every kernel launch of later calls."""
+    lib().vqs_profile(int(bool(enable)))
+
+
+def profile_read(stream=None, max_records: int = 4096) -> list:
+    arr = (KernelTime * max_records)()
+    cnt = ctypes.c_int(0)
+    rc = lib().vqs_profile_read(ctypes.c_void_p(_stream_handle(stream)), arr, max_records, ctypes.byref(cnt))
+    if rc != 0:
+        raise VqsError(rc, "vqs_profile_read")
+    return [{"kind": KERNEL_KINDS.get(arr[i].kind, str(arr[i].kind)), "level": arr[i].level,
+             "keys": int(arr[i].keys), "ms": float(arr[i].ms)} for i in range(cnt.value)]

@@ -1,0 +1,62 @@
+"""The C-ABI library: it loads on a machine without a GPU and exports every entry
+point include/vqs.h declares; argument checks that return before any HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vqs.h")
+LIB = os.path.join(ROOT, "paper_2205_05982_amd", "libvqs.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(vqs_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2205_05982_amd import build
+        build.build(verbose=False)
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_interface():
+    names = declared_functions()
+    for n in ("vqs_sort", "vqs_sort_segmented", "vqs_sort_ex", "vqs_sort_segmented_ex",
+              "vqs_get_stats", "vqs_strerror", "vqs_workspace_bytes"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_strerror_and_version(lib):
+    lib.vqs_strerror.restype = ctypes.c_char_p
+    assert lib.vqs_strerror(0) == b"success"
+    assert lib.vqs_strerror(-2) == b"unknown key type"
+    assert lib.vqs_version() >= 10000
+
+
+def test_argument_errors_return_before_any_device_call(lib):
+    vp, u64, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int
+    lib.vqs_sort_ex.argtypes = [vp, u64, i32, i32, vp, vp]
+    assert lib.vqs_sort_ex(None, 10, 9, 1, None, None) == -2      # unknown key type
+    assert lib.vqs_sort_ex(None, 10, 3, 2, None, None) == -1      # ascending not 0/1
+    assert lib.vqs_sort_ex(None, 0, 3, 1, None, None) == 0        # nothing to sort
+    assert lib.vqs_sort_ex(None, 10, 3, 1, None, None) == -1      # null keys
+    assert lib.vqs_sort_ex(ctypes.c_void_p(0x1004), 10, 3, 1, None, None) == -1   # misaligned u64
+
+
+def test_options_layout_matches_binding():
+    from paper_2205_05982_amd import vqs
+    # struct vqs_options: 2*u32, u64, i64, 2*u32, u64, 4*u32, 3*float, 7*u32 (+ padding)
+    assert ctypes.sizeof(vqs.Options) == 96
+    assert vqs.Options.train_steps.offset == 48
+    assert ctypes.sizeof(vqs.Stats) == 16 * 8
