@@ -49,6 +49,7 @@ struct ProfRec {
 };
 
 bool g_profile = false;
+unsigned long long* g_dbg = nullptr;  // per-phase cycle totals (instrumented builds)
 
 struct Workspace {
   int device = 0;
@@ -407,6 +408,14 @@ int sort_impl(void* keys, const int64_t* offsets, uint64_t nseg, uint64_t n, int
   base.level = 0;
   ws->have_result = false;
   base.fixed_limit = pl.depth_limit;
+#ifdef VQS_PHASE_TIMING
+  static unsigned long long* dbg = nullptr;
+  if (!dbg && hipMalloc(&dbg, 64) == hipSuccess) (void)hipMemset(dbg, 0, 64);
+  base.dbg = dbg;
+  g_dbg = dbg;
+#else
+  base.dbg = nullptr;
+#endif
   int levels = 0;
   hipError_t e;
   if (learned) {
@@ -620,5 +629,16 @@ const char* vqs_strerror(int code) {
 }
 
 int vqs_version(void) { return VERSION; }
+
+#ifdef VQS_PHASE_TIMING
+// Instrumented builds only: per-phase cycle totals of the level kernel, then reset.
+int vqs_debug_phase_read(uint64_t out[8]) {
+  if (!g_dbg) return VQS_EINVAL;
+  if (hipDeviceSynchronize() != hipSuccess || hipMemcpy(out, g_dbg, 64, hipMemcpyDeviceToHost) != hipSuccess)
+    return VQS_EHIP;
+  (void)hipMemset(g_dbg, 0, 64);
+  return VQS_OK;
+}
+#endif
 
 }  // extern "C"

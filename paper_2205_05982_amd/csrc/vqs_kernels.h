@@ -30,6 +30,30 @@ namespace vqs {
 
 __device__ inline void set_err(const Params& p, uint32_t e) { atomicOr(p.err, e); }
 
+// Optional per-phase cycle accounting of the level kernel (thread 0 of each
+// workgroup), enabled only in instrumented builds with a debug buffer in Params.
+#ifdef VQS_PHASE_TIMING
+#define VQS_PHASE_INIT()            \
+  unsigned long long ph_t = wall_clock64(); \
+  unsigned long long ph_acc[8] = {0, 0, 0, 0, 0, 0, 0, 0}; \
+  int ph_cur = 7;
+#define VQS_PHASE(n)                                     \
+  {                                                      \
+    const unsigned long long ph_now = wall_clock64();    \
+    ph_acc[ph_cur] += ph_now - ph_t;                     \
+    ph_t = ph_now;                                       \
+    ph_cur = (n);                                        \
+  }
+#define VQS_PHASE_FLUSH()                                                  \
+  if (threadIdx.x == 0 && p.dbg) {                                         \
+    for (int ph_i = 0; ph_i < 8; ph_i++) atomicAdd(&p.dbg[ph_i], ph_acc[ph_i]); \
+  }
+#else
+#define VQS_PHASE_INIT()
+#define VQS_PHASE(n)
+#define VQS_PHASE_FLUSH()
+#endif
+
 template <class K>
 __device__ inline void to_words(typename K::R r, uint64_t& lo, uint64_t& hi) {
   K::to_u64x2(r, lo, hi);
@@ -287,20 +311,33 @@ __global__ void __launch_bounds__(LEVEL_P) level_kernel(Params p) {
   constexpr unsigned long long ST_AGG = 1ull << 46, ST_INC = 2ull << 46;
   constexpr unsigned long long VAL_MASK = (1ull << 46) - 1;
   const int tid = threadIdx.x;
+  unsigned long long tiles_done = 0;
+  VQS_PHASE_INIT();
 
   for (;;) {
+    VQS_PHASE(5);
     if (tid == 0) sh_ticket = atomicAdd(&p.lvl_ctr[L].ticket, 1u);
     __syncthreads();
     const unsigned long long g = sh_ticket;
     if (g >= ntiles) break;
-    // segment of tile g: last s with tbase[s] <= g
-    if (tid == 0) {
-      uint32_t lo = 0, hi = nseg;  // invariant: tbase[lo] <= g < tbase[hi] (hi may be nseg)
+    // segment of tile g: last s with tbase[s] <= g; one wave narrows the interval
+    // 64-fold per step
+    VQS_PHASE(0);
+    if (tid < WAVE) {
+      uint32_t lo = 0, hi = nseg;  // invariant: tbase[lo] <= g, and g < tbase[hi] if hi < nseg
       while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) / 2;
-        if (tbase[mid] <= g) lo = mid; else hi = mid;
+        const uint32_t span = hi - lo;
+        const uint32_t step = (span + WAVE - 1) / WAVE;
+        const uint32_t pos = lo + (uint32_t)tid * step;
+        const bool le = pos < hi && tbase[pos] <= g;
+        const uint64_t m = ballot(le);   // lane 0 always true
+        const int last = 63 - __builtin_clzll(m);
+        const uint32_t nlo = lo + (uint32_t)last * step;
+        const uint32_t nhi = (nlo + step < hi) ? nlo + step : hi;
+        lo = nlo;
+        hi = nhi;
       }
-      sh_seg = (int)lo;
+      if (tid == 0) sh_seg = (int)lo;
     }
     __syncthreads();
     const int si = sh_seg;
@@ -311,6 +348,7 @@ __global__ void __launch_bounds__(LEVEL_P) level_kernel(Params p) {
     const uint64_t vs = (k * T > sg.b + p.off) ? k * T : sg.b + p.off;
     const uint64_t ve = ((k + 1) * T < sg.e + p.off) ? (k + 1) * T : sg.e + p.off;
 
+    VQS_PHASE(1);
     R key[I][K::V];
     TL::load(src_aligned, k, vs, ve, tmode, key);
     if (sg.flags & SEG_OVERRIDE) {
@@ -332,36 +370,63 @@ __global__ void __launch_bounds__(LEVEL_P) level_kernel(Params p) {
     R tmin;
     const uint32_t nl = TL::rank_and_stage(stage, sh, key, k, vs, ve, pivot, &tmin);
 
-    // decoupled look-back on the left counts of the range's earlier tiles
-    if (tid == 0) {
-      uint64_t lo, hi;
-      to_words<K>(tmin, lo, hi);
-      p.tilemin[g] = u128k{lo, hi};
+    // decoupled look-back on the left counts of the range's earlier tiles, one wave
+    // reading 64 predecessors per step
+    VQS_PHASE(2);
+    if (tid < WAVE) {
+      const int lane = tid;
+      // Only device-coherent single-word accesses are used here (relaxed agent-scope
+      // atomics): release/acquire fences at agent scope would write back or
+      // invalidate a whole L2 for every tile.  The tile minimum is made visible before
+      // the aggregate by waiting for its store to complete.
+      if (lane == 0) {
+        uint64_t lo, hi;
+        to_words<K>(tmin, lo, hi);
+        __hip_atomic_store(&p.tilemin[g].lo, lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&p.tilemin[g].hi, hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_waitcnt(0);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        if (g != g0)
+          __hip_atomic_store(&p.flags[g], epoch | ST_AGG | nl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
       unsigned long long excl = 0;
       if (g != g0) {
-        __hip_atomic_store(&p.flags[g], epoch | ST_AGG | nl, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        unsigned long long j = g - 1;
+        unsigned long long top = g - 1;   // highest predecessor not yet summed
         uint32_t spins = 0;
         for (;;) {
-          const unsigned long long f = __hip_atomic_load(&p.flags[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          if ((f & ~((1ull << 48) - 1)) != epoch || (f & (3ull << 46)) == 0) {
+          const bool inr = top >= g0 + (unsigned long long)lane;   // lane reads tile top - lane
+          unsigned long long f = 0;
+          if (inr) f = __hip_atomic_load(&p.flags[top - lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          const bool ready = inr && (f & ~((1ull << 48) - 1)) == epoch && (f & (3ull << 46)) != 0;
+          const bool inc = ready && (f & ST_INC);
+          const uint64_t incm = ballot(inc), readym = ballot(ready), inrm = ballot(inr);
+          // lanes up to the nearest inclusive tile must all be ready
+          const int first_inc = incm ? __builtin_ctzll(incm) : WAVE;
+          const uint64_t need = (first_inc >= WAVE - 1) ? inrm : (((2ull << first_inc) - 1) & inrm);
+          if ((need & ~readym) != 0) {
             ++spins;
-            if ((spins & 1023u) == 0 &&
-                (spins > (1u << 22) || __hip_atomic_load(p.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
-              set_err(p, ERR_SPIN);
+            if ((spins & 255u) == 0 &&
+                (spins > (1u << 20) || __hip_atomic_load(p.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+              if (lane == 0) set_err(p, ERR_SPIN);
               break;
             }
             __builtin_amdgcn_s_sleep(1);
             continue;
           }
-          excl += f & VAL_MASK;
-          if (f & ST_INC) break;
-          j--;
+          unsigned long long v = (((need >> lane) & 1ull) != 0) ? (f & VAL_MASK) : 0ull;
+#pragma unroll
+          for (int m = 1; m < WAVE; m <<= 1) v += (unsigned long long)__shfl_xor((long long)v, m);
+          excl += v;
+          if (incm) break;
+          if (top < g0 + WAVE) break;   // cannot happen: tile g0 is always inclusive
+          top -= WAVE;
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       }
-      __hip_atomic_store(&p.flags[g], epoch | ST_INC | (excl + nl), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      sh_excl = excl;
+      if (lane == 0) {
+        __hip_atomic_store(&p.flags[g], epoch | ST_INC | (excl + nl), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        sh_excl = excl;
+      }
     }
     __syncthreads();
     const unsigned long long excl_l = sh_excl;
@@ -369,6 +434,7 @@ __global__ void __launch_bounds__(LEVEL_P) level_kernel(Params p) {
     const uint64_t before = vs - (sg.b + p.off);             // keys of the range before this tile
     const uint64_t excl_r = before - excl_l;
     const uint32_t nr = nvalid - nl;
+    VQS_PHASE(3);
     TL::write_out(stage, dst, nl, nvalid, sg.b + excl_l, sg.e - excl_r - nr, 0, p.n_total);
 
     if (g == g0 + ntile_seg - 1) {
@@ -379,8 +445,9 @@ __global__ void __launch_bounds__(LEVEL_P) level_kernel(Params p) {
         // degenerate: the minimum of the range decides (Alg. 1, ScanMinMax)
         R m = K::maxv();
         for (unsigned long long t = g0 + tid; t <= g; t += LEVEL_P) {
-          const u128k w = p.tilemin[t];
-          m = K::kmin(m, K::from_u64x2(w.lo, w.hi));
+          const uint64_t wlo = __hip_atomic_load(&p.tilemin[t].lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          const uint64_t whi = __hip_atomic_load(&p.tilemin[t].hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          m = K::kmin(m, K::from_u64x2(wlo, whi));
         }
         m = wave_min<K>(m);
         if ((tid & (WAVE - 1)) == 0) sh.wmin[tid / WAVE] = m;
@@ -449,9 +516,12 @@ __global__ void __launch_bounds__(LEVEL_P) level_kernel(Params p) {
         route_child<K, T>(p, bound, sg.e, sg.depth + 1, sg.limit, dst_scratch, L + 1);
       }
     }
-    if (tid == 0) atomicAdd(&p.stats->level_tiles, 1ull);
+    tiles_done++;
+    VQS_PHASE(4);
     __syncthreads();
   }
+  if (tid == 0 && tiles_done) atomicAdd(&p.stats->level_tiles, tiles_done);
+  VQS_PHASE_FLUSH();
 }
 
 // ---- base case: 16x16 sorting network in registers (Sec. 2.3, Sec. 3) ------------------
@@ -1078,8 +1148,14 @@ __global__ void seed_kernel(Params p, const int64_t* offsets, uint64_t nseg) {
     s.depth = 1;
     s.limit = p.fixed_limit >= 0 ? (uint32_t)p.fixed_limit : depth_limit_of(e - b);
     s.flags = SEG_RAW;
-    if (e - b <= p.solo_max) push_solo(p, s);
-    else push_level<K, TL::T>(p, 0, s);
+    if (e - b <= p.solo_max) {
+      push_solo(p, s);
+    } else if (s.depth > s.limit) {
+      s.flags |= SEG_FALLBACK;
+      push_solo(p, s);
+    } else {
+      push_level<K, TL::T>(p, 0, s);
+    }
   }
 }
 
