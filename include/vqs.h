@@ -141,7 +141,8 @@ int vqs_last_error_bits(void* stream, uint32_t* out);
  * records were last read, measured with HIP events recorded on that stream around
  * the launch. */
 typedef struct vqs_kernel_time {
-    int32_t kind;               /* 0 clear, 1 seed, 2 level partition, 3 solo, 4.. learned */
+    int32_t kind;               /* 0 clear, 1 seed, 2 level partition, 3 solo, 4..7 learned,
+                                   8 level pivots */
     int32_t level;              /* recursion level of a level launch, else -1 */
     uint64_t keys;              /* keys the launch partitions (level launches), else 0 */
     double ms;                  /* event-measured duration */

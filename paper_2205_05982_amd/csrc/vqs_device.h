@@ -240,16 +240,12 @@ __device__ typename K::R choose_pivot_wave(Load load, uint64_t b, uint64_t e, ui
     u[2 * i] = (uint32_t)r;
     u[2 * i + 1] = (uint32_t)(r >> 32);
   }
-  uint64_t off[9];
-#pragma unroll
-  for (int i = 0; i < 9; i++) off[i] = (((uint64_t)u[i] * nch) >> 32) * W;
-  // chunk start of chunk c, selected without dynamic register indexing
-  auto chunk_at = [&](int c) -> uint64_t {
-    uint64_t r = off[0];
-#pragma unroll
-    for (int i = 1; i < 9; i++) r = (c == i) ? off[i] : r;
-    return r;
-  };
+  // the nine chunk starts (uniform across the wave: scalar registers)
+  const uint64_t o0 = (((uint64_t)u[0] * nch) >> 32) * W, o1 = (((uint64_t)u[1] * nch) >> 32) * W,
+                 o2 = (((uint64_t)u[2] * nch) >> 32) * W, o3 = (((uint64_t)u[3] * nch) >> 32) * W,
+                 o4 = (((uint64_t)u[4] * nch) >> 32) * W, o5 = (((uint64_t)u[5] * nch) >> 32) * W,
+                 o6 = (((uint64_t)u[6] * nch) >> 32) * W, o7 = (((uint64_t)u[7] * nch) >> 32) * W,
+                 o8 = (((uint64_t)u[8] * nch) >> 32) * W;
 
   // slot m lives in lane m % 64, register m / 64
   R v[NR];
@@ -258,8 +254,11 @@ __device__ typename K::R choose_pivot_wave(Load load, uint64_t b, uint64_t e, ui
     const int m = r * WAVE + lane;
     v[r] = K::maxv();
     if (m < M0) {
-      const int g = m / W, j = m % W;
-      R x0 = load(chunk_at(3 * g) + j), x1 = load(chunk_at(3 * g + 1) + j), x2 = load(chunk_at(3 * g + 2) + j);
+      const int g = m / W, j = m % W;   // chunk group g uses chunks 3g, 3g+1, 3g+2
+      const uint64_t c0 = g == 0 ? o0 : (g == 1 ? o3 : o6);
+      const uint64_t c1 = g == 0 ? o1 : (g == 1 ? o4 : o7);
+      const uint64_t c2 = g == 0 ? o2 : (g == 1 ? o5 : o8);
+      R x0 = load(c0 + j), x1 = load(c1 + j), x2 = load(c2 + j);
       v[r] = med3<K>(x0, x1, x2);
     }
   }

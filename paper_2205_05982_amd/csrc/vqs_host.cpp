@@ -26,6 +26,7 @@ struct Geometry {
   int num_cu = 256;
   int level_grid = 2048;
   int solo_grid = 512;
+  int pivot_grid = 256;
 };
 
 struct GraphKey {
@@ -310,6 +311,8 @@ hipError_t launch_all(Workspace* ws, const Params& base, const Plan& pl, const G
       for (; L < pl.max_levels - 1; L++) {
         Params p = base;
         p.level = L;
+        e = ws->timed(8, L, [&] { return Launch<B>::pivots(p, g.pivot_grid, s); });
+        if (e != hipSuccess) return e;
         e = ws->timed(2, L, [&] { return Launch<B>::level(p, g.level_grid, s); });
         if (e != hipSuccess) return e;
       }
@@ -327,6 +330,8 @@ hipError_t launch_all(Workspace* ws, const Params& base, const Plan& pl, const G
         for (; L < upto; L++) {
           Params p = base;
           p.level = L;
+          e = ws->timed(8, L, [&] { return Launch<B>::pivots(p, g.pivot_grid, s); });
+          if (e != hipSuccess) return e;
           e = ws->timed(2, L, [&] { return Launch<B>::level(p, g.level_grid, s); });
           if (e != hipSuccess) return e;
         }

@@ -351,7 +351,7 @@ __global__ void __launch_bounds__(LEVEL_P) level_kernel(Params p) {
     VQS_PHASE(1);
     R key[I][K::V];
     TL::load(src_aligned, k, vs, ve, tmode, key);
-    if (sg.flags & SEG_OVERRIDE) {
+    if (sg.flags & SEG_PIVOT) {
       if (tid == 0) sh.pivot = K::from_u64x2(sg.pv_lo, sg.pv_hi);
     } else if (tid < WAVE) {
       const S* sb = src + sg.b;
@@ -499,7 +499,7 @@ __global__ void __launch_bounds__(LEVEL_P) level_kernel(Params p) {
           s.e = sg.e;
           s.depth = sg.depth + 1;
           s.limit = sg.limit;
-          s.flags = SEG_OVERRIDE | (dst_scratch ? SEG_SCRATCH : 0u);
+          s.flags = SEG_OVERRIDE | SEG_PIVOT | (dst_scratch ? SEG_SCRATCH : 0u);
           to_words<K>(mn, s.pv_lo, s.pv_hi);
           if (s.depth > s.limit) {
             s.flags = SEG_FALLBACK | (dst_scratch ? SEG_SCRATCH : 0u);
@@ -522,6 +522,45 @@ __global__ void __launch_bounds__(LEVEL_P) level_kernel(Params p) {
   }
   if (tid == 0 && tiles_done) atomicAdd(&p.stats->level_tiles, tiles_done);
   VQS_PHASE_FLUSH();
+}
+
+// ChoosePivot for every range of a level, one wave per range, before the level's
+// partition launch: the tiles then read the pivot with the range record.
+constexpr int PIVOT_P = 256;
+
+template <class K>
+__global__ void __launch_bounds__(PIVOT_P) pivot_kernel(Params p) {
+  using R = typename K::R;
+  using S = typename K::S;
+  const int L = p.level;
+  const unsigned long long packed = p.lvl_ctr[L].packed;
+  const uint32_t nseg = (uint32_t)(packed >> 40);
+  if (nseg == 0) return;
+  Seg* segs = p.lvl_segs[L & 1];
+  const S* src = (const S*)((L & 1) ? p.scratch : p.keys);
+  const int tmode = (L == 0) ? p.mode : 0;
+  const uint32_t wave = (blockIdx.x * PIVOT_P + threadIdx.x) / WAVE;
+  const uint32_t nwaves = gridDim.x * (PIVOT_P / WAVE);
+  for (uint32_t si = wave; si < nseg; si += nwaves) {
+    const Seg sg = segs[si];
+    if (sg.flags & (SEG_OVERRIDE | SEG_PIVOT)) continue;
+    const S* sb = src + sg.b;
+    const R pv = choose_pivot_wave<K>(
+        [&](uint64_t i) -> R {
+          S sv = sb[i];
+          R r;
+          if constexpr (sizeof(S) == sizeof(R)) r = sv; else r = (R)sv;
+          return tmode ? K::load_t(sv, tmode) : r;
+        },
+        sg.b, sg.e, p.seed);
+    if (lane_id() == 0) {
+      uint64_t lo, hi;
+      to_words<K>(pv, lo, hi);
+      segs[si].pv_lo = lo;
+      segs[si].pv_hi = hi;
+      segs[si].flags = sg.flags | SEG_PIVOT;
+    }
+  }
 }
 
 // ---- base case: 16x16 sorting network in registers (Sec. 2.3, Sec. 3) ------------------
@@ -767,18 +806,17 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
           else set_err(p, ERR_LOCAL_OVERFLOW);
         }
       } else if (lane == 0) {
-        const uint32_t cb[2] = {lb, bound}, ce[2] = {bound, le};
-        for (int c = 0; c < 2; c++) {
-          const uint32_t len = ce[c] - cb[c];
-          if (len == 0) continue;
+        auto push_child = [&](uint32_t cb, uint32_t ce) {
+          const uint32_t len = ce - cb;
+          if (len == 0) return;
           if (len <= p.nb) {
             const uint32_t s = atomicAdd(&ls.nbc, 1u);
-            if (s < BC_CAP) ls.bc[s] = ((cb[c] << 9) | (len - 1)) << 1 | nbuf;
+            if (s < BC_CAP) ls.bc[s] = ((cb << 9) | (len - 1)) << 1 | nbuf;
             else set_err(p, ERR_LOCAL_OVERFLOW);
           } else {
             LocalItem<K> ci;
-            ci.lb = cb[c];
-            ci.le = ce[c];
+            ci.lb = cb;
+            ci.le = ce;
             ci.depth = it.depth + 1;
             ci.flags = nbuf;
             ci.pv = pivot;
@@ -786,7 +824,9 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
             if (s < LIST_CAP) ls.list[cur ^ 1][s] = ci;
             else set_err(p, ERR_LOCAL_OVERFLOW);
           }
-        }
+        };
+        push_child(lb, bound);
+        push_child(bound, le);
       }
     }
     __syncthreads();
@@ -1094,11 +1134,15 @@ __global__ void __launch_bounds__(SOLO_P) solo_kernel(Params p) {
         l.flags = r.flags = child_flags;
         // larger first, so the smaller range is taken next (stack depth <= log2 n)
         const bool left_small = (bound - cur.b) <= (cur.e - bound);
-        const Seg& first = left_small ? r : l;
-        const Seg& second = left_small ? l : r;
         if (sp + 2 <= STACK_CAP) {
-          stack[sp++] = first;
-          stack[sp++] = second;
+          if (left_small) {
+            stack[sp] = r;
+            stack[sp + 1] = l;
+          } else {
+            stack[sp] = l;
+            stack[sp + 1] = r;
+          }
+          sp += 2;
         } else {
           set_err(p, ERR_STACK);
         }

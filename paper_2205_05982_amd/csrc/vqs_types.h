@@ -27,6 +27,7 @@ enum : uint32_t {
   SEG_RAW = 4u,        // data not yet transformed (caller's array, never touched)
   SEG_FALLBACK = 8u,   // depth limit exceeded: bounded-time fallback sort
   SEG_FILL = 16u,      // all keys equal: write pv to [b, e) of the caller's array
+  SEG_PIVOT = 32u,     // pv holds the range's pivot (computed before the level's launch)
 };
 
 struct Seg {

@@ -60,7 +60,7 @@ class KernelTime(ctypes.Structure):
 
 
 KERNEL_KINDS = {0: "clear", 1: "seed", 2: "level_partition", 3: "solo", 4: "learned_sample",
-                5: "learned_train", 6: "learned_thresholds", 7: "learned_scatter"}
+                5: "learned_train", 6: "learned_thresholds", 7: "learned_scatter", 8: "pivots"}
 
 _lib = None
 
