@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--workload", default="c2_uniform", choices=sorted(WORKLOADS))
     ap.add_argument("--n", type=int, default=0, help="override the key count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=20_000_000)
+    ap.add_argument("--cpu-sample", type=int, default=100_000_000)
     ap.add_argument("--profile-json", default="", help="write per-launch kernel times here")
     return ap.parse_args()
 

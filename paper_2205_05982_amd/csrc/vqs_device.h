@@ -172,6 +172,33 @@ __device__ inline uint32_t mbcnt(uint64_t mask) {
 
 __device__ inline uint64_t ballot(bool p) { return __ballot(p); }
 
+// Lane exchange inside 16-lane rows, partner lane = lane ^ M, by DPP (data-parallel
+// primitives: a VALU move with a lane pattern) where one exists: quad_perm for
+// M = 1, 2, 3, row_half_mirror for M = 7, row_mirror for M = 15; ds_swizzle in
+// bit mode for M = 4.
+template <int M>
+__device__ inline uint32_t xor_lanes32(uint32_t v) {
+  static_assert(M == 1 || M == 2 || M == 3 || M == 4 || M == 7 || M == 15, "pattern");
+  if constexpr (M == 1) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, true);
+  if constexpr (M == 2) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, true);
+  if constexpr (M == 3) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x1B, 0xF, 0xF, true);
+  if constexpr (M == 7) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, true);
+  if constexpr (M == 15) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xF, 0xF, true);
+  if constexpr (M == 4) return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x101F);
+  return v;
+}
+
+template <int M>
+__device__ inline uint32_t xor_lanes(uint32_t v) { return xor_lanes32<M>(v); }
+template <int M>
+__device__ inline uint64_t xor_lanes(uint64_t v) {
+  return ((uint64_t)xor_lanes32<M>((uint32_t)(v >> 32)) << 32) | xor_lanes32<M>((uint32_t)v);
+}
+template <int M>
+__device__ inline u128k xor_lanes(u128k v) {
+  return u128k{xor_lanes<M>(v.lo), xor_lanes<M>(v.hi)};
+}
+
 // ---- random numbers for the pivot sampler (Sec. 2.2) ---------------------------------
 
 // SplitMix64 (Steele, Lea, Flood): golden-ratio increment, variant-13 finalizer.
@@ -224,8 +251,19 @@ __device__ inline typename K::R med3(typename K::R x0, typename K::R x1, typenam
 // chunk groups, then reduction by medians of three (whole groups of W lanes while 3W
 // remain, then consecutive triples, 0..2 leftovers dropped) until fewer than three
 // remain; the first is the pivot.  All lanes return the pivot.
+// A wave-uniform 64-bit value placed in scalar registers (lets the compiler run the
+// sampler's integer arithmetic on the scalar unit).
+__device__ inline uint64_t uniform64(uint64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
 template <class K, class Load>
 __device__ typename K::R choose_pivot_wave(Load load, uint64_t b, uint64_t e, uint64_t seed) {
+  b = uniform64(b);
+  e = uniform64(e);
+  seed = uniform64(seed);
   using R = typename K::R;
   constexpr int W = 64 / K::SIZE;
   constexpr int M0 = 3 * W;               // 96, 48, 24 or 12 medians

@@ -415,7 +415,7 @@ int sort_impl(void* keys, const int64_t* offsets, uint64_t nseg, uint64_t n, int
   base.fixed_limit = pl.depth_limit;
 #ifdef VQS_PHASE_TIMING
   static unsigned long long* dbg = nullptr;
-  if (!dbg && hipMalloc(&dbg, 64) == hipSuccess) (void)hipMemset(dbg, 0, 64);
+  if (!dbg && hipMalloc(&dbg, 256) == hipSuccess) (void)hipMemset(dbg, 0, 256);
   base.dbg = dbg;
   g_dbg = dbg;
 #else
@@ -637,11 +637,11 @@ int vqs_version(void) { return VERSION; }
 
 #ifdef VQS_PHASE_TIMING
 // Instrumented builds only: per-phase cycle totals of the level kernel, then reset.
-int vqs_debug_phase_read(uint64_t out[8]) {
+int vqs_debug_phase_read(uint64_t out[32]) {
   if (!g_dbg) return VQS_EINVAL;
-  if (hipDeviceSynchronize() != hipSuccess || hipMemcpy(out, g_dbg, 64, hipMemcpyDeviceToHost) != hipSuccess)
+  if (hipDeviceSynchronize() != hipSuccess || hipMemcpy(out, g_dbg, 256, hipMemcpyDeviceToHost) != hipSuccess)
     return VQS_EHIP;
-  (void)hipMemset(g_dbg, 0, 64);
+  (void)hipMemset(g_dbg, 0, 256);
   return VQS_OK;
 }
 #endif

@@ -26,6 +26,8 @@
 #include "vqs_device.h"
 #include "vqs_types.h"
 
+#include <type_traits>
+
 namespace vqs {
 
 __device__ inline void set_err(const Params& p, uint32_t e) { atomicOr(p.err, e); }
@@ -44,11 +46,13 @@ __device__ inline void set_err(const Params& p, uint32_t e) { atomicOr(p.err, e)
     ph_t = ph_now;                                       \
     ph_cur = (n);                                        \
   }
-#define VQS_PHASE_FLUSH()                                                  \
-  if (threadIdx.x == 0 && p.dbg) {                                         \
-    for (int ph_i = 0; ph_i < 8; ph_i++) atomicAdd(&p.dbg[ph_i], ph_acc[ph_i]); \
+#define VQS_PHASE_FLUSH_AT(base)                                                  \
+  if (threadIdx.x == 0 && p.dbg) {                                                \
+    for (int ph_i = 0; ph_i < 8; ph_i++) atomicAdd(&p.dbg[(base) + ph_i], ph_acc[ph_i]); \
   }
+#define VQS_PHASE_FLUSH() VQS_PHASE_FLUSH_AT(0)
 #else
+#define VQS_PHASE_FLUSH_AT(base)
 #define VQS_PHASE_INIT()
 #define VQS_PHASE(n)
 #define VQS_PHASE_FLUSH()
@@ -584,6 +588,45 @@ __global__ void __launch_bounds__(PIVOT_P) pivot_kernel(Params p) {
 // pairs lane l, register r with lane l ^ (2w-1), register 15-r, bringing the two nodes
 // of every module to the same register of two lanes; half-cleaners at lane distances
 // w/2..1 exchange the same register; the last four stages are inside each lane.
+template <class K, int W>
+__device__ inline void merge_stage16(typename K::R (&x)[16], int gl) {
+  using R = typename K::R;
+  // flip stage: lane l, register r  <->  lane l ^ (2W-1), register 15-r
+  {
+    const bool up = (gl & W) != 0;
+    R y[16];
+#pragma unroll
+    for (int r = 0; r < 16; r++) y[r] = xor_lanes<2 * W - 1>(x[15 - r]);
+#pragma unroll
+    for (int r = 0; r < 16; r++) x[r] = up ? K::kmax(x[r], y[r]) : K::kmin(x[r], y[r]);
+  }
+  // half-cleaners across lanes (distance W/2 .. 1)
+  auto cross = [&](auto dtag) {
+    constexpr int D = decltype(dtag)::value;
+    const bool up = (gl & D) != 0;
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+      R y = xor_lanes<D>(x[r]);
+      x[r] = up ? K::kmax(x[r], y) : K::kmin(x[r], y);
+    }
+  };
+  if constexpr (W >= 8) cross(std::integral_constant<int, 4>{});
+  if constexpr (W >= 4) cross(std::integral_constant<int, 2>{});
+  if constexpr (W >= 2) cross(std::integral_constant<int, 1>{});
+  // half-cleaners inside each lane (register distance 8, 4, 2, 1)
+#pragma unroll
+  for (int d = 8; d >= 1; d /= 2) {
+#pragma unroll
+    for (int r = 0; r < 16; r++)
+      if ((r & d) == 0) {
+        R lo = K::kmin(x[r], x[r + d]);
+        R hi = K::kmax(x[r], x[r + d]);
+        x[r] = lo;
+        x[r + d] = hi;
+      }
+  }
+}
+
 template <class K>
 __device__ inline void network16x16(typename K::R (&x)[16]) {
   using R = typename K::R;
@@ -596,33 +639,11 @@ __device__ inline void network16x16(typename K::R (&x)[16]) {
     x[b] = hi_;                      \
   }
   VQS_GREEN16(VQS_CE)
-#pragma unroll
-  for (int w = 1; w < 16; w *= 2) {
-    {
-      const bool up = (gl & w) != 0;
-      R y[16];
-#pragma unroll
-      for (int r = 0; r < 16; r++) y[r] = K::shfl_xor(x[15 - r], 2 * w - 1);
-#pragma unroll
-      for (int r = 0; r < 16; r++) x[r] = up ? K::kmax(x[r], y[r]) : K::kmin(x[r], y[r]);
-    }
-#pragma unroll
-    for (int d = w / 2; d >= 1; d /= 2) {
-      const bool up = (gl & d) != 0;
-#pragma unroll
-      for (int r = 0; r < 16; r++) {
-        R y = K::shfl_xor(x[r], d);
-        x[r] = up ? K::kmax(x[r], y) : K::kmin(x[r], y);
-      }
-    }
-#pragma unroll
-    for (int d = 8; d >= 1; d /= 2) {
-#pragma unroll
-      for (int r = 0; r < 16; r++)
-        if ((r & d) == 0) VQS_CE(r, r + d)
-    }
-  }
 #undef VQS_CE
+  merge_stage16<K, 1>(x, gl);
+  merge_stage16<K, 2>(x, gl);
+  merge_stage16<K, 4>(x, gl);
+  merge_stage16<K, 8>(x, gl);
 }
 
 // ---- local sort in LDS (workgroup) --------------------------------------------------------
@@ -693,6 +714,17 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
   const int wave = tid / WAVE;
   const uint32_t n = (uint32_t)(e - b);
   const int tmode = raw ? p.mode : 0;
+#ifdef VQS_PHASE_TIMING
+  unsigned long long lt0 = wall_clock64(), lacc[4] = {0, 0, 0, 0};
+#define VQS_LPH(i)                                   \
+  {                                                  \
+    const unsigned long long lt1 = wall_clock64();   \
+    lacc[i] += lt1 - lt0;                            \
+    lt0 = lt1;                                       \
+  }
+#else
+#define VQS_LPH(i)
+#endif
 
   // 1. load into bufA[0, n) (16-byte aligned chunks in v-space)
   {
@@ -738,6 +770,7 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
     }
   }
   __syncthreads();
+  VQS_LPH(0);
 
   int cur = 0;
   for (;;) {
@@ -757,28 +790,60 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
         continue;
       }
       R pivot;
+#ifdef VQS_PHASE_TIMING
+      unsigned long long wt0 = wall_clock64();
+#endif
       if (it.flags & 2u) {
         pivot = it.pv;
       } else {
         const S* sb = s_buf + lb;
         pivot = choose_pivot_wave<K>([&](uint64_t i) -> R { return (R)sb[i]; }, b + lb, b + le, p.seed);
       }
+#ifdef VQS_PHASE_TIMING
+      unsigned long long wt1 = wall_clock64();
+#endif
       uint32_t l = lb, r = le;
       R mn = K::maxv();
-      for (uint32_t base = lb; base < le; base += WAVE) {
-        const uint32_t i = base + lane;
-        const bool valid = i < le;
-        R kx = valid ? (R)s_buf[i] : K::maxv();
-        const bool isl = valid && !K::lt(pivot, kx);
-        const bool isr = valid && !isl;
-        if (valid) mn = K::kmin(mn, kx);
-        const uint64_t ml = ballot(isl), mr = ballot(isr);
-        if (isl) d_buf[l + mbcnt(ml)] = (S)kx;
-        if (isr) d_buf[r - 1 - mbcnt(mr)] = (S)kx;
-        l += __popcll(ml);
-        r -= __popcll(mr);
+      // four 64-key groups per step: independent loads, ballots and stores
+      constexpr int U = 4;
+      for (uint32_t base = lb; base < le; base += U * WAVE) {
+        R kx[U];
+        bool valid[U], isl[U];
+        uint64_t ml[U], mr[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+          const uint32_t i = base + u * WAVE + lane;
+          valid[u] = i < le;
+          kx[u] = valid[u] ? (R)s_buf[i] : K::maxv();
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+          isl[u] = valid[u] && !K::lt(pivot, kx[u]);
+          if (valid[u]) mn = K::kmin(mn, kx[u]);
+          ml[u] = ballot(isl[u]);
+          mr[u] = ballot(valid[u] && !isl[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+          if (isl[u]) d_buf[l + mbcnt(ml[u])] = (S)kx[u];
+          else if (valid[u]) d_buf[r - 1 - mbcnt(mr[u])] = (S)kx[u];
+          l += __popcll(ml[u]);
+          r -= __popcll(mr[u]);
+        }
       }
+#ifdef VQS_PHASE_TIMING
+      unsigned long long wt2 = wall_clock64();
+#endif
       mn = wave_min<K>(mn);
+#ifdef VQS_PHASE_TIMING
+      unsigned long long wt3 = wall_clock64();
+      if (lane == 0 && p.dbg) {
+        atomicAdd(&p.dbg[24], wt1 - wt0);
+        atomicAdd(&p.dbg[25], wt2 - wt1);
+        atomicAdd(&p.dbg[26], wt3 - wt2);
+        atomicAdd(&p.dbg[27], 1ull);
+      }
+#endif
       const uint32_t bound = l;
       const uint32_t nbuf = (it.flags & 1u) ? 0u : 1u;   // children live in d_buf
       if (lane == 0) {
@@ -830,8 +895,12 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
       }
     }
     __syncthreads();
-    // 3. base cases of this level: four per wave, one per 16-lane group
-    const uint32_t nbc = ls.nbc < BC_CAP ? ls.nbc : BC_CAP;
+    VQS_LPH(1);
+    // 3. base cases, four per wave (one per 16-lane group); they are collected over
+    // recursion levels and sorted together once the list could overflow at the next
+    // level or no range is left to partition
+    const bool flush_bc = ls.nbc > (uint32_t)(BC_CAP - 2 * LIST_CAP) || ls.nlist[cur ^ 1] == 0;
+    const uint32_t nbc = flush_bc ? (ls.nbc < BC_CAP ? ls.nbc : BC_CAP) : 0u;
     for (uint32_t q0 = wave * 4; q0 < nbc; q0 += SOLO_NW * 4) {
       const uint32_t qi = q0 + (lane >> 4);
       const int gl = lane & 15;
@@ -858,6 +927,7 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
     }
     // 4. fallbacks of this level (whole workgroup, one range at a time)
     __syncthreads();
+    VQS_LPH(2);
     const uint32_t nfb = ls.nfb < LIST_CAP ? ls.nfb : LIST_CAP;
     for (uint32_t f = 0; f < nfb; f++) {
       const LocalItem<K> it = ls.fb[f];
@@ -873,8 +943,10 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
       __syncthreads();
     }
     if (tid == 0) {
-      ls.stat_bc += ls.nbc;
-      ls.nbc = 0;
+      if (flush_bc) {
+        ls.stat_bc += ls.nbc;
+        ls.nbc = 0;
+      }
       ls.nfb = 0;
       ls.nlist[cur] = 0;
     }
@@ -883,12 +955,19 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
     if (ls.nlist[cur] == 0) break;
   }
   __syncthreads();
+  VQS_LPH(1);
   // 5. write out
   for (uint32_t i = tid; i < n; i += SOLO_P) {
     S val = bufA[i];
     if (!out_internal && p.mode) val = K::store_t((R)val, p.mode);
     out[b + i] = val;
   }
+  VQS_LPH(3);
+#ifdef VQS_PHASE_TIMING
+  if (tid == 0 && p.dbg)
+    for (int i = 0; i < 4; i++) atomicAdd(&p.dbg[16 + i], lacc[i]);
+#endif
+#undef VQS_LPH
   if (tid == 0) {
     if (ls.stat_part) {
       atomicAdd(&p.stats->partitions, (unsigned long long)ls.stat_part);
@@ -1022,7 +1101,9 @@ __global__ void __launch_bounds__(SOLO_P) solo_kernel(Params p) {
   const unsigned long long count = p.solo_ctr->count;
   const unsigned long long nitems = count < p.cap_solo ? count : p.cap_solo;
 
+  VQS_PHASE_INIT();
   for (;;) {
+    VQS_PHASE(0);
     if (tid == 0) sh_item = atomicAdd(&p.solo_ctr->ticket, 1ull);
     __syncthreads();
     const unsigned long long ii = sh_item;
@@ -1053,10 +1134,13 @@ __global__ void __launch_bounds__(SOLO_P) solo_kernel(Params p) {
         continue;
       }
       if (n <= p.local_cap) {
+        VQS_PHASE(2);
         local_sort<K>(p, ls, bufA, bufB, src, raw, cur.b, cur.e, cur.depth, cur.limit,
                       (cur.flags & SEG_OVERRIDE) != 0, K::from_u64x2(cur.pv_lo, cur.pv_hi), (S*)p.keys, false);
+        VQS_PHASE(0);
         continue;
       }
+      VQS_PHASE(1);
       if (cur.depth > cur.limit) {
         fallback_global<K>(p, bufA, cur);
         __syncthreads();
@@ -1150,6 +1234,7 @@ __global__ void __launch_bounds__(SOLO_P) solo_kernel(Params p) {
       __syncthreads();
     }
   }
+  VQS_PHASE_FLUSH_AT(8);
 }
 
 // ---- setup ----------------------------------------------------------------------------------

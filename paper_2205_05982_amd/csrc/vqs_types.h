@@ -13,7 +13,10 @@ constexpr int MODE_FLOAT = 1;
 constexpr int MODE_DESC = 2;
 
 constexpr int LEVEL_P = 256;        // threads per level-kernel workgroup
-constexpr int LEVEL_I = 4;          // 16-byte chunks per thread: 16 KB tiles
+#ifndef VQS_LEVEL_I
+#define VQS_LEVEL_I 8
+#endif
+constexpr int LEVEL_I = VQS_LEVEL_I;  // 16-byte chunks per thread: 32 KB tiles
 constexpr int SOLO_P = 256;         // threads per solo-kernel workgroup
 constexpr int SOLO_I = 8;           // 16-byte chunks per thread per solo tile (32 KB)
 constexpr int LOCAL_BYTES = 32768;  // one LDS buffer of the local sort
