@@ -128,7 +128,8 @@ def main():
         raise RuntimeError(f"bench output check failed: sorted={sorted_ok} multiset={sum_ok}")
 
     # roofline of the dominant kernel: the level (device-wide partition) kernel
-    lv = [r for r in recs if r["kind"] == "level_partition" and r["keys"] > 0]
+    lv_all = [r for r in recs if r["kind"] == "level_partition"]
+    lv = [r for r in lv_all if r["keys"] > 0]
     solo = [r for r in recs if r["kind"] == "solo"]
     lv_bytes = sum(2 * r["keys"] * ks for r in lv)
     lv_ms = sum(r["ms"] for r in lv)
@@ -176,6 +177,10 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": None,
             "launches_per_step": round(levels_per_step, 2),
+            # every level launch of the timed steps, empty ones included (the
+            # population rocprofv3 averages over)
+            "launch_avg_us_all": round(1e3 * sum(r["ms"] for r in lv_all) / max(len(lv_all), 1), 1),
+            "bytes_per_launch_all": int(lv_bytes / max(len(lv_all), 1)),
             "level_ms_per_step": round(lv_ms / args.steps, 4),
             "solo_ms_per_step": round(solo_ms, 4),
             "kernels_ms_per_step": round(all_ms, 4),
