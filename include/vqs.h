@@ -89,7 +89,10 @@ typedef struct vqs_options {
     float overflow_factor;      /* a bucket above overflow_factor * n/256 keys is left
                                    to the plain method; default 2.0 */
     float learning_rate;        /* Adam step size; default 0.01 */
-    uint32_t reserved[7];
+    uint64_t model_seed;        /* seed of the model's initial weights; default 16 */
+    uint64_t sample_seed;       /* seed of the 1 % chunk sample and of the minibatches;
+                                   default 17 */
+    uint32_t reserved[3];
 } vqs_options;
 
 /* Counters of the last call on a stream (copied with synchronisation).  The first
@@ -136,6 +139,46 @@ int vqs_get_stats(void* stream, vqs_stats* out);
 
 /* Device error bits of the last call on `stream` (0 if none); waits for it. */
 int vqs_last_error_bits(void* stream, uint32_t* out);
+
+/* ---- learned splitter pieces (method VQS_METHOD_LEARNED runs all of them) --------
+ * The model is a 1 -> 32 -> 32 -> 1 perceptron with clamp-to-[0,1] activations and
+ * non-negative weight matrices: its parameter block is 1155 floats on the device,
+ * w1[32] b1[32] W2[32][32] (row j = second-layer unit j) b2[32] w3[32] b3 x0 xs.
+ * Input of a key k: x(k) = float(bits(float(k))) * 2^-31; xn = (x - x0) * xs;
+ * bucket(k) = min(255, floor(256 * y)).  All pointers are device pointers. */
+
+/* Sample sample_fraction of the u64 keys in random 64-byte chunks, sort the sample,
+ * compute mid-rank CDF targets and train (train_steps Adam steps; 0 returns the
+ * untrained model).  Writes the parameter block to params (1155 floats). */
+int vqs_learned_fit(const void* keys, uint64_t n, const vqs_options* options, float* params, void* stream);
+
+/* y = model(x) for m inputs. */
+int vqs_mlp_forward(const float* params, const float* x, uint64_t m, float* y, void* stream);
+
+/* Gradient (1153 floats) and mean squared error of the model on m <= 192 samples
+ * (x, target t). */
+int vqs_mlp_gradient(const float* params, const float* x, const float* t, uint32_t m, float* grad, float* loss,
+                     void* stream);
+
+/* steps Adam steps on minibatches of `batch` <= 192 samples (random, from sample_seed,
+ * or consecutive when sequential != 0).  moments holds 2*1153+1 floats (first and
+ * second moments, zero to start; the last receives the final minibatch loss). */
+int vqs_mlp_train(float* params, float* moments, const float* x, const float* t, uint64_t m, uint32_t steps,
+                  uint32_t batch, float learning_rate, uint64_t sample_seed, int sequential, void* stream);
+
+/* Initial (untrained) parameters for inputs x[0..m) sorted ascending. */
+int vqs_mlp_init(float* params, uint64_t model_seed, const float* x, uint64_t m, void* stream);
+
+/* bucket(k) by the model's forward pass, per key. */
+int vqs_mlp_buckets(const float* params, const uint64_t* keys, uint64_t n, int32_t* out, void* stream);
+
+/* The 255 exact thresholds t_j = min{k : bucket(k) >= j} (j = 1..255) and the number of
+ * them that exist (bucket(2^64-1)); bucket(k) = #{j <= nvalid : t_j <= k}. */
+int vqs_learned_thresholds(const float* params, uint64_t* thresholds, uint32_t* nvalid, void* stream);
+
+/* bucket(k) by binary search over the thresholds, per key. */
+int vqs_learned_classify(const uint64_t* keys, uint64_t n, const uint64_t* thresholds, const uint32_t* nvalid,
+                         int32_t* out, void* stream);
 
 /* Kernel timing records (profiling): one per kernel launch on a stream since the
  * records were last read, measured with HIP events recorded on that stream around

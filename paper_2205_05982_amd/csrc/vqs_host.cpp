@@ -64,7 +64,22 @@ struct Workspace {
   unsigned long long* host_pinned = nullptr;
   int last_levels = 0;
   bool have_result = false;
-  LearnedState learned;
+  // learned splitter buffers
+  char* lmem = nullptr;
+  uint64_t lcap_m = 0, lcap_tiles = 0;
+  uint64_t* l_sample = nullptr;
+  float* l_x = nullptr;
+  float* l_t = nullptr;
+  float* l_params = nullptr;
+  float* l_moments = nullptr;
+  uint64_t* l_thr = nullptr;
+  uint32_t* l_nvalid = nullptr;
+  uint32_t* l_hist = nullptr;
+  uint64_t* l_totals = nullptr;
+  int64_t* l_offsets = nullptr;
+  uint64_t* l_summary = nullptr;
+  bool learned_ran = false;
+  std::unique_ptr<Workspace> inner;  // for sorting the sample
   hipGraphExec_t graph = nullptr;
   GraphKey graph_key{};
   bool graph_valid = false;
@@ -96,7 +111,7 @@ struct Workspace {
     if (graph) (void)hipGraphExecDestroy(graph);
     if (mem) (void)hipFree(mem);
     if (host_pinned) (void)hipHostFree(host_pinned);
-    learned.release();
+    if (lmem) (void)hipFree(lmem);
   }
 };
 
@@ -305,7 +320,7 @@ hipError_t launch_all(Workspace* ws, const Params& base, const Plan& pl, const G
   e = ws->timed(1, -1, [&] { return Launch<B>::seed(base, offsets, nseg, s); });
   if (e != hipSuccess) return e;
   // the level loop: launch levels in batches, then read the next level's counter
-  int L = 0;
+  int L = base.seed_level;
   if (pl.n > pl.solo) {
     if (capture) {
       for (; L < pl.max_levels - 1; L++) {
@@ -376,60 +391,58 @@ int check_offsets_host(const int64_t* offsets, uint64_t nseg, uint64_t* total, h
   return rc;
 }
 
-int sort_impl(void* keys, const int64_t* offsets, uint64_t nseg, uint64_t n, int kt, int asc,
-              const vqs_options* o, hipStream_t stream) {
-  if (o && o->struct_size != 0 && o->struct_size < offsetof(vqs_options, train_steps)) return VQS_EINVAL;
-  const int bits = key_bits(kt);
-  if (!bits) return VQS_ETYPE;
-  if (asc != 0 && asc != 1) return VQS_EINVAL;
-  if (n == 0) return VQS_OK;
-  if (!keys) return VQS_EINVAL;
-  const int ks = bits / 8;
-  const uintptr_t addr = (uintptr_t)keys;
-  if (addr % (uintptr_t)std::min(ks, 16)) return VQS_EINVAL;
-  std::lock_guard<std::mutex> lock(g_mu);
-  Workspace* ws = workspace_for(stream);
+int learned_locked(Workspace* ws, void* keys, uint64_t n, const vqs_options* o, hipStream_t stream, bool fit_only,
+                   float* params_out);
+
+// Prepare base parameters for keys on ws (caller holds g_mu).
+int prepare(Workspace* ws, void* keys, uint64_t n, uint64_t nseg, int kt, int asc, const vqs_options* o, Plan* pl,
+            Params* base) {
   const Geometry g = geometry(ws->device);
-  Plan pl;
-  int rc = make_plan(n, nseg, kt, asc, o, g, &pl);
+  int rc = make_plan(n, nseg, kt, asc, o, g, pl);
   if (rc != VQS_OK) return rc;
-  const bool learned = o && o->method == VQS_METHOD_LEARNED;
-  if (o && o->method > VQS_METHOD_LEARNED) return VQS_EINVAL;
-  if (learned && (bits != 64 || (kt == VQS_F64) || offsets)) return VQS_EINVAL;
-  rc = ensure_workspace(ws, pl);
+  rc = ensure_workspace(ws, *pl);
   if (rc != VQS_OK) return rc;
-  Params base = ws->p;
-  base.keys = keys;
-  base.off = (int)((addr % 16) / (uintptr_t)ks);
+  const int ks = pl->ks;
+  const uintptr_t addr = (uintptr_t)keys;
+  Params& b = *base;
+  b = ws->p;
+  b.keys = keys;
+  b.off = (int)((addr % 16) / (uintptr_t)ks);
   // scratch shares the keys' offset from a 16-byte boundary
-  base.scratch = (void*)(((uintptr_t)ws->p.scratch + 15) / 16 * 16 + (addr % 16));
-  base.n_total = n;
-  base.mode = pl.mode;
-  base.seed = pl.seed;
-  base.nb = pl.nb;
-  base.local_cap = pl.local;
-  base.solo_max = pl.solo;
-  base.max_levels = pl.max_levels;
-  base.level = 0;
-  ws->have_result = false;
-  base.fixed_limit = pl.depth_limit;
+  b.scratch = (void*)(((uintptr_t)ws->p.scratch + 15) / 16 * 16 + (addr % 16));
+  b.n_total = n;
+  b.mode = pl->mode;
+  b.seed = pl->seed;
+  b.nb = pl->nb;
+  b.local_cap = pl->local;
+  b.solo_max = pl->solo;
+  b.max_levels = pl->max_levels;
+  b.level = 0;
+  b.seed_level = 0;
+  b.fixed_limit = pl->depth_limit;
 #ifdef VQS_PHASE_TIMING
   static unsigned long long* dbg = nullptr;
   if (!dbg && hipMalloc(&dbg, 256) == hipSuccess) (void)hipMemset(dbg, 0, 256);
-  base.dbg = dbg;
+  b.dbg = dbg;
   g_dbg = dbg;
 #else
-  base.dbg = nullptr;
+  b.dbg = nullptr;
 #endif
+  return VQS_OK;
+}
+
+// The plain method on keys (one array, or nseg segments); caller holds g_mu.
+int sort_locked(Workspace* ws, void* keys, const int64_t* offsets, uint64_t nseg, uint64_t n, int kt, int asc,
+                const vqs_options* o, hipStream_t stream) {
+  Plan pl;
+  Params base;
+  int rc = prepare(ws, keys, n, nseg, kt, asc, o, &pl, &base);
+  if (rc != VQS_OK) return rc;
+  const Geometry g = geometry(ws->device);
+  ws->have_result = false;
+  ws->learned_ran = false;
   int levels = 0;
   hipError_t e;
-  if (learned) {
-    rc = learned_sort(ws->learned, base, pl.n, o, stream, &levels);
-    if (rc != VQS_OK) return rc;
-    ws->last_levels = levels;
-    ws->have_result = true;
-    return VQS_OK;
-  }
   const bool use_graph = o && o->use_graph && offsets;
   if (use_graph) {
     GraphKey gk{keys, offsets, nseg, n, kt, asc, pl.seed, pl.depth_limit, pl.nb, pl.local, pl.solo};
@@ -468,6 +481,162 @@ int sort_impl(void* keys, const int64_t* offsets, uint64_t nseg, uint64_t n, int
   if (e != hipSuccess) return VQS_EHIP;
   ws->last_levels = levels;
   ws->have_result = true;
+  return VQS_OK;
+}
+
+int sort_impl(void* keys, const int64_t* offsets, uint64_t nseg, uint64_t n, int kt, int asc,
+              const vqs_options* o, hipStream_t stream) {
+  if (o && o->struct_size != 0 && o->struct_size < offsetof(vqs_options, train_steps)) return VQS_EINVAL;
+  const int bits = key_bits(kt);
+  if (!bits) return VQS_ETYPE;
+  if (asc != 0 && asc != 1) return VQS_EINVAL;
+  if (o && o->method > VQS_METHOD_LEARNED) return VQS_EINVAL;
+  const bool learned = o && o->method == VQS_METHOD_LEARNED;
+  if (learned && (kt != VQS_U64 || offsets || !asc)) return VQS_EINVAL;
+  if (n == 0) return VQS_OK;
+  if (!keys) return VQS_EINVAL;
+  const int ks = bits / 8;
+  if ((uintptr_t)keys % (uintptr_t)std::min(ks, 16)) return VQS_EINVAL;
+  std::lock_guard<std::mutex> lock(g_mu);
+  Workspace* ws = workspace_for(stream);
+  if (learned) return learned_locked(ws, keys, n, o, stream, false, nullptr);
+  return sort_locked(ws, keys, offsets, nseg, n, kt, asc, o, stream);
+}
+
+// ---- learned splitter ------------------------------------------------------------------
+
+int ensure_learned(Workspace* ws, uint64_t m, uint64_t ntiles) {
+  if (ws->lmem && m <= ws->lcap_m && ntiles <= ws->lcap_tiles) return VQS_OK;
+  if (ws->lmem) {
+    (void)hipStreamSynchronize(ws->stream);
+    (void)hipFree(ws->lmem);
+    ws->lmem = nullptr;
+  }
+  m = std::max(m, ws->lcap_m);
+  ntiles = std::max(ntiles, ws->lcap_tiles);
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    size_t o = off;
+    off = align_up(off + b, 256);
+    return o;
+  };
+  const size_t o_sample = take(m * 8), o_x = take(m * 4), o_t = take(m * 4), o_p = take(MLP_NBLOCK * 4),
+               o_mom = take((2 * MLP_NPARAM + 1) * 4), o_thr = take(NBUCKET * 8), o_nv = take(16),
+               o_hist = take(ntiles * NBUCKET * 4), o_tot = take(NBUCKET * 8), o_off = take((NBUCKET + 1) * 8),
+               o_sum = take(64);
+  void* mem = nullptr;
+  if (hipMalloc(&mem, off) != hipSuccess || !mem) {
+    (void)hipGetLastError();
+    return VQS_ENOMEM;
+  }
+  char* b = (char*)mem;
+  ws->lmem = b;
+  ws->lcap_m = m;
+  ws->lcap_tiles = ntiles;
+  ws->l_sample = (uint64_t*)(b + o_sample);
+  ws->l_x = (float*)(b + o_x);
+  ws->l_t = (float*)(b + o_t);
+  ws->l_params = (float*)(b + o_p);
+  ws->l_moments = (float*)(b + o_mom);
+  ws->l_thr = (uint64_t*)(b + o_thr);
+  ws->l_nvalid = (uint32_t*)(b + o_nv);
+  ws->l_hist = (uint32_t*)(b + o_hist);
+  ws->l_totals = (uint64_t*)(b + o_tot);
+  ws->l_offsets = (int64_t*)(b + o_off);
+  ws->l_summary = (uint64_t*)(b + o_sum);
+  return VQS_OK;
+}
+
+Workspace* inner_for(Workspace* ws) {
+  if (!ws->inner) {
+    ws->inner = std::make_unique<Workspace>();
+    ws->inner->device = ws->device;
+    ws->inner->stream = ws->stream;
+  }
+  return ws->inner.get();
+}
+
+// Sample, sort the sample, targets, model init and training; then (unless fit_only)
+// thresholds, histogram, scan, scatter into scratch and the plain method on the 256
+// buckets.  Caller holds g_mu.
+int learned_locked(Workspace* ws, void* keys, uint64_t n, const vqs_options* o, hipStream_t stream, bool fit_only,
+                   float* params_out) {
+  const float frac = (o && o->sample_fraction > 0.f) ? o->sample_fraction : 0.01f;
+  const uint32_t steps = (o && o->train_steps) ? o->train_steps : 600;
+  const uint32_t batch = (o && o->batch) ? std::min<uint32_t>(o->batch, MLP_MAX_BATCH) : MLP_MAX_BATCH;
+  const float lr = (o && o->learning_rate > 0.f) ? o->learning_rate : 0.01f;
+  const float over = (o && o->overflow_factor > 0.f) ? o->overflow_factor : 2.0f;
+  const uint64_t model_seed = (o && o->model_seed) ? o->model_seed : 16;
+  const uint64_t sample_seed = (o && o->sample_seed) ? o->sample_seed : 17;
+  if (n < 64) return fit_only ? VQS_EINVAL : sort_locked(ws, keys, nullptr, 1, n, VQS_U64, 1, o, stream);
+  uint64_t chunks = (uint64_t)((double)frac * (double)n / 8.0);
+  chunks = std::max<uint64_t>(chunks, 8);
+  chunks = std::min<uint64_t>(chunks, n / 8);
+  const uint64_t m = chunks * 8;
+  const uint64_t ntiles = (n + LEARN_TILE - 1) / LEARN_TILE;
+  // the workspace for the final plain phase first: it owns the scatter target
+  Plan pl;
+  Params base;
+  vqs_options plain{};
+  if (o) plain = *o;
+  plain.struct_size = sizeof(vqs_options);
+  plain.method = VQS_METHOD_PLAIN;
+  int rc = VQS_OK;
+  if (!fit_only) {
+    rc = prepare(ws, keys, n, NBUCKET, VQS_U64, 1, &plain, &pl, &base);
+    if (rc != VQS_OK) return rc;
+  }
+  rc = ensure_learned(ws, m, ntiles);
+  if (rc != VQS_OK) return rc;
+  ws->have_result = false;
+  ws->learned_ran = false;
+  hipError_t e = ws->timed(4, -1, [&] { return launch_sample((const uint64_t*)keys, n, ws->l_sample, chunks, sample_seed, stream); });
+  if (e != hipSuccess) return VQS_EHIP;
+  Workspace* in = inner_for(ws);
+  in->stream = stream;
+  vqs_options sopt{};
+  sopt.struct_size = sizeof(vqs_options);
+  sopt.seed = o ? o->seed : 0;
+  rc = sort_locked(in, ws->l_sample, nullptr, 1, m, VQS_U64, 1, &sopt, stream);
+  if (rc != VQS_OK) return rc;
+  e = ws->timed(5, -1, [&] {
+    hipError_t r = launch_targets(ws->l_sample, m, ws->l_x, ws->l_t, stream);
+    if (r == hipSuccess) r = launch_init(ws->l_params, model_seed, ws->l_x, m, stream);
+    if (r == hipSuccess) r = hipMemsetAsync(ws->l_moments, 0, (2 * MLP_NPARAM + 1) * 4, stream);
+    if (r == hipSuccess && steps > 0) {
+      TrainArgs a{ws->l_x, ws->l_t, m, steps, batch, lr, sample_seed, 0};
+      r = launch_train(ws->l_params, ws->l_moments, a, stream);
+    }
+    return r;
+  });
+  if (e != hipSuccess) return VQS_EHIP;
+  if (fit_only) {
+    if (params_out &&
+        hipMemcpyAsync(params_out, ws->l_params, MLP_NBLOCK * 4, hipMemcpyDeviceToDevice, stream) != hipSuccess)
+      return VQS_EHIP;
+    return VQS_OK;
+  }
+  e = ws->timed(6, -1, [&] { return launch_thresholds(ws->l_params, ws->l_thr, ws->l_nvalid, stream); });
+  if (e != hipSuccess) return VQS_EHIP;
+  e = ws->timed(7, -1, [&] {
+    hipError_t r = launch_histogram((const uint64_t*)keys, n, ws->l_thr, ws->l_nvalid, ws->l_hist, ntiles, stream);
+    if (r == hipSuccess) r = launch_scan(ws->l_hist, ntiles, ws->l_totals, stream);
+    if (r == hipSuccess) r = launch_offsets(ws->l_totals, n, over, ws->l_offsets, ws->l_summary, stream);
+    if (r == hipSuccess)
+      r = launch_scatter((const uint64_t*)keys, n, ws->l_thr, ws->l_nvalid, ws->l_hist, ntiles, ws->l_offsets,
+                         (uint64_t*)base.scratch, stream);
+    return r;
+  });
+  if (e != hipSuccess) return VQS_EHIP;
+  // the 256 buckets, now in scratch, are sorted as segments starting at level 1
+  base.seed_level = 1;
+  int levels = 0;
+  const Geometry g = geometry(ws->device);
+  e = dispatch_launch(ws, base, pl, g, ws->l_offsets, NBUCKET, false, &levels);
+  if (e != hipSuccess) return VQS_EHIP;
+  ws->last_levels = levels;
+  ws->have_result = true;
+  ws->learned_ran = true;
   return VQS_OK;
 }
 
@@ -556,8 +725,69 @@ int vqs_get_stats(void* stream, vqs_stats* out) {
       if (h[i].packed) out->levels++;
   }
   free(h);
-  ws->learned.fill_stats(out);
+  if (ws->learned_ran) {
+    uint64_t sum[3] = {0, 0, 0};
+    float loss = 0.f;
+    if (hipMemcpy(sum, ws->l_summary, sizeof(sum), hipMemcpyDeviceToHost) == hipSuccess &&
+        hipMemcpy(&loss, ws->l_moments + 2 * MLP_NPARAM, 4, hipMemcpyDeviceToHost) == hipSuccess) {
+      out->learned_buckets = NBUCKET;
+      out->max_bucket = sum[0];
+      out->overflow_buckets = sum[1];
+      out->train_loss = loss;
+    }
+  }
   return VQS_OK;
+}
+
+int vqs_learned_fit(const void* keys, uint64_t n, const vqs_options* options, float* params, void* stream) {
+  if (!keys || !params || n < 64) return VQS_EINVAL;
+  if ((uintptr_t)keys % 8) return VQS_EINVAL;
+  std::lock_guard<std::mutex> lock(g_mu);
+  Workspace* ws = workspace_for((hipStream_t)stream);
+  return learned_locked(ws, const_cast<void*>(keys), n, options, (hipStream_t)stream, true, params);
+}
+
+int vqs_mlp_forward(const float* params, const float* x, uint64_t m, float* y, void* stream) {
+  if (!params || (m && (!x || !y))) return VQS_EINVAL;
+  if (m == 0) return VQS_OK;
+  return launch_forward(params, x, m, y, (hipStream_t)stream) == hipSuccess ? VQS_OK : VQS_EHIP;
+}
+
+int vqs_mlp_gradient(const float* params, const float* x, const float* t, uint32_t m, float* grad, float* loss,
+                     void* stream) {
+  if (!params || !x || !t || !grad || !loss || m == 0 || m > (uint32_t)MLP_MAX_BATCH) return VQS_EINVAL;
+  return launch_gradient(params, x, t, m, grad, loss, (hipStream_t)stream) == hipSuccess ? VQS_OK : VQS_EHIP;
+}
+
+int vqs_mlp_train(float* params, float* moments, const float* x, const float* t, uint64_t m, uint32_t steps,
+                  uint32_t batch, float learning_rate, uint64_t sample_seed, int sequential, void* stream) {
+  if (!params || !moments || !x || !t || m == 0 || batch == 0 || batch > (uint32_t)MLP_MAX_BATCH) return VQS_EINVAL;
+  if (steps == 0) return VQS_OK;
+  TrainArgs a{x, t, m, steps, batch, learning_rate, sample_seed, sequential ? 1 : 0};
+  return launch_train(params, moments, a, (hipStream_t)stream) == hipSuccess ? VQS_OK : VQS_EHIP;
+}
+
+int vqs_mlp_init(float* params, uint64_t model_seed, const float* x, uint64_t m, void* stream) {
+  if (!params || !x || m == 0) return VQS_EINVAL;
+  return launch_init(params, model_seed, x, m, (hipStream_t)stream) == hipSuccess ? VQS_OK : VQS_EHIP;
+}
+
+int vqs_mlp_buckets(const float* params, const uint64_t* keys, uint64_t n, int32_t* out, void* stream) {
+  if (!params || (n && (!keys || !out))) return VQS_EINVAL;
+  if (n == 0) return VQS_OK;
+  return launch_buckets(params, keys, n, out, (hipStream_t)stream) == hipSuccess ? VQS_OK : VQS_EHIP;
+}
+
+int vqs_learned_thresholds(const float* params, uint64_t* thresholds, uint32_t* nvalid, void* stream) {
+  if (!params || !thresholds || !nvalid) return VQS_EINVAL;
+  return launch_thresholds(params, thresholds, nvalid, (hipStream_t)stream) == hipSuccess ? VQS_OK : VQS_EHIP;
+}
+
+int vqs_learned_classify(const uint64_t* keys, uint64_t n, const uint64_t* thresholds, const uint32_t* nvalid,
+                         int32_t* out, void* stream) {
+  if (!thresholds || !nvalid || (n && (!keys || !out))) return VQS_EINVAL;
+  if (n == 0) return VQS_OK;
+  return launch_classify(keys, n, thresholds, nvalid, out, (hipStream_t)stream) == hipSuccess ? VQS_OK : VQS_EHIP;
 }
 
 int vqs_last_error_bits(void* stream, uint32_t* out) {

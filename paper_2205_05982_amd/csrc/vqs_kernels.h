@@ -1276,14 +1276,14 @@ __global__ void seed_kernel(Params p, const int64_t* offsets, uint64_t nseg) {
     s.e = e;
     s.depth = 1;
     s.limit = p.fixed_limit >= 0 ? (uint32_t)p.fixed_limit : depth_limit_of(e - b);
-    s.flags = SEG_RAW;
+    s.flags = p.seed_level ? SEG_SCRATCH : SEG_RAW;
     if (e - b <= p.solo_max) {
       push_solo(p, s);
     } else if (s.depth > s.limit) {
       s.flags |= SEG_FALLBACK;
       push_solo(p, s);
     } else {
-      push_level<K, TL::T>(p, 0, s);
+      push_level<K, TL::T>(p, p.seed_level, s);
     }
   }
 }

@@ -1,24 +1,579 @@
-// vqs_learned.hip -- learned splitter: placeholder until the model kernels land.
+// vqs_learned.hip -- kernels of the learned 256-bucket splitter (u64 keys).
+//
+// Pipeline (host side in vqs_host.cpp): sample 1% of the keys in random aligned
+// 64-byte chunks (the pivot sampler's unit); sort the sample with the plain method;
+// mid-rank CDF targets; train the model with Adam in one workgroup; compile the
+// monotone bucket map into 255 exact thresholds; per-tile 256-bin histograms; a
+// per-bucket scan over tiles; one scatter pass into 256 contiguous buckets; then
+// the buckets are sorted as segments by the plain method.
+//
+// Every FP32 operation of the model's forward pass is a single correctly rounded
+// operation in a fixed order (explicit fused multiply-adds, no contraction), so
+// bucket ids are bit-identical to a scalar FP32 reference of the same steps.
+#pragma clang fp contract(off)
 #include "vqs_learned.h"
+#include "vqs_device.h"
 
 namespace vqs {
 
-void LearnedState::release() {
-  if (mem) (void)hipFree(mem);
-  mem = nullptr;
-  bytes = 0;
+namespace {
+
+// ---- model ------------------------------------------------------------------------
+
+__device__ inline float clamp01(float a) { return fminf(fmaxf(a, 0.0f), 1.0f); }
+
+// x(k): k rounded to float, its bit pattern as an unsigned integer, to float, * 2^-31
+__device__ inline float key_to_x(uint64_t k) {
+  const float f = __ull2float_rn(k);
+  const uint32_t bits = __float_as_uint(f);
+  return __fmul_rn(__uint2float_rn(bits), 0x1p-31f);
 }
 
-void LearnedState::fill_stats(vqs_stats* out) const {
-  if (!valid) return;
-  out->learned_buckets = last.learned_buckets;
-  out->overflow_buckets = last.overflow_buckets;
-  out->max_bucket = last.max_bucket;
-  out->train_loss = last.train_loss;
+__device__ inline float mlp_forward(const float* P, float x) {
+  const float xn = __fmul_rn(__fsub_rn(x, P[MLP_X0]), P[MLP_XS]);
+  float h1[MLP_H];
+#pragma unroll
+  for (int i = 0; i < MLP_H; i++) h1[i] = clamp01(__fmaf_rn(P[MLP_W1 + i], xn, P[MLP_B1 + i]));
+  float y = P[MLP_B3];
+  for (int j = 0; j < MLP_H; j++) {
+    float a = P[MLP_B2 + j];
+#pragma unroll
+    for (int i = 0; i < MLP_H; i++) a = __fmaf_rn(P[MLP_W2 + j * MLP_H + i], h1[i], a);
+    y = __fmaf_rn(P[MLP_W3 + j], clamp01(a), y);
+  }
+  return clamp01(y);
 }
 
-int learned_sort(LearnedState&, const Params&, uint64_t, const vqs_options*, hipStream_t, int*) {
-  return VQS_EINVAL;
+__device__ inline int bucket_of_y(float y) {
+  const int b = (int)__fmul_rn(y, (float)NBUCKET);   // y in [0, 1]: exact scaling, then floor
+  return b < NBUCKET - 1 ? b : NBUCKET - 1;
+}
+
+__device__ inline int mlp_bucket(const float* P, uint64_t k) { return bucket_of_y(mlp_forward(P, key_to_x(k))); }
+
+// counter-based SplitMix64: output number c of the sequence started at seed
+__device__ inline uint64_t splitmix_at(uint64_t seed, uint64_t c) {
+  uint64_t z = seed + (c + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// number of the first nvalid thresholds that are <= k (thresholds non-decreasing)
+__device__ inline int classify(const uint64_t* thr, int nvalid, uint64_t k) {
+  int b = 0;
+#pragma unroll
+  for (int step = 128; step >= 1; step >>= 1) {
+    const int c = b + step;
+    if (c <= nvalid && thr[c - 1] <= k) b = c;
+  }
+  return b;
+}
+
+// ---- sampling and targets ----------------------------------------------------------
+
+// chunk c: 8 keys (64 bytes) at chunk offset (u * chunks) >> 32, u the high half of
+// SplitMix64 output c of the seed; chunks are counted from the array start
+__global__ void sample_kernel(const uint64_t* keys, uint64_t n, uint64_t* sample, uint64_t nsample_chunks,
+                              uint64_t seed) {
+  const uint64_t nch = n / 8;
+  for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nsample_chunks;
+       c += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t u = (uint32_t)(splitmix_at(seed, c) >> 32);
+    const uint64_t off = (((uint64_t)u * nch) >> 32) * 8;
+#pragma unroll
+    for (int j = 0; j < 8; j++) sample[c * 8 + j] = keys[off + j];
+  }
+}
+
+// x(k) of each sorted sample and its mid-rank CDF target (first + last + 1) / 2 / m
+__global__ void targets_kernel(const uint64_t* s, uint64_t m, float* x, float* t) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t k = s[i];
+    uint64_t lo = 0, hi = i;          // first index with s[idx] == k
+    while (lo < hi) {
+      const uint64_t mid = (lo + hi) / 2;
+      if (s[mid] < k) lo = mid + 1; else hi = mid;
+    }
+    const uint64_t first = lo;
+    lo = i;
+    hi = m;                           // first index with s[idx] > k
+    while (lo < hi) {
+      const uint64_t mid = (lo + hi) / 2;
+      if (s[mid] <= k) lo = mid + 1; else hi = mid;
+    }
+    const uint64_t last = lo - 1;
+    x[i] = key_to_x(k);
+    t[i] = (float)(((double)first + (double)last + 1.0) * 0.5 / (double)m);
+  }
+}
+
+// untrained model: unit ramps tiling xn in [0,1] (w1 = 32, b1 = -i), second layer
+// (1 + 0.5 (u - 0.5)) / 32 with u from SplitMix64 outputs of the seed, biases
+// 0.1 (u - 0.5), output weights 1/32; x0 = x of the smallest sample, xs = 1 / range
+__global__ void init_kernel(float* P, uint64_t seed, const float* x, uint64_t m) {
+  for (int i = threadIdx.x; i < MLP_NBLOCK; i += blockDim.x) {
+    double v;
+    if (i < MLP_B1) v = 32.0;
+    else if (i < MLP_W2) v = -(double)(i - MLP_B1);
+    else if (i < MLP_B2) {
+      const double u = (double)(splitmix_at(seed, (uint64_t)(i - MLP_W2)) >> 40) / 16777216.0;
+      v = (1.0 + 0.5 * (u - 0.5)) / 32.0;
+    } else if (i < MLP_W3) {
+      const double u = (double)(splitmix_at(seed, (uint64_t)(i - MLP_W2)) >> 40) / 16777216.0;
+      v = 0.1 * (u - 0.5);
+    } else if (i < MLP_B3) v = 1.0 / 32.0;
+    else if (i == MLP_B3) v = 0.0;
+    else if (i == MLP_X0) v = (double)x[0];
+    else {
+      const float r = __fsub_rn(x[m - 1], x[0]);
+      v = (double)(r > 0.0f ? __fdiv_rn(1.0f, r) : 1.0f);
+    }
+    P[i] = (float)v;
+  }
+}
+
+// ---- training ------------------------------------------------------------------------
+
+constexpr int TRAIN_P = 256;
+constexpr int ROW = MLP_H + 1;   // padded LDS rows
+
+struct TrainShared {
+  float P[MLP_NBLOCK];
+  float G[MLP_NPARAM];
+  float H1[MLP_MAX_BATCH][ROW];
+  float H2[MLP_MAX_BATCH][ROW];
+  float DA2[MLP_MAX_BATCH][ROW];
+  float DA1[MLP_MAX_BATCH][ROW];
+  float XN[MLP_MAX_BATCH];
+  float D3[MLP_MAX_BATCH];
+  float LOSS[TRAIN_P];
+};
+
+// forward and backward of the samples (x[s], t[s]) for s < B, then the gradient of
+// the mean squared error into S.G and the loss sum into S.LOSS[0]
+__device__ void batch_gradient(TrainShared& S, float xs_in, float ts_in, int B) {
+  const int tid = threadIdx.x;
+  float l = 0.0f;
+  if (tid < B) {
+    const float* P = S.P;
+    const float xn = __fmul_rn(__fsub_rn(xs_in, P[MLP_X0]), P[MLP_XS]);
+    float h1[MLP_H], h2[MLP_H];
+    uint32_t m1 = 0, m2 = 0;
+#pragma unroll
+    for (int i = 0; i < MLP_H; i++) {
+      const float a = __fmaf_rn(P[MLP_W1 + i], xn, P[MLP_B1 + i]);
+      h1[i] = clamp01(a);
+      m1 |= (a > 0.0f && a < 1.0f) ? (1u << i) : 0u;
+      S.H1[tid][i] = h1[i];
+    }
+    float a3 = P[MLP_B3];
+    for (int j = 0; j < MLP_H; j++) {
+      float a = P[MLP_B2 + j];
+#pragma unroll
+      for (int i = 0; i < MLP_H; i++) a = __fmaf_rn(P[MLP_W2 + j * MLP_H + i], h1[i], a);
+      h2[j] = clamp01(a);
+      m2 |= (a > 0.0f && a < 1.0f) ? (1u << j) : 0u;
+      S.H2[tid][j] = h2[j];
+      a3 = __fmaf_rn(P[MLP_W3 + j], h2[j], a3);
+    }
+    const float y = clamp01(a3);
+    const float r = y - ts_in;
+    l = r * r;
+    const float d3 = (a3 > 0.0f && a3 < 1.0f) ? (2.0f / (float)B) * r : 0.0f;
+    S.XN[tid] = xn;
+    S.D3[tid] = d3;
+    float dh1[MLP_H];
+#pragma unroll
+    for (int i = 0; i < MLP_H; i++) dh1[i] = 0.0f;
+    for (int j = 0; j < MLP_H; j++) {
+      const float da2 = ((m2 >> j) & 1u) ? d3 * P[MLP_W3 + j] : 0.0f;
+      S.DA2[tid][j] = da2;
+#pragma unroll
+      for (int i = 0; i < MLP_H; i++) dh1[i] = fmaf(da2, P[MLP_W2 + j * MLP_H + i], dh1[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < MLP_H; i++) S.DA1[tid][i] = ((m1 >> i) & 1u) ? dh1[i] : 0.0f;
+  }
+  S.LOSS[tid] = l;
+  __syncthreads();
+  for (int q = tid; q < MLP_NPARAM; q += TRAIN_P) {
+    float g = 0.0f;
+    if (q >= MLP_W2 && q < MLP_B2) {
+      const int j = (q - MLP_W2) / MLP_H, i = (q - MLP_W2) % MLP_H;
+      for (int s = 0; s < B; s++) g = fmaf(S.DA2[s][j], S.H1[s][i], g);
+    } else if (q < MLP_B1) {
+      for (int s = 0; s < B; s++) g = fmaf(S.DA1[s][q], S.XN[s], g);
+    } else if (q < MLP_W2) {
+      for (int s = 0; s < B; s++) g += S.DA1[s][q - MLP_B1];
+    } else if (q < MLP_W3) {
+      for (int s = 0; s < B; s++) g += S.DA2[s][q - MLP_B2];
+    } else if (q < MLP_B3) {
+      for (int s = 0; s < B; s++) g = fmaf(S.D3[s], S.H2[s][q - MLP_W3], g);
+    } else {
+      for (int s = 0; s < B; s++) g += S.D3[s];
+    }
+    S.G[q] = g;
+  }
+  // loss sum (tree in LDS)
+  for (int w = TRAIN_P / 2; w >= 1; w >>= 1) {
+    __syncthreads();
+    if (tid < w) S.LOSS[tid] += S.LOSS[tid + w];
+  }
+  __syncthreads();
+}
+
+// Adam (Kingma & Ba) with bias correction; step size decays linearly from lr to
+// lr / 10; the first layer's parameters take 32x the step (their scale is 32x);
+// weight matrices are projected onto w >= 0 after every step.
+__global__ void __launch_bounds__(TRAIN_P) train_kernel(float* params, float* moments, TrainArgs a) {
+  __shared__ TrainShared S;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < MLP_NBLOCK; i += TRAIN_P) S.P[i] = params[i];
+  constexpr int PER = (MLP_NPARAM + TRAIN_P - 1) / TRAIN_P;
+  float mo[PER], ve[PER];
+#pragma unroll
+  for (int q = 0; q < PER; q++) {
+    const int i = tid + q * TRAIN_P;
+    mo[q] = i < MLP_NPARAM ? moments[i] : 0.0f;
+    ve[q] = i < MLP_NPARAM ? moments[MLP_NPARAM + i] : 0.0f;
+  }
+  __syncthreads();
+  const int B = (int)(a.batch < (uint32_t)MLP_MAX_BATCH ? a.batch : MLP_MAX_BATCH);
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  float b1t = 1.0f, b2t = 1.0f;
+  for (uint32_t step = 1; step <= a.steps; step++) {
+    float xv = 0.0f, tv = 0.0f;
+    if (tid < B) {
+      const uint64_t draw = (uint64_t)(step - 1) * (uint64_t)B + (uint64_t)tid;
+      uint64_t idx;
+      if (a.sequential) idx = draw % a.m;
+      else idx = ((splitmix_at(a.seed, draw) >> 32) * a.m) >> 32;
+      xv = a.x[idx];
+      tv = a.t[idx];
+    }
+    batch_gradient(S, xv, tv, B);
+    b1t *= b1;
+    b2t *= b2;
+    const float lr = a.lr * (1.0f - 0.9f * (float)(step - 1) / (float)(a.steps > 1 ? a.steps - 1 : 1));
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+      const int i = tid + q * TRAIN_P;
+      if (i < MLP_NPARAM) {
+        const float g = S.G[i];
+        mo[q] = b1 * mo[q] + (1.0f - b1) * g;
+        ve[q] = b2 * ve[q] + (1.0f - b2) * g * g;
+        const float mh = mo[q] / (1.0f - b1t), vh = ve[q] / (1.0f - b2t);
+        const float mult = i < MLP_W2 ? 32.0f : 1.0f;
+        float v = S.P[i] - lr * mult * mh / (sqrtf(vh) + eps);
+        const bool nonneg = i < MLP_B1 || (i >= MLP_W2 && i < MLP_B2) || (i >= MLP_W3 && i < MLP_B3);
+        if (nonneg) v = fmaxf(v, 0.0f);
+        S.P[i] = v;
+      }
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < MLP_NBLOCK; i += TRAIN_P) params[i] = S.P[i];
+#pragma unroll
+  for (int q = 0; q < PER; q++) {
+    const int i = tid + q * TRAIN_P;
+    if (i < MLP_NPARAM) {
+      moments[i] = mo[q];
+      moments[MLP_NPARAM + i] = ve[q];
+    }
+  }
+  if (tid == 0) moments[2 * MLP_NPARAM] = S.LOSS[0] / (float)(B > 0 ? B : 1);
+}
+
+// gradient of the mean squared error over m <= MLP_MAX_BATCH samples
+__global__ void __launch_bounds__(TRAIN_P) gradient_kernel(const float* params, const float* x, const float* t,
+                                                           uint32_t m, float* grad, float* loss) {
+  __shared__ TrainShared S;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < MLP_NBLOCK; i += TRAIN_P) S.P[i] = params[i];
+  __syncthreads();
+  const int B = (int)m;
+  batch_gradient(S, tid < B ? x[tid] : 0.0f, tid < B ? t[tid] : 0.0f, B);
+  for (int i = tid; i < MLP_NPARAM; i += TRAIN_P) grad[i] = S.G[i];
+  if (tid == 0) *loss = S.LOSS[0] / (float)B;
+}
+
+// ---- inference, thresholds, classification ----------------------------------------------
+
+__global__ void forward_kernel(const float* params, const float* x, uint64_t m, float* y) {
+  __shared__ float P[MLP_NBLOCK];
+  for (int i = threadIdx.x; i < MLP_NBLOCK; i += blockDim.x) P[i] = params[i];
+  __syncthreads();
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (uint64_t)gridDim.x * blockDim.x)
+    y[i] = mlp_forward(P, x[i]);
+}
+
+__global__ void buckets_kernel(const float* params, const uint64_t* keys, uint64_t n, int32_t* out) {
+  __shared__ float P[MLP_NBLOCK];
+  for (int i = threadIdx.x; i < MLP_NBLOCK; i += blockDim.x) P[i] = params[i];
+  __syncthreads();
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    out[i] = mlp_bucket(P, keys[i]);
+}
+
+// t_j = min{k : b(k) >= j} for j = 1..255 by binary search over all 64-bit keys;
+// nvalid = b(2^64 - 1): thresholds j > nvalid do not exist
+__global__ void thresholds_kernel(const float* params, uint64_t* thr, uint32_t* nvalid) {
+  __shared__ float P[MLP_NBLOCK];
+  for (int i = threadIdx.x; i < MLP_NBLOCK; i += blockDim.x) P[i] = params[i];
+  __syncthreads();
+  const int j = blockIdx.x * blockDim.x + threadIdx.x + 1;
+  if (j == 1) *nvalid = (uint32_t)mlp_bucket(P, ~0ull);
+  if (j >= NBUCKET) return;
+  if (mlp_bucket(P, ~0ull) < j) {
+    thr[j - 1] = ~0ull;
+    return;
+  }
+  uint64_t lo = 0, hi = ~0ull;
+  while (lo < hi) {
+    const uint64_t mid = lo + (hi - lo) / 2;
+    if (mlp_bucket(P, mid) >= j) hi = mid; else lo = mid + 1;
+  }
+  thr[j - 1] = lo;
+}
+
+__global__ void classify_kernel(const uint64_t* keys, uint64_t n, const uint64_t* thr, const uint32_t* nvalid,
+                                int32_t* out) {
+  __shared__ uint64_t T[NBUCKET];
+  for (int i = threadIdx.x; i < NBUCKET - 1; i += blockDim.x) T[i] = thr[i];
+  __syncthreads();
+  const int J = (int)*nvalid;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    out[i] = classify(T, J, keys[i]);
+}
+
+// ---- 256-way partition ---------------------------------------------------------------------
+
+constexpr int LT_P = 256;
+constexpr int LT_PER = LEARN_TILE / LT_P;   // 16 keys per thread
+
+// per-tile bucket counts, stored bucket-major: hist[b * ntiles + tile]
+__global__ void __launch_bounds__(LT_P) histogram_kernel(const uint64_t* keys, uint64_t n, const uint64_t* thr,
+                                                         const uint32_t* nvalid, uint32_t* hist, uint64_t ntiles) {
+  __shared__ uint64_t T[NBUCKET];
+  __shared__ uint32_t C[NBUCKET];
+  for (int i = threadIdx.x; i < NBUCKET - 1; i += LT_P) T[i] = thr[i];
+  const int J = (int)*nvalid;
+  for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    C[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t base = tile * LEARN_TILE;
+#pragma unroll 4
+    for (int q = 0; q < LT_PER; q++) {
+      const uint64_t i = base + (uint64_t)q * LT_P + threadIdx.x;
+      if (i < n) atomicAdd(&C[classify(T, J, keys[i])], 1u);
+    }
+    __syncthreads();
+    hist[(uint64_t)threadIdx.x * ntiles + tile] = C[threadIdx.x];
+    __syncthreads();
+  }
+}
+
+// exclusive scan of each bucket's row over tiles, in place; totals[b] = row sum
+__global__ void __launch_bounds__(LT_P) scan_kernel(uint32_t* hist, uint64_t ntiles, uint64_t* totals) {
+  __shared__ uint64_t W[LT_P / WAVE];
+  const uint64_t b = blockIdx.x;
+  uint32_t* row = hist + b * ntiles;
+  uint64_t carry = 0;
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  for (uint64_t c0 = 0; c0 < ntiles; c0 += LT_P) {
+    const uint64_t i = c0 + threadIdx.x;
+    const uint64_t v = i < ntiles ? row[i] : 0;
+    uint64_t inc = v;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+      const uint64_t o = (uint64_t)__shfl_up((long long)inc, d);
+      if (lane >= d) inc += o;
+    }
+    if (lane == WAVE - 1) W[w] = inc;
+    __syncthreads();
+    uint64_t before = carry;
+    for (int k = 0; k < w; k++) before += W[k];
+    uint64_t tot = 0;
+    for (int k = 0; k < LT_P / WAVE; k++) tot += W[k];
+    if (i < ntiles) row[i] = (uint32_t)(before + inc - v);
+    carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) totals[b] = carry;
+}
+
+// bucket starts (offsets[0..256]) and a summary: [0] largest bucket, [1] buckets above
+// overflow_factor * n / 256, [2] non-empty buckets
+__global__ void offsets_kernel(const uint64_t* totals, uint64_t n, float overflow_factor, int64_t* offsets,
+                               uint64_t* summary) {
+  if (threadIdx.x != 0) return;
+  uint64_t acc = 0, mx = 0, over = 0, nonempty = 0;
+  const double bound = (double)overflow_factor * (double)n / (double)NBUCKET;
+  for (int b = 0; b < NBUCKET; b++) {
+    offsets[b] = (int64_t)acc;
+    acc += totals[b];
+    mx = totals[b] > mx ? totals[b] : mx;
+    over += (double)totals[b] > bound ? 1 : 0;
+    nonempty += totals[b] ? 1 : 0;
+  }
+  offsets[NBUCKET] = (int64_t)acc;
+  summary[0] = mx;
+  summary[1] = over;
+  summary[2] = nonempty;
+}
+
+// one pass: classify, rank inside the tile per bucket, stage bucket-major in LDS, write
+// every bucket's run of the tile to offsets[b] + (keys of bucket b in earlier tiles)
+__global__ void __launch_bounds__(LT_P) scatter_kernel(const uint64_t* keys, uint64_t n, const uint64_t* thr,
+                                                       const uint32_t* nvalid, const uint32_t* hist,
+                                                       uint64_t ntiles, const int64_t* offsets, uint64_t* out) {
+  __shared__ uint64_t T[NBUCKET];
+  __shared__ uint32_t C[NBUCKET];
+  __shared__ uint32_t LO[NBUCKET];
+  __shared__ uint64_t DST[NBUCKET];
+  __shared__ uint64_t stage[LEARN_TILE];
+  __shared__ uint8_t bid[LEARN_TILE];
+  __shared__ uint32_t W[LT_P / WAVE];
+  for (int i = threadIdx.x; i < NBUCKET - 1; i += LT_P) T[i] = thr[i];
+  const int J = (int)*nvalid;
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    C[threadIdx.x] = 0;
+    DST[threadIdx.x] = (uint64_t)offsets[threadIdx.x] + hist[(uint64_t)threadIdx.x * ntiles + tile];
+    __syncthreads();
+    const uint64_t base = tile * LEARN_TILE;
+    uint64_t k[LT_PER];
+    uint32_t r[LT_PER];
+    uint8_t bb[LT_PER];
+#pragma unroll
+    for (int q = 0; q < LT_PER; q++) {
+      const uint64_t i = base + (uint64_t)q * LT_P + threadIdx.x;
+      if (i < n) {
+        k[q] = keys[i];
+        const int b = classify(T, J, k[q]);
+        bb[q] = (uint8_t)b;
+        r[q] = atomicAdd(&C[b], 1u);
+      }
+    }
+    __syncthreads();
+    // exclusive scan of the tile's bucket counts
+    {
+      const uint32_t v = C[threadIdx.x];
+      uint32_t inc = v;
+#pragma unroll
+      for (int d = 1; d < WAVE; d <<= 1) {
+        const uint32_t o = (uint32_t)__shfl_up((int)inc, d);
+        if (lane >= d) inc += o;
+      }
+      if (lane == WAVE - 1) W[w] = inc;
+      __syncthreads();
+      uint32_t before = 0;
+      for (int kk = 0; kk < w; kk++) before += W[kk];
+      LO[threadIdx.x] = before + inc - v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < LT_PER; q++) {
+      const uint64_t i = base + (uint64_t)q * LT_P + threadIdx.x;
+      if (i < n) {
+        const uint32_t pos = LO[bb[q]] + r[q];
+        stage[pos] = k[q];
+        bid[pos] = bb[q];
+      }
+    }
+    __syncthreads();
+    const uint32_t cnt = (uint32_t)((n - base) < (uint64_t)LEARN_TILE ? (n - base) : (uint64_t)LEARN_TILE);
+    for (uint32_t s = threadIdx.x; s < cnt; s += LT_P) {
+      const int b = bid[s];
+      const uint64_t d = DST[b] + (s - LO[b]);
+      if (d < n) out[d] = stage[s];
+    }
+    __syncthreads();
+  }
+}
+
+int grid_for(uint64_t work, int per, int cap) {
+  uint64_t g = (work + per - 1) / per;
+  if (g < 1) g = 1;
+  if (g > (uint64_t)cap) g = cap;
+  return (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_sample(const uint64_t* keys, uint64_t n, uint64_t* sample, uint64_t chunks, uint64_t seed,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(sample_kernel, dim3(grid_for(chunks, 256, 4096)), dim3(256), 0, s, keys, n, sample, chunks, seed);
+  return hipGetLastError();
+}
+
+hipError_t launch_targets(const uint64_t* sorted, uint64_t m, float* x, float* t, hipStream_t s) {
+  hipLaunchKernelGGL(targets_kernel, dim3(grid_for(m, 256, 8192)), dim3(256), 0, s, sorted, m, x, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_init(float* params, uint64_t seed, const float* x, uint64_t m, hipStream_t s) {
+  hipLaunchKernelGGL(init_kernel, dim3(1), dim3(256), 0, s, params, seed, x, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_train(float* params, float* moments, const TrainArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(train_kernel, dim3(1), dim3(TRAIN_P), 0, s, params, moments, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_gradient(const float* params, const float* x, const float* t, uint32_t m, float* grad, float* loss,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(gradient_kernel, dim3(1), dim3(TRAIN_P), 0, s, params, x, t, m, grad, loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_forward(const float* params, const float* x, uint64_t m, float* y, hipStream_t s) {
+  hipLaunchKernelGGL(forward_kernel, dim3(grid_for(m, 256, 4096)), dim3(256), 0, s, params, x, m, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_buckets(const float* params, const uint64_t* keys, uint64_t n, int32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(buckets_kernel, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, params, keys, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_thresholds(const float* params, uint64_t* thr, uint32_t* nvalid, hipStream_t s) {
+  hipLaunchKernelGGL(thresholds_kernel, dim3(4), dim3(64), 0, s, params, thr, nvalid);
+  return hipGetLastError();
+}
+
+hipError_t launch_classify(const uint64_t* keys, uint64_t n, const uint64_t* thr, const uint32_t* nvalid, int32_t* out,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(classify_kernel, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, keys, n, thr, nvalid, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_histogram(const uint64_t* keys, uint64_t n, const uint64_t* thr, const uint32_t* nvalid,
+                            uint32_t* hist, uint64_t ntiles, hipStream_t s) {
+  hipLaunchKernelGGL(histogram_kernel, dim3(grid_for(ntiles, 1, 4096)), dim3(LT_P), 0, s, keys, n, thr, nvalid, hist,
+                     ntiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(uint32_t* hist, uint64_t ntiles, uint64_t* totals, hipStream_t s) {
+  hipLaunchKernelGGL(scan_kernel, dim3(NBUCKET), dim3(LT_P), 0, s, hist, ntiles, totals);
+  return hipGetLastError();
+}
+
+hipError_t launch_offsets(const uint64_t* totals, uint64_t n, float overflow_factor, int64_t* offsets,
+                          uint64_t* summary, hipStream_t s) {
+  hipLaunchKernelGGL(offsets_kernel, dim3(1), dim3(64), 0, s, totals, n, overflow_factor, offsets, summary);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(const uint64_t* keys, uint64_t n, const uint64_t* thr, const uint32_t* nvalid,
+                          const uint32_t* hist, uint64_t ntiles, const int64_t* offsets, uint64_t* out,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(scatter_kernel, dim3(grid_for(ntiles, 1, 2048)), dim3(LT_P), 0, s, keys, n, thr, nvalid, hist,
+                     ntiles, offsets, out);
+  return hipGetLastError();
 }
 
 }  // namespace vqs

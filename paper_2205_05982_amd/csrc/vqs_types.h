@@ -92,6 +92,7 @@ struct Params {
   int max_levels;
   int64_t fixed_limit;   // < 0: 2*floor(log2 len)+4 per input range; else this limit
   unsigned long long* dbg;  // instrumented builds only (null otherwise)
+  int seed_level;        // level of the first partition (1: input ranges live in scratch)
 };
 
 constexpr uint64_t FILL_CHUNK = 1ull << 16;

@@ -40,7 +40,8 @@ class Options(ctypes.Structure):
                 ("validate", ctypes.c_uint32), ("train_steps", ctypes.c_uint32),
                 ("batch", ctypes.c_uint32), ("sample_fraction", ctypes.c_float),
                 ("overflow_factor", ctypes.c_float), ("learning_rate", ctypes.c_float),
-                ("reserved", ctypes.c_uint32 * 7)]
+                ("model_seed", ctypes.c_uint64), ("sample_seed", ctypes.c_uint64),
+                ("reserved", ctypes.c_uint32 * 3)]
 
 
 class Stats(ctypes.Structure):
@@ -201,3 +202,92 @@ def profile_read(stream=None, max_records: int = 4096) -> list:
         raise VqsError(rc, "vqs_profile_read")
     return [{"kind": KERNEL_KINDS.get(arr[i].kind, str(arr[i].kind)), "level": arr[i].level,
              "keys": int(arr[i].keys), "ms": float(arr[i].ms)} for i in range(cnt.value)]
+
+
+# ---- learned splitter pieces ----------------------------------------------------------
+
+MLP_NBLOCK = 1155
+MLP_NPARAM = 1153
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _sig():
+    L = lib()
+    vp, u64, u32, i32, f32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, ctypes.c_float
+    L.vqs_learned_fit.argtypes = [vp, u64, ctypes.POINTER(Options), vp, vp]
+    L.vqs_mlp_forward.argtypes = [vp, vp, u64, vp, vp]
+    L.vqs_mlp_gradient.argtypes = [vp, vp, vp, u32, vp, vp, vp]
+    L.vqs_mlp_train.argtypes = [vp, vp, vp, vp, u64, u32, u32, f32, u64, i32, vp]
+    L.vqs_mlp_init.argtypes = [vp, u64, vp, u64, vp]
+    L.vqs_mlp_buckets.argtypes = [vp, vp, u64, vp, vp]
+    L.vqs_learned_thresholds.argtypes = [vp, vp, vp, vp]
+    L.vqs_learned_classify.argtypes = [vp, u64, vp, vp, vp, vp]
+    for n in ("vqs_learned_fit", "vqs_mlp_forward", "vqs_mlp_gradient", "vqs_mlp_train", "vqs_mlp_init",
+              "vqs_mlp_buckets", "vqs_learned_thresholds", "vqs_learned_classify"):
+        getattr(L, n).restype = i32
+    return L
+
+
+def _rc(rc, what):
+    if rc != 0:
+        raise VqsError(rc, what)
+
+
+def learned_fit(keys: torch.Tensor, stream=None, **opts) -> torch.Tensor:
+    """Sample, sort the sample, compute targets and train; returns the 1155-float model."""
+    _check(keys)
+    params = torch.empty(MLP_NBLOCK, dtype=torch.float32, device=keys.device)
+    o = make_options(**opts)
+    _rc(_sig().vqs_learned_fit(_p(keys), keys.numel() * keys.element_size() // 8, ctypes.byref(o), _p(params),
+                               ctypes.c_void_p(_stream_handle(stream))), "vqs_learned_fit")
+    return params
+
+
+def mlp_forward(params, x, stream=None):
+    y = torch.empty_like(x)
+    _rc(_sig().vqs_mlp_forward(_p(params), _p(x), x.numel(), _p(y), ctypes.c_void_p(_stream_handle(stream))),
+        "vqs_mlp_forward")
+    return y
+
+
+def mlp_gradient(params, x, t, stream=None):
+    g = torch.empty(MLP_NPARAM, dtype=torch.float32, device=x.device)
+    loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    _rc(_sig().vqs_mlp_gradient(_p(params), _p(x), _p(t), x.numel(), _p(g), _p(loss),
+                                ctypes.c_void_p(_stream_handle(stream))), "vqs_mlp_gradient")
+    return g, loss
+
+
+def mlp_train(params, moments, x, t, steps, batch, lr, seed=17, sequential=False, stream=None):
+    _rc(_sig().vqs_mlp_train(_p(params), _p(moments), _p(x), _p(t), x.numel(), steps, batch, lr, seed,
+                             int(bool(sequential)), ctypes.c_void_p(_stream_handle(stream))), "vqs_mlp_train")
+
+
+def mlp_init(params, seed, x, stream=None):
+    _rc(_sig().vqs_mlp_init(_p(params), seed, _p(x), x.numel(), ctypes.c_void_p(_stream_handle(stream))),
+        "vqs_mlp_init")
+
+
+def mlp_buckets(params, keys, stream=None):
+    out = torch.empty(keys.numel(), dtype=torch.int32, device=keys.device)
+    _rc(_sig().vqs_mlp_buckets(_p(params), _p(keys), keys.numel(), _p(out), ctypes.c_void_p(_stream_handle(stream))),
+        "vqs_mlp_buckets")
+    return out
+
+
+def learned_thresholds(params, stream=None):
+    thr = torch.empty(255, dtype=torch.int64, device=params.device)
+    nvalid = torch.empty(1, dtype=torch.int32, device=params.device)
+    _rc(_sig().vqs_learned_thresholds(_p(params), _p(thr), _p(nvalid), ctypes.c_void_p(_stream_handle(stream))),
+        "vqs_learned_thresholds")
+    return thr, nvalid
+
+
+def learned_classify(keys, thr, nvalid, stream=None):
+    out = torch.empty(keys.numel(), dtype=torch.int32, device=keys.device)
+    _rc(_sig().vqs_learned_classify(_p(keys), keys.numel(), _p(thr), _p(nvalid), _p(out),
+                                    ctypes.c_void_p(_stream_handle(stream))), "vqs_learned_classify")
+    return out

@@ -56,7 +56,8 @@ def test_argument_errors_return_before_any_device_call(lib):
 
 def test_options_layout_matches_binding():
     from paper_2205_05982_amd import vqs
-    # struct vqs_options: 2*u32, u64, i64, 2*u32, u64, 4*u32, 3*float, 7*u32 (+ padding)
-    assert ctypes.sizeof(vqs.Options) == 96
+    # struct vqs_options: 2*u32, u64, i64, 2*u32, u64, 4*u32, 3*float, (pad) 2*u64, 3*u32 (+ pad)
+    assert ctypes.sizeof(vqs.Options) == 104
+    assert vqs.Options.model_seed.offset == 72
     assert vqs.Options.train_steps.offset == 48
     assert ctypes.sizeof(vqs.Stats) == 16 * 8

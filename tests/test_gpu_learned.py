@@ -1,0 +1,149 @@
+"""GPU parity of the learned splitter: forward pass and bucket ids bit-exact with the
+FP32 reference, thresholds exact, gradients and an Adam step against the double
+reference, the end-to-end learned sort bit-exact against the plain definition, and
+the balance the trained model gains over the untrained one."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp
+from paper_2205_05982_amd import workloads as W
+from tests.helpers import to_gpu, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vqs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a visible GPU")
+    from paper_2205_05982_amd import vqs as v
+    return v
+
+
+def _params(seed, x0=0.53, xs=6.0):
+    rng = np.random.default_rng(seed)
+    p = np.zeros(mlp.NBLOCK)
+    p[mlp.SL["w1"]] = rng.uniform(1.0, 20.0, mlp.H)
+    p[mlp.SL["b1"]] = rng.uniform(-10.0, 2.0, mlp.H)
+    p[mlp.SL["W2"]] = rng.uniform(0.0, 0.12, mlp.H * mlp.H)
+    p[mlp.SL["b2"]] = rng.uniform(-0.5, 0.3, mlp.H)
+    p[mlp.SL["w3"]] = rng.uniform(0.0, 0.08, mlp.H)
+    p[mlp.SL["b3"]] = 0.05
+    p[mlp.X0], p[mlp.XS] = x0, xs
+    return p.astype(np.float32)
+
+
+def test_forward_bit_exact(vqs):
+    import torch
+    p = _params(1)
+    x = np.random.default_rng(2).uniform(0.5, 0.8, 100_000).astype(np.float32)
+    y = to_host(vqs.mlp_forward(to_gpu(p), to_gpu(x)))
+    np.testing.assert_array_equal(y, mlp.forward_f32(p, x))
+
+
+def test_buckets_bit_exact_and_thresholds_exact(vqs):
+    import torch
+    for seed in (3, 4):
+        p = _params(seed)
+        keys = W.lognormal_mixture_u64(300_000, 15)
+        keys = np.concatenate([keys, np.array([0, 1, 2**64 - 1], dtype=np.uint64)])
+        kg = to_gpu(keys)
+        pg = to_gpu(p)
+        b_gpu = to_host(vqs.mlp_buckets(pg, kg))
+        np.testing.assert_array_equal(b_gpu, mlp.buckets_f32(p, keys))
+        thr, nv = vqs.learned_thresholds(pg)
+        b_thr = to_host(vqs.learned_classify(kg, thr, nv))
+        np.testing.assert_array_equal(b_thr, b_gpu)
+        # thresholds are the first keys of their buckets
+        t = to_host(thr).view(np.uint64)[: int(to_host(nv)[0])]
+        assert (np.diff(t.astype(object)) >= 0).all()
+        j = np.arange(1, t.size + 1)
+        assert (mlp.buckets_f32(p, t) >= j).all()            # t_j reaches bucket j ...
+        prev = mlp.buckets_f32(p, t[t > 0] - np.uint64(1))
+        assert (prev < j[t > 0]).all()                      # ... and t_j - 1 does not
+
+
+def test_gradient_matches_double_reference(vqs):
+    p = _params(5)
+    rng = np.random.default_rng(6)
+    x = rng.uniform(0.53, 0.69, 192).astype(np.float32)
+    t = np.sort(rng.uniform(0, 1, 192)).astype(np.float32)
+    g, loss = vqs.mlp_gradient(to_gpu(p), to_gpu(x), to_gpu(t))
+    lw, gw = mlp.loss_and_grad(p.astype(np.float64), x.astype(np.float64), t.astype(np.float64))
+    g = to_host(g).astype(np.float64)
+    rel = np.linalg.norm(g - gw[:mlp.NPARAM]) / np.linalg.norm(gw[:mlp.NPARAM])
+    assert rel < 1e-4, rel
+    assert abs(float(to_host(loss)[0]) - lw) < 1e-6 + 1e-4 * lw
+
+
+def test_one_adam_step_matches_reference(vqs):
+    import torch
+    p = _params(7)
+    rng = np.random.default_rng(8)
+    x = rng.uniform(0.53, 0.69, 192).astype(np.float32)
+    t = np.sort(rng.uniform(0, 1, 192)).astype(np.float32)
+    pg = to_gpu(p)
+    mom = torch.zeros(2 * mlp.NPARAM + 1, dtype=torch.float32, device="cuda")
+    vqs.mlp_train(pg, mom, to_gpu(x), to_gpu(t), steps=1, batch=192, lr=1e-3, sequential=True)
+    _, g = mlp.loss_and_grad(p.astype(np.float64), x.astype(np.float64), t.astype(np.float64))
+    want, _, _ = mlp.adam_step(p.astype(np.float64), g, np.zeros(mlp.NBLOCK), np.zeros(mlp.NBLOCK), 1,
+                               mlp.lr_at(1, 1, 1e-3))
+    got = to_host(pg).astype(np.float64)
+    # the first Adam step moves each parameter by ~lr * sign(g): compare where |g| is
+    # clearly nonzero (where it is tiny, FP32 rounding can flip the step)
+    sel = np.abs(g[:mlp.NPARAM]) > 1e-5
+    np.testing.assert_allclose(got[:mlp.NPARAM][sel], want[:mlp.NPARAM][sel], rtol=1e-5, atol=1e-6)
+
+
+def test_init_matches_reference(vqs):
+    import torch
+    x = np.sort(np.random.default_rng(9).uniform(0.55, 0.7, 1000)).astype(np.float32)
+    pg = torch.empty(mlp.NBLOCK, dtype=torch.float32, device="cuda")
+    vqs.mlp_init(pg, 16, to_gpu(x))
+    x0 = np.float32(x[0])
+    xs = np.float32(1.0) / (np.float32(x[-1]) - x0)
+    np.testing.assert_array_equal(to_host(pg), mlp.init_params(16, x0, xs).astype(np.float32))
+
+
+@pytest.mark.parametrize("n", [2_000_000, 5_000_000])
+def test_learned_sort_bit_exact(vqs, n):
+    import torch
+    keys = W.lognormal_mixture_u64(n, 15)
+    t = to_gpu(keys)
+    vqs.sort(t, key_type=3, method=1)
+    torch.cuda.synchronize()
+    assert vqs.last_error_bits() == 0
+    np.testing.assert_array_equal(to_host(t), np.sort(keys))
+    st = vqs.get_stats()
+    assert st["learned_buckets"] == 256 and st["max_bucket"] > 0
+
+
+def test_learned_sort_overflow_rule_and_degenerate_inputs(vqs):
+    import torch
+    for keys in (W.few_distinct_u64(1_000_000, 4), np.full(200_000, 5, dtype=np.uint64),
+                 W.uniform_u64(1_000_000, 2)):
+        t = to_gpu(keys)
+        vqs.sort(t, key_type=3, method=1, overflow_factor=0.5)
+        torch.cuda.synchronize()
+        assert vqs.last_error_bits() == 0
+        np.testing.assert_array_equal(to_host(t), np.sort(keys))
+        st = vqs.get_stats()
+        assert st["overflow_buckets"] >= 1
+
+
+def test_trained_model_balances_better_than_untrained(vqs):
+    import torch
+    n = 4_000_000
+    keys = W.lognormal_mixture_u64(n, 15)
+    kg = to_gpu(keys)
+    trained = vqs.learned_fit(kg, train_steps=600)
+    xs_all = mlp.key_to_x(np.array([keys.min(), keys.max()], dtype=np.uint64))
+    untrained = mlp.init_params(16, xs_all[0], np.float32(1.0) / (xs_all[1] - xs_all[0])).astype(np.float32)
+    bt = np.bincount(to_host(vqs.mlp_buckets(trained, kg)), minlength=256)
+    bu = np.bincount(to_host(vqs.mlp_buckets(to_gpu(untrained), kg)), minlength=256)
+    jt, ju = mlp.balance(bt, n), mlp.balance(bu, n)
+    print("trained", jt, "untrained", ju)
+    assert jt["rms_rel_dev"] < 0.75 * ju["rms_rel_dev"]
+    assert bt.max() < bu.max()
