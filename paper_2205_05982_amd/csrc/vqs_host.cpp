@@ -212,7 +212,10 @@ int make_plan(uint64_t n, uint64_t nseg, int kt, int asc, const vqs_options* o, 
     if (pl->depth_limit > 200) return VQS_EINVAL;
     lim = (uint32_t)pl->depth_limit;
   }
-  pl->max_levels = (int)lim + 3;
+  // A range reaches the paper's depth limit by level lim (one more when the ranges are
+  // seeded at level 1); past it, fallback mode may take depth_limit_for(n) more levels.
+  // Levels 0 .. max_levels - 2 are launched.
+  pl->max_levels = (int)lim + (int)depth_limit_for(std::max<uint64_t>(n, 2)) + 4;
   const uint64_t T = level_tile_keys(bits);
   pl->cap_lvl = n / (pl->solo + 1) + 2;
   pl->cap_tiles = n / T + 2 * pl->cap_lvl + 2;

@@ -132,11 +132,11 @@ struct Tile {
     }
   }
 
-  // Classify against the pivot, rank stably, stage in LDS (left keys from 0 upward,
-  // right keys from nvalid-1 downward).  Returns the tile's left count; *tmin gets
+  // Classify against the pivot (left: not after it; strict: before it), rank stably,
+  // stage in LDS (left keys from 0 upward, right keys from nvalid-1 downward).  Returns the tile's left count; *tmin gets
   // the tile minimum (thread 0).  Ends with a barrier.
   __device__ static uint32_t rank_and_stage(S* stage, Aux& sh, const R (&key)[I][V], uint64_t k,
-                                            uint64_t vs, uint64_t ve, R pivot, R* tmin) {
+                                            uint64_t vs, uint64_t ve, R pivot, bool strict, R* tmin) {
     const int tid = threadIdx.x;
     const int w = tid / WAVE;
     uint32_t pre[I];
@@ -149,7 +149,7 @@ struct Tile {
 #pragma unroll
       for (int q = 0; q < V; q++) {
         const bool valid = (v0 + q >= vs) && (v0 + q < ve);
-        const bool left = valid && !K::lt(pivot, key[j][q]);
+        const bool left = valid && (strict ? K::lt(key[j][q], pivot) : !K::lt(pivot, key[j][q]));
         if (valid) mn = K::kmin(mn, key[j][q]);
         const uint64_t m = ballot(left);
         lanepre += mbcnt(m);
@@ -244,7 +244,7 @@ __device__ inline void push_solo(const Params& p, const Seg& s) {
 
 template <class K, int T>
 __device__ inline void push_level(const Params& p, int next_level, const Seg& s) {
-  if (next_level >= p.max_levels) {
+  if (next_level >= p.max_levels - 1) {   // the last level is never launched
     set_err(p, ERR_LEVEL_OVERFLOW);
     return;
   }
@@ -260,26 +260,45 @@ __device__ inline void push_level(const Params& p, int next_level, const Seg& s)
   atomicAdd(&p.lvl_ctr[next_level].keys, (unsigned long long)(s.e - s.b));
 }
 
-// Route a child range [b, e) (data in the buffer `scratch_side`) after a partition.
+// Route a range after a partition: short ranges go to the solo list (which checks
+// their depth itself), long ones to the next level.  A long range past the paper's
+// depth limit continues in fallback mode (counted once as the paper's fallback of
+// its length); past the fallback mode's own limit it takes the bounded-time sort.
 template <class K, int T>
-__device__ inline void route_child(const Params& p, uint64_t b, uint64_t e, uint32_t depth, uint32_t limit,
-                                   bool scratch_side, int next_level) {
+__device__ inline void route(const Params& p, Seg s, int next_level) {
+  const uint64_t len = s.e - s.b;
+  if (len == 0) return;
+  if (len <= p.solo_max) {
+    push_solo(p, s);
+    return;
+  }
+  if (s.depth > s.limit) {
+    if (!(s.flags & SEG_FALLBACK)) {
+      atomicAdd(&p.stats->fallbacks, 1ull);
+      atomicAdd(&p.stats->fallback_keys, (unsigned long long)len);
+      s.flags = (s.flags & SEG_SCRATCH) | SEG_FALLBACK;
+      s.depth = 1;
+      s.limit = depth_limit_of(len);
+    } else {
+      s.flags = (s.flags & SEG_SCRATCH) | SEG_FALLBACK | SEG_BOUNDED;
+      push_solo(p, s);
+      return;
+    }
+  }
+  push_level<K, T>(p, next_level, s);
+}
+
+template <class K>
+__device__ inline Seg make_seg(uint64_t b, uint64_t e, uint32_t depth, uint32_t limit, uint32_t flags,
+                               typename K::R pv) {
   Seg s{};
   s.b = b;
   s.e = e;
   s.depth = depth;
   s.limit = limit;
-  s.flags = scratch_side ? SEG_SCRATCH : 0u;
-  const uint64_t len = e - b;
-  if (len == 0) return;
-  if (len <= p.solo_max) {
-    push_solo(p, s);
-  } else if (depth > limit) {
-    s.flags |= SEG_FALLBACK;
-    push_solo(p, s);
-  } else {
-    push_level<K, T>(p, next_level, s);
-  }
+  s.flags = flags;
+  to_words<K>(pv, s.pv_lo, s.pv_hi);
+  return s;
 }
 
 // ---- level kernel ------------------------------------------------------------------------
@@ -298,6 +317,7 @@ __global__ void __launch_bounds__(LEVEL_P) level_kernel(Params p) {
   __shared__ unsigned long long sh_excl;
   __shared__ R sh_segmin;
   __shared__ int sh_seg;
+  __shared__ unsigned long long sh_fill0;
 
   const int L = p.level;
   const unsigned long long packed = p.lvl_ctr[L].packed;
@@ -372,7 +392,7 @@ __global__ void __launch_bounds__(LEVEL_P) level_kernel(Params p) {
     __syncthreads();
     const R pivot = sh.pivot;
     R tmin;
-    const uint32_t nl = TL::rank_and_stage(stage, sh, key, k, vs, ve, pivot, &tmin);
+    const uint32_t nl = TL::rank_and_stage(stage, sh, key, k, vs, ve, pivot, (sg.flags & SEG_STRICT) != 0, &tmin);
 
     // decoupled look-back on the left counts of the range's earlier tiles, one wave
     // reading 64 predecessors per step
@@ -445,7 +465,53 @@ __global__ void __launch_bounds__(LEVEL_P) level_kernel(Params p) {
       // last tile of the range: the range is partitioned; plan what follows
       const uint64_t bound = sg.b + excl_l + nl;
       const bool dst_scratch = !src_scratch;
-      if (bound == sg.e) {
+      const bool fb = (sg.flags & SEG_FALLBACK) != 0;
+      const uint32_t cf = (dst_scratch ? SEG_SCRATCH : 0u) | (fb ? SEG_FALLBACK : 0u);
+      if (tid == 0) {
+        if (!fb) {
+          atomicAdd(&p.stats->partitions, 1ull);
+          atomicAdd(&p.stats->keys_partitioned, (unsigned long long)(sg.e - sg.b));
+          atomicMax(&p.stats->max_depth, (unsigned long long)sg.depth);
+        } else {
+          atomicAdd(&p.stats->fallback_partitions, 1ull);
+        }
+      }
+      // keys of [fb_, fe_) all equal the pivot and are final.  The caller's array holds
+      // them already unless it holds transformed keys there (whole range: it holds the
+      // range's keys in some order), or, for a part of the range, unless the partition
+      // wrote the caller's array (otherwise it holds the unpartitioned range)
+      auto retire_equal = [&](uint64_t fb_, uint64_t fe_, bool part) {
+        const bool need = part ? (dst_scratch || p.mode != 0) : (p.mode != 0 && L > 0);
+        if (!need || fe_ <= fb_) return;
+        const uint64_t nch = (fe_ - fb_ + FILL_CHUNK - 1) / FILL_CHUNK;
+        if (tid == 0) {
+          sh_fill0 = atomicAdd(&p.solo_ctr->count, (unsigned long long)nch);
+          atomicAdd(&p.stats->solo_items, (unsigned long long)nch);
+        }
+        __syncthreads();
+        uint64_t lo, hi;
+        to_words<K>(pivot, lo, hi);
+        for (uint64_t c = tid; c < nch; c += LEVEL_P) {
+          const unsigned long long i = sh_fill0 + c;
+          if (i >= p.cap_solo) {
+            set_err(p, ERR_SOLO_OVERFLOW);
+            continue;
+          }
+          Seg f{};
+          f.b = fb_ + c * FILL_CHUNK;
+          f.e = (f.b + FILL_CHUNK < fe_) ? f.b + FILL_CHUNK : fe_;
+          f.flags = SEG_FILL;
+          f.pv_lo = lo;
+          f.pv_hi = hi;
+          p.solo[i] = f;
+        }
+      };
+      if (sg.flags & SEG_STRICT) {
+        // fallback mode after a degenerate partition: [b, bound) holds the keys before
+        // the pivot, [bound, e) the keys equal to it, which are final
+        retire_equal(bound, sg.e, true);
+        if (tid == 0) route<K, T>(p, make_seg<K>(sg.b, bound, sg.depth + 1, sg.limit, cf, pivot), L + 1);
+      } else if (bound == sg.e && !fb) {
         // degenerate: the minimum of the range decides (Alg. 1, ScanMinMax)
         R m = K::maxv();
         for (unsigned long long t = g0 + tid; t <= g; t += LEVEL_P) {
@@ -463,61 +529,21 @@ __global__ void __launch_bounds__(LEVEL_P) level_kernel(Params p) {
         }
         __syncthreads();
         const R mn = sh_segmin;
-        if (tid == 0) {
-          atomicAdd(&p.stats->partitions, 1ull);
-          atomicAdd(&p.stats->keys_partitioned, (unsigned long long)(sg.e - sg.b));
-          atomicMax(&p.stats->max_depth, (unsigned long long)sg.depth);
-          atomicAdd(&p.stats->degenerate, 1ull);
-        }
+        if (tid == 0) atomicAdd(&p.stats->degenerate, 1ull);
         if (K::eq(mn, pivot)) {
           if (tid == 0) atomicAdd(&p.stats->all_equal, 1ull);
-          if (p.mode != 0 && L > 0) {
-            // the caller's array holds the value in transformed form: write it back
-            const uint64_t nch = (sg.e - sg.b + FILL_CHUNK - 1) / FILL_CHUNK;
-            __shared__ unsigned long long sh_fill0;
-            if (tid == 0) {
-              sh_fill0 = atomicAdd(&p.solo_ctr->count, (unsigned long long)nch);
-              atomicAdd(&p.stats->solo_items, (unsigned long long)nch);
-            }
-            __syncthreads();
-            uint64_t lo, hi;
-            to_words<K>(pivot, lo, hi);
-            for (uint64_t c = tid; c < nch; c += LEVEL_P) {
-              const unsigned long long i = sh_fill0 + c;
-              if (i >= p.cap_solo) {
-                set_err(p, ERR_SOLO_OVERFLOW);
-                continue;
-              }
-              Seg f{};
-              f.b = sg.b + c * FILL_CHUNK;
-              f.e = (f.b + FILL_CHUNK < sg.e) ? f.b + FILL_CHUNK : sg.e;
-              f.flags = SEG_FILL;
-              f.pv_lo = lo;
-              f.pv_hi = hi;
-              p.solo[i] = f;
-            }
-          }
+          retire_equal(sg.b, sg.e, false);
         } else if (tid == 0) {
-          Seg s{};
-          s.b = sg.b;
-          s.e = sg.e;
-          s.depth = sg.depth + 1;
-          s.limit = sg.limit;
-          s.flags = SEG_OVERRIDE | SEG_PIVOT | (dst_scratch ? SEG_SCRATCH : 0u);
-          to_words<K>(mn, s.pv_lo, s.pv_hi);
-          if (s.depth > s.limit) {
-            s.flags = SEG_FALLBACK | (dst_scratch ? SEG_SCRATCH : 0u);
-            push_solo(p, s);
-          } else {
-            push_level<K, T>(p, L + 1, s);
-          }
+          route<K, T>(p, make_seg<K>(sg.b, sg.e, sg.depth + 1, sg.limit, cf | SEG_OVERRIDE | SEG_PIVOT, mn), L + 1);
         }
+      } else if (bound == sg.e) {
+        // fallback mode, degenerate: split off the keys equal to the pivot (the maximum)
+        if (tid == 0)
+          route<K, T>(p, make_seg<K>(sg.b, sg.e, sg.depth + 1, sg.limit, cf | SEG_OVERRIDE | SEG_PIVOT | SEG_STRICT, pivot),
+                      L + 1);
       } else if (tid == 0) {
-        atomicAdd(&p.stats->partitions, 1ull);
-        atomicAdd(&p.stats->keys_partitioned, (unsigned long long)(sg.e - sg.b));
-        atomicMax(&p.stats->max_depth, (unsigned long long)sg.depth);
-        route_child<K, T>(p, sg.b, bound, sg.depth + 1, sg.limit, dst_scratch, L + 1);
-        route_child<K, T>(p, bound, sg.e, sg.depth + 1, sg.limit, dst_scratch, L + 1);
+        route<K, T>(p, make_seg<K>(sg.b, bound, sg.depth + 1, sg.limit, cf, pivot), L + 1);
+        route<K, T>(p, make_seg<K>(bound, sg.e, sg.depth + 1, sg.limit, cf, pivot), L + 1);
       }
     }
     tiles_done++;
@@ -652,28 +678,36 @@ constexpr int SOLO_NW = SOLO_P / WAVE;
 constexpr int LIST_CAP = LOCAL_LIST_CAP;
 constexpr int BC_CAP = 256;     // base cases per LDS recursion level
 
+// LDS item flags
+enum : uint32_t {
+  LI_INB = 1u,       // the range's keys are in buffer B
+  LI_OVERRIDE = 2u,  // pivot given
+  LI_FB = 4u,        // fallback mode (past the paper's depth limit)
+  LI_STRICT = 8u,    // split into keys before the pivot and keys equal to it
+};
+
 template <class K>
 struct LocalItem {
   uint32_t lb, le;
-  uint32_t depth;
-  uint32_t flags;  // bit0: in buffer B, bit1: override pivot
+  uint32_t depth, limit;
+  uint32_t flags;
   typename K::R pv;
 };
 
 template <class K>
 struct LocalShared {
   LocalItem<K> list[2][LIST_CAP];
-  uint32_t bc[BC_CAP];      // (lb << 9 | len-1) << 1 | buffer   (len <= 256)
-  LocalItem<K> fb[LIST_CAP];  // fallbacks of this level
+  uint32_t bc[BC_CAP];          // lb << 10 | (len-1) << 2 | fallback-mode << 1 | in B
+  LocalItem<K> bounded[LIST_CAP];  // ranges past the fallback-mode limit
   uint32_t nlist[2];
-  uint32_t nbc, nfb;
+  uint32_t nbc, nbounded;
   uint32_t stat_part, stat_bc, stat_deg, stat_eq, stat_fb, stat_fbkeys, stat_maxd, stat_pkeys;
 };
 
 // Bitonic sort (flip form: every module puts the smaller key at the lower index) of
 // a[0, n) in LDS by the whole workgroup; virtual positions >= n act as +inf and never
-// move, so no padding is stored.  Bounded time: the fallback when the recursion gets
-// deeper than the limit (Sec. 2.2 uses Heapsort there).
+// move, so no padding is stored.  Bounded time; used for ranges that exceed the
+// fallback mode's own depth limit.
 template <class K, class S>
 __device__ void wg_bitonic_lds(S* a, uint32_t n) {
   using R = typename K::R;
@@ -700,11 +734,20 @@ __device__ void wg_bitonic_lds(S* a, uint32_t n) {
 
 // Sort keys [b, e) of `src` (n <= local_cap) in LDS and write them to `out` (the
 // caller's array, output transform applied) or, if out_internal, to `out` in internal
-// form.  bufA/bufB hold local_cap keys each.
+// form.  bufA/bufB hold local_cap keys each.  item_flags: LI_OVERRIDE / LI_FB /
+// LI_STRICT of the range (pv is the given pivot).
+//
+// Past the paper's depth limit (where its Heapsort runs) a range continues in fallback
+// mode: same partitions, but a degenerate partition is repeated with the strict
+// predicate "key before pivot", which splits off every key equal to the pivot (the
+// range's maximum) at once; a fallback-mode range deeper than its own limit
+// 2*log2(len)+4 is sorted by the bounded-time bitonic network.  Work in fallback mode
+// is not counted as the paper's partitions or base cases (the paper's fallback is one
+// leaf); entering it is counted as one fallback of the range's length.
 template <class K>
 __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* bufA, typename K::S* bufB,
                            const typename K::S* src, bool raw, uint64_t b, uint64_t e, uint32_t depth,
-                           uint32_t limit, bool override_pv, typename K::R pv, typename K::S* out,
+                           uint32_t limit, uint32_t item_flags, typename K::R pv, typename K::S* out,
                            bool out_internal) {
   using R = typename K::R;
   using S = typename K::S;
@@ -750,19 +793,20 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
     ls.nlist[0] = 0;
     ls.nlist[1] = 0;
     ls.nbc = 0;
-    ls.nfb = 0;
+    ls.nbounded = 0;
     ls.stat_part = ls.stat_bc = ls.stat_deg = ls.stat_eq = ls.stat_fb = ls.stat_fbkeys = ls.stat_maxd = 0;
     ls.stat_pkeys = 0;
     if (n > 0) {
       if (n <= p.nb) {
-        ls.bc[0] = ((0u << 9) | (n - 1)) << 1;
+        ls.bc[0] = (0u << 10) | ((n - 1) << 2) | ((item_flags & LI_FB) ? 2u : 0u);
         ls.nbc = 1;
       } else {
         LocalItem<K> it;
         it.lb = 0;
         it.le = n;
         it.depth = depth;
-        it.flags = override_pv ? 2u : 0u;
+        it.limit = limit;
+        it.flags = item_flags & (LI_OVERRIDE | LI_FB | LI_STRICT);
         it.pv = pv;
         ls.list[0][0] = it;
         ls.nlist[0] = 1;
@@ -778,30 +822,37 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
     // 2. partition this level's ranges, one wave per range
     for (uint32_t it_i = wave; it_i < nitems; it_i += SOLO_NW) {
       LocalItem<K> it = ls.list[cur][it_i];
-      S* s_buf = (it.flags & 1u) ? bufB : bufA;
-      S* d_buf = (it.flags & 1u) ? bufA : bufB;
       const uint32_t lb = it.lb, le = it.le;
-      if (it.depth > limit) {
-        if (lane == 0) {
-          const uint32_t f = atomicAdd(&ls.nfb, 1u);
-          if (f < LIST_CAP) ls.fb[f] = it;
-          else set_err(p, ERR_LOCAL_OVERFLOW);
+      if (it.depth > it.limit) {
+        if (!(it.flags & LI_FB)) {
+          // the paper's depth limit: continue this range in fallback mode
+          if (lane == 0) {
+            atomicAdd(&ls.stat_fb, 1u);
+            atomicAdd(&ls.stat_fbkeys, le - lb);
+          }
+          it.flags = (it.flags & LI_INB) | LI_FB;
+          it.depth = 1;
+          it.limit = depth_limit_of(le - lb);
+        } else {
+          if (lane == 0) {
+            const uint32_t f = atomicAdd(&ls.nbounded, 1u);
+            if (f < LIST_CAP) ls.bounded[f] = it;
+            else set_err(p, ERR_LOCAL_OVERFLOW);
+          }
+          continue;
         }
-        continue;
       }
+      const bool fb = (it.flags & LI_FB) != 0;
+      const bool strict = (it.flags & LI_STRICT) != 0;
+      S* s_buf = (it.flags & LI_INB) ? bufB : bufA;
+      S* d_buf = (it.flags & LI_INB) ? bufA : bufB;
       R pivot;
-#ifdef VQS_PHASE_TIMING
-      unsigned long long wt0 = wall_clock64();
-#endif
-      if (it.flags & 2u) {
+      if (it.flags & LI_OVERRIDE) {
         pivot = it.pv;
       } else {
         const S* sb = s_buf + lb;
         pivot = choose_pivot_wave<K>([&](uint64_t i) -> R { return (R)sb[i]; }, b + lb, b + le, p.seed);
       }
-#ifdef VQS_PHASE_TIMING
-      unsigned long long wt1 = wall_clock64();
-#endif
       uint32_t l = lb, r = le;
       R mn = K::maxv();
       // four 64-key groups per step: independent loads, ballots and stores
@@ -818,7 +869,7 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
         }
 #pragma unroll
         for (int u = 0; u < U; u++) {
-          isl[u] = valid[u] && !K::lt(pivot, kx[u]);
+          isl[u] = valid[u] && (strict ? K::lt(kx[u], pivot) : !K::lt(pivot, kx[u]));
           if (valid[u]) mn = K::kmin(mn, kx[u]);
           ml[u] = ballot(isl[u]);
           mr[u] = ballot(valid[u] && !isl[u]);
@@ -831,67 +882,60 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
           r -= __popcll(mr[u]);
         }
       }
-#ifdef VQS_PHASE_TIMING
-      unsigned long long wt2 = wall_clock64();
-#endif
-      mn = wave_min<K>(mn);
-#ifdef VQS_PHASE_TIMING
-      unsigned long long wt3 = wall_clock64();
-      if (lane == 0 && p.dbg) {
-        atomicAdd(&p.dbg[24], wt1 - wt0);
-        atomicAdd(&p.dbg[25], wt2 - wt1);
-        atomicAdd(&p.dbg[26], wt3 - wt2);
-        atomicAdd(&p.dbg[27], 1ull);
-      }
-#endif
       const uint32_t bound = l;
-      const uint32_t nbuf = (it.flags & 1u) ? 0u : 1u;   // children live in d_buf
-      if (lane == 0) {
+      const uint32_t nbuf = (it.flags & LI_INB) ? 0u : LI_INB;   // children live in d_buf
+      if (!fb && lane == 0) {
         atomicAdd(&ls.stat_part, 1u);
         atomicAdd(&ls.stat_pkeys, le - lb);
         atomicMax(&ls.stat_maxd, it.depth);
       }
-      if (bound == le) {
-        if (lane == 0) atomicAdd(&ls.stat_deg, 1u);
-        if (K::eq(mn, pivot)) {
-          // all equal: done; make sure the keys sit in bufA
-          if (lane == 0) atomicAdd(&ls.stat_eq, 1u);
-          if (nbuf == 1) {
-            for (uint32_t i = lb + lane; i < le; i += WAVE) bufA[i] = bufB[i];
-          }
-        } else if (lane == 0) {
-          LocalItem<K> c;
-          c.lb = lb;
-          c.le = le;
-          c.depth = it.depth + 1;
-          c.flags = nbuf | 2u;
-          c.pv = mn;
+      auto push_child = [&](uint32_t cb, uint32_t ce, uint32_t cflags, R cpv) {
+        const uint32_t len = ce - cb;
+        if (len == 0) return;
+        if (len <= p.nb) {
+          const uint32_t s = atomicAdd(&ls.nbc, 1u);
+          if (s < BC_CAP) ls.bc[s] = (cb << 10) | ((len - 1) << 2) | (fb ? 2u : 0u) | (nbuf ? 1u : 0u);
+          else set_err(p, ERR_LOCAL_OVERFLOW);
+        } else {
+          LocalItem<K> ci;
+          ci.lb = cb;
+          ci.le = ce;
+          ci.depth = it.depth + 1;
+          ci.limit = it.limit;
+          ci.flags = nbuf | (fb ? LI_FB : 0u) | cflags;
+          ci.pv = cpv;
           const uint32_t s = atomicAdd(&ls.nlist[cur ^ 1], 1u);
-          if (s < LIST_CAP) ls.list[cur ^ 1][s] = c;
+          if (s < LIST_CAP) ls.list[cur ^ 1][s] = ci;
           else set_err(p, ERR_LOCAL_OVERFLOW);
         }
-      } else if (lane == 0) {
-        auto push_child = [&](uint32_t cb, uint32_t ce) {
-          const uint32_t len = ce - cb;
-          if (len == 0) return;
-          if (len <= p.nb) {
-            const uint32_t s = atomicAdd(&ls.nbc, 1u);
-            if (s < BC_CAP) ls.bc[s] = ((cb << 9) | (len - 1)) << 1 | nbuf;
-            else set_err(p, ERR_LOCAL_OVERFLOW);
-          } else {
-            LocalItem<K> ci;
-            ci.lb = cb;
-            ci.le = ce;
-            ci.depth = it.depth + 1;
-            ci.flags = nbuf;
-            ci.pv = pivot;
-            const uint32_t s = atomicAdd(&ls.nlist[cur ^ 1], 1u);
-            if (s < LIST_CAP) ls.list[cur ^ 1][s] = ci;
-            else set_err(p, ERR_LOCAL_OVERFLOW);
+      };
+      auto finish_equal = [&](uint32_t cb, uint32_t ce) {
+        // all keys of [cb, ce) are equal: done; they must sit in bufA
+        if (nbuf)
+          for (uint32_t i = cb + lane; i < ce; i += WAVE) bufA[i] = bufB[i];
+      };
+      if (strict) {
+        // [lb, bound): keys before the pivot; [bound, le): keys equal to it
+        finish_equal(bound, le);
+        if (lane == 0) push_child(lb, bound, 0u, pivot);
+      } else if (bound == le) {
+        if (!fb) {
+          mn = wave_min<K>(mn);
+          if (lane == 0) atomicAdd(&ls.stat_deg, 1u);
+          if (K::eq(mn, pivot)) {
+            if (lane == 0) atomicAdd(&ls.stat_eq, 1u);
+            finish_equal(lb, le);
+          } else if (lane == 0) {
+            // Alg. 1: repeat with the first key in sort order as the pivot
+            push_child(lb, le, LI_OVERRIDE, mn);
           }
-        };
-        push_child(lb, bound);
-        push_child(bound, le);
+        } else if (lane == 0) {
+          // fallback mode: split off the keys equal to the pivot (the maximum)
+          push_child(lb, le, LI_OVERRIDE | LI_STRICT, pivot);
+        }
+      } else if (lane == 0) {
+        push_child(lb, bound, 0u, pivot);
+        push_child(bound, le, 0u, pivot);
       }
     }
     __syncthreads();
@@ -904,13 +948,15 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
     for (uint32_t q0 = wave * 4; q0 < nbc; q0 += SOLO_NW * 4) {
       const uint32_t qi = q0 + (lane >> 4);
       const int gl = lane & 15;
-      uint32_t lb = 0, len = 0, inb = 0;
+      uint32_t lb = 0, len = 0, inb = 0, isfb = 0;
       if (qi < nbc) {
         const uint32_t w = ls.bc[qi];
         inb = w & 1u;
-        len = ((w >> 1) & 511u) + 1;
+        isfb = (w >> 1) & 1u;
+        len = ((w >> 2) & 255u) + 1;
         lb = w >> 10;
       }
+      if (gl == 0 && qi < nbc && !isfb) atomicAdd(&ls.stat_bc, 1u);
       const S* s_buf = inb ? bufB : bufA;
       R x[16];
 #pragma unroll
@@ -925,29 +971,22 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
         if (pos < len) bufA[lb + pos] = (S)x[r];
       }
     }
-    // 4. fallbacks of this level (whole workgroup, one range at a time)
+    // 4. bounded-time sorts of this level (whole workgroup, one range at a time)
     __syncthreads();
     VQS_LPH(2);
-    const uint32_t nfb = ls.nfb < LIST_CAP ? ls.nfb : LIST_CAP;
-    for (uint32_t f = 0; f < nfb; f++) {
-      const LocalItem<K> it = ls.fb[f];
-      S* a = (it.flags & 1u) ? bufB : bufA;
+    const uint32_t nbd = ls.nbounded < LIST_CAP ? ls.nbounded : LIST_CAP;
+    for (uint32_t f = 0; f < nbd; f++) {
+      const LocalItem<K> it = ls.bounded[f];
+      S* a = (it.flags & LI_INB) ? bufB : bufA;
       wg_bitonic_lds<K, S>(a + it.lb, it.le - it.lb);
-      if (it.flags & 1u) {
+      if (it.flags & LI_INB) {
         for (uint32_t i = it.lb + tid; i < it.le; i += SOLO_P) bufA[i] = bufB[i];
-      }
-      if (tid == 0) {
-        ls.stat_fb++;
-        ls.stat_fbkeys += it.le - it.lb;
       }
       __syncthreads();
     }
     if (tid == 0) {
-      if (flush_bc) {
-        ls.stat_bc += ls.nbc;
-        ls.nbc = 0;
-      }
-      ls.nfb = 0;
+      if (flush_bc) ls.nbc = 0;
+      ls.nbounded = 0;
       ls.nlist[cur] = 0;
     }
     __syncthreads();
@@ -985,7 +1024,6 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
   }
   __syncthreads();
 }
-
 
 // ---- solo kernel: whole ranges per workgroup ------------------------------------------
 
@@ -1028,9 +1066,10 @@ __device__ void wg_merge(const typename K::S* a, uint64_t na, const typename K::
   }
 }
 
-// Bounded-time fallback for a range past the depth limit (Sec. 2.2 uses Heapsort):
-// sort LDS-sized chunks with the bitonic network, then merge runs pairwise through the
-// two global buffers; the result goes to the caller's array.  O(n log n) work.
+// Bounded-time sort for a range past the fallback mode's own depth limit: sort
+// LDS-sized chunks with the bitonic network, then merge runs pairwise through the two
+// global buffers; the result goes to the caller's array.  O(n log^2 n) work at most.
+// Not counted: the range was counted when it entered fallback mode.
 template <class K>
 __device__ void fallback_global(const Params& p, typename K::S* bufA, const Seg& it) {
   using R = typename K::R;
@@ -1075,10 +1114,6 @@ __device__ void fallback_global(const Params& p, typename K::S* bufA, const Seg&
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    atomicAdd(&p.stats->fallbacks, 1ull);
-    atomicAdd(&p.stats->fallback_keys, (unsigned long long)n);
-  }
 }
 
 template <class K>
@@ -1120,7 +1155,7 @@ __global__ void __launch_bounds__(SOLO_P) solo_kernel(Params p) {
     }
     __syncthreads();
     while (sp > 0) {
-      const Seg cur = stack[sp - 1];
+      Seg cur = stack[sp - 1];
       __syncthreads();
       if (tid == 0) sp--;
       const uint64_t n = cur.e - cur.b;
@@ -1128,24 +1163,38 @@ __global__ void __launch_bounds__(SOLO_P) solo_kernel(Params p) {
       const S* src = (const S*)(in_scratch ? p.scratch : p.keys);
       S* dst = (S*)(in_scratch ? p.keys : p.scratch);
       const bool raw = (cur.flags & SEG_RAW) != 0;
-      if (cur.flags & SEG_FALLBACK) {
+      if (cur.flags & SEG_BOUNDED) {
         fallback_global<K>(p, bufA, cur);
         __syncthreads();
         continue;
       }
       if (n <= p.local_cap) {
         VQS_PHASE(2);
-        local_sort<K>(p, ls, bufA, bufB, src, raw, cur.b, cur.e, cur.depth, cur.limit,
-                      (cur.flags & SEG_OVERRIDE) != 0, K::from_u64x2(cur.pv_lo, cur.pv_hi), (S*)p.keys, false);
+        const uint32_t lf = ((cur.flags & SEG_OVERRIDE) ? LI_OVERRIDE : 0u) |
+                            ((cur.flags & SEG_FALLBACK) ? LI_FB : 0u) | ((cur.flags & SEG_STRICT) ? LI_STRICT : 0u);
+        local_sort<K>(p, ls, bufA, bufB, src, raw, cur.b, cur.e, cur.depth, cur.limit, lf,
+                      K::from_u64x2(cur.pv_lo, cur.pv_hi), (S*)p.keys, false);
         VQS_PHASE(0);
         continue;
       }
       VQS_PHASE(1);
       if (cur.depth > cur.limit) {
-        fallback_global<K>(p, bufA, cur);
-        __syncthreads();
-        continue;
+        if (cur.flags & SEG_FALLBACK) {
+          fallback_global<K>(p, bufA, cur);
+          __syncthreads();
+          continue;
+        }
+        // the paper's depth limit: continue this range in fallback mode
+        if (tid == 0) {
+          atomicAdd(&p.stats->fallbacks, 1ull);
+          atomicAdd(&p.stats->fallback_keys, (unsigned long long)n);
+        }
+        cur.flags = (cur.flags & (SEG_SCRATCH | SEG_RAW)) | SEG_FALLBACK;
+        cur.depth = 1;
+        cur.limit = depth_limit_of(n);
       }
+      const bool fb = (cur.flags & SEG_FALLBACK) != 0;
+      const bool strict = (cur.flags & SEG_STRICT) != 0;
       // pivot
       if (cur.flags & SEG_OVERRIDE) {
         if (tid == 0) aux.pivot = K::from_u64x2(cur.pv_lo, cur.pv_hi);
@@ -1175,7 +1224,7 @@ __global__ void __launch_bounds__(SOLO_P) solo_kernel(Params p) {
         R key[SOLO_I][K::V];
         TL::load(src_aligned, k, vs, ve, raw ? p.mode : 0, key);
         R tmin;
-        const uint32_t nl = TL::rank_and_stage(bufA, aux, key, k, vs, ve, pivot, &tmin);
+        const uint32_t nl = TL::rank_and_stage(bufA, aux, key, k, vs, ve, pivot, strict, &tmin);
         const uint32_t nvalid = (uint32_t)(ve - vs);
         const uint32_t nr = nvalid - nl;
         TL::write_out(bufA, dst, nl, nvalid, cur.b + excl_l, cur.e - excl_r - nr, 0, p.n_total);
@@ -1187,48 +1236,55 @@ __global__ void __launch_bounds__(SOLO_P) solo_kernel(Params p) {
       const uint64_t bound = cur.b + excl_l;
       if (tid == 0) {
         sh_min = mn;
-        atomicAdd(&p.stats->partitions, 1ull);
-        atomicAdd(&p.stats->global_solo_partitions, 1ull);
-        atomicAdd(&p.stats->keys_partitioned, (unsigned long long)n);
-        atomicMax(&p.stats->max_depth, (unsigned long long)cur.depth);
+        if (!fb) {
+          atomicAdd(&p.stats->partitions, 1ull);
+          atomicAdd(&p.stats->global_solo_partitions, 1ull);
+          atomicAdd(&p.stats->keys_partitioned, (unsigned long long)n);
+          atomicMax(&p.stats->max_depth, (unsigned long long)cur.depth);
+        } else {
+          atomicAdd(&p.stats->fallback_partitions, 1ull);
+        }
       }
       __syncthreads();
-      const uint32_t child_flags = in_scratch ? 0u : SEG_SCRATCH;
-      if (bound == cur.e) {
+      const uint32_t cf = (in_scratch ? 0u : SEG_SCRATCH) | (fb ? SEG_FALLBACK : 0u);
+      // keys of [fb_, fe_) equal the pivot and are final.  Whole range: the caller's
+      // array holds the range's keys (source or partition output), so only transformed
+      // keys need writing back; part of a range: unless the partition wrote the
+      // caller's array untransformed, it holds other keys there
+      auto retire_equal = [&](uint64_t fb_, uint64_t fe_, bool part) {
+        const bool need = part ? (!in_scratch || p.mode != 0) : (p.mode != 0 && !raw);
+        if (need && fe_ > fb_) fill_range<K>(p, fb_, fe_, pivot);
+      };
+      auto push = [&](const Seg& sgn) {
+        if (sgn.e <= sgn.b) return;
+        if (sp < STACK_CAP) stack[sp++] = sgn;
+        else set_err(p, ERR_STACK);
+      };
+      if (strict) {
+        retire_equal(bound, cur.e, true);
+        if (tid == 0) push(make_seg<K>(cur.b, bound, cur.depth + 1, cur.limit, cf, pivot));
+      } else if (bound == cur.e && !fb) {
         const R segmin = sh_min;
         if (tid == 0) atomicAdd(&p.stats->degenerate, 1ull);
         if (K::eq(segmin, pivot)) {
           if (tid == 0) atomicAdd(&p.stats->all_equal, 1ull);
-          // the caller's array holds the value already, transformed unless raw
-          if (p.mode != 0 && !raw) fill_range<K>(p, cur.b, cur.e, pivot);
-          __syncthreads();
+          retire_equal(cur.b, cur.e, false);
         } else if (tid == 0) {
-          Seg s = cur;
-          s.depth = cur.depth + 1;
-          s.flags = child_flags | SEG_OVERRIDE;
-          to_words<K>(segmin, s.pv_lo, s.pv_hi);
-          if (sp < STACK_CAP) stack[sp++] = s;
-          else set_err(p, ERR_STACK);
+          push(make_seg<K>(cur.b, cur.e, cur.depth + 1, cur.limit, cf | SEG_OVERRIDE, segmin));
         }
+      } else if (bound == cur.e) {
+        if (tid == 0) push(make_seg<K>(cur.b, cur.e, cur.depth + 1, cur.limit, cf | SEG_OVERRIDE | SEG_STRICT, pivot));
       } else if (tid == 0) {
-        Seg l = cur, r = cur;
-        l.e = bound;
-        r.b = bound;
-        l.depth = r.depth = cur.depth + 1;
-        l.flags = r.flags = child_flags;
         // larger first, so the smaller range is taken next (stack depth <= log2 n)
         const bool left_small = (bound - cur.b) <= (cur.e - bound);
-        if (sp + 2 <= STACK_CAP) {
-          if (left_small) {
-            stack[sp] = r;
-            stack[sp + 1] = l;
-          } else {
-            stack[sp] = l;
-            stack[sp + 1] = r;
-          }
-          sp += 2;
+        const Seg l = make_seg<K>(cur.b, bound, cur.depth + 1, cur.limit, cf, pivot);
+        const Seg r = make_seg<K>(bound, cur.e, cur.depth + 1, cur.limit, cf, pivot);
+        if (left_small) {
+          push(r);
+          push(l);
         } else {
-          set_err(p, ERR_STACK);
+          push(l);
+          push(r);
         }
       }
       __syncthreads();
@@ -1277,14 +1333,7 @@ __global__ void seed_kernel(Params p, const int64_t* offsets, uint64_t nseg) {
     s.depth = 1;
     s.limit = p.fixed_limit >= 0 ? (uint32_t)p.fixed_limit : depth_limit_of(e - b);
     s.flags = p.seed_level ? SEG_SCRATCH : SEG_RAW;
-    if (e - b <= p.solo_max) {
-      push_solo(p, s);
-    } else if (s.depth > s.limit) {
-      s.flags |= SEG_FALLBACK;
-      push_solo(p, s);
-    } else {
-      push_level<K, TL::T>(p, p.seed_level, s);
-    }
+    route<K, TL::T>(p, s, p.seed_level);
   }
 }
 

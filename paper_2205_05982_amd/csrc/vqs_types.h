@@ -28,9 +28,11 @@ enum : uint32_t {
   SEG_OVERRIDE = 1u,   // pivot given (degenerate re-partition with the first key)
   SEG_SCRATCH = 2u,    // data lives in the scratch buffer (else in the caller's array)
   SEG_RAW = 4u,        // data not yet transformed (caller's array, never touched)
-  SEG_FALLBACK = 8u,   // depth limit exceeded: bounded-time fallback sort
+  SEG_FALLBACK = 8u,   // past the paper's depth limit: fallback mode
   SEG_FILL = 16u,      // all keys equal: write pv to [b, e) of the caller's array
   SEG_PIVOT = 32u,     // pv holds the range's pivot (computed before the level's launch)
+  SEG_STRICT = 64u,    // split into keys before the pivot and keys equal to it
+  SEG_BOUNDED = 128u,  // past the fallback mode's own depth limit: bounded-time sort
 };
 
 struct Seg {
@@ -58,6 +60,7 @@ struct DevStats {
   unsigned long long partitions, keys_partitioned, degenerate, all_equal, basecases, fallbacks,
       fallback_keys, max_depth;
   unsigned long long level_tiles, solo_items, lds_partitions, global_solo_partitions;
+  unsigned long long fallback_partitions;
 };
 
 enum : uint32_t {
