@@ -83,12 +83,12 @@ typedef struct vqs_options {
                                    arguments */
     uint32_t validate;          /* check offsets for monotonicity (synchronises) */
     /* learned splitter (method VQS_METHOD_LEARNED, u64 keys) */
-    uint32_t train_steps;       /* optimiser steps; default 300 */
-    uint32_t batch;             /* training minibatch; default 8192 */
+    uint32_t train_steps;       /* optimiser steps; default 100 */
+    uint32_t batch;             /* training minibatch, at most 256; default 256 */
     float sample_fraction;      /* fraction of keys sampled; default 0.01 */
     float overflow_factor;      /* a bucket above overflow_factor * n/256 keys is left
                                    to the plain method; default 2.0 */
-    float learning_rate;        /* Adam step size; default 0.01 */
+    float learning_rate;        /* Adam step size; default 0.003 */
     uint64_t model_seed;        /* seed of the model's initial weights; default 16 */
     uint64_t sample_seed;       /* seed of the 1 % chunk sample and of the minibatches;
                                    default 17 */
@@ -148,19 +148,20 @@ int vqs_last_error_bits(void* stream, uint32_t* out);
  * bucket(k) = min(255, floor(256 * y)).  All pointers are device pointers. */
 
 /* Sample sample_fraction of the u64 keys in random 64-byte chunks, sort the sample,
- * compute mid-rank CDF targets and train (train_steps Adam steps; 0 returns the
- * untrained model).  Writes the parameter block to params (1155 floats). */
+ * compute mid-rank CDF targets and train (train_steps Adam steps, 0 meaning the
+ * default; vqs_mlp_init gives the untrained model).  Writes the parameter block to
+ * params (1155 floats). */
 int vqs_learned_fit(const void* keys, uint64_t n, const vqs_options* options, float* params, void* stream);
 
 /* y = model(x) for m inputs. */
 int vqs_mlp_forward(const float* params, const float* x, uint64_t m, float* y, void* stream);
 
-/* Gradient (1153 floats) and mean squared error of the model on m <= 192 samples
+/* Gradient (1153 floats) and mean squared error of the model on m <= 256 samples
  * (x, target t). */
 int vqs_mlp_gradient(const float* params, const float* x, const float* t, uint32_t m, float* grad, float* loss,
                      void* stream);
 
-/* steps Adam steps on minibatches of `batch` <= 192 samples (random, from sample_seed,
+/* steps Adam steps on minibatches of `batch` <= 256 samples (random, from sample_seed,
  * or consecutive when sequential != 0).  moments holds 2*1153+1 floats (first and
  * second moments, zero to start; the last receives the final minibatch loss). */
 int vqs_mlp_train(float* params, float* moments, const float* x, const float* t, uint64_t m, uint32_t steps,

@@ -565,9 +565,9 @@ Workspace* inner_for(Workspace* ws) {
 int learned_locked(Workspace* ws, void* keys, uint64_t n, const vqs_options* o, hipStream_t stream, bool fit_only,
                    float* params_out) {
   const float frac = (o && o->sample_fraction > 0.f) ? o->sample_fraction : 0.01f;
-  const uint32_t steps = (o && o->train_steps) ? o->train_steps : 600;
+  const uint32_t steps = (o && o->train_steps) ? o->train_steps : 100;
   const uint32_t batch = (o && o->batch) ? std::min<uint32_t>(o->batch, MLP_MAX_BATCH) : MLP_MAX_BATCH;
-  const float lr = (o && o->learning_rate > 0.f) ? o->learning_rate : 0.01f;
+  const float lr = (o && o->learning_rate > 0.f) ? o->learning_rate : 0.003f;
   const float over = (o && o->overflow_factor > 0.f) ? o->overflow_factor : 2.0f;
   const uint64_t model_seed = (o && o->model_seed) ? o->model_seed : 16;
   const uint64_t sample_seed = (o && o->sample_seed) ? o->sample_seed : 17;

@@ -20,7 +20,7 @@ constexpr int MLP_NPARAM = MLP_H + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1;  /
 constexpr int MLP_NBLOCK = MLP_NPARAM + 2;                                      // + x0, xs
 constexpr int MLP_W1 = 0, MLP_B1 = 32, MLP_W2 = 64, MLP_B2 = 64 + 1024, MLP_W3 = MLP_B2 + 32,
               MLP_B3 = MLP_W3 + 32, MLP_X0 = MLP_B3 + 1, MLP_XS = MLP_X0 + 1;
-constexpr int MLP_MAX_BATCH = 192;     // samples per optimiser step (one workgroup)
+constexpr int MLP_MAX_BATCH = 256;     // samples per optimiser step (one workgroup)
 constexpr int LEARN_TILE = 4096;       // keys per histogram / scatter tile
 constexpr int NBUCKET = 256;
 

@@ -135,92 +135,259 @@ __global__ void init_kernel(float* P, uint64_t seed, const float* x, uint64_t m)
 
 // ---- training ------------------------------------------------------------------------
 
-constexpr int TRAIN_P = 256;
-constexpr int ROW = MLP_H + 1;   // padded LDS rows
+// One workgroup of 512 threads trains on minibatches of up to 256 samples.  Thread t
+// takes sample t % 256 and half t / 256 of the hidden units (both halves compute the
+// first layer; each computes 16 second-layer units and 16 first-layer gradients).
+// The weight-matrix gradient dL/dW2 = DA2^T H1 is a 32 x 256 x 32 product done in 4x4
+// register tiles, one wave per group of 32 samples, then reduced over the groups.
+constexpr int TRAIN_P = 512;
+constexpr int TRAIN_NW = TRAIN_P / WAVE;       // 8 waves = 8 sample groups of 32
+constexpr int TB = MLP_MAX_BATCH;              // 256
+constexpr int SG = TB / TRAIN_NW;              // samples per group in the W2 product
 
-struct TrainShared {
-  float P[MLP_NBLOCK];
-  float G[MLP_NPARAM];
-  float H1[MLP_MAX_BATCH][ROW];
-  float H2[MLP_MAX_BATCH][ROW];
-  float DA2[MLP_MAX_BATCH][ROW];
-  float DA1[MLP_MAX_BATCH][ROW];
-  float XN[MLP_MAX_BATCH];
-  float D3[MLP_MAX_BATCH];
-  float LOSS[TRAIN_P];
+struct __attribute__((aligned(16))) TrainShared {
+  float P[MLP_NBLOCK + 1];
+  float H1[TB * MLP_H];     // per-sample rows of 32, float4 chunks XOR-swizzled by row;
+                            // the gradient G aliases it after the W2 product
+  float DA2[TB * MLP_H];
+  float H2[TB * MLP_H];     // the W2 partials (8 x 1024) alias it after use
+  float DA1[TB * MLP_H];
+  float XN[TB];
+  float D3[TB];
+  float A3P[2][TB];
+  float SM[4][128];
+  float WSUM[2][TRAIN_NW];
 };
 
-// forward and backward of the samples (x[s], t[s]) for s < B, then the gradient of
-// the mean squared error into S.G and the loss sum into S.LOSS[0]
-__device__ void batch_gradient(TrainShared& S, float xs_in, float ts_in, int B) {
+// chunk c (4 floats) of row s: rows of 8 chunks, chunk index XOR (s & 7) so that 64
+// lanes storing one chunk of 64 consecutive rows, or reading 8 chunks of one row,
+// touch distinct banks
+__device__ inline float4* tchunk(float* A, int s, int c) {
+  return reinterpret_cast<float4*>(A + s * MLP_H + 4 * (c ^ (s & 7)));
+}
+__device__ inline float telem(const float* A, int s, int i) { return A[s * MLP_H + 4 * ((i >> 2) ^ (s & 7)) + (i & 3)]; }
+
+// Workgroup barrier that waits for this wave's LDS accesses only: global loads in
+// flight (the next minibatch) stay in flight.  The empty asm statements keep the
+// compiler from moving memory accesses across it.
+__device__ __forceinline__ void lds_sync() {
+  __asm__ __volatile__("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0); vmcnt, expcnt unconstrained
+  __builtin_amdgcn_s_barrier();
+  __asm__ __volatile__("" ::: "memory");
+}
+
+__device__ inline float4 f4(float a, float b, float c, float d) {
+  float4 v;
+  v.x = a;
+  v.y = b;
+  v.z = c;
+  v.w = d;
+  return v;
+}
+
+// Forward and backward of sample (xv, tv) for this thread's sample slot (s < B
+// valid), the gradient of the mean squared error over the B samples into G (which
+// aliases H1) and the loss sum into *loss_sum (thread 128).  Starts after P is
+// visible; ends with G visible to all threads.
+__device__ float* batch_gradient(TrainShared& S, float xv, float tv, int B, float* loss_sum) {
   const int tid = threadIdx.x;
-  float l = 0.0f;
-  if (tid < B) {
-    const float* P = S.P;
-    const float xn = __fmul_rn(__fsub_rn(xs_in, P[MLP_X0]), P[MLP_XS]);
-    float h1[MLP_H], h2[MLP_H];
-    uint32_t m1 = 0, m2 = 0;
+  const int s = tid & (TB - 1);
+  const int hf = tid / TB;
+  const int lane = tid & (WAVE - 1), w = tid / WAVE;
+  const bool valid = s < B;
+  const float* P = S.P;
+
+  // F1: first layer (recomputed per chunk of 4 units), second layer (own 16 units),
+  // partial output.  Each unit's sum runs over i = 0..31 in order.
+  const float xn = __fmul_rn(__fsub_rn(xv, P[MLP_X0]), P[MLP_XS]);
+  uint32_t m1 = 0;
+  float a2[16];
 #pragma unroll
-    for (int i = 0; i < MLP_H; i++) {
-      const float a = __fmaf_rn(P[MLP_W1 + i], xn, P[MLP_B1 + i]);
-      h1[i] = clamp01(a);
-      m1 |= (a > 0.0f && a < 1.0f) ? (1u << i) : 0u;
-      S.H1[tid][i] = h1[i];
+  for (int jj = 0; jj < 16; jj++) a2[jj] = P[MLP_B2 + 16 * hf + jj];
+#pragma nounroll
+  for (int c = 0; c < 8; c++) {
+    const float4 wv1 = *reinterpret_cast<const float4*>(P + MLP_W1 + 4 * c);
+    const float4 bv1 = *reinterpret_cast<const float4*>(P + MLP_B1 + 4 * c);
+    const float e0 = __fmaf_rn(wv1.x, xn, bv1.x), e1 = __fmaf_rn(wv1.y, xn, bv1.y),
+                e2 = __fmaf_rn(wv1.z, xn, bv1.z), e3 = __fmaf_rn(wv1.w, xn, bv1.w);
+    const float h0 = clamp01(e0), h1v = clamp01(e1), h2v = clamp01(e2), h3 = clamp01(e3);
+    m1 |= (((e0 > 0.0f && e0 < 1.0f) ? 1u : 0u) | ((e1 > 0.0f && e1 < 1.0f) ? 2u : 0u) |
+           ((e2 > 0.0f && e2 < 1.0f) ? 4u : 0u) | ((e3 > 0.0f && e3 < 1.0f) ? 8u : 0u))
+          << (4 * c);
+    if ((c >> 2) == hf) *tchunk(S.H1, s, c) = f4(h0, h1v, h2v, h3);
+#pragma unroll
+    for (int jj = 0; jj < 16; jj++) {
+      const float4 wv = *reinterpret_cast<const float4*>(P + MLP_W2 + (16 * hf + jj) * MLP_H + 4 * c);
+      float a = a2[jj];
+      a = __fmaf_rn(wv.x, h0, a);
+      a = __fmaf_rn(wv.y, h1v, a);
+      a = __fmaf_rn(wv.z, h2v, a);
+      a = __fmaf_rn(wv.w, h3, a);
+      a2[jj] = a;
     }
-    float a3 = P[MLP_B3];
-    for (int j = 0; j < MLP_H; j++) {
-      float a = P[MLP_B2 + j];
-#pragma unroll
-      for (int i = 0; i < MLP_H; i++) a = __fmaf_rn(P[MLP_W2 + j * MLP_H + i], h1[i], a);
-      h2[j] = clamp01(a);
-      m2 |= (a > 0.0f && a < 1.0f) ? (1u << j) : 0u;
-      S.H2[tid][j] = h2[j];
-      a3 = __fmaf_rn(P[MLP_W3 + j], h2[j], a3);
-    }
-    const float y = clamp01(a3);
-    const float r = y - ts_in;
-    l = r * r;
-    const float d3 = (a3 > 0.0f && a3 < 1.0f) ? (2.0f / (float)B) * r : 0.0f;
-    S.XN[tid] = xn;
-    S.D3[tid] = d3;
-    float dh1[MLP_H];
-#pragma unroll
-    for (int i = 0; i < MLP_H; i++) dh1[i] = 0.0f;
-    for (int j = 0; j < MLP_H; j++) {
-      const float da2 = ((m2 >> j) & 1u) ? d3 * P[MLP_W3 + j] : 0.0f;
-      S.DA2[tid][j] = da2;
-#pragma unroll
-      for (int i = 0; i < MLP_H; i++) dh1[i] = fmaf(da2, P[MLP_W2 + j * MLP_H + i], dh1[i]);
-    }
-#pragma unroll
-    for (int i = 0; i < MLP_H; i++) S.DA1[tid][i] = ((m1 >> i) & 1u) ? dh1[i] : 0.0f;
   }
-  S.LOSS[tid] = l;
-  __syncthreads();
-  for (int q = tid; q < MLP_NPARAM; q += TRAIN_P) {
-    float g = 0.0f;
-    if (q >= MLP_W2 && q < MLP_B2) {
-      const int j = (q - MLP_W2) / MLP_H, i = (q - MLP_W2) % MLP_H;
-      for (int s = 0; s < B; s++) g = fmaf(S.DA2[s][j], S.H1[s][i], g);
-    } else if (q < MLP_B1) {
-      for (int s = 0; s < B; s++) g = fmaf(S.DA1[s][q], S.XN[s], g);
-    } else if (q < MLP_W2) {
-      for (int s = 0; s < B; s++) g += S.DA1[s][q - MLP_B1];
-    } else if (q < MLP_W3) {
-      for (int s = 0; s < B; s++) g += S.DA2[s][q - MLP_B2];
-    } else if (q < MLP_B3) {
-      for (int s = 0; s < B; s++) g = fmaf(S.D3[s], S.H2[s][q - MLP_W3], g);
-    } else {
-      for (int s = 0; s < B; s++) g += S.D3[s];
+  uint32_t m2 = 0;
+  float a3p = hf ? 0.0f : P[MLP_B3];
+  {
+    float h2[16];
+#pragma unroll
+    for (int jj = 0; jj < 16; jj++) {
+      h2[jj] = clamp01(a2[jj]);
+      m2 |= (a2[jj] > 0.0f && a2[jj] < 1.0f) ? (1u << jj) : 0u;
+      a3p = __fmaf_rn(P[MLP_W3 + 16 * hf + jj], h2[jj], a3p);
     }
-    S.G[q] = g;
+#pragma unroll
+    for (int c = 0; c < 4; c++)
+      *tchunk(S.H2, s, 4 * hf + c) = f4(h2[4 * c], h2[4 * c + 1], h2[4 * c + 2], h2[4 * c + 3]);
   }
-  // loss sum (tree in LDS)
-  for (int w = TRAIN_P / 2; w >= 1; w >>= 1) {
-    __syncthreads();
-    if (tid < w) S.LOSS[tid] += S.LOSS[tid + w];
+  S.A3P[hf][s] = a3p;
+  lds_sync();
+
+  // F2: output, residual, output delta; second-layer deltas of own units
+  const float a3 = __fadd_rn(S.A3P[0][s], S.A3P[1][s]);
+  const float r = clamp01(a3) - tv;
+  const float l = valid ? r * r : 0.0f;
+  const float d3 = (valid && a3 > 0.0f && a3 < 1.0f) ? (2.0f / (float)B) * r : 0.0f;
+  if (hf == 0) {
+    S.XN[s] = xn;
+    S.D3[s] = d3;
   }
-  __syncthreads();
+  float da2[16];
+#pragma unroll
+  for (int jj = 0; jj < 16; jj++) da2[jj] = ((m2 >> jj) & 1u) ? d3 * P[MLP_W3 + 16 * hf + jj] : 0.0f;
+#pragma unroll
+  for (int c = 0; c < 4; c++)
+    *tchunk(S.DA2, s, 4 * hf + c) = f4(da2[4 * c], da2[4 * c + 1], da2[4 * c + 2], da2[4 * c + 3]);
+  {
+    float sl = l, sd = d3;
+#pragma unroll
+    for (int m = 1; m < WAVE; m <<= 1) {
+      sl += __shfl_xor(sl, m);
+      sd += __shfl_xor(sd, m);
+    }
+    if (lane == 0) {
+      S.WSUM[0][w] = hf ? 0.0f : sl;
+      S.WSUM[1][w] = hf ? 0.0f : sd;
+    }
+  }
+  lds_sync();
+
+  // F3: first-layer deltas of own units from all 32 second-layer deltas
+  {
+    float acc[16];
+#pragma unroll
+    for (int ii = 0; ii < 16; ii++) acc[ii] = 0.0f;
+#pragma nounroll
+    for (int c = 0; c < 8; c++) {
+      const float4 dv = *tchunk(S.DA2, s, c);
+      const float dj[4] = {dv.x, dv.y, dv.z, dv.w};
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        const float4* wr = reinterpret_cast<const float4*>(P + MLP_W2 + (4 * c + e) * MLP_H + 16 * hf);
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+          const float4 wv = wr[q];
+          acc[4 * q] = fmaf(dj[e], wv.x, acc[4 * q]);
+          acc[4 * q + 1] = fmaf(dj[e], wv.y, acc[4 * q + 1]);
+          acc[4 * q + 2] = fmaf(dj[e], wv.z, acc[4 * q + 2]);
+          acc[4 * q + 3] = fmaf(dj[e], wv.w, acc[4 * q + 3]);
+        }
+      }
+    }
+    const uint32_t mh = m1 >> (16 * hf);
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+      float4 v;
+      v.x = ((mh >> (4 * c)) & 1u) ? acc[4 * c] : 0.0f;
+      v.y = ((mh >> (4 * c + 1)) & 1u) ? acc[4 * c + 1] : 0.0f;
+      v.z = ((mh >> (4 * c + 2)) & 1u) ? acc[4 * c + 2] : 0.0f;
+      v.w = ((mh >> (4 * c + 3)) & 1u) ? acc[4 * c + 3] : 0.0f;
+      *tchunk(S.DA1, s, 4 * hf + c) = v;
+    }
+  }
+  lds_sync();
+
+  // G1: W2 gradient tile (rows 4jb.., columns 4ib..) over this wave's 32 samples, and
+  // the vector gradients over a quarter of the samples
+  const int jb = lane & 7, ib = lane >> 3;
+  float g[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int b = 0; b < 4; b++) g[a][b] = 0.0f;
+#pragma unroll 2
+  for (int q = 0; q < SG; q++) {
+    const int s2 = w * SG + q;
+    const float4 d = *tchunk(S.DA2, s2, jb);
+    const float4 h = *tchunk(S.H1, s2, ib);
+    const float dv[4] = {d.x, d.y, d.z, d.w};
+    const float hv[4] = {h.x, h.y, h.z, h.w};
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+      for (int b = 0; b < 4; b++) g[a][b] = fmaf(dv[a], hv[b], g[a][b]);
+  }
+  const int o = tid & 127, qq = tid >> 7;
+  float sm = 0.0f;
+#pragma unroll 4
+  for (int q = 0; q < TB / 4; q++) {
+    const int s2 = qq * (TB / 4) + q;
+    if (o < 32) sm = fmaf(telem(S.DA1, s2, o), S.XN[s2], sm);
+    else if (o < 64) sm += telem(S.DA1, s2, o - 32);
+    else if (o < 96) sm += telem(S.DA2, s2, o - 64);
+    else sm = fmaf(S.D3[s2], telem(S.H2, s2, o - 96), sm);
+  }
+  lds_sync();
+
+  // G2: partials to LDS (the W2 partials over H2, which is no longer read)
+  float* red = S.H2;
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+    *reinterpret_cast<float4*>(red + w * (MLP_H * MLP_H) + (4 * jb + a) * MLP_H + 4 * ib) =
+        f4(g[a][0], g[a][1], g[a][2], g[a][3]);
+  S.SM[qq][o] = sm;
+  lds_sync();
+
+  // G3: reduce into G (over H1, no longer read)
+  float* G = S.H1;
+  for (int e = tid; e < MLP_H * MLP_H; e += TRAIN_P) {
+    float v = 0.0f;
+#pragma unroll
+    for (int k = 0; k < TRAIN_NW; k++) v += red[k * (MLP_H * MLP_H) + e];
+    G[MLP_W2 + e] = v;
+  }
+  if (tid < 128) {
+    const float v = ((S.SM[0][tid] + S.SM[1][tid]) + S.SM[2][tid]) + S.SM[3][tid];
+    const int dst = tid < 32 ? MLP_W1 + tid : tid < 64 ? MLP_B1 + (tid - 32) : tid < 96 ? MLP_B2 + (tid - 64)
+                                                                                       : MLP_W3 + (tid - 96);
+    G[dst] = v;
+  } else if (tid == 128) {
+    float sd = 0.0f, sl = 0.0f;
+#pragma unroll
+    for (int k = 0; k < TRAIN_NW; k++) {
+      sd += S.WSUM[1][k];
+      sl += S.WSUM[0][k];
+    }
+    G[MLP_B3] = sd;
+    *loss_sum = sl;
+  }
+  lds_sync();
+  return G;
+}
+
+__device__ inline void draw_sample(const TrainArgs& a, uint32_t step, int B, int s, float* xv, float* tv) {
+  if (s < B && step <= a.steps) {
+    const uint64_t draw = (uint64_t)(step - 1) * (uint64_t)B + (uint64_t)s;
+    uint64_t idx;
+    if (a.sequential) idx = draw % a.m;
+    else idx = ((splitmix_at(a.seed, draw) >> 32) * a.m) >> 32;
+    *xv = a.x[idx];
+    *tv = a.t[idx];
+  } else {
+    *xv = 0.0f;
+    *tv = 0.0f;
+  }
 }
 
 // Adam (Kingma & Ba) with bias correction; step size decays linearly from lr to
@@ -239,20 +406,17 @@ __global__ void __launch_bounds__(TRAIN_P) train_kernel(float* params, float* mo
     ve[q] = i < MLP_NPARAM ? moments[MLP_NPARAM + i] : 0.0f;
   }
   __syncthreads();
-  const int B = (int)(a.batch < (uint32_t)MLP_MAX_BATCH ? a.batch : MLP_MAX_BATCH);
+  const int B = (int)(a.batch < (uint32_t)TB ? a.batch : TB);
+  const int s = tid & (TB - 1);
   const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
   float b1t = 1.0f, b2t = 1.0f;
+  float loss_sum = 0.0f;
+  float xv, tv;
+  draw_sample(a, 1, B, s, &xv, &tv);
   for (uint32_t step = 1; step <= a.steps; step++) {
-    float xv = 0.0f, tv = 0.0f;
-    if (tid < B) {
-      const uint64_t draw = (uint64_t)(step - 1) * (uint64_t)B + (uint64_t)tid;
-      uint64_t idx;
-      if (a.sequential) idx = draw % a.m;
-      else idx = ((splitmix_at(a.seed, draw) >> 32) * a.m) >> 32;
-      xv = a.x[idx];
-      tv = a.t[idx];
-    }
-    batch_gradient(S, xv, tv, B);
+    float xn_, tn_;
+    draw_sample(a, step + 1, B, s, &xn_, &tn_);   // next minibatch, in flight meanwhile
+    float* G = batch_gradient(S, xv, tv, B, &loss_sum);
     b1t *= b1;
     b2t *= b2;
     const float lr = a.lr * (1.0f - 0.9f * (float)(step - 1) / (float)(a.steps > 1 ? a.steps - 1 : 1));
@@ -260,7 +424,7 @@ __global__ void __launch_bounds__(TRAIN_P) train_kernel(float* params, float* mo
     for (int q = 0; q < PER; q++) {
       const int i = tid + q * TRAIN_P;
       if (i < MLP_NPARAM) {
-        const float g = S.G[i];
+        const float g = G[i];
         mo[q] = b1 * mo[q] + (1.0f - b1) * g;
         ve[q] = b2 * ve[q] + (1.0f - b2) * g * g;
         const float mh = mo[q] / (1.0f - b1t), vh = ve[q] / (1.0f - b2t);
@@ -271,8 +435,11 @@ __global__ void __launch_bounds__(TRAIN_P) train_kernel(float* params, float* mo
         S.P[i] = v;
       }
     }
-    __syncthreads();
+    lds_sync();
+    xv = xn_;
+    tv = tn_;
   }
+  __syncthreads();
   for (int i = tid; i < MLP_NBLOCK; i += TRAIN_P) params[i] = S.P[i];
 #pragma unroll
   for (int q = 0; q < PER; q++) {
@@ -282,7 +449,7 @@ __global__ void __launch_bounds__(TRAIN_P) train_kernel(float* params, float* mo
       moments[MLP_NPARAM + i] = ve[q];
     }
   }
-  if (tid == 0) moments[2 * MLP_NPARAM] = S.LOSS[0] / (float)(B > 0 ? B : 1);
+  if (tid == 128) moments[2 * MLP_NPARAM] = loss_sum / (float)(B > 0 ? B : 1);
 }
 
 // gradient of the mean squared error over m <= MLP_MAX_BATCH samples
@@ -293,9 +460,11 @@ __global__ void __launch_bounds__(TRAIN_P) gradient_kernel(const float* params, 
   for (int i = tid; i < MLP_NBLOCK; i += TRAIN_P) S.P[i] = params[i];
   __syncthreads();
   const int B = (int)m;
-  batch_gradient(S, tid < B ? x[tid] : 0.0f, tid < B ? t[tid] : 0.0f, B);
-  for (int i = tid; i < MLP_NPARAM; i += TRAIN_P) grad[i] = S.G[i];
-  if (tid == 0) *loss = S.LOSS[0] / (float)B;
+  const int s = tid & (TB - 1);
+  float loss_sum = 0.0f;
+  const float* G = batch_gradient(S, s < B ? x[s] : 0.0f, s < B ? t[s] : 0.0f, B, &loss_sum);
+  for (int i = tid; i < MLP_NPARAM; i += TRAIN_P) grad[i] = G[i];
+  if (tid == 128) *loss = loss_sum / (float)B;
 }
 
 // ---- inference, thresholds, classification ----------------------------------------------
@@ -316,25 +485,41 @@ __global__ void buckets_kernel(const float* params, const uint64_t* keys, uint64
     out[i] = mlp_bucket(P, keys[i]);
 }
 
-// t_j = min{k : b(k) >= j} for j = 1..255 by binary search over all 64-bit keys;
-// nvalid = b(2^64 - 1): thresholds j > nvalid do not exist
-__global__ void thresholds_kernel(const float* params, uint64_t* thr, uint32_t* nvalid) {
+// t_j = min{k : b(k) >= j} for j = 1..255, one wave per threshold: a 64-way search
+// over all 64-bit keys (each round probes 64 evenly spaced keys of the interval that
+// holds the answer, about 11 rounds); it relies on b being non-decreasing.
+// nvalid = b(2^64 - 1): thresholds j > nvalid do not exist.
+constexpr int THR_P = 256;
+__global__ void __launch_bounds__(THR_P) thresholds_kernel(const float* params, uint64_t* thr, uint32_t* nvalid) {
   __shared__ float P[MLP_NBLOCK];
   for (int i = threadIdx.x; i < MLP_NBLOCK; i += blockDim.x) P[i] = params[i];
   __syncthreads();
-  const int j = blockIdx.x * blockDim.x + threadIdx.x + 1;
-  if (j == 1) *nvalid = (uint32_t)mlp_bucket(P, ~0ull);
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int j = blockIdx.x * (THR_P / WAVE) + threadIdx.x / WAVE + 1;
+  const int top = mlp_bucket(P, ~0ull);
+  if (j == 1 && lane == 0) *nvalid = (uint32_t)top;
   if (j >= NBUCKET) return;
-  if (mlp_bucket(P, ~0ull) < j) {
-    thr[j - 1] = ~0ull;
+  if (top < j) {
+    if (lane == 0) thr[j - 1] = ~0ull;
     return;
   }
-  uint64_t lo = 0, hi = ~0ull;
+  uint64_t lo = 0, hi = ~0ull;   // the answer lies in [lo, hi]; b(hi) >= j
   while (lo < hi) {
-    const uint64_t mid = lo + (hi - lo) / 2;
-    if (mlp_bucket(P, mid) >= j) hi = mid; else lo = mid + 1;
+    const uint64_t span = hi - lo;
+    // probe l: lo + floor(span * l / 64) (exact), l = 0..63, all below hi
+    const uint64_t pr = lo + (span >> 6) * (uint64_t)lane + (((span & 63) * (uint64_t)lane) >> 6);
+    const uint64_t m = ballot(mlp_bucket(P, pr) >= j);
+    if (m) {
+      const int f = __builtin_ctzll(m);
+      const uint64_t pf = (uint64_t)__shfl((long long)pr, f);
+      const uint64_t pb = (uint64_t)__shfl((long long)pr, f > 0 ? f - 1 : 0);
+      hi = pf;
+      if (f > 0) lo = pb + 1;
+    } else {
+      lo = (uint64_t)__shfl((long long)pr, WAVE - 1) + 1;
+    }
   }
-  thr[j - 1] = lo;
+  if (lane == 0) thr[j - 1] = lo;
 }
 
 __global__ void classify_kernel(const uint64_t* keys, uint64_t n, const uint64_t* thr, const uint32_t* nvalid,
@@ -540,7 +725,7 @@ hipError_t launch_buckets(const float* params, const uint64_t* keys, uint64_t n,
 }
 
 hipError_t launch_thresholds(const float* params, uint64_t* thr, uint32_t* nvalid, hipStream_t s) {
-  hipLaunchKernelGGL(thresholds_kernel, dim3(4), dim3(64), 0, s, params, thr, nvalid);
+  hipLaunchKernelGGL(thresholds_kernel, dim3(NBUCKET / (THR_P / WAVE)), dim3(THR_P), 0, s, params, thr, nvalid);
   return hipGetLastError();
 }
 
