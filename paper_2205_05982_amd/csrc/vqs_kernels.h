@@ -133,10 +133,14 @@ struct Tile {
   }
 
   // Classify against the pivot (left: not after it; strict: before it), rank stably,
-  // stage in LDS (left keys from 0 upward, right keys from nvalid-1 downward).  Returns the tile's left count; *tmin gets
-  // the tile minimum (thread 0).  Ends with a barrier.
+  // stage in LDS (left keys from 0 upward, right keys from nvalid-1 downward).  Returns
+  // the tile's left count; *tmin gets the tile minimum (thread 0), and thread 0 calls
+  // publish(left count, minimum) as soon as both are known, before the keys are
+  // staged.  Ends with a barrier.
+  template <class Pub>
   __device__ static uint32_t rank_and_stage(S* stage, Aux& sh, const R (&key)[I][V], uint64_t k,
-                                            uint64_t vs, uint64_t ve, R pivot, bool strict, R* tmin) {
+                                            uint64_t vs, uint64_t ve, R pivot, bool strict, R* tmin,
+                                            Pub&& publish) {
     const int tid = threadIdx.x;
     const int w = tid / WAVE;
     uint32_t pre[I];
@@ -173,6 +177,14 @@ struct Tile {
 #pragma unroll
       for (int ww = 0; ww < NW; ww++) total += sh.cnt[j][ww];
     }
+    // the counts are known before the keys are staged: hand them out first
+    if (tid == 0) {
+      R m2 = sh.wmin[0];
+#pragma unroll
+      for (int ww = 1; ww < NW; ww++) m2 = K::kmin(m2, sh.wmin[ww]);
+      *tmin = m2;
+      publish(total, m2);
+    }
     const uint32_t nvalid = (uint32_t)(ve - vs);
 #pragma unroll
     for (int j = 0; j < I; j++) {
@@ -198,12 +210,6 @@ struct Tile {
           }
         }
       }
-    }
-    if (tid == 0) {
-      R m2 = sh.wmin[0];
-#pragma unroll
-      for (int ww = 1; ww < NW; ww++) m2 = K::kmin(m2, sh.wmin[ww]);
-      *tmin = m2;
     }
     __syncthreads();
     return total;
@@ -303,12 +309,17 @@ __device__ inline Seg make_seg(uint64_t b, uint64_t e, uint32_t depth, uint32_t 
 
 // ---- level kernel ------------------------------------------------------------------------
 
+#ifndef VQS_LEVEL_WAVES
+#define VQS_LEVEL_WAVES 4
+#endif
+constexpr int LEVEL_WAVES = VQS_LEVEL_WAVES;   // waves per SIMD the 8- and 16-byte level kernels target
+
 
 template <class K>
-__global__ void __launch_bounds__(LEVEL_P) level_kernel(Params p) {
+__global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(sizeof(typename K::R) >= 8 ? LEVEL_WAVES : 1))) level_kernel(Params p) {
   using R = typename K::R;
   using S = typename K::S;
-  constexpr int I = LEVEL_I;
+  constexpr int I = level_chunks(8 * K::SIZE);
   using TL = Tile<K, LEVEL_P, I>;
   constexpr int T = TL::T;
   __shared__ S stage[T];
@@ -337,6 +348,9 @@ __global__ void __launch_bounds__(LEVEL_P) level_kernel(Params p) {
   const int tid = threadIdx.x;
   unsigned long long tiles_done = 0;
   VQS_PHASE_INIT();
+#ifdef VQS_PHASE_TIMING
+  unsigned long long lb_n = 0, lb_it = 0, lb_sp = 0, lb_sp0 = 0, lb_lat = 0;
+#endif
 
   for (;;) {
     VQS_PHASE(5);
@@ -392,7 +406,23 @@ __global__ void __launch_bounds__(LEVEL_P) level_kernel(Params p) {
     __syncthreads();
     const R pivot = sh.pivot;
     R tmin;
-    const uint32_t nl = TL::rank_and_stage(stage, sh, key, k, vs, ve, pivot, (sg.flags & SEG_STRICT) != 0, &tmin);
+    // publish the tile minimum, then the left count (the minimum is made visible
+    // before the count by waiting for its stores to complete)
+    const uint32_t nl = TL::rank_and_stage(stage, sh, key, k, vs, ve, pivot, (sg.flags & SEG_STRICT) != 0, &tmin,
+                                           [&](uint32_t cnt, R m) {
+                                             uint64_t lo, hi;
+                                             to_words<K>(m, lo, hi);
+                                             __hip_atomic_store(&p.tilemin[g].lo, lo, __ATOMIC_RELAXED,
+                                                                __HIP_MEMORY_SCOPE_AGENT);
+                                             __hip_atomic_store(&p.tilemin[g].hi, hi, __ATOMIC_RELAXED,
+                                                                __HIP_MEMORY_SCOPE_AGENT);
+                                             __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                                             __builtin_amdgcn_s_waitcnt(0);
+                                             __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                                             if (g != g0)
+                                               __hip_atomic_store(&p.flags[g], epoch | ST_AGG | cnt, __ATOMIC_RELAXED,
+                                                                  __HIP_MEMORY_SCOPE_AGENT);
+                                           });
 
     // decoupled look-back on the left counts of the range's earlier tiles, one wave
     // reading 64 predecessors per step
@@ -401,35 +431,41 @@ __global__ void __launch_bounds__(LEVEL_P) level_kernel(Params p) {
       const int lane = tid;
       // Only device-coherent single-word accesses are used here (relaxed agent-scope
       // atomics): release/acquire fences at agent scope would write back or
-      // invalidate a whole L2 for every tile.  The tile minimum is made visible before
-      // the aggregate by waiting for its store to complete.
-      if (lane == 0) {
-        uint64_t lo, hi;
-        to_words<K>(tmin, lo, hi);
-        __hip_atomic_store(&p.tilemin[g].lo, lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&p.tilemin[g].hi, hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        __builtin_amdgcn_s_waitcnt(0);
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        if (g != g0)
-          __hip_atomic_store(&p.flags[g], epoch | ST_AGG | nl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
+      // invalidate a whole L2 for every tile.
       unsigned long long excl = 0;
       if (g != g0) {
         unsigned long long top = g - 1;   // highest predecessor not yet summed
         uint32_t spins = 0;
+#ifdef VQS_PHASE_TIMING
+        bool lb_first = true;
+        lb_n++;
+#endif
         for (;;) {
+#ifdef VQS_PHASE_TIMING
+          const unsigned long long lb_t0 = wall_clock64();
+          lb_it++;
+#endif
           const bool inr = top >= g0 + (unsigned long long)lane;   // lane reads tile top - lane
           unsigned long long f = 0;
           if (inr) f = __hip_atomic_load(&p.flags[top - lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           const bool ready = inr && (f & ~((1ull << 48) - 1)) == epoch && (f & (3ull << 46)) != 0;
           const bool inc = ready && (f & ST_INC);
           const uint64_t incm = ballot(inc), readym = ballot(ready), inrm = ballot(inr);
+#ifdef VQS_PHASE_TIMING
+          if (lb_first) {
+            lb_lat += wall_clock64() - lb_t0;
+            lb_first = false;
+          }
+#endif
           // lanes up to the nearest inclusive tile must all be ready
           const int first_inc = incm ? __builtin_ctzll(incm) : WAVE;
           const uint64_t need = (first_inc >= WAVE - 1) ? inrm : (((2ull << first_inc) - 1) & inrm);
           if ((need & ~readym) != 0) {
             ++spins;
+#ifdef VQS_PHASE_TIMING
+            lb_sp++;
+            if (!(readym & 1ull)) lb_sp0++;   // the nearest predecessor has no count yet
+#endif
             if ((spins & 255u) == 0 &&
                 (spins > (1u << 20) || __hip_atomic_load(p.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
               if (lane == 0) set_err(p, ERR_SPIN);
@@ -552,6 +588,15 @@ __global__ void __launch_bounds__(LEVEL_P) level_kernel(Params p) {
   }
   if (tid == 0 && tiles_done) atomicAdd(&p.stats->level_tiles, tiles_done);
   VQS_PHASE_FLUSH();
+#ifdef VQS_PHASE_TIMING
+  if (tid == 0 && p.dbg) {
+    atomicAdd(&p.dbg[20], lb_n);
+    atomicAdd(&p.dbg[21], lb_it);
+    atomicAdd(&p.dbg[22], lb_sp);
+    atomicAdd(&p.dbg[23], lb_lat);
+    atomicAdd(&p.dbg[28], lb_sp0);
+  }
+#endif
 }
 
 // ChoosePivot for every range of a level, one wave per range, before the level's
@@ -1224,7 +1269,7 @@ __global__ void __launch_bounds__(SOLO_P) solo_kernel(Params p) {
         R key[SOLO_I][K::V];
         TL::load(src_aligned, k, vs, ve, raw ? p.mode : 0, key);
         R tmin;
-        const uint32_t nl = TL::rank_and_stage(bufA, aux, key, k, vs, ve, pivot, strict, &tmin);
+        const uint32_t nl = TL::rank_and_stage(bufA, aux, key, k, vs, ve, pivot, strict, &tmin, [](uint32_t, R) {});
         const uint32_t nvalid = (uint32_t)(ve - vs);
         const uint32_t nr = nvalid - nl;
         TL::write_out(bufA, dst, nl, nvalid, cur.b + excl_l, cur.e - excl_r - nr, 0, p.n_total);
@@ -1320,7 +1365,7 @@ __global__ void clear_kernel(Params p) {
 // Route the input ranges: offsets (nseg + 1 entries), or [0, n) when offsets is null.
 template <class K>
 __global__ void seed_kernel(Params p, const int64_t* offsets, uint64_t nseg) {
-  using TL = Tile<K, LEVEL_P, LEVEL_I>;
+  using TL = Tile<K, LEVEL_P, level_chunks(8 * K::SIZE)>;
   const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = gid; i < nseg; i += stride) {

@@ -12,11 +12,18 @@ struct u128k {
 constexpr int MODE_FLOAT = 1;
 constexpr int MODE_DESC = 2;
 
-constexpr int LEVEL_P = 256;        // threads per level-kernel workgroup
-#ifndef VQS_LEVEL_I
-#define VQS_LEVEL_I 8
+#ifndef VQS_LEVEL_P
+#define VQS_LEVEL_P 256
 #endif
-constexpr int LEVEL_I = VQS_LEVEL_I;  // 16-byte chunks per thread: 32 KB tiles
+constexpr int LEVEL_P = VQS_LEVEL_P;  // threads per level-kernel workgroup
+// 16-byte chunks per thread of a level tile, by key width: as many as keep three
+// workgroups per CU (u16 keys take one register each, so their tiles are smaller):
+// 16 KB tiles for u16, 32 KB for u32, 48 KB for u64 and u128
+#ifdef VQS_LEVEL_I
+constexpr int level_chunks(int) { return VQS_LEVEL_I; }
+#else
+constexpr int level_chunks(int bits) { return bits == 16 ? 4 : bits == 32 ? 8 : 12; }
+#endif
 constexpr int SOLO_P = 256;         // threads per solo-kernel workgroup
 constexpr int SOLO_I = 8;           // 16-byte chunks per thread per solo tile (32 KB)
 constexpr int LOCAL_BYTES = 32768;  // one LDS buffer of the local sort
