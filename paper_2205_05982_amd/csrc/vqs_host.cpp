@@ -199,8 +199,10 @@ int make_plan(uint64_t n, uint64_t nseg, int kt, int asc, const vqs_options* o, 
     pl->solo = o->solo_max;
     if (pl->solo < pl->local) return VQS_EINVAL;
   } else {
-    // enough ranges for every solo workgroup, each at most 2^20 keys
-    uint64_t s = n / ((uint64_t)g.solo_grid * 4);
+    // ranges above 16K keys are partitioned by the device-wide level kernel, which
+    // moves data faster than one workgroup's partitions; a few times more ranges than
+    // solo workgroups keep the solo kernel busy on very large inputs
+    uint64_t s = n / ((uint64_t)g.solo_grid * 16);
     s = std::max<uint64_t>(s, std::max<uint64_t>(pl->local, 1u << 14));
     s = std::min<uint64_t>(s, 1ull << 20);
     pl->solo = std::max<uint64_t>(s, pl->local);

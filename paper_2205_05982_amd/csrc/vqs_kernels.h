@@ -744,6 +744,8 @@ struct LocalShared {
   LocalItem<K> list[2][LIST_CAP];
   uint32_t bc[BC_CAP];          // lb << 10 | (len-1) << 2 | fallback-mode << 1 | in B
   LocalItem<K> bounded[LIST_CAP];  // ranges past the fallback-mode limit
+  typename K::R gpiv[2], gmin[SOLO_NW];   // wave groups: pivots, part minima
+  uint32_t gcnt[SOLO_NW];                  // wave groups: left counts of the parts
   uint32_t nlist[2];
   uint32_t nbc, nbounded;
   uint32_t stat_part, stat_bc, stat_deg, stat_eq, stat_fb, stat_fbkeys, stat_maxd, stat_pkeys;
@@ -803,7 +805,7 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
   const uint32_t n = (uint32_t)(e - b);
   const int tmode = raw ? p.mode : 0;
 #ifdef VQS_PHASE_TIMING
-  unsigned long long lt0 = wall_clock64(), lacc[4] = {0, 0, 0, 0};
+  unsigned long long lt0 = wall_clock64(), lacc[4] = {0, 0, 0, 0}, lst[6] = {0, 0, 0, 0, 0, 0};
 #define VQS_LPH(i)                                   \
   {                                                  \
     const unsigned long long lt1 = wall_clock64();   \
@@ -861,78 +863,55 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
   __syncthreads();
   VQS_LPH(0);
 
+  // this wave's recursion counts (wave-uniform), added to the workgroup's at the end
+  uint32_t w_part = 0, w_pkeys = 0, w_maxd = 0, w_deg = 0, w_eq = 0;
   int cur = 0;
   for (;;) {
     const uint32_t nitems = ls.nlist[cur];
-    // 2. partition this level's ranges, one wave per range
-    for (uint32_t it_i = wave; it_i < nitems; it_i += SOLO_NW) {
-      LocalItem<K> it = ls.list[cur][it_i];
+    // 2. partition this level's ranges: one wave per range, or, while there are fewer
+    // ranges than waves, G = 4 / nitems waves per range
+    const int G = nitems == 1 ? 4 : nitems == 2 ? 2 : 1;
+    static_assert(SOLO_NW == 4, "wave groups assume four waves");
+    // depth check of an item: true if it is to be partitioned (possibly now in
+    // fallback mode); false if it went to the bounded-time list (by lane 0 of the
+    // wave that reports it)
+    auto admit = [&](LocalItem<K>& it, bool report) -> bool {
+      if (it.depth <= it.limit) return true;
       const uint32_t lb = it.lb, le = it.le;
-      if (it.depth > it.limit) {
-        if (!(it.flags & LI_FB)) {
-          // the paper's depth limit: continue this range in fallback mode
-          if (lane == 0) {
-            atomicAdd(&ls.stat_fb, 1u);
-            atomicAdd(&ls.stat_fbkeys, le - lb);
-          }
-          it.flags = (it.flags & LI_INB) | LI_FB;
-          it.depth = 1;
-          it.limit = depth_limit_of(le - lb);
-        } else {
-          if (lane == 0) {
-            const uint32_t f = atomicAdd(&ls.nbounded, 1u);
-            if (f < LIST_CAP) ls.bounded[f] = it;
-            else set_err(p, ERR_LOCAL_OVERFLOW);
-          }
-          continue;
+      if (!(it.flags & LI_FB)) {
+        // the paper's depth limit: continue this range in fallback mode
+        if (report && lane == 0) {
+          atomicAdd(&ls.stat_fb, 1u);
+          atomicAdd(&ls.stat_fbkeys, le - lb);
         }
+        it.flags = (it.flags & LI_INB) | LI_FB;
+        it.depth = 1;
+        it.limit = depth_limit_of(le - lb);
+        return true;
       }
+      if (report && lane == 0) {
+        const uint32_t f = atomicAdd(&ls.nbounded, 1u);
+        if (f < LIST_CAP) ls.bounded[f] = it;
+        else set_err(p, ERR_LOCAL_OVERFLOW);
+      }
+      return false;
+    };
+    auto pick_pivot = [&](const LocalItem<K>& it, const S* s_buf) -> R {
+      if (it.flags & LI_OVERRIDE) return it.pv;
+      const S* sb = s_buf + it.lb;
+      return choose_pivot_wave<K>([&](uint64_t i) -> R { return (R)sb[i]; }, b + it.lb, b + it.le, p.seed);
+    };
+    // after the partition of it into d_buf ([lb, bound) left): children, equal runs,
+    // statistics.  Run by one whole wave; mn is the range minimum (wave-uniform).
+    auto plan = [&](const LocalItem<K>& it, uint32_t bound, R mn, R pivot) {
+      const uint32_t lb = it.lb, le = it.le;
       const bool fb = (it.flags & LI_FB) != 0;
       const bool strict = (it.flags & LI_STRICT) != 0;
-      S* s_buf = (it.flags & LI_INB) ? bufB : bufA;
-      S* d_buf = (it.flags & LI_INB) ? bufA : bufB;
-      R pivot;
-      if (it.flags & LI_OVERRIDE) {
-        pivot = it.pv;
-      } else {
-        const S* sb = s_buf + lb;
-        pivot = choose_pivot_wave<K>([&](uint64_t i) -> R { return (R)sb[i]; }, b + lb, b + le, p.seed);
-      }
-      uint32_t l = lb, r = le;
-      R mn = K::maxv();
-      // four 64-key groups per step: independent loads, ballots and stores
-      constexpr int U = 4;
-      for (uint32_t base = lb; base < le; base += U * WAVE) {
-        R kx[U];
-        bool valid[U], isl[U];
-        uint64_t ml[U], mr[U];
-#pragma unroll
-        for (int u = 0; u < U; u++) {
-          const uint32_t i = base + u * WAVE + lane;
-          valid[u] = i < le;
-          kx[u] = valid[u] ? (R)s_buf[i] : K::maxv();
-        }
-#pragma unroll
-        for (int u = 0; u < U; u++) {
-          isl[u] = valid[u] && (strict ? K::lt(kx[u], pivot) : !K::lt(pivot, kx[u]));
-          if (valid[u]) mn = K::kmin(mn, kx[u]);
-          ml[u] = ballot(isl[u]);
-          mr[u] = ballot(valid[u] && !isl[u]);
-        }
-#pragma unroll
-        for (int u = 0; u < U; u++) {
-          if (isl[u]) d_buf[l + mbcnt(ml[u])] = (S)kx[u];
-          else if (valid[u]) d_buf[r - 1 - mbcnt(mr[u])] = (S)kx[u];
-          l += __popcll(ml[u]);
-          r -= __popcll(mr[u]);
-        }
-      }
-      const uint32_t bound = l;
       const uint32_t nbuf = (it.flags & LI_INB) ? 0u : LI_INB;   // children live in d_buf
-      if (!fb && lane == 0) {
-        atomicAdd(&ls.stat_part, 1u);
-        atomicAdd(&ls.stat_pkeys, le - lb);
-        atomicMax(&ls.stat_maxd, it.depth);
+      if (!fb) {
+        w_part++;
+        w_pkeys += le - lb;
+        w_maxd = it.depth > w_maxd ? it.depth : w_maxd;
       }
       auto push_child = [&](uint32_t cb, uint32_t ce, uint32_t cflags, R cpv) {
         const uint32_t len = ce - cb;
@@ -965,10 +944,9 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
         if (lane == 0) push_child(lb, bound, 0u, pivot);
       } else if (bound == le) {
         if (!fb) {
-          mn = wave_min<K>(mn);
-          if (lane == 0) atomicAdd(&ls.stat_deg, 1u);
+          w_deg++;
           if (K::eq(mn, pivot)) {
-            if (lane == 0) atomicAdd(&ls.stat_eq, 1u);
+            w_eq++;
             finish_equal(lb, le);
           } else if (lane == 0) {
             // Alg. 1: repeat with the first key in sort order as the pivot
@@ -978,10 +956,139 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
           // fallback mode: split off the keys equal to the pivot (the maximum)
           push_child(lb, le, LI_OVERRIDE | LI_STRICT, pivot);
         }
-      } else if (lane == 0) {
-        push_child(lb, bound, 0u, pivot);
-        push_child(bound, le, 0u, pivot);
+      } else if (lane < 2) {
+        // both children at once (their LDS atomics issue as one instruction)
+        push_child(lane == 0 ? lb : bound, lane == 0 ? bound : le, 0u, pivot);
       }
+    };
+    constexpr int U = 4;   // four 64-key groups per step: independent loads, ballots, stores
+    // keys of [pb, pe) (a multiple of U*WAVE from the range start) to d_buf: left keys
+    // in order from l, right keys in order downward from r - 1
+    // keys of [pb, pe) (a multiple of U*WAVE from the range start) to d_buf: left keys
+    // in order from l, right keys in order downward from r - 1.  Branch-free: loads are
+    // clamped into the range, both predicates are evaluated, one masked store per key.
+    auto scatter = [&](const S* s_buf, S* d_buf, uint32_t pb, uint32_t pe, uint32_t l, uint32_t r, R pivot,
+                       bool strict, R& mn) -> uint32_t {
+      const uint32_t last = pe - 1;
+      for (uint32_t base = pb; base < pe; base += U * WAVE) {
+        R kx[U];
+        bool valid[U], isl[U];
+        uint64_t ml[U], vm[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+          const uint32_t i = base + u * WAVE + lane;
+          valid[u] = i < pe;
+          kx[u] = (R)s_buf[i < pe ? i : last];
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+          const bool before = K::lt(kx[u], pivot), not_after = !K::lt(pivot, kx[u]);
+          isl[u] = valid[u] && (strict ? before : not_after);
+          mn = valid[u] ? K::kmin(mn, kx[u]) : mn;
+          ml[u] = ballot(isl[u]);
+          vm[u] = ballot(valid[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+          const uint32_t lrank = mbcnt(ml[u]), vrank = mbcnt(vm[u]);
+          const uint32_t d = isl[u] ? l + lrank : r - 1 - (vrank - lrank);
+          if (valid[u]) d_buf[d] = (S)kx[u];
+          const uint32_t nlft = (uint32_t)__popcll(ml[u]);
+          l += nlft;
+          r -= (uint32_t)__popcll(vm[u]) - nlft;
+        }
+      }
+      return l;
+    };
+    if (G == 1) {
+      for (uint32_t it_i = wave; it_i < nitems; it_i += SOLO_NW) {
+        LocalItem<K> it = ls.list[cur][it_i];
+        if (!admit(it, true)) continue;
+        const bool strict = (it.flags & LI_STRICT) != 0;
+        S* s_buf = (it.flags & LI_INB) ? bufB : bufA;
+        S* d_buf = (it.flags & LI_INB) ? bufA : bufB;
+#ifdef VQS_PHASE_TIMING
+        const unsigned long long q0 = wall_clock64();
+#endif
+        const R pivot = pick_pivot(it, s_buf);
+#ifdef VQS_PHASE_TIMING
+        const unsigned long long q1 = wall_clock64();
+#endif
+        R mn = K::maxv();
+        const uint32_t bound = scatter(s_buf, d_buf, it.lb, it.le, it.lb, it.le, pivot, strict, mn);
+#ifdef VQS_PHASE_TIMING
+        const unsigned long long q2 = wall_clock64();
+#endif
+        plan(it, bound, wave_min<K>(mn), pivot);
+#ifdef VQS_PHASE_TIMING
+        if (tid == 0) {
+          lst[2] += q1 - q0;
+          lst[3] += q2 - q1;
+          lst[4] += wall_clock64() - q2;
+          lst[5]++;
+        }
+#endif
+      }
+    } else {
+      // wave group: wave sw of item wave / G takes the sw-th part of the range; a
+      // counting pass gives every part its output positions, so the result is the one
+      // a single wave scanning the whole range would write
+      const int item = wave / G, sw = wave % G;
+      LocalItem<K> it = ls.list[cur][item];
+      const bool go = admit(it, sw == 0);
+      const bool strict = (it.flags & LI_STRICT) != 0;
+      S* s_buf = (it.flags & LI_INB) ? bufB : bufA;
+      S* d_buf = (it.flags & LI_INB) ? bufA : bufB;
+      const uint32_t len = it.le - it.lb;
+      const uint32_t per = ((len + G - 1) / G + U * WAVE - 1) / (U * WAVE) * (U * WAVE);
+      auto part_b = [&](int q) { const uint32_t o = (uint32_t)q * per; return it.lb + (o < len ? o : len); };
+      if (go && sw == 0) {
+        const R pv = pick_pivot(it, s_buf);
+        if (lane == 0) ls.gpiv[item] = pv;
+      }
+      __syncthreads();
+      const R pivot = ls.gpiv[item];
+      const uint32_t pb = part_b(sw), pe = part_b(sw + 1);
+      uint32_t cnt = 0;
+      R mn = K::maxv();
+      if (go) {
+        for (uint32_t base = pb; base < pe; base += U * WAVE) {
+#pragma unroll
+          for (int u = 0; u < U; u++) {
+            const uint32_t i = base + u * WAVE + lane;
+            const bool valid = i < pe;
+            const R kx = (R)s_buf[i < pe ? i : pe - 1];
+            const bool before = K::lt(kx, pivot), not_after = !K::lt(pivot, kx);
+            const bool isl = valid && (strict ? before : not_after);
+            mn = valid ? K::kmin(mn, kx) : mn;
+            cnt += (uint32_t)__popcll(ballot(isl));
+          }
+        }
+        mn = wave_min<K>(mn);
+        if (lane == 0) {
+          ls.gcnt[wave] = cnt;
+          ls.gmin[wave] = mn;
+        }
+      }
+      __syncthreads();
+      uint32_t ltot = 0;
+      R gm = K::maxv();
+      if (go) {
+        uint32_t lbef = 0, rbef = 0;
+        for (int q = 0; q < G; q++) {
+          const uint32_t c = ls.gcnt[item * G + q];
+          if (q < sw) {
+            lbef += c;
+            rbef += (part_b(q + 1) - part_b(q)) - c;
+          }
+          ltot += c;
+          gm = K::kmin(gm, ls.gmin[item * G + q]);
+        }
+        R unused = K::maxv();
+        scatter(s_buf, d_buf, pb, pe, it.lb + lbef, it.le - rbef, pivot, strict, unused);
+      }
+      __syncthreads();   // the whole partition is in d_buf before runs of it are copied
+      if (go && sw == 0) plan(it, it.lb + ltot, gm, pivot);
     }
     __syncthreads();
     VQS_LPH(1);
@@ -1038,6 +1145,15 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
     cur ^= 1;
     if (ls.nlist[cur] == 0) break;
   }
+  if (lane == 0) {
+    if (w_part) {
+      atomicAdd(&ls.stat_part, w_part);
+      atomicAdd(&ls.stat_pkeys, w_pkeys);
+      atomicMax(&ls.stat_maxd, w_maxd);
+    }
+    if (w_deg) atomicAdd(&ls.stat_deg, w_deg);
+    if (w_eq) atomicAdd(&ls.stat_eq, w_eq);
+  }
   __syncthreads();
   VQS_LPH(1);
   // 5. write out
@@ -1050,6 +1166,15 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
 #ifdef VQS_PHASE_TIMING
   if (tid == 0 && p.dbg)
     for (int i = 0; i < 4; i++) atomicAdd(&p.dbg[16 + i], lacc[i]);
+  if (tid == 0 && p.dbg) {
+    atomicAdd(&p.dbg[24], lst[0]);
+    atomicAdd(&p.dbg[25], lst[1]);
+    atomicAdd(&p.dbg[26], lst[2]);
+    atomicAdd(&p.dbg[27], lst[3]);
+    atomicAdd(&p.dbg[29], lst[4]);
+    atomicAdd(&p.dbg[30], lst[5]);
+    atomicAdd(&p.dbg[31], 1ull);
+  }
 #endif
 #undef VQS_LPH
   if (tid == 0) {
@@ -1165,7 +1290,8 @@ template <class K>
 __global__ void __launch_bounds__(SOLO_P) solo_kernel(Params p) {
   using R = typename K::R;
   using S = typename K::S;
-  using TL = Tile<K, SOLO_P, SOLO_I>;
+  constexpr int SI = solo_chunks(8 * K::SIZE);
+  using TL = Tile<K, SOLO_P, SI>;
   constexpr int T = TL::T;
   static_assert(T * sizeof(S) <= LOCAL_BYTES, "tile staging must fit one LDS buffer");
   __shared__ __attribute__((aligned(16))) char lds_raw[2 * LOCAL_BYTES];
@@ -1266,7 +1392,7 @@ __global__ void __launch_bounds__(SOLO_P) solo_kernel(Params p) {
       for (uint64_t k = k0; k <= k1; k++) {
         const uint64_t vs = (k * T > cur.b + p.off) ? k * T : cur.b + p.off;
         const uint64_t ve = ((k + 1) * T < cur.e + p.off) ? (k + 1) * T : cur.e + p.off;
-        R key[SOLO_I][K::V];
+        R key[SI][K::V];
         TL::load(src_aligned, k, vs, ve, raw ? p.mode : 0, key);
         R tmin;
         const uint32_t nl = TL::rank_and_stage(bufA, aux, key, k, vs, ve, pivot, strict, &tmin, [](uint32_t, R) {});
