@@ -7,6 +7,10 @@ and the in-LDS base cases) of one array of synthetic keys.  Every timed step sor
 its own pre-staged copy of the input, so all inputs are resident in HBM when the
 timed region starts and nothing but sorting is timed.  Prints one JSON line.
 
+The line also carries "learned_vs_plain": the 5e8-key lognormal-mixture workload
+sorted by both methods (median of a few sorts each), the speedup of the learned
+256-bucket splitter and whether both outputs are identical.
+
 Roofline: the dominant kernel is the device-wide partition (level kernel).  Its
 algorithmic traffic per launch is 2 * keys * key_size bytes (each key of the level
 read once and written once); HIP events around every launch on the library's
@@ -48,7 +52,79 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=100_000_000)
     ap.add_argument("--profile-json", default="", help="write per-launch kernel times here")
+    ap.add_argument("--learned-n", type=int, default=500_000_000,
+                    help="keys of the learned-splitter vs plain comparison (0: skip it)")
+    ap.add_argument("--learned-reps", type=int, default=3)
     return ap.parse_args()
+
+
+def learned_vs_plain(n: int, reps: int) -> dict:
+    """The 5e8-key lognormal-mixture workload sorted by the plain method and by the
+    learned 256-bucket splitter: median time of each over `reps` sorts (each of a
+    fresh copy of the input already in HBM), whether the outputs are identical, and
+    the splitter's own figures (training time, largest bucket, overflow buckets)."""
+    import torch
+    from paper_2205_05982_amd import vqs
+    from paper_2205_05982_amd import workloads as W
+    t0 = time.time()
+    host = W.lognormal_mixture_u64(n, 15)
+    print(f"# mixture input n={n} generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    dev = torch.device("cuda", 0)
+    src = torch.from_numpy(host).to(dev)
+    del host
+    work = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    res = {}
+    outs = {}
+    for name, method in (("plain", 0), ("learned", 1)):
+        times = []
+        # the first call warms up and, with per-launch timing on, gives the phase times
+        for r in range(reps + 1):
+            work.copy_(src)
+            torch.cuda.synchronize()
+            if r == 0:
+                vqs.profile(True)
+                vqs.profile_read()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            vqs.sort(work, key_type=3, method=method)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            if vqs.last_error_bits():
+                raise RuntimeError(f"device error bits {vqs.last_error_bits():#x}")
+            if r == 0:
+                recs = vqs.profile_read()
+                vqs.profile(False)
+                phases = {}
+                for x in recs:
+                    phases[x["kind"]] = phases.get(x["kind"], 0.0) + x["ms"]
+                continue
+            times.append(e0.elapsed_time(e1))
+        st = vqs.get_stats()
+        res[name] = {"ms": round(float(np.median(times)), 3), "ms_all": [round(t, 3) for t in times],
+                     "phase_ms": {k: round(v, 3) for k, v in phases.items() if v >= 0.005}}
+        if method == 1:
+            res[name].update({"max_bucket_over_expected": round(st["max_bucket"] / (n / 256), 3),
+                              "overflow_buckets": st["overflow_buckets"],
+                              "train_loss": st["train_loss"]})
+        outs[name] = work.clone() if method == 0 else work
+    identical = bool(torch.equal(outs["plain"].view(torch.int64), outs["learned"].view(torch.int64)))
+    o = outs["learned"].view(torch.int64) ^ torch.tensor(-(2**63), dtype=torch.int64, device=dev)
+    sorted_ok = bool((o[1:] >= o[:-1]).all().item())
+    return {
+        "workload": f"{n:.0e} u64: 90% mixture of 8 lognormals + 10% Zipf(1.2) duplicates, seed 15",
+        "plain_ms": res["plain"]["ms"],
+        "learned_ms": res["learned"]["ms"],
+        "speedup": round(res["plain"]["ms"] / res["learned"]["ms"], 3),
+        "plain_gkeys": round(n / res["plain"]["ms"] / 1e6, 3),
+        "learned_gkeys": round(n / res["learned"]["ms"] / 1e6, 3),
+        "identical_output": identical,
+        "sorted": sorted_ok,
+        "learned": {k: v for k, v in res["learned"].items() if k != "ms"},
+        "plain": {k: v for k, v in res["plain"].items() if k != "ms"},
+        "reps": reps,
+    }
 
 
 def make_input(name: str, n: int) -> np.ndarray:
@@ -143,6 +219,11 @@ def main():
         with open(args.profile_json, "w") as f:
             json.dump({"records": recs, "stats": stats}, f, indent=1)
 
+    # free the timed buffers before the larger comparison
+    del bufs, out, o64, i64
+    torch.cuda.empty_cache()
+    lvp = learned_vs_plain(args.learned_n, args.learned_reps) if args.learned_n else None
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -190,6 +271,7 @@ def main():
         "stats": {k: stats[k] for k in ("partitions", "degenerate", "basecases", "fallbacks", "max_depth",
                                        "levels", "solo_items")},
         "cpu_baseline": cpu,
+        "learned_vs_plain": lvp,
     }
     print(json.dumps(line), flush=True)
 
