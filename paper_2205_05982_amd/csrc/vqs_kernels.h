@@ -744,7 +744,7 @@ struct LocalShared {
   LocalItem<K> list[2][LIST_CAP];
   uint32_t bc[BC_CAP];          // lb << 10 | (len-1) << 2 | fallback-mode << 1 | in B
   LocalItem<K> bounded[LIST_CAP];  // ranges past the fallback-mode limit
-  typename K::R gpiv[2], gmin[SOLO_NW];   // wave groups: pivots, part minima
+  typename K::R gpiv[SOLO_NW / 2], gmin[SOLO_NW];   // wave groups: pivots, part minima
   uint32_t gcnt[SOLO_NW];                  // wave groups: left counts of the parts
   uint32_t nlist[2];
   uint32_t nbc, nbounded;
@@ -868,10 +868,11 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
   int cur = 0;
   for (;;) {
     const uint32_t nitems = ls.nlist[cur];
-    // 2. partition this level's ranges: one wave per range, or, while there are fewer
-    // ranges than waves, G = 4 / nitems waves per range
-    const int G = nitems == 1 ? 4 : nitems == 2 ? 2 : 1;
-    static_assert(SOLO_NW == 4, "wave groups assume four waves");
+    // 2. partition this level's ranges: one wave per range, or, while there are at
+    // most half as many ranges as waves, G waves per range (the largest power of two
+    // with nitems * G <= waves)
+    int G = 1;
+    while (nitems > 0 && 2u * G * nitems <= (uint32_t)SOLO_NW) G *= 2;
     // depth check of an item: true if it is to be partitioned (possibly now in
     // fallback mode); false if it went to the bounded-time list (by lane 0 of the
     // wave that reports it)
@@ -1034,8 +1035,9 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
       // counting pass gives every part its output positions, so the result is the one
       // a single wave scanning the whole range would write
       const int item = wave / G, sw = wave % G;
-      LocalItem<K> it = ls.list[cur][item];
-      const bool go = admit(it, sw == 0);
+      const bool have = (uint32_t)item < nitems;   // waves past the last range only keep step
+      LocalItem<K> it = ls.list[cur][have ? item : 0];
+      const bool go = have && admit(it, sw == 0);
       const bool strict = (it.flags & LI_STRICT) != 0;
       S* s_buf = (it.flags & LI_INB) ? bufB : bufA;
       S* d_buf = (it.flags & LI_INB) ? bufA : bufB;
@@ -1199,6 +1201,12 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
 
 constexpr int STACK_CAP = 48;
 
+// waves per SIMD the solo kernel is compiled for: four (two 512-thread workgroups per
+// CU, which their LDS allows) except for 16-byte keys, whose network needs more
+// registers
+template <int SIZE>
+constexpr int solo_waves() { return SIZE == 16 ? 2 : 4; }
+
 // Fill keys[b, e) of the caller's array with one value (output transform applied).
 template <class K>
 __device__ void fill_range(const Params& p, uint64_t b, uint64_t e, typename K::R v) {
@@ -1287,7 +1295,7 @@ __device__ void fallback_global(const Params& p, typename K::S* bufA, const Seg&
 }
 
 template <class K>
-__global__ void __launch_bounds__(SOLO_P) solo_kernel(Params p) {
+__global__ void __launch_bounds__(SOLO_P) __attribute__((amdgpu_waves_per_eu(solo_waves<K::SIZE>()))) solo_kernel(Params p) {
   using R = typename K::R;
   using S = typename K::S;
   constexpr int SI = solo_chunks(8 * K::SIZE);

@@ -24,10 +24,13 @@ constexpr int level_chunks(int) { return VQS_LEVEL_I; }
 #else
 constexpr int level_chunks(int bits) { return bits == 16 ? 4 : bits == 32 ? 8 : 12; }
 #endif
-constexpr int SOLO_P = 256;         // threads per solo-kernel workgroup
+#ifndef VQS_SOLO_P
+#define VQS_SOLO_P 512
+#endif
+constexpr int SOLO_P = VQS_SOLO_P;  // threads per solo-kernel workgroup
 // 16-byte chunks per thread of a solo-kernel tile (32 KB tiles; 16 KB for u16, whose
 // keys take one register each)
-constexpr int solo_chunks(int bits) { return bits == 16 ? 4 : 8; }
+constexpr int solo_chunks(int bits) { return (bits == 16 ? 1024 : 2048) / SOLO_P; }
 constexpr int LOCAL_BYTES = 32768;  // one LDS buffer of the local sort
 constexpr int LOCAL_LIST_CAP = 64;  // ranges per LDS recursion level
 

@@ -147,6 +147,56 @@ def segmented_keys(offsets: np.ndarray, kt: int, seed: int) -> np.ndarray:
     raise ValueError("segmented workloads use u32 or u64 keys")
 
 
+# ---- counter-based keys (random access: any range of the stream can be produced on
+# its own, on the host or on the GPU, with identical values) ------------------------
+
+_GAMMA = 0x9E3779B97F4A7C15
+_M1 = 0xBF58476D1CE4E5B9
+_M2 = 0x94D049BB133111EB
+
+
+def counter_u64(seed: int, start: int, count: int) -> np.ndarray:
+    """Outputs start .. start+count-1 of SplitMix64 from initial state `seed`: output i
+    is mix(seed + (i + 1) * 0x9E3779B97F4A7C15) (all arithmetic mod 2^64)."""
+    i = np.arange(start + 1, start + count + 1, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + i * np.uint64(_GAMMA)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(_M1)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(_M2)
+    return z ^ (z >> np.uint64(31))
+
+
+def counter_u32(seed: int, start: int, count: int) -> np.ndarray:
+    """High halves of counter_u64."""
+    return (counter_u64(seed, start, count) >> np.uint64(32)).astype(np.uint32)
+
+
+def _signed(c: int) -> int:
+    return c - (1 << 64) if c >= 1 << 63 else c
+
+
+def counter_torch(seed: int, start: int, count: int, bits: int, device) -> "torch.Tensor":
+    """counter_u64 (bits 64, as int64) or counter_u32 (bits 32, as int32) computed on
+    `device` with int64 arithmetic (wrapping multiplies; right shifts masked to be
+    logical), in pieces of 2^26."""
+    import torch
+    out = torch.empty(count, dtype=torch.int64 if bits == 64 else torch.int32, device=device)
+    piece = 1 << 26
+    for p0 in range(0, count, piece):
+        m = min(piece, count - p0)
+        i = torch.arange(start + p0 + 1, start + p0 + m + 1, dtype=torch.int64, device=device)
+        z = _signed(seed % (1 << 64)) + i * _signed(_GAMMA)
+        z = (z ^ ((z >> 30) & ((1 << 34) - 1))) * _signed(_M1)
+        z = (z ^ ((z >> 27) & ((1 << 37) - 1))) * _signed(_M2)
+        z = z ^ ((z >> 31) & ((1 << 33) - 1))
+        if bits == 64:
+            out[p0:p0 + m] = z
+        else:
+            hi = (z >> 32) & 0xFFFFFFFF                 # the high half, in [0, 2^32)
+            out[p0:p0 + m] = torch.where(hi >= (1 << 31), hi - (1 << 32), hi).to(torch.int32)
+    return out
+
+
 def lognormal_mixture_u64(n: int, seed: int = 15, ncomp: int = 8, dup_frac: float = 0.10,
                           dup_pool: int = 1 << 20, dup_s: float = 1.2) -> np.ndarray:
     """Mixture of ncomp lognormal components (weights 1/ncomp, mu ~ U[10, 40],
