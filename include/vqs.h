@@ -131,6 +131,25 @@ int vqs_sort_ex(void* keys, uint64_t n, int key_type, int ascending, const vqs_o
 int vqs_sort_segmented_ex(void* keys, const int64_t* offsets, uint64_t nseg, int key_type,
                           int ascending, const vqs_options* options, void* stream);
 
+/* Autotuner of the batched (segmented) sort.  Times the sort with every combination
+ * of the run-time tunables -- solo_max (ranges up to this many keys are finished by
+ * one workgroup each, longer ones are partitioned by the device-wide level kernel) in
+ * {0 = the library's size rule, 2^14, 2^16, 2^18, 2^20}, local_keys (size of the
+ * in-LDS sort) in {full buffer, half}, base_case in {256, 128} -- on a copy of the
+ * segments (all of them when max_keys is 0, else the longest prefix with at most
+ * max_keys keys, at least one segment), best of two timed runs after a warm-up each,
+ * and writes the fastest combination into options->solo_max, local_keys and base_case
+ * (the other fields are kept and used for the runs; method is plain).  keys and
+ * offsets are device pointers as for vqs_sort_segmented; the caller's keys are not
+ * modified.  Allocates the copy (hipMalloc, freed before return) and synchronises the
+ * stream.  *best_ms (if not NULL) receives the best time.  Errors: VQS_EINVAL for
+ * null pointers, nseg == 0 or a short options struct, VQS_EOFFSETS, VQS_ENOMEM,
+ * VQS_EHIP.  A prefix represents the batch only when the segment order carries no
+ * size trend, and the best solo_max depends on how many ranges run at once, so a
+ * prefix may prefer a smaller one than the whole batch. */
+int vqs_autotune_segmented(const void* keys, const int64_t* offsets, uint64_t nseg, int key_type, int ascending,
+                           uint64_t max_keys, vqs_options* options, float* best_ms, void* stream);
+
 /* Device bytes of the workspace a sort of n keys (in nseg segments) needs. */
 uint64_t vqs_workspace_bytes(uint64_t n, uint64_t nseg, int key_type, const vqs_options* options);
 

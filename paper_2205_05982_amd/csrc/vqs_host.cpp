@@ -683,6 +683,101 @@ int vqs_sort_segmented_ex(void* keys, const int64_t* offsets, uint64_t nseg, int
   return sort_impl(keys, offsets, nseg, total, key_type, ascending, options, s);
 }
 
+int vqs_autotune_segmented(const void* keys, const int64_t* offsets, uint64_t nseg, int key_type, int ascending,
+                           uint64_t max_keys, vqs_options* options, float* best_ms, void* stream) {
+  const int bits = key_bits(key_type);
+  if (!bits) return VQS_ETYPE;
+  if (!keys || !offsets || !options || nseg == 0 || (ascending != 0 && ascending != 1)) return VQS_EINVAL;
+  if (options->struct_size != 0 && options->struct_size < sizeof(vqs_options)) return VQS_EINVAL;
+  if (max_keys == 0) max_keys = ~0ull;   // the whole batch
+  hipStream_t s = (hipStream_t)stream;
+  const size_t ks = (size_t)bits / 8;
+  // the sample: the longest prefix of segments holding at most max_keys keys (at
+  // least one segment), rebased to offset 0
+  std::vector<int64_t> h(nseg + 1);
+  if (hipMemcpyAsync(h.data(), offsets, (nseg + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return VQS_EHIP;
+  if (h[0] < 0) return VQS_EOFFSETS;
+  for (uint64_t i = 0; i < nseg; i++)
+    if (h[i + 1] < h[i]) return VQS_EOFFSETS;
+  uint64_t k = 1;
+  while (k < nseg && (uint64_t)(h[k + 1] - h[0]) <= max_keys) k++;
+  const uint64_t sub = (uint64_t)(h[k] - h[0]);
+  if (sub == 0) return VQS_OK;
+  std::vector<int64_t> rb(k + 1);
+  for (uint64_t i = 0; i <= k; i++) rb[i] = h[i] - h[0];
+  void* tk = nullptr;
+  int64_t* to = nullptr;
+  if (hipMalloc(&tk, sub * ks) != hipSuccess || hipMalloc((void**)&to, (k + 1) * sizeof(int64_t)) != hipSuccess) {
+    (void)hipGetLastError();
+    if (tk) (void)hipFree(tk);
+    return VQS_ENOMEM;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = VQS_OK;
+  if (hipMemcpyAsync(to, rb.data(), (k + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    rc = VQS_EHIP;
+  const char* src = (const char*)keys + (size_t)h[0] * ks;
+  const uint32_t full = (uint32_t)local_buffer_keys(bits);
+  const uint64_t solos[] = {0, 1ull << 14, 1ull << 16, 1ull << 18, 1ull << 20};   // 0: the size rule
+  const uint32_t locals[] = {full, full / 2};
+  const uint32_t bases[] = {256, 128};
+  float best = -1.0f;
+  vqs_options base{};
+  std::memcpy(&base, options, sizeof(vqs_options));
+  base.struct_size = sizeof(vqs_options);
+  base.method = VQS_METHOD_PLAIN;
+  base.use_graph = 0;
+  vqs_options chosen = base;
+  for (uint64_t sm : solos)
+    for (uint32_t lk : locals)
+      for (uint32_t nb : bases) {
+        if (rc != VQS_OK) break;
+        vqs_options c = base;
+        c.solo_max = sm;
+        c.local_keys = lk;
+        c.base_case = nb;
+        float t_min = -1.0f;
+        for (int rep = 0; rep < 3 && rc == VQS_OK; rep++) {   // the first run warms up
+          if (hipMemcpyAsync(tk, src, sub * ks, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+              hipEventRecord(e0, s) != hipSuccess) {
+            rc = VQS_EHIP;
+            break;
+          }
+          const int r = sort_impl(tk, to, k, sub, key_type, ascending, &c, s);
+          if (r == VQS_EINVAL) break;          // a combination the library rejects
+          if (r != VQS_OK) {
+            rc = r;
+            break;
+          }
+          float ms = 0.0f;
+          if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+              hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = VQS_EHIP;
+            break;
+          }
+          if (rep > 0 && (t_min < 0.0f || ms < t_min)) t_min = ms;
+        }
+        if (rc == VQS_OK && t_min >= 0.0f && (best < 0.0f || t_min < best)) {
+          best = t_min;
+          chosen = c;
+        }
+      }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(tk);
+  (void)hipFree(to);
+  if (rc != VQS_OK) return rc;
+  options->solo_max = chosen.solo_max;
+  options->local_keys = chosen.local_keys;
+  options->base_case = chosen.base_case;
+  if (best_ms) *best_ms = best;
+  return VQS_OK;
+}
+
 int vqs_sort_segmented(void* keys, const int64_t* offsets, uint64_t nseg, int key_type, int ascending) {
   return vqs_sort_segmented_ex(keys, offsets, nseg, key_type, ascending, nullptr, nullptr);
 }

@@ -160,6 +160,52 @@ def sort_segmented(t: torch.Tensor, offsets: torch.Tensor, ascending: bool = Tru
     return t
 
 
+TUNED_FIELDS = ("solo_max", "local_keys", "base_case")
+
+
+def autotune_segmented(t: torch.Tensor, offsets: torch.Tensor, ascending: bool = True,
+                       key_type: int | None = None, max_keys: int = 0, cache: str | None = None,
+                       stream=None, **opts) -> dict:
+    """Run the library's autotuner (vqs_autotune_segmented) on a copy of a prefix of
+    the segments of t; returns {"solo_max", "local_keys", "base_case", "best_ms"}.
+
+    With cache (a JSON file path), a result stored for the same key type, segment
+    count, key count and device is returned without tuning, and a new result is
+    stored there.  Pass the returned settings (minus best_ms) to sort_segmented."""
+    import json
+    _check(t)
+    if offsets.dtype != torch.int64 or not offsets.is_cuda or not offsets.is_contiguous():
+        raise ValueError("offsets must be a contiguous int64 GPU tensor")
+    kt = key_type_of(t, key_type)
+    nseg = offsets.numel() - 1
+    tag = f"{kt}:{int(bool(ascending))}:{nseg}:{_nkeys(t, kt)}:{max_keys}:{torch.cuda.get_device_name(t.device)}"
+    store = {}
+    if cache and os.path.exists(cache):
+        with open(cache) as f:
+            store = json.load(f)
+        if tag in store:
+            return dict(store[tag])
+    o = make_options(**opts)
+    best = ctypes.c_float(0.0)
+    L = lib()
+    L.vqs_autotune_segmented.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
+                                         ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(Options),
+                                         ctypes.POINTER(ctypes.c_float), ctypes.c_void_p]
+    L.vqs_autotune_segmented.restype = ctypes.c_int
+    rc = L.vqs_autotune_segmented(ctypes.c_void_p(t.data_ptr()), ctypes.c_void_p(offsets.data_ptr()), nseg, kt,
+                                  int(bool(ascending)), max_keys, ctypes.byref(o), ctypes.byref(best),
+                                  ctypes.c_void_p(_stream_handle(stream)))
+    if rc != 0:
+        raise VqsError(rc, "vqs_autotune_segmented")
+    res = {k: int(getattr(o, k)) for k in TUNED_FIELDS}
+    res["best_ms"] = float(best.value)
+    if cache:
+        store[tag] = res
+        with open(cache, "w") as f:
+            json.dump(store, f, indent=1)
+    return res
+
+
 def get_stats(stream=None) -> dict:
     st = Stats()
     rc = lib().vqs_get_stats(ctypes.c_void_p(_stream_handle(stream)), ctypes.byref(st))

@@ -160,6 +160,35 @@ def test_segmented_graph_replay(vqs):
         np.testing.assert_array_equal(to_host(t), want)
 
 
+def test_autotune_segmented(vqs, tmp_path):
+    """The tuner returns one of its candidates, leaves the caller's keys alone, the
+    tuned sort matches the oracle run with the same base-case threshold (so the
+    recursion counts agree too), and a cached result is returned as stored."""
+    import torch
+    off = W.segment_offsets(1500, seed=12, lo=16, hi=1 << 16)
+    keys = W.segmented_keys(off, U32, 13)
+    t = to_gpu(keys)
+    o = to_gpu(off)
+    cache = str(tmp_path / "tune.json")
+    res = vqs.autotune_segmented(t, o, key_type=U32, max_keys=1_500_000, cache=cache)
+    torch.cuda.synchronize()
+    assert res["solo_max"] in (0, 1 << 14, 1 << 16, 1 << 18, 1 << 20)
+    assert res["base_case"] in (128, 256)
+    assert res["local_keys"] in (8192, 4096)
+    assert res["best_ms"] > 0
+    np.testing.assert_array_equal(to_host(t), keys)          # untouched
+    tuned = {k: res[k] for k in vqs.TUNED_FIELDS}
+    want = keys.copy()
+    ost = oracle.sort_segmented(want, off, U32, nb=tuned["base_case"], stats=True)
+    vqs.sort_segmented(t, o, key_type=U32, **tuned)
+    torch.cuda.synchronize()
+    assert vqs.last_error_bits() == 0
+    np.testing.assert_array_equal(to_host(t), want)
+    assert_stats_equal(ost, vqs.get_stats())
+    again = vqs.autotune_segmented(t, o, key_type=U32, max_keys=1_500_000, cache=cache)
+    assert again == res
+
+
 @pytest.mark.parametrize("n", [4, 9, 16, 20])
 def test_base_case_every_zero_one_input(vqs, n):
     import torch
