@@ -127,6 +127,22 @@ def learned_vs_plain(n: int, reps: int) -> dict:
     }
 
 
+def measured_traffic():
+    """HBM bytes per level-kernel launch (read + written) from the committed rocprofv3
+    counter runs of this workload, or None when the kernel sources have changed since
+    the counters were taken."""
+    from paper_2205_05982_amd.profile_summary import kernel_source_hash
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                        "level_kernel_u64_1e8_uniform.traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        js = json.load(f)
+    if js.get("source_hash") != kernel_source_hash():
+        return None
+    return int(js["traffic_bytes_per_launch"])
+
+
 def make_input(name: str, n: int) -> np.ndarray:
     from paper_2205_05982_amd import workloads as W
     kt, _, dist, _ = WORKLOADS[name]
@@ -256,7 +272,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": measured_traffic() if (args.workload == "c2_uniform" and n == 100_000_000) else None,
             "launches_per_step": round(levels_per_step, 2),
             # every level launch of the timed steps, empty ones included (the
             # population rocprofv3 averages over)

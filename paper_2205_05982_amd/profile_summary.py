@@ -1,0 +1,119 @@
+"""Summaries of rocprofv3 runs of bench.py: kernel times and HBM traffic.
+
+    python -m paper_2205_05982_amd.profile_summary KT_DIR FETCH_CSV WRITE_CSV OUT_MD "COMMANDS" "TITLE"
+
+KT_DIR holds the ``--kernel-trace --stats`` CSV files (kt_kernel_stats.csv,
+kt_kernel_trace.csv); FETCH_CSV and WRITE_CSV are the counter_collection.csv files
+of a ``--pmc FETCH_SIZE`` and a ``--pmc WRITE_SIZE`` run of the same command.
+Counter values are KiB per dispatch; they are scaled by what the same counter reads
+for the device-to-device copies of the input buffers that bench.py makes (a copy of
+B bytes reads and writes B bytes).  Writes OUT_MD and, beside it, a JSON file with
+the level kernel's average HBM bytes per launch and the hash of the kernel sources
+they were measured on (bench.py reports the traffic only while the hash matches).
+"""
+from __future__ import annotations
+
+import csv
+import hashlib
+import json
+import os
+import statistics
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def kernel_source_hash() -> str:
+    """sha256 of the HIP sources of the sorting kernels."""
+    d = os.path.join(HERE, "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".h", ".hip", ".inc")) and "learned" not in f:
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def _rows(path):
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def _short(n: str) -> str:
+    n = n.replace("void ", "")
+    for a, b in (("vqs::Key<64> ", "u64"), ("(vqs::Params)", ""), ("vqs::", "")):
+        n = n.replace(a, b)
+    return n[:60]
+
+
+def summarize(kt_dir, fetch_csv, write_csv, commands, title, copy_bytes=800_000_000):
+    out = [f"# {title}\n",
+           "Commands (from the repository root on the MI355X box, after `cd /tmp && export TMPDIR=/tmp`):\n"]
+    out += [f"    {c.strip()}" for c in commands.split(";;")]
+    out.append("")
+    stats = _rows(os.path.join(kt_dir, "kt_kernel_stats.csv"))
+    out.append("## Kernel time (rocprofv3 --kernel-trace --stats)\n")
+    out.append("| kernel | calls | total ms | average us | min us | max us | % |")
+    out.append("|---|---|---|---|---|---|---|")
+    for r in stats[:8]:
+        out.append(f"| {_short(r['Name'])} | {r['Calls']} | {int(r['TotalDurationNs']) / 1e6:.3f} | "
+                   f"{float(r['AverageNs']) / 1e3:.1f} | {int(r['MinNs']) / 1e3:.1f} | {int(r['MaxNs']) / 1e3:.1f} | "
+                   f"{r['Percentage']} |")
+    tr = _rows(os.path.join(kt_dir, "kt_kernel_trace.csv"))
+    lv = [r for r in tr if "level_kernel" in r["Kernel_Name"]]
+    durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in lv]
+    lv_avg_us = statistics.mean(durs) if durs else 0.0
+    out.append("")
+    out.append(f"level_kernel launches: {len(durs)}, average {lv_avg_us:.1f} us; the last step's launches (us): "
+               + ", ".join(f"{d:.0f}" for d in durs[-20:]))
+
+    f, w = _rows(fetch_csv), _rows(write_csv)
+    alg_kib = copy_bytes / 1024
+
+    def copies(rows):
+        vals = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        big = max(vals)
+        return [v for v in vals if v > 0.9 * big]
+
+    fc, wc = copies(f), copies(w)
+    ff, wf = alg_kib / statistics.mean(fc), alg_kib / statistics.mean(wc)
+    out.append("\n## HBM traffic (rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE; KiB per dispatch)\n")
+    out.append(f"Calibration: the {copy_bytes / 1e6:.0f} MB device-to-device copies of the input "
+               f"(`__amd_rocclr_copyBuffer`) read and write {alg_kib:.0f} KiB each; they report FETCH_SIZE = "
+               f"{statistics.mean(fc):.0f} KiB (factor {ff:.3f}) and WRITE_SIZE = {statistics.mean(wc):.0f} KiB "
+               f"(factor {wf:.3f}).\n")
+    lvf = [float(r["Counter_Value"]) for r in f if "level_kernel" in r["Kernel_Name"]]
+    lvw = [float(r["Counter_Value"]) for r in w if "level_kernel" in r["Kernel_Name"]]
+    full_f = [v for v in lvf if v > 0.9 * max(lvf)]
+    full_w = [v for v in lvw if v > 0.9 * max(lvw)]
+    mf, mw = statistics.mean(full_f) * ff, statistics.mean(full_w) * wf
+    out.append(f"level_kernel on a full level (every key once; algorithmic {alg_kib:.0f} KiB read + "
+               f"{alg_kib:.0f} KiB written): read {mf:.0f} KiB ({mf / alg_kib:.3f} of algorithmic), written "
+               f"{mw:.0f} KiB ({mw / alg_kib:.3f}).")
+    per_launch = (statistics.mean(lvf) * ff + statistics.mean(lvw) * wf) * 1024
+    out.append(f"Average over all {len(lvf)} level_kernel dispatches: {per_launch / 1e6:.1f} MB per launch "
+               f"(read + written, scaled).")
+    sf = [float(r["Counter_Value"]) for r in f if "solo_kernel" in r["Kernel_Name"]]
+    sw = [float(r["Counter_Value"]) for r in w if "solo_kernel" in r["Kernel_Name"]]
+    if sf:
+        out.append(f"\nsolo_kernel per launch: read {statistics.mean(sf) * ff:.0f} KiB, written "
+                   f"{statistics.mean(sw) * wf:.0f} KiB (scaled).")
+    js = {"kernel": "level_kernel", "traffic_bytes_per_launch": per_launch, "launches": len(lvf),
+          "avg_launch_us_trace": lv_avg_us, "fetch_factor": ff, "write_factor": wf,
+          "full_level_read_frac": mf / alg_kib, "full_level_write_frac": mw / alg_kib,
+          "source_hash": kernel_source_hash()}
+    return "\n".join(out) + "\n", js
+
+
+def main(argv):
+    kt_dir, fetch_csv, write_csv, out_md, commands, title = argv[1:7]
+    md, js = summarize(kt_dir, fetch_csv, write_csv, commands, title)
+    with open(out_md, "w") as f:
+        f.write(md)
+    with open(os.path.splitext(out_md)[0] + ".traffic.json", "w") as f:
+        json.dump(js, f, indent=1)
+    print(md)
+
+
+if __name__ == "__main__":
+    main(sys.argv)
