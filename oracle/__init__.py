@@ -163,6 +163,36 @@ def minmax(keys: np.ndarray, b: int, e: int, kt: int, ascending: bool = True):
     return (f, l) if kt == U128 else (f[0], l[0])
 
 
+def plain_split_sizes(keys: np.ndarray, kt: int, levels: int = 8, seed: int = 0,
+                      ascending: bool = True, nb: int = NB_DEFAULT, return_keys: bool = False):
+    """Sizes of the ranges the paper's recursion (Alg. 1) holds after `levels` rounds of
+    partitioning keys[0, n) (a copy): every range longer than the base-case size is
+    split at ChoosePivot; a degenerate split repeats with the first key in sort order
+    as pivot within the same round, and an all-equal range stays whole.  Ranges that
+    stop splitting early keep their size.  Judges a 2^levels-way splitter: these are
+    the buckets plain pivot sampling makes."""
+    a = np.ascontiguousarray(keys).copy()
+    n = nkeys(a, kt)
+    ranges = [(0, n)]
+    for _ in range(levels):
+        nxt = []
+        for b, e in ranges:
+            if e - b <= nb:
+                nxt.append((b, e))
+                continue
+            bound = partition(a, b, e, choose_pivot(a, b, e, kt, ascending, seed), kt, ascending)
+            if bound == e:
+                first, last = minmax(a, b, e, kt, ascending)
+                if np.array_equal(np.asarray(first), np.asarray(last)):
+                    nxt.append((b, e))
+                    continue
+                bound = partition(a, b, e, first, kt, ascending)
+            nxt += [(b, bound), (bound, e)]
+        ranges = nxt
+    sizes = np.array([e - b for b, e in ranges], dtype=np.int64)
+    return (sizes, a) if return_keys else sizes
+
+
 def basecase(keys: np.ndarray, kt: int, ascending: bool = True) -> None:
     _check_keys(keys, kt)
     if lib().vqo_basecase(_ptr(keys), nkeys(keys, kt), kt, int(bool(ascending))) != 0:

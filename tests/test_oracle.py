@@ -457,3 +457,32 @@ def test_median3_killer_drives_textbook_quicksort_linear():
     st = oracle.sort(got, oracle.U64, stats=True)
     assert st["heapsorts"] == 0 and st["max_depth"] < 40
     assert (got == np.arange(1, 200_001, dtype=np.uint64)).all()
+
+
+# ---- the plain splitter that judges the learned bucket map ---------------------------------
+
+U64 = W.U64
+
+def test_plain_split_sizes_partition_the_keys_in_order():
+    keys = W.lognormal_mixture_u64(300_000, 15)
+    sizes, arranged = oracle.plain_split_sizes(keys, U64, levels=6, return_keys=True)
+    assert sizes.sum() == keys.size and sizes.size <= 64 and (sizes > 0).all()
+    np.testing.assert_array_equal(np.sort(arranged), np.sort(keys))     # a permutation
+    ends = np.cumsum(sizes)
+    for i in range(sizes.size - 1):                                      # bucket i before bucket i+1
+        assert arranged[ends[i] - sizes[i]:ends[i]].max() <= arranged[ends[i]:ends[i] + sizes[i + 1]].min()
+
+
+def test_plain_split_one_level_is_one_partition():
+    keys = W.uniform_u64(100_000, 2)
+    p = oracle.choose_pivot(keys, 0, keys.size, U64)
+    sizes = oracle.plain_split_sizes(keys, U64, levels=1)
+    np.testing.assert_array_equal(sizes, [np.count_nonzero(keys <= p), np.count_nonzero(keys > p)])
+
+
+def test_plain_split_degenerate_rule_and_equal_ranges():
+    assert oracle.plain_split_sizes(np.full(10_000, 7, np.uint64), U64, levels=8).tolist() == [10_000]
+    # two values: whatever the pivot, the round ends with the two runs of equal keys
+    keys = np.array([3] * 7_000 + [9] * 5_000, dtype=np.uint64)
+    np.random.default_rng(1).shuffle(keys)
+    np.testing.assert_array_equal(oracle.plain_split_sizes(keys, U64, levels=1), [7_000, 5_000])
