@@ -103,31 +103,31 @@ struct Tile {
   __device__ static void load(const S* base_aligned, uint64_t k, uint64_t vs, uint64_t ve, int tmode,
                               R (&key)[I][V]) {
     const int tid = threadIdx.x;
+    // All chunk loads are issued, unconditionally, before any value is used, so they
+    // are in flight together (a use or a branch between them makes each wait for its
+    // predecessor).  A chunk with no key of [vs, ve) reads the nearest chunk that has
+    // one instead (always a safe address); its values are never used.
+    const uint64_t cmin = vs / V, cmax = (ve - 1) / V;
+    uint4 raw[I];
 #pragma unroll
     for (int j = 0; j < I; j++) {
-      const uint64_t c = k * TC + (uint64_t)j * P + tid;
-      const uint64_t v0 = c * V;
-      if (v0 + V > vs && v0 < ve) {
-        const uint4 raw = *reinterpret_cast<const uint4*>(reinterpret_cast<const char*>(base_aligned) + c * 16);
-        R tmp[V];
-        K::unpack(raw, tmp);
+      uint64_t c = k * TC + (uint64_t)j * P + tid;
+      c = c < cmin ? cmin : (c > cmax ? cmax : c);
+      raw[j] = *reinterpret_cast<const uint4*>(reinterpret_cast<const char*>(base_aligned) + c * 16);
+    }
 #pragma unroll
-        for (int q = 0; q < V; q++) key[j][q] = tmp[q];
-        if (tmode) {
+    for (int j = 0; j < I; j++) {
+      R tmp[V];
+      K::unpack(raw[j], tmp);
 #pragma unroll
-          for (int q = 0; q < V; q++) {
-            S s;
-            if constexpr (sizeof(S) == sizeof(R)) {
-              s = tmp[q];
-            } else {
-              s = (S)tmp[q];
-            }
-            key[j][q] = K::load_t(s, tmode);
-          }
+      for (int q = 0; q < V; q++) {
+        S s;
+        if constexpr (sizeof(S) == sizeof(R)) {
+          s = tmp[q];
+        } else {
+          s = (S)tmp[q];
         }
-      } else {
-#pragma unroll
-        for (int q = 0; q < V; q++) key[j][q] = K::maxv();
+        key[j][q] = tmode ? K::load_t(s, tmode) : tmp[q];
       }
     }
   }
@@ -215,23 +215,62 @@ struct Tile {
     return total;
   }
 
-  // Write the staged tile: left run to dst[left_base ...], right run to
-  // dst[right_base ...].  tmode != 0 applies the output transform.
+  // Write the staged tile: stage[0, nleft) to dst[left_base ...] and stage[nleft,
+  // nvalid) to dst[right_base ...].  Each run is written in 16-byte aligned chunks of
+  // the destination (v-space, off = the arrays' key offset from a 16-byte boundary),
+  // one 16-byte store per thread and chunk; only the chunks at the two ends of a run
+  // take single-key stores.  tmode != 0 applies the output transform.
   __device__ static void write_out(const S* stage, S* dst, uint32_t nleft, uint32_t nvalid,
-                                   uint64_t left_base, uint64_t right_base, int tmode, uint64_t n_total) {
+                                   uint64_t left_base, uint64_t right_base, int tmode, uint64_t n_total,
+                                   int off) {
+    write_run(stage, dst, 0, nleft, left_base, tmode, n_total, off);
+    write_run(stage, dst, nleft, nvalid - nleft, right_base, tmode, n_total, off);
+  }
+
+  // The same with one store per key (each thread writes keys s = tid, tid + P, ...):
+  // the workgroup-sequential partitions of the solo kernel measured faster this way.
+  __device__ static void write_out_keys(const S* stage, S* dst, uint32_t nleft, uint32_t nvalid,
+                                        uint64_t left_base, uint64_t right_base, int tmode, uint64_t n_total) {
     for (uint32_t s = threadIdx.x; s < nvalid; s += P) {
-      S val = stage[s];
-      if (tmode) {
-        R r;
-        if constexpr (sizeof(S) == sizeof(R)) {
-          r = val;
-        } else {
-          r = (R)val;
-        }
-        val = K::store_t(r, tmode);
-      }
       const uint64_t idx = s < nleft ? left_base + s : right_base + (s - nleft);
-      if (idx < n_total) dst[idx] = val;
+      if (idx < n_total) dst[idx] = out_t(stage[s], tmode);
+    }
+  }
+
+  __device__ static S out_t(S val, int tmode) {
+    if (!tmode) return val;
+    R r;
+    if constexpr (sizeof(S) == sizeof(R)) {
+      r = val;
+    } else {
+      r = (R)val;
+    }
+    return K::store_t(r, tmode);
+  }
+
+  __device__ static void write_run(const S* stage, S* dst, uint32_t s0, uint32_t len, uint64_t rb, int tmode,
+                                   uint64_t n_total, int off) {
+    if (len == 0) return;
+    const uint64_t vb = rb + (uint64_t)off, ve = vb + len;
+    const uint64_t c0 = vb / V, c1 = (ve + V - 1) / V;
+    char* dbase = reinterpret_cast<char*>(dst - off);   // 16-byte aligned
+    for (uint64_t c = c0 + threadIdx.x; c < c1; c += P) {
+      const uint64_t v = c * V;
+      if (v >= vb && v + V <= ve) {
+        const S* from = stage + s0 + (v - vb);
+        S tmp[V];
+#pragma unroll
+        for (int q = 0; q < V; q++) tmp[q] = out_t(from[q], tmode);
+        uint4 u;
+        __builtin_memcpy(&u, tmp, 16);
+        *reinterpret_cast<uint4*>(dbase + c * 16) = u;
+      } else {
+#pragma unroll
+        for (int q = 0; q < V; q++) {
+          const uint64_t vv = v + q;
+          if (vv >= vb && vv < ve && vv - off < n_total) dst[vv - off] = out_t(stage[s0 + (vv - vb)], tmode);
+        }
+      }
     }
   }
 };
@@ -495,7 +534,7 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
     const uint64_t excl_r = before - excl_l;
     const uint32_t nr = nvalid - nl;
     VQS_PHASE(3);
-    TL::write_out(stage, dst, nl, nvalid, sg.b + excl_l, sg.e - excl_r - nr, 0, p.n_total);
+    TL::write_out(stage, dst, nl, nvalid, sg.b + excl_l, sg.e - excl_r - nr, 0, p.n_total, p.off);
 
     if (g == g0 + ntile_seg - 1) {
       // last tile of the range: the range is partitioned; plan what follows
@@ -1406,7 +1445,7 @@ __global__ void __launch_bounds__(SOLO_P) __attribute__((amdgpu_waves_per_eu(sol
         const uint32_t nl = TL::rank_and_stage(bufA, aux, key, k, vs, ve, pivot, strict, &tmin, [](uint32_t, R) {});
         const uint32_t nvalid = (uint32_t)(ve - vs);
         const uint32_t nr = nvalid - nl;
-        TL::write_out(bufA, dst, nl, nvalid, cur.b + excl_l, cur.e - excl_r - nr, 0, p.n_total);
+        TL::write_out_keys(bufA, dst, nl, nvalid, cur.b + excl_l, cur.e - excl_r - nr, 0, p.n_total);
         excl_l += nl;
         excl_r += nr;
         if (tid == 0) mn = K::kmin(mn, tmin);

@@ -16,13 +16,13 @@ constexpr int MODE_DESC = 2;
 #define VQS_LEVEL_P 256
 #endif
 constexpr int LEVEL_P = VQS_LEVEL_P;  // threads per level-kernel workgroup
-// 16-byte chunks per thread of a level tile, by key width: as many as keep three
-// workgroups per CU (u16 keys take one register each, so their tiles are smaller):
-// 16 KB tiles for u16, 32 KB for u32, 48 KB for u64 and u128
+// 16-byte chunks per thread of a level tile, by key width (measured): 16 KB tiles for
+// u16 (its keys take one register each), 32 KB for u32, 40 KB for u64, 32 KB for u128
+// (three or four workgroups per CU)
 #ifdef VQS_LEVEL_I
 constexpr int level_chunks(int) { return VQS_LEVEL_I; }
 #else
-constexpr int level_chunks(int bits) { return bits == 16 ? 4 : bits == 32 ? 8 : 12; }
+constexpr int level_chunks(int bits) { return bits == 16 ? 4 : bits == 32 ? 8 : bits == 64 ? 10 : 8; }
 #endif
 #ifndef VQS_SOLO_P
 #define VQS_SOLO_P 512
