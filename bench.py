@@ -39,6 +39,14 @@ WORKLOADS = {
     "c2_almost": (3, 100_000_000, "almost", "1e8 u64 sorted + 1% random pair swaps"),
     "c2_m3killer": (3, 100_000_000, "m3killer", "1e8 u64 median-of-3 killer permutation"),
     "c1_u32": (2, 1_000_000, None, "1e6 u32 uniform, seed 1"),
+    "c3_f32_normal": (5, 250_000_000, "f32_normal", "2.5e8 f32 Normal(0,1), seed 7"),
+    "c3_f32_exponential": (5, 250_000_000, "f32_exponential", "2.5e8 f32 Exponential(1), seed 8"),
+    "c3_f64_uniform": (6, 100_000_000, "f64_uniform", "1e8 f64 uniform [0,1), seed 9"),
+    "c3_u16_uniform": (1, 200_000_000, "u16_uniform", "2e8 u16 uniform, seed 10"),
+    "c3_u128": (4, 50_000_000, "u128", "5e7 u128, hi over 2^16 values, seed 11"),
+    # batched: 65,536 segments with log-uniform lengths in [16, 2^20], one hipGraph
+    "c4_u32": (2, 0, "c4", "65,536 segments, lengths log-uniform [16, 2^20] (seed 12), u32 keys (seed 13)"),
+    "c4_u64": (3, 0, "c4", "65,536 segments, lengths log-uniform [16, 2^20] (seed 12), u64 keys (seed 14)"),
 }
 
 
@@ -55,7 +63,60 @@ def parse():
     ap.add_argument("--learned-n", type=int, default=500_000_000,
                     help="keys of the learned-splitter vs plain comparison (0: skip it)")
     ap.add_argument("--learned-reps", type=int, default=3)
+    ap.add_argument("--per-array", action="store_true",
+                    help="batched workloads: also time one vqs_sort call per segment")
     return ap.parse_args()
+
+
+def bench_batched(args, kt: int, desc: str) -> None:
+    """The 65,536-segment batch: keys generated on the GPU (SplitMix64 by index), the
+    whole batch sorted by one vqs_sort_segmented call captured in a hipGraph."""
+    import torch
+    from paper_2205_05982_amd import vqs
+    from paper_2205_05982_amd import workloads as W
+    off = W.segment_offsets(65536, 12)
+    n = int(off[-1])
+    bits, seed = (32, 13) if kt == 2 else (64, 14)
+    dev = torch.device("cuda", 0)
+    src = W.counter_torch(seed, 0, n, bits, dev)
+    work = torch.empty_like(src)
+    o = torch.from_numpy(off).to(dev)
+    stream = torch.cuda.current_stream()
+    times = []
+    for r in range(args.warmup + args.steps):
+        work.copy_(src)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        vqs.sort_segmented(work, o, key_type=kt, use_graph=1)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if vqs.last_error_bits():
+            raise RuntimeError(f"device error bits {vqs.last_error_bits():#x}")
+        if r >= args.warmup:
+            times.append(e0.elapsed_time(e1))
+    ms = float(np.mean(times))
+    per_array = None
+    if args.per_array:
+        work.copy_(src)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for i in range(65536):
+            vqs.sort(work[int(off[i]):int(off[i + 1])], key_type=kt)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        per_array = {"ms": round(e0.elapsed_time(e1), 1), "calls": 65536,
+                     "speedup_of_batch": round(e0.elapsed_time(e1) / ms, 1)}
+    ks = bits // 8
+    line = {
+        "metric": METRIC, "value": round(n / ms / 1e6, 4), "unit": "Gkeys/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": {2: "u32", 3: "u64"}[kt], "data": "synthetic",
+        "config": {"workload": desc, "n": n, "segments": 65536, "method": "plain, one hipGraph", "key_bytes": ks},
+        "per_array_calls": per_array,
+    }
+    print(json.dumps(line), flush=True)
 
 
 def learned_vs_plain(n: int, reps: int) -> dict:
@@ -127,6 +188,32 @@ def learned_vs_plain(n: int, reps: int) -> dict:
     }
 
 
+def check_output(out, src, kt):
+    """(sorted, same multiset) for the sorted tensor out of input src: non-decreasing
+    in the key order; equal sums and sums of squares (mod 2^64) of the keys' words."""
+    import torch
+    sign = torch.tensor(-(2**63), dtype=torch.int64, device=out.device)
+    if kt == 4:                                     # (lo, hi) pairs, compared (hi, lo)
+        ow, iw = out.view(torch.int64), src.view(torch.int64)
+        words = [(ow[:, 0], iw[:, 0]), (ow[:, 1], iw[:, 1])]
+        hi, lo = ow[:, 1] ^ sign, ow[:, 0] ^ sign
+        bad = (hi[1:] < hi[:-1]) | ((hi[1:] == hi[:-1]) & (lo[1:] < lo[:-1]))
+    else:
+        if kt in (3, 6):
+            ow, iw = out.view(torch.int64), src.view(torch.int64)
+        elif kt in (2, 5):
+            ow, iw = (t.view(torch.int32).to(torch.int64) & 0xFFFFFFFF for t in (out, src))
+        else:
+            ow, iw = (t.view(torch.int16).to(torch.int64) & 0xFFFF for t in (out, src))
+        words = [(ow, iw)]
+        okey = out if kt in (5, 6) else (ow ^ sign if kt == 3 else ow)
+        bad = okey[1:] < okey[:-1]
+    sorted_ok = not bool(bad.any().item())
+    sum_ok = all(bool((a.sum() == b.sum()).item()) and bool(((a * a).sum() == (b * b).sum()).item())
+                 for a, b in words)
+    return sorted_ok, sum_ok
+
+
 def measured_traffic():
     """HBM bytes per level-kernel launch (read + written) from the committed rocprofv3
     counter runs of this workload, or None when the kernel sources have changed since
@@ -148,6 +235,8 @@ def make_input(name: str, n: int) -> np.ndarray:
     kt, _, dist, _ = WORKLOADS[name]
     if name == "c1_u32":
         return W.uniform_u32(n, 1)
+    if name.startswith("c3_"):
+        return W.C3_CASES[dist][1](n)
     return W.c2(dist, n)
 
 
@@ -160,7 +249,10 @@ def main():
     import torch
     from paper_2205_05982_amd import vqs
 
-    kt, n_default, _, desc = WORKLOADS[args.workload]
+    kt, n_default, gen, desc = WORKLOADS[args.workload]
+    if gen == "c4":
+        bench_batched(args, kt, desc)
+        return
     n = args.n or n_default
     ks = vqs.KEY_SIZE[kt]
     dev = torch.device("cuda", 0)
@@ -207,15 +299,7 @@ def main():
 
     # correctness of the last output: sorted, same multiset as the input
     out = bufs[-1]
-    sgn = torch.tensor(-(2**63), dtype=torch.int64, device=dev) if ks == 8 else None
-    o64 = out.view(torch.int64) if ks == 8 else out.to(torch.int64)
-    i64 = src.view(torch.int64) if ks == 8 else src.to(torch.int64)
-    if ks == 8:
-        o_s = o64 ^ sgn
-    else:
-        o_s = o64
-    sorted_ok = bool((o_s[1:] >= o_s[:-1]).all().item())
-    sum_ok = bool((o64.sum() == i64.sum()).item()) and bool(((o64 * o64).sum() == (i64 * i64).sum()).item())
+    sorted_ok, sum_ok = check_output(out, src, kt)
     if not (sorted_ok and sum_ok):
         raise RuntimeError(f"bench output check failed: sorted={sorted_ok} multiset={sum_ok}")
 
@@ -236,7 +320,7 @@ def main():
             json.dump({"records": recs, "stats": stats}, f, indent=1)
 
     # free the timed buffers before the larger comparison
-    del bufs, out, o64, i64
+    del bufs, out
     torch.cuda.empty_cache()
     lvp = learned_vs_plain(args.learned_n, args.learned_reps) if args.learned_n else None
 
@@ -262,7 +346,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {2: "u32", 3: "u64"}.get(kt, str(kt)),
+        "dtype": {1: "u16", 2: "u32", 3: "u64", 4: "u128", 5: "f32", 6: "f64"}[kt],
         "data": "synthetic",
         "config": {"workload": desc, "n": n, "method": "plain", "key_bytes": ks},
         "roofline": {
