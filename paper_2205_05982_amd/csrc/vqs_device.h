@@ -259,31 +259,48 @@ __device__ inline uint64_t uniform64(uint64_t x) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-template <class K, class Load>
-__device__ typename K::R choose_pivot_wave(Load load, uint64_t b, uint64_t e, uint64_t seed) {
-  b = uniform64(b);
-  e = uniform64(e);
-  seed = uniform64(seed);
-  using R = typename K::R;
+// The nine chunk starts (keys from the range start) ChoosePivot samples for [b, e):
+// computed by each thread for its own range, so one wave can do it for 64 ranges.
+template <class K>
+__device__ inline void pivot_chunk_starts(uint64_t b, uint64_t e, uint64_t seed, uint64_t (&o)[9]) {
   constexpr int W = 64 / K::SIZE;
-  constexpr int M0 = 3 * W;               // 96, 48, 24 or 12 medians
-  constexpr int NR = (M0 + WAVE - 1) / WAVE;
-  const int lane = lane_id();
   const uint64_t nch = (e - b) / W;
   Sfc64 rng = range_rng(seed, b, e);
   uint32_t u[10];
 #pragma unroll
   for (int i = 0; i < 5; i++) {
-    uint64_t r = rng.next();
+    const uint64_t r = rng.next();
     u[2 * i] = (uint32_t)r;
     u[2 * i + 1] = (uint32_t)(r >> 32);
   }
-  // the nine chunk starts (uniform across the wave: scalar registers)
-  const uint64_t o0 = (((uint64_t)u[0] * nch) >> 32) * W, o1 = (((uint64_t)u[1] * nch) >> 32) * W,
-                 o2 = (((uint64_t)u[2] * nch) >> 32) * W, o3 = (((uint64_t)u[3] * nch) >> 32) * W,
-                 o4 = (((uint64_t)u[4] * nch) >> 32) * W, o5 = (((uint64_t)u[5] * nch) >> 32) * W,
-                 o6 = (((uint64_t)u[6] * nch) >> 32) * W, o7 = (((uint64_t)u[7] * nch) >> 32) * W,
-                 o8 = (((uint64_t)u[8] * nch) >> 32) * W;
+#pragma unroll
+  for (int i = 0; i < 9; i++) o[i] = (((uint64_t)u[i] * nch) >> 32) * W;
+}
+
+template <class K, class Load>
+__device__ typename K::R choose_pivot_from(Load load, uint64_t o0, uint64_t o1, uint64_t o2, uint64_t o3,
+                                           uint64_t o4, uint64_t o5, uint64_t o6, uint64_t o7, uint64_t o8);
+
+template <class K, class Load>
+__device__ typename K::R choose_pivot_wave(Load load, uint64_t b, uint64_t e, uint64_t seed) {
+  b = uniform64(b);
+  e = uniform64(e);
+  seed = uniform64(seed);
+  uint64_t o[9];
+  pivot_chunk_starts<K>(b, e, seed, o);
+  return choose_pivot_from<K>(load, o[0], o[1], o[2], o[3], o[4], o[5], o[6], o[7], o[8]);
+}
+
+// Lanewise medians of the nine sampled chunks, then the median reduction; the chunk
+// starts are wave-uniform.
+template <class K, class Load>
+__device__ typename K::R choose_pivot_from(Load load, uint64_t o0, uint64_t o1, uint64_t o2, uint64_t o3,
+                                           uint64_t o4, uint64_t o5, uint64_t o6, uint64_t o7, uint64_t o8) {
+  using R = typename K::R;
+  constexpr int W = 64 / K::SIZE;
+  constexpr int M0 = 3 * W;               // 96, 48, 24 or 12 medians
+  constexpr int NR = (M0 + WAVE - 1) / WAVE;
+  const int lane = lane_id();
 
   // slot m lives in lane m % 64, register m / 64
   R v[NR];

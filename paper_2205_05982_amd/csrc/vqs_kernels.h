@@ -783,6 +783,7 @@ struct LocalShared {
   LocalItem<K> list[2][LIST_CAP];
   uint32_t bc[BC_CAP];          // lb << 10 | (len-1) << 2 | fallback-mode << 1 | in B
   LocalItem<K> bounded[LIST_CAP];  // ranges past the fallback-mode limit
+  uint32_t pvoff[2][LIST_CAP][9];          // the ranges' ChoosePivot chunk starts
   typename K::R gpiv[SOLO_NW / 2], gmin[SOLO_NW];   // wave groups: pivots, part minima
   uint32_t gcnt[SOLO_NW];                  // wave groups: left counts of the parts
   uint32_t nlist[2];
@@ -896,6 +897,10 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
         it.pv = pv;
         ls.list[0][0] = it;
         ls.nlist[0] = 1;
+        uint64_t o[9];
+        pivot_chunk_starts<K>(b, e, p.seed, o);
+#pragma unroll
+        for (int i = 0; i < 9; i++) ls.pvoff[0][0][i] = (uint32_t)o[i];
       }
     }
   }
@@ -936,10 +941,13 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
       }
       return false;
     };
-    auto pick_pivot = [&](const LocalItem<K>& it, const S* s_buf) -> R {
+    // ChoosePivot from the chunk starts computed for the level's ranges in advance
+    auto pick_pivot = [&](const LocalItem<K>& it, uint32_t idx, const S* s_buf) -> R {
       if (it.flags & LI_OVERRIDE) return it.pv;
       const S* sb = s_buf + it.lb;
-      return choose_pivot_wave<K>([&](uint64_t i) -> R { return (R)sb[i]; }, b + it.lb, b + it.le, p.seed);
+      const uint32_t* o = ls.pvoff[cur][idx];
+      return choose_pivot_from<K>([&](uint64_t i) -> R { return (R)sb[i]; }, o[0], o[1], o[2], o[3], o[4], o[5],
+                                  o[6], o[7], o[8]);
     };
     // after the partition of it into d_buf ([lb, bound) left): children, equal runs,
     // statistics.  Run by one whole wave; mn is the range minimum (wave-uniform).
@@ -1050,7 +1058,7 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
 #ifdef VQS_PHASE_TIMING
         const unsigned long long q0 = wall_clock64();
 #endif
-        const R pivot = pick_pivot(it, s_buf);
+        const R pivot = pick_pivot(it, it_i, s_buf);
 #ifdef VQS_PHASE_TIMING
         const unsigned long long q1 = wall_clock64();
 #endif
@@ -1084,7 +1092,7 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
       const uint32_t per = ((len + G - 1) / G + U * WAVE - 1) / (U * WAVE) * (U * WAVE);
       auto part_b = [&](int q) { const uint32_t o = (uint32_t)q * per; return it.lb + (o < len ? o : len); };
       if (go && sw == 0) {
-        const R pv = pick_pivot(it, s_buf);
+        const R pv = pick_pivot(it, (uint32_t)item, s_buf);
         if (lane == 0) ls.gpiv[item] = pv;
       }
       __syncthreads();
@@ -1133,6 +1141,19 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
     }
     __syncthreads();
     VQS_LPH(1);
+    // the next level's ranges are known: one wave computes their ChoosePivot chunk
+    // starts, one range per lane (the random-number chain is serial per range, so
+    // this takes the time of one range instead of one per range)
+    if (wave == SOLO_NW - 1) {
+      const uint32_t nn = ls.nlist[cur ^ 1] < (uint32_t)LIST_CAP ? ls.nlist[cur ^ 1] : (uint32_t)LIST_CAP;
+      if ((uint32_t)lane < nn) {
+        const LocalItem<K> ni = ls.list[cur ^ 1][lane];
+        uint64_t o[9];
+        pivot_chunk_starts<K>(b + ni.lb, b + ni.le, p.seed, o);
+#pragma unroll
+        for (int i = 0; i < 9; i++) ls.pvoff[cur ^ 1][lane][i] = (uint32_t)o[i];
+      }
+    }
     // 3. base cases, four per wave (one per 16-lane group); they are collected over
     // recursion levels and sorted together once the list could overflow at the next
     // level or no range is left to partition
