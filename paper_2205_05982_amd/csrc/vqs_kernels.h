@@ -701,6 +701,9 @@ __global__ void __launch_bounds__(PIVOT_P) pivot_kernel(Params p) {
 template <class K, int W>
 __device__ inline void merge_stage16(typename K::R (&x)[16], int gl) {
   using R = typename K::R;
+  // A lane keeps the smaller key of its pair (up = false) or the larger (up = true):
+  // it takes the partner's key y when (y before x) differs from up; for equal keys it
+  // may take y, which is the same key.  One compare per key.
   // flip stage: lane l, register r  <->  lane l ^ (2W-1), register 15-r
   {
     const bool up = (gl & W) != 0;
@@ -708,7 +711,7 @@ __device__ inline void merge_stage16(typename K::R (&x)[16], int gl) {
 #pragma unroll
     for (int r = 0; r < 16; r++) y[r] = xor_lanes<2 * W - 1>(x[15 - r]);
 #pragma unroll
-    for (int r = 0; r < 16; r++) x[r] = up ? K::kmax(x[r], y[r]) : K::kmin(x[r], y[r]);
+    for (int r = 0; r < 16; r++) x[r] = (K::lt(y[r], x[r]) != up) ? y[r] : x[r];
   }
   // half-cleaners across lanes (distance W/2 .. 1)
   auto cross = [&](auto dtag) {
@@ -717,7 +720,7 @@ __device__ inline void merge_stage16(typename K::R (&x)[16], int gl) {
 #pragma unroll
     for (int r = 0; r < 16; r++) {
       R y = xor_lanes<D>(x[r]);
-      x[r] = up ? K::kmax(x[r], y) : K::kmin(x[r], y);
+      x[r] = (K::lt(y, x[r]) != up) ? y : x[r];
     }
   };
   if constexpr (W >= 8) cross(std::integral_constant<int, 4>{});
@@ -729,8 +732,9 @@ __device__ inline void merge_stage16(typename K::R (&x)[16], int gl) {
 #pragma unroll
     for (int r = 0; r < 16; r++)
       if ((r & d) == 0) {
-        R lo = K::kmin(x[r], x[r + d]);
-        R hi = K::kmax(x[r], x[r + d]);
+        const bool sw = K::lt(x[r + d], x[r]);
+        const R lo = sw ? x[r + d] : x[r];
+        const R hi = sw ? x[r] : x[r + d];
         x[r] = lo;
         x[r + d] = hi;
       }
@@ -741,12 +745,13 @@ template <class K>
 __device__ inline void network16x16(typename K::R (&x)[16]) {
   using R = typename K::R;
   const int gl = lane_id() & 15;
-#define VQS_CE(a, b)                 \
-  {                                  \
-    R lo_ = K::kmin(x[a], x[b]);     \
-    R hi_ = K::kmax(x[a], x[b]);     \
-    x[a] = lo_;                      \
-    x[b] = hi_;                      \
+#define VQS_CE(a, b)                     \
+  {                                      \
+    const bool sw_ = K::lt(x[b], x[a]);  \
+    const R lo_ = sw_ ? x[b] : x[a];     \
+    const R hi_ = sw_ ? x[a] : x[b];     \
+    x[a] = lo_;                          \
+    x[b] = hi_;                          \
   }
   VQS_GREEN16(VQS_CE)
 #undef VQS_CE
