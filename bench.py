@@ -220,7 +220,7 @@ def measured_traffic():
     the counters were taken."""
     from paper_2205_05982_amd.profile_summary import kernel_source_hash
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                        "level_kernel_u64_1e8_uniform.traffic.json")
+                        "level_runs_kernel_u64_1e8_uniform.traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -351,7 +351,8 @@ def main():
         "config": {"workload": desc, "n": n, "method": "plain", "key_bytes": ks},
         "roofline": {
             "bound": "hbm",
-            "kernel": "level_kernel (device-wide partition)",
+            "kernel": ("level_runs_kernel (device-wide partition into tile-local runs)" if ks >= 8
+                       else "level_kernel (device-wide partition, decoupled look-back)"),
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -65,6 +65,23 @@ enum vqs_method {
     VQS_METHOD_LEARNED = 1   /* learned 256-bucket splitter first, then the plain method */
 };
 
+/* How the device-wide partition levels place a tile's output (vqs_options.level_mode).
+ * Both give identical results and recursion counts.
+ *  - LOOKBACK: each tile finds its offsets inside its range from the left counts of
+ *    the range's earlier tiles (a decoupled look-back), and the partition is written
+ *    contiguously.
+ *  - RUNS: each tile partitions into its own interval, with no waiting.  A child range
+ *    is then held as one run per tile of its parent.  The next level gathers it
+ *    through a run table, and a range leaving for a single workgroup is first gathered
+ *    into place by one copy pass.
+ *  - AUTO: RUNS for 8- and 16-byte keys, LOOKBACK for 2- and 4-byte keys, whose
+ *    one-key gathers cost more than the look-back saves. */
+enum vqs_level_mode {
+    VQS_LEVEL_AUTO = 0,
+    VQS_LEVEL_LOOKBACK = 1,
+    VQS_LEVEL_RUNS = 2
+};
+
 /* Options of the extended entry points.  Zero-initialise and set struct_size;
  * every zero field selects the default. */
 typedef struct vqs_options {
@@ -92,7 +109,8 @@ typedef struct vqs_options {
     uint64_t model_seed;        /* seed of the model's initial weights; default 16 */
     uint64_t sample_seed;       /* seed of the 1 % chunk sample and of the minibatches;
                                    default 17 */
-    uint32_t reserved[3];
+    uint32_t level_mode;        /* enum vqs_level_mode; default VQS_LEVEL_AUTO */
+    uint32_t reserved[2];
 } vqs_options;
 
 /* Counters of the last call on a stream (copied with synchronisation).  The first

@@ -39,6 +39,7 @@ struct Key<16> {
   __device__ static R maxv() { return 0xFFFFu; }
   __device__ static R kmin(R a, R b) { return a < b ? a : b; }
   __device__ static R kmax(R a, R b) { return a < b ? b : a; }
+  __device__ static R sel(bool c, R a, R b) { return c ? a : b; }
   __device__ static R shfl(R v, int lane) { return (R)__shfl((int)v, lane); }
   __device__ static R shfl_xor(R v, int m) { return (R)__shfl_xor((int)v, m); }
   __device__ static void unpack(const uint4& c, R (&k)[V]) {
@@ -75,6 +76,7 @@ struct Key<32> {
   __device__ static R maxv() { return 0xFFFFFFFFu; }
   __device__ static R kmin(R a, R b) { return a < b ? a : b; }
   __device__ static R kmax(R a, R b) { return a < b ? b : a; }
+  __device__ static R sel(bool c, R a, R b) { return c ? a : b; }
   __device__ static R shfl(R v, int lane) { return (R)__shfl((int)v, lane); }
   __device__ static R shfl_xor(R v, int m) { return (R)__shfl_xor((int)v, m); }
   __device__ static void unpack(const uint4& c, R (&k)[V]) {
@@ -109,6 +111,7 @@ struct Key<64> {
   __device__ static R maxv() { return ~0ull; }
   __device__ static R kmin(R a, R b) { return a < b ? a : b; }
   __device__ static R kmax(R a, R b) { return a < b ? b : a; }
+  __device__ static R sel(bool c, R a, R b) { return c ? a : b; }
   __device__ static R shfl(R v, int lane) {
     return ((R)(uint32_t)__shfl((int)(uint32_t)(v >> 32), lane) << 32) |
            (uint32_t)__shfl((int)(uint32_t)v, lane);
@@ -144,8 +147,11 @@ struct Key<128> {
   __device__ static bool lt(R a, R b) { return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo); }
   __device__ static bool eq(R a, R b) { return a.hi == b.hi && a.lo == b.lo; }
   __device__ static R maxv() { return R{~0ull, ~0ull}; }
-  __device__ static R kmin(R a, R b) { return lt(b, a) ? b : a; }
-  __device__ static R kmax(R a, R b) { return lt(b, a) ? a : b; }
+  // field-wise select: a select of whole structs becomes a select of their addresses,
+  // which keeps them out of registers
+  __device__ static R sel(bool c, R a, R b) { return R{c ? a.lo : b.lo, c ? a.hi : b.hi}; }
+  __device__ static R kmin(R a, R b) { return sel(lt(b, a), b, a); }
+  __device__ static R kmax(R a, R b) { return sel(lt(b, a), a, b); }
   __device__ static R shfl(R v, int lane) { return R{Key<64>::shfl(v.lo, lane), Key<64>::shfl(v.hi, lane)}; }
   __device__ static R shfl_xor(R v, int m) {
     return R{Key<64>::shfl_xor(v.lo, m), Key<64>::shfl_xor(v.hi, m)};

@@ -27,6 +27,7 @@ struct Geometry {
   int level_grid = 2048;
   int solo_grid = 512;
   int pivot_grid = 256;
+  int plan_grid = 512;
 };
 
 struct GraphKey {
@@ -38,9 +39,11 @@ struct GraphKey {
   int64_t depth_limit;
   uint32_t nb, local;
   uint64_t solo;
+  int run_mode;
   bool operator<(const GraphKey& o) const {
-    return std::tie(keys, offsets, nseg, n, kt, asc, seed, depth_limit, nb, local, solo) <
-           std::tie(o.keys, o.offsets, o.nseg, o.n, o.kt, o.asc, o.seed, o.depth_limit, o.nb, o.local, o.solo);
+    return std::tie(keys, offsets, nseg, n, kt, asc, seed, depth_limit, nb, local, solo, run_mode) <
+           std::tie(o.keys, o.offsets, o.nseg, o.n, o.kt, o.asc, o.seed, o.depth_limit, o.nb, o.local, o.solo,
+                    o.run_mode);
   }
 };
 
@@ -127,6 +130,7 @@ Geometry geometry(int dev) {
   if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0) g.num_cu = prop.multiProcessorCount;
   g.level_grid = g.num_cu * 8;
   g.solo_grid = g.num_cu * 2;
+  g.plan_grid = g.num_cu * 2;
   g_geom[dev] = g;
   return g;
 }
@@ -174,6 +178,7 @@ struct Plan {
   uint64_t cap_lvl, cap_tiles, cap_solo;
   uint64_t seed;
   int64_t depth_limit;  // < 0: default per range, else this limit for every range
+  int run_mode;         // level partitions write tile-local runs
 };
 
 int make_plan(uint64_t n, uint64_t nseg, int kt, int asc, const vqs_options* o, const Geometry& g, Plan* pl) {
@@ -207,6 +212,11 @@ int make_plan(uint64_t n, uint64_t nseg, int kt, int asc, const vqs_options* o, 
     s = std::min<uint64_t>(s, 1ull << 20);
     pl->solo = std::max<uint64_t>(s, pl->local);
   }
+  // (level_mode is read only from a struct that holds it)
+  const bool has_lm = o && (o->struct_size == 0 || o->struct_size >= offsetof(vqs_options, level_mode) + 4);
+  const uint32_t lm = has_lm ? o->level_mode : (uint32_t)VQS_LEVEL_AUTO;
+  if (lm > VQS_LEVEL_RUNS) return VQS_EINVAL;
+  pl->run_mode = lm == VQS_LEVEL_RUNS || (lm == VQS_LEVEL_AUTO && bits >= 64);
   pl->depth_limit = -1;
   uint32_t lim = depth_limit_for(std::max<uint64_t>(n, 2));
   if (o && o->depth_limit != 0) {
@@ -217,9 +227,13 @@ int make_plan(uint64_t n, uint64_t nseg, int kt, int asc, const vqs_options* o, 
   // A range reaches the paper's depth limit by level lim (one more when the ranges are
   // seeded at level 1); past it, fallback mode may take depth_limit_for(n) more levels.
   // Levels 0 .. max_levels - 2 are launched.
-  pl->max_levels = (int)lim + (int)depth_limit_for(std::max<uint64_t>(n, 2)) + 4;
+  // (one more: in run mode a range leaving for the solo list is gathered by a copy
+  // entry of the next level)
+  pl->max_levels = (int)lim + (int)depth_limit_for(std::max<uint64_t>(n, 2)) + 5;
   const uint64_t T = level_tile_keys(bits);
-  pl->cap_lvl = n / (pl->solo + 1) + 2;
+  // a level holds at most n / (solo + 1) ranges longer than solo, and up to twice as
+  // many copy entries
+  pl->cap_lvl = 3 * (n / (pl->solo + 1)) + 4;
   pl->cap_tiles = n / T + 2 * pl->cap_lvl + 2;
   pl->cap_solo = nseg + 2ull * (uint64_t)pl->max_levels * pl->cap_lvl + n / FILL_CHUNK + 64;
   return VQS_OK;
@@ -262,6 +276,9 @@ int ensure_workspace(Workspace* ws, const Plan& pl) {
   const size_t o_ctr = take((size_t)cap_levels * sizeof(LevelCtr));
   const size_t o_flags = take(cap_tiles * 8);
   const size_t o_tmin = take(cap_tiles * sizeof(u128k));
+  const size_t o_run0 = take(cap_tiles * sizeof(TileRun));
+  const size_t o_run1 = take(cap_tiles * sizeof(TileRun));
+  const size_t o_frun = take(cap_tiles * sizeof(uint32_t));
   const size_t o_solo = take(cap_solo * sizeof(Seg));
   const size_t o_sctr = take(sizeof(SoloCtr));
   const size_t o_stats = take(sizeof(DevStats));
@@ -287,6 +304,9 @@ int ensure_workspace(Workspace* ws, const Plan& pl) {
   p.lvl_ctr = (LevelCtr*)(ws->mem + o_ctr);
   p.flags = (unsigned long long*)(ws->mem + o_flags);
   p.tilemin = (u128k*)(ws->mem + o_tmin);
+  p.runs[0] = (TileRun*)(ws->mem + o_run0);
+  p.runs[1] = (TileRun*)(ws->mem + o_run1);
+  p.frun = (uint32_t*)(ws->mem + o_frun);
   p.solo = (Seg*)(ws->mem + o_solo);
   p.solo_ctr = (SoloCtr*)(ws->mem + o_sctr);
   p.stats = (DevStats*)(ws->mem + o_stats);
@@ -326,7 +346,54 @@ hipError_t launch_all(Workspace* ws, const Params& base, const Plan& pl, const G
   if (e != hipSuccess) return e;
   // the level loop: launch levels in batches, then read the next level's counter
   int L = base.seed_level;
-  if (pl.n > pl.solo) {
+  if (pl.n > pl.solo && base.run_mode) {
+    // run mode: plan(L) plans level L-1's ranges into level L and gives level L its
+    // pivots, then level(L) partitions it; after the last level with work, one more
+    // plan routes its children
+    auto step = [&](int lv, bool part) -> hipError_t {
+      Params p = base;
+      p.level = lv;
+      hipError_t e2 = ws->timed(8, lv, [&] { return Launch<B>::plan(p, g.plan_grid, s); });
+      if (e2 != hipSuccess || !part) return e2;
+      return ws->timed(2, lv, [&] { return Launch<B>::level(p, g.level_grid, s); });
+    };
+    if (capture) {
+      for (; L < pl.max_levels - 1; L++) {
+        e = step(L, true);
+        if (e != hipSuccess) return e;
+      }
+      e = step(L, false);
+      if (e != hipSuccess) return e;
+    } else {
+      int batch = 2;
+      {
+        uint64_t x = pl.n / std::max<uint64_t>(pl.solo, 1);
+        while (x > 1) {
+          batch++;
+          x >>= 1;
+        }
+      }
+      for (;;) {
+        const int upto = std::min(L + batch, pl.max_levels - 1);
+        for (; L < upto; L++) {
+          e = step(L, true);
+          if (e != hipSuccess) return e;
+        }
+        // the last launched level had no work: nothing is left to plan
+        e = hipMemcpyAsync(ws->host_pinned, &base.lvl_ctr[L - 1].packed, 8, hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return e;
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return e;
+        if (ws->host_pinned[0] == 0) break;
+        if (L >= pl.max_levels - 1) {
+          e = step(L, false);
+          if (e != hipSuccess) return e;
+          break;
+        }
+        batch = 2;
+      }
+    }
+  } else if (pl.n > pl.solo) {
     if (capture) {
       for (; L < pl.max_levels - 1; L++) {
         Params p = base;
@@ -425,6 +492,7 @@ int prepare(Workspace* ws, void* keys, uint64_t n, uint64_t nseg, int kt, int as
   b.level = 0;
   b.seed_level = 0;
   b.fixed_limit = pl->depth_limit;
+  b.run_mode = pl->run_mode;
 #ifdef VQS_PHASE_TIMING
   static unsigned long long* dbg = nullptr;
   if (!dbg && hipMalloc(&dbg, 256) == hipSuccess) (void)hipMemset(dbg, 0, 256);
@@ -450,7 +518,7 @@ int sort_locked(Workspace* ws, void* keys, const int64_t* offsets, uint64_t nseg
   hipError_t e;
   const bool use_graph = o && o->use_graph && offsets;
   if (use_graph) {
-    GraphKey gk{keys, offsets, nseg, n, kt, asc, pl.seed, pl.depth_limit, pl.nb, pl.local, pl.solo};
+    GraphKey gk{keys, offsets, nseg, n, kt, asc, pl.seed, pl.depth_limit, pl.nb, pl.local, pl.solo, pl.run_mode};
     if (!(ws->graph_valid && !(gk < ws->graph_key) && !(ws->graph_key < gk))) {
       if (ws->graph) {
         (void)hipGraphExecDestroy(ws->graph);
@@ -789,7 +857,8 @@ uint64_t vqs_workspace_bytes(uint64_t n, uint64_t nseg, int key_type, const vqs_
   if (make_plan(n, nseg ? nseg : 1, key_type, 1, options, g, &pl) != VQS_OK) return 0;
   uint64_t b = (n + 32) * (uint64_t)pl.ks + 64;
   b += 2 * pl.cap_lvl * (sizeof(Seg) + 8) + (uint64_t)pl.max_levels * sizeof(LevelCtr);
-  b += pl.cap_tiles * (8 + sizeof(u128k)) + pl.cap_solo * sizeof(Seg) + 4096;
+  b += pl.cap_tiles * (8 + sizeof(u128k) + 2 * sizeof(TileRun) + sizeof(uint32_t)) + pl.cap_solo * sizeof(Seg) +
+       4096;
   return b;
 }
 

@@ -287,50 +287,104 @@ __device__ inline void push_solo(const Params& p, const Seg& s) {
   atomicAdd(&p.stats->solo_items, 1ull);
 }
 
-template <class K, int T>
-__device__ inline void push_level(const Params& p, int next_level, const Seg& s) {
+// A place in a level's range list and its tiles (idx = ~0 on overflow, error set).
+template <int T>
+__device__ inline void reserve_level(const Params& p, int next_level, const Seg& s, unsigned long long& idx,
+                                     unsigned long long& tb) {
+  idx = ~0ull;
+  tb = 0;
   if (next_level >= p.max_levels - 1) {   // the last level is never launched
     set_err(p, ERR_LEVEL_OVERFLOW);
     return;
   }
   const unsigned long long nt = tiles_of(s.b, s.e, p.off, (uint64_t)T);
   const unsigned long long old = atomicAdd(&p.lvl_ctr[next_level].packed, (1ull << 40) | nt);
-  const unsigned long long idx = old >> 40, tb = old & TILE_MASK40;
-  if (idx >= p.cap_lvl || tb + nt > p.cap_tiles) {
+  if ((old >> 40) >= p.cap_lvl || (old & TILE_MASK40) + nt > p.cap_tiles) {
     set_err(p, ERR_LEVEL_OVERFLOW);
     return;
   }
+  idx = old >> 40;
+  tb = old & TILE_MASK40;
+}
+
+__device__ inline void write_level(const Params& p, int next_level, const Seg& s, unsigned long long idx,
+                                   unsigned long long tb) {
   p.lvl_segs[next_level & 1][idx] = s;
   p.lvl_tbase[next_level & 1][idx] = tb;
   atomicAdd(&p.lvl_ctr[next_level].keys, (unsigned long long)(s.e - s.b));
+}
+
+template <class K, int T>
+__device__ inline void push_level(const Params& p, int next_level, const Seg& s) {
+  unsigned long long idx, tb;
+  reserve_level<T>(p, next_level, s, idx, tb);
+  if (idx != ~0ull) write_level(p, next_level, s, idx, tb);
 }
 
 // Route a range after a partition: short ranges go to the solo list (which checks
 // their depth itself), long ones to the next level.  A long range past the paper's
 // depth limit continues in fallback mode (counted once as the paper's fallback of
 // its length); past the fallback mode's own limit it takes the bounded-time sort.
+//
+// A range held as runs (run mode) reaches the solo list through a copy entry of the
+// next level, which gathers its runs into [b, e) of that level's destination before
+// later levels overwrite them.
 template <class K, int T>
-__device__ inline void route(const Params& p, Seg s, int next_level) {
-  const uint64_t len = s.e - s.b;
-  if (len == 0) return;
-  if (len <= p.solo_max) {
-    push_solo(p, s);
-    return;
+__device__ inline void to_solo(const Params& p, Seg s, int next_level) {
+  if (s.flags & SEG_RUNS) {
+    Seg c = s;
+    c.flags = (s.flags & (SEG_RUNS | SEG_RIGHT)) | SEG_COPY;
+    push_level<K, T>(p, next_level, c);
+    const uint32_t keep = SEG_OVERRIDE | SEG_FALLBACK | SEG_BOUNDED | SEG_STRICT;
+    s.flags = (s.flags & keep) | ((next_level & 1) ? 0u : SEG_SCRATCH);
   }
-  if (s.depth > s.limit) {
+  push_solo(p, s);
+}
+
+// Where a range goes (the decision only, so that a caller can still give a range
+// bound for a level its pivot), then the pushes and counts.
+enum : int { RT_NONE = 0, RT_SOLO = 1, RT_LEVEL = 2 };
+struct Routed {
+  Seg s;
+  int dest;
+  bool fb_enter;   // enters fallback mode here (counted as the paper's fallback)
+};
+
+__device__ inline Routed route_decide(const Params& p, Seg s) {
+  Routed r{s, RT_LEVEL, false};
+  const uint64_t len = s.e - s.b;
+  constexpr uint32_t RUNBITS = SEG_RUNS | SEG_RIGHT;
+  if (len == 0) {
+    r.dest = RT_NONE;
+  } else if (len <= p.solo_max) {
+    r.dest = RT_SOLO;
+  } else if (s.depth > s.limit) {
     if (!(s.flags & SEG_FALLBACK)) {
-      atomicAdd(&p.stats->fallbacks, 1ull);
-      atomicAdd(&p.stats->fallback_keys, (unsigned long long)len);
-      s.flags = (s.flags & SEG_SCRATCH) | SEG_FALLBACK;
-      s.depth = 1;
-      s.limit = depth_limit_of(len);
+      r.fb_enter = true;
+      r.s.flags = (s.flags & (SEG_SCRATCH | RUNBITS)) | SEG_FALLBACK;
+      r.s.depth = 1;
+      r.s.limit = depth_limit_of(len);
     } else {
-      s.flags = (s.flags & SEG_SCRATCH) | SEG_FALLBACK | SEG_BOUNDED;
-      push_solo(p, s);
-      return;
+      r.s.flags = (s.flags & (SEG_SCRATCH | RUNBITS)) | SEG_FALLBACK | SEG_BOUNDED;
+      r.dest = RT_SOLO;
     }
   }
-  push_level<K, T>(p, next_level, s);
+  return r;
+}
+
+template <class K, int T>
+__device__ inline void route_commit(const Params& p, const Routed& r, int next_level) {
+  if (r.fb_enter) {
+    atomicAdd(&p.stats->fallbacks, 1ull);
+    atomicAdd(&p.stats->fallback_keys, (unsigned long long)(r.s.e - r.s.b));
+  }
+  if (r.dest == RT_SOLO) to_solo<K, T>(p, r.s, next_level);
+  else if (r.dest == RT_LEVEL) push_level<K, T>(p, next_level, r.s);
+}
+
+template <class K, int T>
+__device__ inline void route(const Params& p, Seg s, int next_level) {
+  route_commit<K, T>(p, route_decide(p, s), next_level);
 }
 
 template <class K>
@@ -638,6 +692,794 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
 #endif
 }
 
+// ---- run mode: ranges held as runs of the previous level's tiles --------------------
+//
+// In run mode a level tile writes its partition into its own interval of the
+// destination (left keys in input order, then the right keys in reverse input order),
+// so no tile waits for another.  A child range is then the concatenation of one run
+// per tile of its parent: the left child takes the tiles' left parts in tile order,
+// the right child their right parts in reverse tile order.  That is the key sequence
+// the contiguous partition writes, so pivots and the recursion are unchanged.  The
+// parent's last tile records every tile's run starts inside both children (TileRun).
+
+// start (child-relative) of run u of a run-held range, and the source position of its
+// first key
+__device__ inline void run_info(const TileRun* tab, const Seg& s, uint64_t u, uint64_t& start, uint64_t& first) {
+  const bool right = (s.flags & SEG_RIGHT) != 0;
+  const TileRun& r = tab[right ? (uint64_t)s.rt_b + (s.rt_n - 1 - u) : (uint64_t)s.rt_b + u];
+  start = right ? r.rp : r.lp;
+  first = right ? r.pos + r.nl : r.pos;
+}
+
+__device__ inline uint64_t run_start(const TileRun* tab, const Seg& s, uint64_t u) {
+  const bool right = (s.flags & SEG_RIGHT) != 0;
+  return right ? tab[(uint64_t)s.rt_b + (s.rt_n - 1 - u)].rp : tab[(uint64_t)s.rt_b + u].lp;
+}
+
+// source position of key j (child-relative) of a run-held range: the last run starting
+// at or before j (runs may be empty; the last one starting at or before a valid j is not)
+__device__ inline uint64_t run_pos(const TileRun* tab, const Seg& s, uint64_t j, uint64_t lo = 0) {
+  uint64_t hi = s.rt_n;
+  while (hi - lo > 1) {
+    const uint64_t mid = (lo + hi) / 2;
+    if (run_start(tab, s, mid) <= j) lo = mid;
+    else hi = mid;
+  }
+  uint64_t st, first;
+  run_info(tab, s, lo, st, first);
+  return first + (j - st);
+}
+
+__device__ inline uint64_t wave_incl_scan64(uint64_t v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+    const uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)v, d);
+    const uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(v >> 32), d);
+    if (lane >= d) v += ((uint64_t)hi << 32) | lo;
+  }
+  return v;
+}
+
+// one entry per run a tile touches: key at tile slot s of run i sits at mbase + s
+struct RunEnt {
+  int64_t mbase;
+  int32_t rst;   // first tile slot of the run (0 for the run holding slot 0)
+  int32_t pad;
+};
+
+// Level partition in run mode: the same tiles, classification, ranks and LDS staging
+// as level_kernel, but each tile writes its interval [vs, ve) of the destination, so
+// there is no look-back.  A tile of a run-held range reads its keys through the runs
+// (the runs it touches are listed in LDS first).  Each tile leaves its left count and
+// minimum; runs_plan_kernel plans the ranges afterwards.  Copy entries only gather
+// their runs into [b, e) for the solo kernel.
+template <class K>
+__global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(sizeof(typename K::R) >= 8 ? LEVEL_WAVES : 1))) level_runs_kernel(Params p) {
+  using R = typename K::R;
+  using S = typename K::S;
+  constexpr int I = level_chunks(8 * K::SIZE);
+  using TL = Tile<K, LEVEL_P, I>;
+  constexpr int T = TL::T;
+  constexpr int TC = TL::TC;
+  constexpr int V = K::V;
+  constexpr int NW = LEVEL_P / WAVE;
+  constexpr int RMAX = (int)(T * sizeof(S) / sizeof(RunEnt));
+  __shared__ __align__(16) S stage[T];
+  __shared__ typename TL::Aux sh;
+  __shared__ unsigned long long sh_ticket;
+  __shared__ int sh_seg;
+  RunEnt* ent = reinterpret_cast<RunEnt*>(stage);
+
+  const int L = p.level;
+  const unsigned long long packed = p.lvl_ctr[L].packed;
+  const uint32_t nseg = (uint32_t)(packed >> 40);
+  const unsigned long long ntiles = packed & TILE_MASK40;
+  if (ntiles == 0) return;
+  Seg* segs = p.lvl_segs[L & 1];
+  const unsigned long long* tbase = p.lvl_tbase[L & 1];
+  const bool src_scratch = (L & 1) != 0;
+  const S* src = (const S*)(src_scratch ? p.scratch : p.keys);
+  S* dst = (S*)(src_scratch ? p.keys : p.scratch);
+  const S* src_aligned = src - p.off;
+  const int tmode = (L == 0) ? p.mode : 0;   // only the first level reads untransformed keys
+  const TileRun* prev = p.runs[(L + 1) & 1];
+  TileRun* cur = p.runs[L & 1];
+  const int tid = threadIdx.x;
+  const int w = tid / WAVE;
+  unsigned long long tiles_done = 0;
+
+  for (;;) {
+    if (tid == 0) sh_ticket = atomicAdd(&p.lvl_ctr[L].ticket, 1u);
+    __syncthreads();
+    const unsigned long long g = sh_ticket;
+    if (g >= ntiles) break;
+    if (tid < WAVE) {
+      uint32_t lo = 0, hi = nseg;  // invariant: tbase[lo] <= g, and g < tbase[hi] if hi < nseg
+      while (hi - lo > 1) {
+        const uint32_t span = hi - lo;
+        const uint32_t step = (span + WAVE - 1) / WAVE;
+        const uint32_t pos = lo + (uint32_t)tid * step;
+        const bool le = pos < hi && tbase[pos] <= g;
+        const uint64_t m = ballot(le);   // lane 0 always true
+        const int last = 63 - __builtin_clzll(m);
+        const uint32_t nlo = lo + (uint32_t)last * step;
+        const uint32_t nhi = (nlo + step < hi) ? nlo + step : hi;
+        lo = nlo;
+        hi = nhi;
+      }
+      if (tid == 0) sh_seg = (int)lo;
+    }
+    __syncthreads();
+    const int si = sh_seg;
+    const Seg sg = segs[si];
+    const unsigned long long g0 = tbase[si];
+    const uint64_t nt = tiles_of(sg.b, sg.e, p.off, T);
+    const uint64_t k = (sg.b + p.off) / T + (g - g0);
+    const uint64_t vs = (k * T > sg.b + p.off) ? k * T : sg.b + p.off;
+    const uint64_t ve = ((k + 1) * T < sg.e + p.off) ? (k + 1) * T : sg.e + p.off;
+    const uint32_t nvalid = (uint32_t)(ve - vs);
+
+    R key[I][V];
+    if (!(sg.flags & SEG_RUNS)) {
+      TL::load(src_aligned, k, vs, ve, tmode, key);
+    } else {
+      // the runs the tile touches into LDS (from the first one, recorded by the
+      // planning launch), then every key from its run
+      const uint64_t j0 = vs - p.off - sg.b, j1 = j0 + nvalid;
+      const uint64_t u0 = p.frun[g];   // recorded by the planning launch
+      uint32_t nr = 0;
+      for (uint32_t r = 0;; r++) {
+        const uint64_t u = u0 + (uint64_t)r * LEVEL_P + tid;
+        bool in = false;
+        if (u < sg.rt_n) {
+          uint64_t st, first;
+          run_info(prev, sg, u, st, first);
+          in = st < j1 || u == u0;
+          const uint32_t idx = r * LEVEL_P + tid;
+          if (in && idx < (uint32_t)RMAX) {
+            ent[idx].rst = st <= j0 ? 0 : (int32_t)(st - j0);
+            ent[idx].mbase = (int64_t)first - (int64_t)st + (int64_t)j0;
+          }
+        }
+        const int cnt = __syncthreads_count(in);
+        nr += (uint32_t)cnt;
+        if (cnt < LEVEL_P) break;
+      }
+      S raw[I][V];
+      if (nr <= (uint32_t)RMAX) {
+        // a thread's slots increase with (j, q): walk the run list forward
+        int i = 0;
+        int32_t nxt = nr > 1 ? ent[1].rst : INT32_MAX;
+        int64_t mb = ent[0].mbase;
+#pragma unroll
+        for (int j = 0; j < I; j++) {
+#pragma unroll
+          for (int q = 0; q < V; q++) {
+            const uint64_t v = (k * TC + (uint64_t)j * LEVEL_P + tid) * V + q;
+            const int32_t sl = v < vs ? 0 : (v >= ve ? (int32_t)nvalid - 1 : (int32_t)(v - vs));
+            while (sl >= nxt) {
+              i++;
+              mb = ent[i].mbase;
+              nxt = (i + 1 < (int)nr) ? ent[i + 1].rst : INT32_MAX;
+            }
+            raw[j][q] = src[mb + sl];
+          }
+        }
+      } else {
+        // more runs than the LDS list holds: search each key's run, in sequence into
+        // LDS, then read the tile from there
+        for (uint32_t sl = tid; sl < nvalid; sl += LEVEL_P) stage[sl] = src[run_pos(prev, sg, j0 + sl, u0)];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < I; j++) {
+#pragma unroll
+          for (int q = 0; q < V; q++) {
+            const uint64_t v = (k * TC + (uint64_t)j * LEVEL_P + tid) * V + q;
+            raw[j][q] = stage[v < vs ? 0 : (v >= ve ? nvalid - 1 : v - vs)];
+          }
+        }
+      }
+      if (sg.flags & SEG_COPY) {
+        // gather only: the keys in sequence to [vs, ve) of the destination
+        char* dbase = reinterpret_cast<char*>(dst - p.off);
+#pragma unroll
+        for (int j = 0; j < I; j++) {
+          const uint64_t c = k * TC + (uint64_t)j * LEVEL_P + tid;
+          const uint64_t v0 = c * V;
+          if (v0 >= vs && v0 + V <= ve) {
+            uint4 u;
+            __builtin_memcpy(&u, raw[j], 16);
+            *reinterpret_cast<uint4*>(dbase + c * 16) = u;
+          } else {
+#pragma unroll
+            for (int q = 0; q < V; q++)
+              if (v0 + q >= vs && v0 + q < ve) dst[v0 + q - p.off] = raw[j][q];
+          }
+        }
+        tiles_done++;
+        __syncthreads();   // the LDS run list is read before the next tile rewrites it
+        continue;
+      }
+#pragma unroll
+      for (int j = 0; j < I; j++) {
+#pragma unroll
+        for (int q = 0; q < V; q++) {
+          if constexpr (sizeof(S) == sizeof(R)) {
+            key[j][q] = raw[j][q];
+          } else {
+            key[j][q] = (R)raw[j][q];
+          }
+        }
+      }
+    }
+    // the pivot kernel gave every range of the level its pivot
+    if (tid == 0) {
+      sh.pivot = K::from_u64x2(sg.pv_lo, sg.pv_hi);
+      if (!(sg.flags & SEG_PIVOT)) set_err(p, ERR_NO_PIVOT);
+    }
+    __syncthreads();   // also: the LDS run list is read before the keys are staged over it
+    const R pivot = sh.pivot;
+    R tmin;
+    // the tile's left count and minimum, for the planning launch after this one
+    const uint32_t nl = TL::rank_and_stage(stage, sh, key, k, vs, ve, pivot, (sg.flags & SEG_STRICT) != 0, &tmin,
+                                           [&](uint32_t cnt, R m) {
+                                             uint64_t lo, hi;
+                                             to_words<K>(m, lo, hi);
+                                             p.tilemin[g].lo = lo;
+                                             p.tilemin[g].hi = hi;
+                                             cur[g].nl = cnt;
+                                           });
+    TL::write_out(stage, dst, nl, nvalid, vs - p.off, vs - p.off + nl, 0, p.n_total, p.off);
+    tiles_done++;
+    __syncthreads();
+  }
+  if (tid == 0 && tiles_done) atomicAdd(&p.stats->level_tiles, tiles_done);
+}
+
+// ---- run mode: planning ------------------------------------------------------------
+
+template <class K>
+struct PlanShared {
+  static constexpr int W = 64 / K::SIZE;   // keys per ChoosePivot chunk
+  unsigned long long wsum[LEVEL_P / WAVE];
+  uint64_t o[2][9];                       // the children's ChoosePivot chunk starts
+  uint64_t spos[2][9 * W];                // source positions of their sampled keys
+  typename K::R wmin[LEVEL_P / WAVE];
+  typename K::R pv[2];
+  typename K::R samp[2][9 * W];           // the sampled keys
+};
+
+// recursion counts of a planning group, added to the device totals once per workgroup
+struct PlanCounts {
+  unsigned long long part, pkeys, maxd, deg, alleq, fbpart, fbs, fbkeys, solo, lvlkeys;
+};
+
+// What the first half of a range's planning leaves for the second: the thread's left
+// keys before its tiles and in them, the range's left count, the routed children, the fills, and
+// what the range needs of the level and solo lists (reserved in between, for several
+// ranges at once).
+struct PlanState {
+  uint64_t lp0, myl, ltot;
+  Routed r0, r1;
+  uint64_t fill_b, fill_e, nfill, nsolo, nt0, nt1;
+  uint32_t ne;   // level entries (0, 1 or 2)
+  bool degenerate, all_equal, piv0, piv1;
+};
+
+// where the reservations put a range's entries
+struct PlanSlots {
+  unsigned long long idx, tb, solo;   // idx = ~0: no level entries (or an overflow)
+};
+
+// a range record made wave-uniform (scalar registers)
+__device__ inline Seg uniform_seg(const Seg& s) {
+  Seg u;
+  const uint32_t* a = reinterpret_cast<const uint32_t*>(&s);
+  uint32_t* b = reinterpret_cast<uint32_t*>(&u);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(Seg) / 4); i++) b[i] = __builtin_amdgcn_readfirstlane(a[i]);
+  return u;
+}
+
+// barrier of a planning group: the workgroup, or one wave
+template <int G>
+__device__ inline void gsync() {
+  if constexpr (G == WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+template <int G>
+__device__ inline uint64_t group_excl_scan(uint64_t v, uint64_t& total, unsigned long long* wsum, int gt) {
+  const uint64_t incl = wave_incl_scan64(v);
+  if constexpr (G == WAVE) {
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)incl, WAVE - 1);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(incl >> 32), WAVE - 1);
+    total = uniform64(((uint64_t)hi << 32) | lo);
+    return incl - v;
+  } else {
+    const int w = gt / WAVE;
+    if ((gt & (WAVE - 1)) == WAVE - 1) wsum[w] = incl;
+    __syncthreads();
+    uint64_t ex = incl - v;
+    total = 0;
+#pragma unroll
+    for (int ww = 0; ww < G / WAVE; ww++) {
+      ex += (ww < w) ? wsum[ww] : 0ull;
+      total += wsum[ww];
+    }
+    total = uniform64(total);
+    __syncthreads();
+    return ex;
+  }
+}
+
+// one reservation of the level list and one of the solo list for a batch of ranges
+// (thread 0); returns the first slots
+__device__ inline PlanSlots plan_reserve(const Params& p, int L, unsigned long long ne, unsigned long long ntiles,
+                                         unsigned long long nsolo) {
+  PlanSlots r{~0ull, 0, 0};
+  if (ne) {
+    if (L >= p.max_levels - 1) {   // the last level is never launched
+      set_err(p, ERR_LEVEL_OVERFLOW);
+    } else {
+      const unsigned long long old = atomicAdd(&p.lvl_ctr[L].packed, (ne << 40) | ntiles);
+      if ((old >> 40) + ne > p.cap_lvl || (old & TILE_MASK40) + ntiles > p.cap_tiles) {
+        set_err(p, ERR_LEVEL_OVERFLOW);
+      } else {
+        r.idx = old >> 40;
+        r.tb = old & TILE_MASK40;
+      }
+    }
+  }
+  if (nsolo) r.solo = atomicAdd(&p.solo_ctr->count, nsolo);
+  return r;
+}
+
+// Planning of one range of level L-1 after its partition, by a group of G threads
+// (the workgroup, or one wave for a range of few tiles); gt is the thread's index in
+// the group.  First half: the tiles' left counts give the bound; the children are
+// routed as in level_kernel.
+template <class K, int G>
+__device__ PlanState plan_first(const Params& p, int L, const Seg& sg, uint64_t g0, uint64_t nt, PlanShared<K>& sm,
+                                int gt) {
+  using R = typename K::R;
+  constexpr int I = level_chunks(8 * K::SIZE);
+  constexpr int T = Tile<K, LEVEL_P, I>::T;
+  const TileRun* tab = p.runs[(L - 1) & 1];
+  const bool dst_scratch = ((L - 1) & 1) == 0;   // where level L-1 wrote
+  const R pivot = K::from_u64x2(sg.pv_lo, sg.pv_hi);
+  PlanState st{};
+  // the range's left count (each thread a block of consecutive tiles)
+  const uint64_t per = (nt + G - 1) / G;
+  const uint64_t ta = (uint64_t)gt * per < nt ? (uint64_t)gt * per : nt;
+  const uint64_t tb = ta + per < nt ? ta + per : nt;
+  constexpr int QB = G == WAVE ? 4 : 16;   // counts read per batch, all in flight
+  uint64_t sl = 0;
+  for (uint64_t a = ta; a < tb; a += QB) {
+    uint32_t cv[QB];
+#pragma unroll
+    for (int q = 0; q < QB; q++) cv[q] = tab[g0 + ((a + q < tb) ? a + q : a)].nl;
+#pragma unroll
+    for (int q = 0; q < QB; q++) sl += (a + q < tb) ? cv[q] : 0u;
+  }
+  st.lp0 = group_excl_scan<G>(sl, st.ltot, sm.wsum, gt);
+  st.myl = sl;
+  const uint64_t bound = sg.b + st.ltot;
+  const bool fb = (sg.flags & SEG_FALLBACK) != 0;
+  const uint32_t cf = (dst_scratch ? SEG_SCRATCH : 0u) | (fb ? SEG_FALLBACK : 0u);
+  // the children (child 0 holds the tiles' left parts, child 1 their right parts)
+  auto child = [&](uint64_t b, uint64_t e, uint32_t flags, R pv, bool right) {
+    Seg c = make_seg<K>(b, e, sg.depth + 1, sg.limit, flags | SEG_RUNS | (right ? SEG_RIGHT : 0u), pv);
+    c.rt_b = (uint32_t)g0;
+    c.rt_n = (uint32_t)nt;
+    return c;
+  };
+  int nc = 0;
+  Seg c0{}, c1{};
+  if (sg.flags & SEG_STRICT) {
+    // fallback mode after a degenerate partition: [b, bound) holds the keys before
+    // the pivot, [bound, e) the keys equal to it
+    st.fill_b = bound;
+    st.fill_e = sg.e;
+    c0 = child(sg.b, bound, cf, pivot, false);
+    nc = 1;
+  } else if (bound == sg.e && !fb) {
+    // degenerate: the minimum of the range decides (Alg. 1, ScanMinMax)
+    st.degenerate = true;
+    R m = K::maxv();
+    for (uint64_t t = g0 + gt; t < g0 + nt; t += G) m = K::kmin(m, K::from_u64x2(p.tilemin[t].lo, p.tilemin[t].hi));
+    m = wave_min<K>(m);
+    R mn = m;
+    if constexpr (G != WAVE) {
+      if ((gt & (WAVE - 1)) == 0) sm.wmin[gt / WAVE] = m;
+      __syncthreads();
+      mn = sm.wmin[0];
+#pragma unroll
+      for (int ww = 1; ww < G / WAVE; ww++) mn = K::kmin(mn, sm.wmin[ww]);
+      __syncthreads();
+    }
+    if (K::eq(mn, pivot)) {
+      st.all_equal = true;
+      st.fill_b = sg.b;
+      st.fill_e = sg.e;
+    } else {
+      c0 = child(sg.b, sg.e, cf | SEG_OVERRIDE | SEG_PIVOT, mn, false);
+      nc = 1;
+    }
+  } else if (bound == sg.e) {
+    // fallback mode, degenerate: split off the keys equal to the pivot (the maximum)
+    c0 = child(sg.b, sg.e, cf | SEG_OVERRIDE | SEG_PIVOT | SEG_STRICT, pivot, false);
+    nc = 1;
+  } else {
+    c0 = child(sg.b, bound, cf, pivot, false);
+    c1 = child(bound, sg.e, cf, pivot, true);
+    nc = 2;
+  }
+  st.r0 = route_decide(p, c0);
+  st.r1 = route_decide(p, c1);
+  if (nc < 1) st.r0.dest = RT_NONE;
+  if (nc < 2) st.r1.dest = RT_NONE;
+  // every child is held as runs: each gets tiles at level L (itself, or its copy entry)
+  st.ne = (st.r0.dest != RT_NONE ? 1u : 0u) + (st.r1.dest != RT_NONE ? 1u : 0u);
+  st.nt0 = st.r0.dest != RT_NONE ? tiles_of(st.r0.s.b, st.r0.s.e, p.off, T) : 0;
+  st.nt1 = st.r1.dest != RT_NONE ? tiles_of(st.r1.s.b, st.r1.s.e, p.off, T) : 0;
+  st.piv0 = st.r0.dest == RT_LEVEL && !(st.r0.s.flags & SEG_PIVOT);
+  st.piv1 = st.r1.dest == RT_LEVEL && !(st.r1.s.flags & SEG_PIVOT);
+  st.nfill = st.fill_e > st.fill_b ? (st.fill_e - st.fill_b + FILL_CHUNK - 1) / FILL_CHUNK : 0;
+  st.nsolo = (st.r0.dest == RT_SOLO ? 1 : 0) + (st.r1.dest == RT_SOLO ? 1 : 0) + st.nfill;
+  return st;
+}
+
+// Second half: every tile's run starts in the children (TileRun); the first run of
+// each child tile at level L; ChoosePivot of each child bound for level L without a
+// given pivot (its nine chunk starts are drawn, the pass over the tiles records where
+// the sampled keys sit, then they are read together); the level and solo entries at
+// the reserved slots; counts go to pc (thread 0 of the group).
+template <class K, int G>
+__device__ void plan_second(const Params& p, int L, const Seg& sg, uint64_t g0, uint64_t nt, PlanShared<K>& sm,
+                            int gt, const PlanState& st, const PlanSlots& sl_, PlanCounts& pc) {
+  using R = typename K::R;
+  using S = typename K::S;
+  constexpr int I = level_chunks(8 * K::SIZE);
+  constexpr int T = Tile<K, LEVEL_P, I>::T;
+  constexpr int W = PlanShared<K>::W;
+  TileRun* tab = p.runs[(L - 1) & 1];
+  const S* src_next = (const S*)((L & 1) ? p.scratch : p.keys);   // what level L reads
+  const R pivot = K::from_u64x2(sg.pv_lo, sg.pv_hi);
+  const uint64_t off = (uint64_t)p.off;
+  const bool fb = (sg.flags & SEG_FALLBACK) != 0;
+  const Routed& r0 = st.r0;
+  const Routed& r1 = st.r1;
+  const bool ok = sl_.idx != ~0ull;
+  const bool have0 = r0.dest != RT_NONE && ok, have1 = r1.dest != RT_NONE && ok;
+  const uint64_t tb_0 = sl_.tb, tb_1 = sl_.tb + st.nt0;
+  if (gt < 2 && (gt == 0 ? st.piv0 : st.piv1)) {
+    const Seg& cc = gt == 0 ? r0.s : r1.s;
+    uint64_t o[9];
+    pivot_chunk_starts<K>(cc.b, cc.e, p.seed, o);
+#pragma unroll
+    for (int i = 0; i < 9; i++) sm.o[gt][i] = o[i];
+  }
+  gsync<G>();
+  const uint64_t per = (nt + G - 1) / G;
+  const uint64_t ta = (uint64_t)gt * per < nt ? (uint64_t)gt * per : nt;
+  const uint64_t tb = ta + per < nt ? ta + per : nt;
+  const uint64_t rtot = (sg.e - sg.b) - st.ltot;
+  // the sampled chunks that meet this thread's part of each child: its left parts are
+  // [lp0, lp0 + its left keys) of child 0, its right parts [rlo, rhi) of child 1
+  uint32_t cm0 = 0, cm1 = 0;
+  if (st.piv0 || st.piv1) {
+    const uint64_t kb = (sg.b + off) / T;
+    const uint64_t kbs = (kb + ta) * T > sg.b + off ? (kb + ta) * T : sg.b + off;
+    const uint64_t kbe = (kb + tb) * T < sg.e + off ? (kb + tb) * T : sg.e + off;
+    const uint64_t mine = tb > ta ? kbe - kbs : 0;                        // keys of my tiles
+    const uint64_t before = tb > ta ? kbs - (sg.b + off) : 0;             // keys of earlier tiles
+    const uint64_t myl = st.myl;
+    const uint64_t rhi = rtot - (before - st.lp0), rlo = rhi - (mine - myl);
+#pragma unroll
+    for (int ch = 0; ch < 9; ch++) {
+      if (st.piv0 && sm.o[0][ch] < st.lp0 + myl && sm.o[0][ch] + W > st.lp0) cm0 |= 1u << ch;
+      if (st.piv1 && sm.o[1][ch] < rhi && sm.o[1][ch] + W > rlo) cm1 |= 1u << ch;
+    }
+  }
+  constexpr int QB = G == WAVE ? 4 : 16;
+  uint64_t lp = st.lp0;
+  for (uint64_t a = ta; a < tb; a += QB) {
+    uint32_t cv[QB];
+#pragma unroll
+    for (int q = 0; q < QB; q++) cv[q] = tab[g0 + ((a + q < tb) ? a + q : a)].nl;
+#pragma unroll
+    for (int q = 0; q < QB; q++) {
+      if (a + q >= tb) break;
+      const uint64_t t = a + q;
+      const uint64_t kk = (sg.b + off) / T + t;
+      const uint64_t tvs = (kk * T > sg.b + off) ? kk * T : sg.b + off;
+      const uint64_t tve = ((kk + 1) * T < sg.e + off) ? (kk + 1) * T : sg.e + off;
+      const uint64_t nv = tve - tvs;
+      const uint64_t before = tvs - (sg.b + off);   // keys of the range's earlier tiles
+      TileRun tr;
+      tr.lp = lp;
+      tr.rp = rtot - ((before + nv) - (lp + cv[q]));   // right keys of later tiles
+      tr.pos = tvs - off;
+      tr.nl = cv[q];
+      tr.nv = (uint32_t)nv;
+      tab[g0 + t] = tr;
+      lp += cv[q];
+#pragma unroll 1
+      for (int side = 0; side < 2; side++) {
+        const bool have = side == 0 ? have0 : have1;
+        const uint32_t cm = side == 0 ? cm0 : cm1;
+        if (!have && !cm) continue;
+        const Seg& cc = side == 0 ? r0.s : r1.s;
+        // this tile's run in the child: [rs, rs + rl), first key at src_next[first]
+        const uint64_t rs = side == 0 ? tr.lp : tr.rp;
+        const uint64_t rl = side == 0 ? tr.nl : nv - tr.nl;
+        const uint64_t first = side == 0 ? tr.pos : tr.pos + tr.nl;
+        if (rl == 0) continue;
+        if (have) {
+          // child tiles starting in the run: tile 0 starts at 0, tile m >= 1 at
+          // (kc0 + m) * T - off - cc.b
+          const uint32_t u = side == 0 ? (uint32_t)t : (uint32_t)(nt - 1 - t);
+          const uint64_t ctb = side == 0 ? tb_0 : tb_1;
+          const uint64_t kc0 = (cc.b + off) / T;
+          const uint64_t ntc = side == 0 ? st.nt0 : st.nt1;
+          const uint64_t A = rs + cc.b + off, B = A + rl;
+          uint64_t mlo = (A + T - 1) / T - kc0, mhi = (B + T - 1) / T - kc0;
+          if (mlo < 1) mlo = 1;
+          if (mhi > ntc) mhi = ntc;
+          if (rs == 0) p.frun[ctb] = u;
+          for (uint64_t m = mlo; m < mhi; m++) p.frun[ctb + m] = u;
+        }
+        for (uint32_t mm = cm; mm; mm &= mm - 1) {
+          const int ch = __builtin_ctz(mm);
+          const uint64_t o = sm.o[side][ch];
+          const uint64_t lo = o > rs ? o : rs;
+          const uint64_t hi = (o + W < rs + rl) ? o + W : rs + rl;
+          for (uint64_t i = lo; i < hi; i++) sm.spos[side][ch * W + (i - o)] = first + (i - rs);
+        }
+      }
+    }
+  }
+  gsync<G>();
+  // the sampled keys, all loads in flight together, then ChoosePivot of each child
+  if (st.piv0 || st.piv1) {
+    for (int k = gt; k < 2 * 9 * W; k += G) {
+      const int side = k / (9 * W), j = k % (9 * W);
+      if (side == 0 ? st.piv0 : st.piv1) {
+        const S sv = src_next[sm.spos[side][j]];
+        R rv;
+        if constexpr (sizeof(S) == sizeof(R)) rv = sv; else rv = (R)sv;
+        sm.samp[side][j] = rv;
+      }
+    }
+    gsync<G>();
+    auto lds_pivot = [&](int side) {
+      return choose_pivot_from<K>([&](uint64_t i) -> R { return sm.samp[side][i]; }, 0, W, 2 * W, 3 * W, 4 * W,
+                                  5 * W, 6 * W, 7 * W, 8 * W);
+    };
+    if constexpr (G == WAVE) {
+      if (st.piv0) {
+        const R v = lds_pivot(0);
+        if (gt == 0) sm.pv[0] = v;
+      }
+      if (st.piv1) {
+        const R v = lds_pivot(1);
+        if (gt == 0) sm.pv[1] = v;
+      }
+    } else {
+      const int w = gt / WAVE;
+      if (w < 2 && (w == 0 ? st.piv0 : st.piv1)) {
+        const R v = lds_pivot(w);
+        if ((gt & (WAVE - 1)) == 0) sm.pv[w] = v;
+      }
+    }
+    gsync<G>();
+  }
+  if (gt == 0) {
+    if (!fb) {
+      pc.part++;
+      pc.pkeys += sg.e - sg.b;
+      pc.maxd = sg.depth > pc.maxd ? sg.depth : pc.maxd;
+    } else {
+      pc.fbpart++;
+    }
+    pc.deg += st.degenerate ? 1 : 0;
+    pc.alleq += st.all_equal ? 1 : 0;
+    pc.solo += st.nsolo;
+    unsigned long long si = sl_.solo, li = sl_.idx;
+#pragma unroll
+    for (int side = 0; side < 2; side++) {
+      Routed r = side == 0 ? r0 : r1;
+      if (r.dest == RT_NONE) continue;
+      if (r.fb_enter) {
+        pc.fbs++;
+        pc.fbkeys += r.s.e - r.s.b;
+      }
+      if ((side == 0 ? st.piv0 : st.piv1)) {
+        to_words<K>(sm.pv[side], r.s.pv_lo, r.s.pv_hi);
+        r.s.flags |= SEG_PIVOT;
+      }
+      if (ok) {
+        // the range itself, or the copy entry that gathers it for the solo list
+        Seg e = r.s;
+        if (r.dest == RT_SOLO) e.flags = (r.s.flags & (SEG_RUNS | SEG_RIGHT)) | SEG_COPY;
+        p.lvl_segs[L & 1][li] = e;
+        p.lvl_tbase[L & 1][li] = side == 0 ? tb_0 : tb_1;
+        pc.lvlkeys += e.e - e.b;
+        li++;
+      }
+      if (r.dest == RT_SOLO) {
+        // gathered into [b, e) of level L's destination by the copy entry
+        Seg so = r.s;
+        const uint32_t keep = SEG_OVERRIDE | SEG_FALLBACK | SEG_BOUNDED | SEG_STRICT;
+        so.flags = (r.s.flags & keep) | ((L & 1) ? 0u : SEG_SCRATCH);
+        if (si < p.cap_solo) p.solo[si] = so;
+        else set_err(p, ERR_SOLO_OVERFLOW);
+        si++;
+      }
+    }
+  }
+  // keys equal to the pivot are final: fill entries of the solo list write them (they
+  // follow the range's other solo entries)
+  if (st.nfill) {
+    const unsigned long long f0 = sl_.solo + st.nsolo - st.nfill;
+    uint64_t lo, hi;
+    to_words<K>(pivot, lo, hi);
+    for (uint64_t c = gt; c < st.nfill; c += G) {
+      const unsigned long long i = f0 + c;
+      if (i >= p.cap_solo) {
+        set_err(p, ERR_SOLO_OVERFLOW);
+        continue;
+      }
+      Seg f{};
+      f.b = st.fill_b + c * FILL_CHUNK;
+      f.e = (f.b + FILL_CHUNK < st.fill_e) ? f.b + FILL_CHUNK : st.fill_e;
+      f.flags = SEG_FILL;
+      f.pv_lo = lo;
+      f.pv_hi = hi;
+      p.solo[i] = f;
+    }
+  }
+  gsync<G>();
+}
+
+// Run mode, before the partition launch of level L: plan every range of level L-1:
+// ranges of many tiles by a workgroup each, the others by a wave each, four at a time
+// per workgroup so that one reservation of each list serves four ranges.  At the first
+// level, the input ranges get their pivots (one wave per range).
+template <class K>
+__global__ void __launch_bounds__(LEVEL_P) runs_plan_kernel(Params p) {
+  using R = typename K::R;
+  using S = typename K::S;
+  constexpr int I = level_chunks(8 * K::SIZE);
+  constexpr int T = Tile<K, LEVEL_P, I>::T;
+  constexpr int NW = LEVEL_P / WAVE;
+  constexpr uint64_t SMALL = 4 * WAVE;   // ranges of at most this many tiles: one wave each
+  __shared__ PlanShared<K> smg;
+  __shared__ PlanShared<K> smw[NW];
+  __shared__ unsigned long long need[NW][3];
+  __shared__ PlanSlots slots[NW];
+  __shared__ unsigned long long cnt_sh[10];
+  const int L = p.level;
+  const int tid = threadIdx.x;
+  const int w = tid / WAVE;
+  const int lane = tid & (WAVE - 1);
+  if (L == p.seed_level) {
+    const unsigned long long packed = p.lvl_ctr[L].packed;
+    const uint32_t nseg = (uint32_t)(packed >> 40);
+    Seg* segs = p.lvl_segs[L & 1];
+    const S* src = (const S*)((L & 1) ? p.scratch : p.keys);
+    const int tmode = (L == 0) ? p.mode : 0;
+    const uint32_t nwaves = gridDim.x * NW;
+    for (uint32_t si = blockIdx.x * NW + w; si < nseg; si += nwaves) {
+      const Seg sg = segs[si];
+      if (sg.flags & (SEG_OVERRIDE | SEG_PIVOT)) continue;
+      const S* sb = src + sg.b;
+      const R pv = choose_pivot_wave<K>(
+          [&](uint64_t i) -> R {
+            S sv = sb[i];
+            R r;
+            if constexpr (sizeof(S) == sizeof(R)) r = sv; else r = (R)sv;
+            return tmode ? K::load_t(sv, tmode) : r;
+          },
+          sg.b, sg.e, p.seed);
+      if (lane == 0) {
+        uint64_t lo, hi;
+        to_words<K>(pv, lo, hi);
+        segs[si].pv_lo = lo;
+        segs[si].pv_hi = hi;
+        segs[si].flags = sg.flags | SEG_PIVOT;
+      }
+    }
+    return;
+  }
+  const int LP = L - 1;
+  const unsigned long long packed = p.lvl_ctr[LP].packed;
+  const uint32_t nseg = (uint32_t)(packed >> 40);
+  if ((packed & TILE_MASK40) == 0) return;
+  const Seg* segs = p.lvl_segs[LP & 1];
+  const unsigned long long* tbase = p.lvl_tbase[LP & 1];
+  if (tid < 10) cnt_sh[tid] = 0;
+  PlanCounts pc{};
+  for (uint32_t si = blockIdx.x; si < nseg; si += gridDim.x) {
+    const Seg sg = uniform_seg(segs[si]);
+    const uint64_t nt = tiles_of(sg.b, sg.e, p.off, T);
+    if ((sg.flags & SEG_COPY) || nt <= SMALL) continue;
+    const uint64_t g0 = uniform64(tbase[si]);
+    const PlanState st = plan_first<K, LEVEL_P>(p, L, sg, g0, nt, smg, tid);
+    if (tid == 0) slots[0] = plan_reserve(p, L, st.ne, st.nt0 + st.nt1, st.nsolo);
+    __syncthreads();
+    const PlanSlots sl_ = slots[0];
+    plan_second<K, LEVEL_P>(p, L, sg, g0, nt, smg, tid, st, sl_, pc);
+  }
+  for (uint32_t base = blockIdx.x * NW; base < nseg; base += gridDim.x * NW) {
+    const uint32_t si = base + w;
+    Seg sg{};
+    uint64_t nt = 0, g0 = 0;
+    bool mine = false;
+    if (si < nseg) {
+      sg = uniform_seg(segs[si]);
+      nt = tiles_of(sg.b, sg.e, p.off, T);
+      mine = !(sg.flags & SEG_COPY) && nt <= SMALL;
+      g0 = uniform64(tbase[si]);
+    }
+    PlanState st{};
+    if (mine) st = plan_first<K, WAVE>(p, L, sg, g0, nt, smw[w], lane);
+    if (lane == 0) {
+      need[w][0] = mine ? st.ne : 0;
+      need[w][1] = mine ? st.nt0 + st.nt1 : 0;
+      need[w][2] = mine ? st.nsolo : 0;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const PlanSlots s0 = plan_reserve(p, L, need[0][0] + need[1][0] + need[2][0] + need[3][0],
+                                        need[0][1] + need[1][1] + need[2][1] + need[3][1],
+                                        need[0][2] + need[1][2] + need[2][2] + need[3][2]);
+      unsigned long long di = 0, dt = 0, ds = 0;
+      for (int ww = 0; ww < NW; ww++) {
+        slots[ww].idx = (s0.idx == ~0ull || need[ww][0] == 0) ? ~0ull : s0.idx + di;
+        slots[ww].tb = s0.tb + dt;
+        slots[ww].solo = s0.solo + ds;
+        di += need[ww][0];
+        dt += need[ww][1];
+        ds += need[ww][2];
+      }
+    }
+    __syncthreads();
+    if (mine) plan_second<K, WAVE>(p, L, sg, g0, nt, smw[w], lane, st, slots[w], pc);
+    __syncthreads();
+  }
+  // the workgroup's counts: one device atomic each
+  __syncthreads();
+  if (lane == 0) {
+    const unsigned long long v[9] = {pc.part, pc.pkeys, pc.deg, pc.alleq, pc.fbpart,
+                                     pc.fbs, pc.fbkeys, pc.solo, pc.lvlkeys};
+#pragma unroll
+    for (int i = 0; i < 9; i++)
+      if (v[i]) atomicAdd(&cnt_sh[i], v[i]);
+    if (pc.maxd) atomicMax(&cnt_sh[9], pc.maxd);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    if (cnt_sh[0]) atomicAdd(&p.stats->partitions, cnt_sh[0]);
+    if (cnt_sh[1]) atomicAdd(&p.stats->keys_partitioned, cnt_sh[1]);
+    if (cnt_sh[2]) atomicAdd(&p.stats->degenerate, cnt_sh[2]);
+    if (cnt_sh[3]) atomicAdd(&p.stats->all_equal, cnt_sh[3]);
+    if (cnt_sh[4]) atomicAdd(&p.stats->fallback_partitions, cnt_sh[4]);
+    if (cnt_sh[5]) atomicAdd(&p.stats->fallbacks, cnt_sh[5]);
+    if (cnt_sh[6]) atomicAdd(&p.stats->fallback_keys, cnt_sh[6]);
+    if (cnt_sh[7]) atomicAdd(&p.stats->solo_items, cnt_sh[7]);
+    if (cnt_sh[8]) atomicAdd(&p.lvl_ctr[L].keys, cnt_sh[8]);
+    if (cnt_sh[9]) atomicMax(&p.stats->max_depth, cnt_sh[9]);
+  }
+}
+
 // ChoosePivot for every range of a level, one wave per range, before the level's
 // partition launch: the tiles then read the pivot with the range record.
 constexpr int PIVOT_P = 256;
@@ -707,11 +1549,14 @@ __device__ inline void merge_stage16(typename K::R (&x)[16], int gl) {
   // flip stage: lane l, register r  <->  lane l ^ (2W-1), register 15-r
   {
     const bool up = (gl & W) != 0;
-    R y[16];
+    // registers r and 15-r in pairs: two temporaries instead of sixteen
 #pragma unroll
-    for (int r = 0; r < 16; r++) y[r] = xor_lanes<2 * W - 1>(x[15 - r]);
-#pragma unroll
-    for (int r = 0; r < 16; r++) x[r] = (K::lt(y[r], x[r]) != up) ? y[r] : x[r];
+    for (int r = 0; r < 8; r++) {
+      const R ya = xor_lanes<2 * W - 1>(x[15 - r]);
+      const R yb = xor_lanes<2 * W - 1>(x[r]);
+      x[r] = K::sel(K::lt(ya, x[r]) != up, ya, x[r]);
+      x[15 - r] = K::sel(K::lt(yb, x[15 - r]) != up, yb, x[15 - r]);
+    }
   }
   // half-cleaners across lanes (distance W/2 .. 1)
   auto cross = [&](auto dtag) {
@@ -720,7 +1565,7 @@ __device__ inline void merge_stage16(typename K::R (&x)[16], int gl) {
 #pragma unroll
     for (int r = 0; r < 16; r++) {
       R y = xor_lanes<D>(x[r]);
-      x[r] = (K::lt(y, x[r]) != up) ? y : x[r];
+      x[r] = K::sel(K::lt(y, x[r]) != up, y, x[r]);
     }
   };
   if constexpr (W >= 8) cross(std::integral_constant<int, 4>{});
@@ -733,8 +1578,8 @@ __device__ inline void merge_stage16(typename K::R (&x)[16], int gl) {
     for (int r = 0; r < 16; r++)
       if ((r & d) == 0) {
         const bool sw = K::lt(x[r + d], x[r]);
-        const R lo = sw ? x[r + d] : x[r];
-        const R hi = sw ? x[r] : x[r + d];
+        const R lo = K::sel(sw, x[r + d], x[r]);
+        const R hi = K::sel(sw, x[r], x[r + d]);
         x[r] = lo;
         x[r + d] = hi;
       }
@@ -748,8 +1593,8 @@ __device__ inline void network16x16(typename K::R (&x)[16]) {
 #define VQS_CE(a, b)                     \
   {                                      \
     const bool sw_ = K::lt(x[b], x[a]);  \
-    const R lo_ = sw_ ? x[b] : x[a];     \
-    const R hi_ = sw_ ? x[a] : x[b];     \
+    const R lo_ = K::sel(sw_, x[b], x[a]); \
+    const R hi_ = K::sel(sw_, x[a], x[b]); \
     x[a] = lo_;                          \
     x[b] = hi_;                          \
   }
@@ -1037,7 +1882,7 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
         for (int u = 0; u < U; u++) {
           const bool before = K::lt(kx[u], pivot), not_after = !K::lt(pivot, kx[u]);
           isl[u] = valid[u] && (strict ? before : not_after);
-          mn = valid[u] ? K::kmin(mn, kx[u]) : mn;
+          mn = K::sel(valid[u], K::kmin(mn, kx[u]), mn);
           ml[u] = ballot(isl[u]);
           vm[u] = ballot(valid[u]);
         }
@@ -1114,7 +1959,7 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
             const R kx = (R)s_buf[i < pe ? i : pe - 1];
             const bool before = K::lt(kx, pivot), not_after = !K::lt(pivot, kx);
             const bool isl = valid && (strict ? before : not_after);
-            mn = valid ? K::kmin(mn, kx) : mn;
+            mn = K::sel(valid, K::kmin(mn, kx), mn);
             cnt += (uint32_t)__popcll(ballot(isl));
           }
         }

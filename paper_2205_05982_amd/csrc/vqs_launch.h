@@ -13,6 +13,7 @@ struct Launch {
   static hipError_t seed(const Params& p, const int64_t* offsets, uint64_t nseg, hipStream_t s);
   static hipError_t level(const Params& p, int grid, hipStream_t s);
   static hipError_t pivots(const Params& p, int grid, hipStream_t s);
+  static hipError_t plan(const Params& p, int grid, hipStream_t s);
   static hipError_t solo(const Params& p, int grid, hipStream_t s);
   static constexpr uint64_t level_tile_keys() { return (uint64_t)LEVEL_P * level_chunks(BITS) * (128 / BITS); }
   static constexpr uint64_t local_buffer_keys() { return (uint64_t)LOCAL_BYTES / (BITS / 8); }

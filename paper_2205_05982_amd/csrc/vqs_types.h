@@ -45,13 +45,25 @@ enum : uint32_t {
   SEG_PIVOT = 32u,     // pv holds the range's pivot (computed before the level's launch)
   SEG_STRICT = 64u,    // split into keys before the pivot and keys equal to it
   SEG_BOUNDED = 128u,  // past the fallback mode's own depth limit: bounded-time sort
+  SEG_RUNS = 256u,     // keys held as runs of the previous level's tiles (run mode)
+  SEG_RIGHT = 512u,    // with SEG_RUNS: the right parts of those tiles, in reverse tile order
+  SEG_COPY = 1024u,    // level entry that only gathers the runs into [b, e) (then solo)
 };
 
 struct Seg {
   uint64_t b, e;
   uint32_t depth, limit;
-  uint32_t flags, pad;
+  uint32_t flags, done;   // done: tiles of the range finished (run mode)
   uint64_t pv_lo, pv_hi;  // override pivot or fill value (internal form)
+  uint32_t rt_b, rt_n;    // SEG_RUNS: the parent range's tiles in the previous level's table
+};
+
+// Run mode: what a level tile left behind in its interval of the destination
+// (pos .. pos + nv: nl left keys in input order, then the right keys reversed), and
+// where its two parts start inside the left child (lp) and the right child (rp).
+struct TileRun {
+  uint64_t lp, rp, pos;
+  uint32_t nl, nv;
 };
 
 struct LevelCtr {
@@ -81,6 +93,7 @@ enum : uint32_t {
   ERR_SPIN = 4u,
   ERR_LOCAL_OVERFLOW = 8u,
   ERR_STACK = 16u,
+  ERR_NO_PIVOT = 32u,
 };
 
 struct Params {
@@ -108,6 +121,9 @@ struct Params {
   int64_t fixed_limit;   // < 0: 2*floor(log2 len)+4 per input range; else this limit
   unsigned long long* dbg;  // instrumented builds only (null otherwise)
   int seed_level;        // level of the first partition (1: input ranges live in scratch)
+  int run_mode;          // level partitions write tile-local runs (no look-back)
+  TileRun* runs[2];      // run mode: per-tile table of the current and the previous level
+  uint32_t* frun;        // run mode: first run of each tile of the level being planned
 };
 
 constexpr uint64_t FILL_CHUNK = 1ull << 16;

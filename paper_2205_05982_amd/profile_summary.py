@@ -34,6 +34,11 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
+def _is_level(name: str) -> bool:
+    """The device-wide partition kernel (either placement of its output)."""
+    return "level_kernel" in name or "level_runs_kernel" in name
+
+
 def _rows(path):
     with open(path) as f:
         return list(csv.DictReader(f))
@@ -60,11 +65,12 @@ def summarize(kt_dir, fetch_csv, write_csv, commands, title, copy_bytes=800_000_
                    f"{float(r['AverageNs']) / 1e3:.1f} | {int(r['MinNs']) / 1e3:.1f} | {int(r['MaxNs']) / 1e3:.1f} | "
                    f"{r['Percentage']} |")
     tr = _rows(os.path.join(kt_dir, "kt_kernel_trace.csv"))
-    lv = [r for r in tr if "level_kernel" in r["Kernel_Name"]]
+    lv = [r for r in tr if _is_level(r["Kernel_Name"])]
+    kname = "level_runs_kernel" if any("level_runs_kernel" in r["Kernel_Name"] for r in lv) else "level_kernel"
     durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in lv]
     lv_avg_us = statistics.mean(durs) if durs else 0.0
     out.append("")
-    out.append(f"level_kernel launches: {len(durs)}, average {lv_avg_us:.1f} us; the last step's launches (us): "
+    out.append(f"{kname} launches: {len(durs)}, average {lv_avg_us:.1f} us; the last step's launches (us): "
                + ", ".join(f"{d:.0f}" for d in durs[-20:]))
 
     f, w = _rows(fetch_csv), _rows(write_csv)
@@ -82,23 +88,23 @@ def summarize(kt_dir, fetch_csv, write_csv, commands, title, copy_bytes=800_000_
                f"(`__amd_rocclr_copyBuffer`) read and write {alg_kib:.0f} KiB each; they report FETCH_SIZE = "
                f"{statistics.mean(fc):.0f} KiB (factor {ff:.3f}) and WRITE_SIZE = {statistics.mean(wc):.0f} KiB "
                f"(factor {wf:.3f}).\n")
-    lvf = [float(r["Counter_Value"]) for r in f if "level_kernel" in r["Kernel_Name"]]
-    lvw = [float(r["Counter_Value"]) for r in w if "level_kernel" in r["Kernel_Name"]]
+    lvf = [float(r["Counter_Value"]) for r in f if _is_level(r["Kernel_Name"])]
+    lvw = [float(r["Counter_Value"]) for r in w if _is_level(r["Kernel_Name"])]
     full_f = [v for v in lvf if v > 0.9 * max(lvf)]
     full_w = [v for v in lvw if v > 0.9 * max(lvw)]
     mf, mw = statistics.mean(full_f) * ff, statistics.mean(full_w) * wf
-    out.append(f"level_kernel on a full level (every key once; algorithmic {alg_kib:.0f} KiB read + "
+    out.append(f"{kname} on a full level (every key once; algorithmic {alg_kib:.0f} KiB read + "
                f"{alg_kib:.0f} KiB written): read {mf:.0f} KiB ({mf / alg_kib:.3f} of algorithmic), written "
                f"{mw:.0f} KiB ({mw / alg_kib:.3f}).")
     per_launch = (statistics.mean(lvf) * ff + statistics.mean(lvw) * wf) * 1024
-    out.append(f"Average over all {len(lvf)} level_kernel dispatches: {per_launch / 1e6:.1f} MB per launch "
+    out.append(f"Average over all {len(lvf)} {kname} dispatches: {per_launch / 1e6:.1f} MB per launch "
                f"(read + written, scaled).")
     sf = [float(r["Counter_Value"]) for r in f if "solo_kernel" in r["Kernel_Name"]]
     sw = [float(r["Counter_Value"]) for r in w if "solo_kernel" in r["Kernel_Name"]]
     if sf:
         out.append(f"\nsolo_kernel per launch: read {statistics.mean(sf) * ff:.0f} KiB, written "
                    f"{statistics.mean(sw) * wf:.0f} KiB (scaled).")
-    js = {"kernel": "level_kernel", "traffic_bytes_per_launch": per_launch, "launches": len(lvf),
+    js = {"kernel": kname, "traffic_bytes_per_launch": per_launch, "launches": len(lvf),
           "avg_launch_us_trace": lv_avg_us, "fetch_factor": ff, "write_factor": wf,
           "full_level_read_frac": mf / alg_kib, "full_level_write_frac": mw / alg_kib,
           "source_hash": kernel_source_hash()}

@@ -41,7 +41,7 @@ class Options(ctypes.Structure):
                 ("batch", ctypes.c_uint32), ("sample_fraction", ctypes.c_float),
                 ("overflow_factor", ctypes.c_float), ("learning_rate", ctypes.c_float),
                 ("model_seed", ctypes.c_uint64), ("sample_seed", ctypes.c_uint64),
-                ("reserved", ctypes.c_uint32 * 3)]
+                ("level_mode", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 2)]
 
 
 class Stats(ctypes.Structure):

@@ -1,0 +1,132 @@
+"""GPU parity of both placements of the device-wide partition levels.
+
+VQS_LEVEL_LOOKBACK writes each partition contiguously (a tile's offsets come from a
+decoupled look-back); VQS_LEVEL_RUNS lets every tile partition into its own interval
+and holds a child range as one run per tile of its parent (gathered through a run
+table at the next level; a range leaving for the solo kernel is gathered into place
+by a copy entry).  The key sequences, and so pivots and recursion, are the same, so
+both are checked element by element and counter by counter against the oracle, on
+cases that take several levels: every key type, the distributions with degenerate
+partitions and fallbacks, the forced depth limit, odd 16-byte offsets, and segments.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2205_05982_amd import workloads as W
+from tests.helpers import (F32, F64, U16, U32, U64, U128, assert_stats_equal, random_keys, to_gpu,
+                           to_host)
+
+pytestmark = pytest.mark.gpu
+
+MODES = {"lookback": 1, "runs": 2}
+
+
+@pytest.fixture(scope="module")
+def vqs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a visible GPU")
+    from paper_2205_05982_amd import vqs as v
+    return v
+
+
+def _check(vqs, keys, kt, mode, asc=True, seed=0, depth_limit=-1, gpu_limit=0, **opts):
+    import torch
+    want = keys.copy()
+    ost = oracle.sort(want, kt, ascending=asc, seed=seed, depth_limit=depth_limit, stats=True)
+    t = to_gpu(keys)
+    vqs.sort(t, ascending=asc, key_type=kt, seed=seed, depth_limit=gpu_limit, level_mode=MODES[mode], **opts)
+    torch.cuda.synchronize()
+    assert vqs.last_error_bits() == 0
+    np.testing.assert_array_equal(to_host(t), want)
+    gst = vqs.get_stats()
+    assert_stats_equal(ost, gst)
+    return gst
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+@pytest.mark.parametrize("kt", [U16, U32, U64, U128, F32, F64])
+@pytest.mark.parametrize("asc", [True, False])
+def test_levels_every_type(vqs, mode, kt, asc):
+    n = 1_500_000 if kt != U128 else 600_000
+    print(f"case: levels mode={mode} kt={kt} asc={asc} n={n}", flush=True)
+    gst = _check(vqs, random_keys(kt, n, seed=300 + kt), kt, mode, asc, seed=7, solo_max=20_000)
+    assert gst["levels"] >= 3
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+@pytest.mark.parametrize("dist", W.C2_DISTRIBUTIONS)
+def test_levels_distributions(vqs, mode, dist):
+    print(f"case: levels mode={mode} C2 {dist} 2e6", flush=True)
+    _check(vqs, W.c2(dist, 2_000_000), U64, mode, seed=3, solo_max=30_000)
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+def test_levels_zipf_fallbacks(vqs, mode):
+    print(f"case: levels mode={mode} zipf 1e6", flush=True)
+    gst = _check(vqs, W.zipf_u64(1_000_000, 3), U64, mode, seed=3, solo_max=20_000)
+    assert gst["fallbacks"] > 0
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+@pytest.mark.parametrize("limit", [1, 3])
+def test_levels_forced_depth_limit(vqs, mode, limit):
+    print(f"case: levels mode={mode} depth limit {limit}", flush=True)
+    gst = _check(vqs, W.uniform_u64(400_000, 2), U64, mode, depth_limit=limit, gpu_limit=limit,
+                 solo_max=20_000)
+    assert gst["fallbacks"] >= 1
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+def test_levels_two_values_and_all_equal(vqs, mode):
+    k = np.array([5] * 600_000 + [9] * 1_400_000, dtype=np.uint32)
+    np.random.default_rng(0).shuffle(k)
+    _check(vqs, k, U32, mode, solo_max=20_000)
+    _check(vqs, np.full(700_000, 3, dtype=np.uint64), U64, mode, solo_max=20_000)
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+@pytest.mark.parametrize("shift", [1, 3])
+def test_levels_unaligned_views(vqs, mode, shift):
+    import torch
+    base = W.uniform_u32(1_200_007, 9)
+    t = to_gpu(base)
+    sub = t[shift:1_200_000 + shift]
+    vqs.sort(sub, key_type=U32, solo_max=20_000, level_mode=MODES[mode])
+    torch.cuda.synchronize()
+    assert vqs.last_error_bits() == 0
+    got = to_host(t)
+    np.testing.assert_array_equal(got[shift:1_200_000 + shift], np.sort(base[shift:1_200_000 + shift]))
+    np.testing.assert_array_equal(got[:shift], base[:shift])
+    np.testing.assert_array_equal(got[1_200_000 + shift:], base[1_200_000 + shift:])
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+@pytest.mark.parametrize("use_graph", [0, 1])
+def test_levels_segmented(vqs, mode, use_graph):
+    import torch
+    off = W.segment_offsets(200, seed=31, lo=16, hi=1 << 18)
+    keys = W.segmented_keys(off, U64, 32)
+    want = keys.copy()
+    ost = oracle.sort_segmented(want, off, U64, seed=2, stats=True)
+    t = to_gpu(keys)
+    o = to_gpu(off)
+    for rep in range(2):
+        t.copy_(to_gpu(keys))
+        torch.cuda.synchronize()
+        vqs.sort_segmented(t, o, key_type=U64, seed=2, solo_max=20_000, use_graph=use_graph,
+                           level_mode=MODES[mode])
+        torch.cuda.synchronize()
+        assert vqs.last_error_bits() == 0
+        np.testing.assert_array_equal(to_host(t), want)
+    if not use_graph:
+        assert_stats_equal(ost, vqs.get_stats())
+
+
+def test_level_mode_rejects_unknown(vqs):
+    import torch
+    t = to_gpu(W.uniform_u64(1000, 1))
+    with pytest.raises(Exception):
+        vqs.sort(t, key_type=U64, level_mode=7)
+    torch.cuda.synchronize()
