@@ -204,11 +204,12 @@ int make_plan(uint64_t n, uint64_t nseg, int kt, int asc, const vqs_options* o, 
     pl->solo = o->solo_max;
     if (pl->solo < pl->local) return VQS_EINVAL;
   } else {
-    // ranges above 16K keys are partitioned by the device-wide level kernel, which
-    // moves data faster than one workgroup's partitions; a few times more ranges than
-    // solo workgroups keep the solo kernel busy on very large inputs
+    // ranges above 32K keys are partitioned by the device-wide level kernel, which
+    // moves data faster than one workgroup's partitions (below that, a level's fixed
+    // costs outweigh it: measured on 1e8 u64 and 2e8 u32); a few times more ranges
+    // than solo workgroups keep the solo kernel busy on very large inputs
     uint64_t s = n / ((uint64_t)g.solo_grid * 16);
-    s = std::max<uint64_t>(s, std::max<uint64_t>(pl->local, 1u << 14));
+    s = std::max<uint64_t>(s, std::max<uint64_t>(pl->local, 1u << 15));
     s = std::min<uint64_t>(s, 1ull << 20);
     pl->solo = std::max<uint64_t>(s, pl->local);
   }
@@ -278,7 +279,7 @@ int ensure_workspace(Workspace* ws, const Plan& pl) {
   const size_t o_tmin = take(cap_tiles * sizeof(u128k));
   const size_t o_run0 = take(cap_tiles * sizeof(TileRun));
   const size_t o_run1 = take(cap_tiles * sizeof(TileRun));
-  const size_t o_frun = take(cap_tiles * sizeof(uint32_t));
+  const size_t o_tref = take(cap_tiles * sizeof(TileRef));
   const size_t o_solo = take(cap_solo * sizeof(Seg));
   const size_t o_sctr = take(sizeof(SoloCtr));
   const size_t o_stats = take(sizeof(DevStats));
@@ -306,7 +307,7 @@ int ensure_workspace(Workspace* ws, const Plan& pl) {
   p.tilemin = (u128k*)(ws->mem + o_tmin);
   p.runs[0] = (TileRun*)(ws->mem + o_run0);
   p.runs[1] = (TileRun*)(ws->mem + o_run1);
-  p.frun = (uint32_t*)(ws->mem + o_frun);
+  p.tref = (TileRef*)(ws->mem + o_tref);
   p.solo = (Seg*)(ws->mem + o_solo);
   p.solo_ctr = (SoloCtr*)(ws->mem + o_sctr);
   p.stats = (DevStats*)(ws->mem + o_stats);
@@ -857,7 +858,7 @@ uint64_t vqs_workspace_bytes(uint64_t n, uint64_t nseg, int key_type, const vqs_
   if (make_plan(n, nseg ? nseg : 1, key_type, 1, options, g, &pl) != VQS_OK) return 0;
   uint64_t b = (n + 32) * (uint64_t)pl.ks + 64;
   b += 2 * pl.cap_lvl * (sizeof(Seg) + 8) + (uint64_t)pl.max_levels * sizeof(LevelCtr);
-  b += pl.cap_tiles * (8 + sizeof(u128k) + 2 * sizeof(TileRun) + sizeof(uint32_t)) + pl.cap_solo * sizeof(Seg) +
+  b += pl.cap_tiles * (8 + sizeof(u128k) + 2 * sizeof(TileRun) + sizeof(TileRef)) + pl.cap_solo * sizeof(Seg) +
        4096;
   return b;
 }

@@ -788,13 +788,21 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
   const int tid = threadIdx.x;
   const int w = tid / WAVE;
   unsigned long long tiles_done = 0;
+  VQS_PHASE_INIT();
 
   for (;;) {
+    VQS_PHASE(5);
     if (tid == 0) sh_ticket = atomicAdd(&p.lvl_ctr[L].ticket, 1u);
     __syncthreads();
     const unsigned long long g = sh_ticket;
     if (g >= ntiles) break;
-    if (tid < WAVE) {
+    VQS_PHASE(0);
+    // a planned level records each tile's range (and first run); the input ranges of
+    // the first level are found by search
+    const bool planned = L != p.seed_level;
+    TileRef tr{0, 0};
+    if (planned) tr = p.tref[g];
+    if (!planned && tid < WAVE) {
       uint32_t lo = 0, hi = nseg;  // invariant: tbase[lo] <= g, and g < tbase[hi] if hi < nseg
       while (hi - lo > 1) {
         const uint32_t span = hi - lo;
@@ -810,8 +818,8 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
       }
       if (tid == 0) sh_seg = (int)lo;
     }
-    __syncthreads();
-    const int si = sh_seg;
+    if (!planned) __syncthreads();
+    const int si = planned ? (int)tr.seg : sh_seg;
     const Seg sg = segs[si];
     const unsigned long long g0 = tbase[si];
     const uint64_t nt = tiles_of(sg.b, sg.e, p.off, T);
@@ -821,13 +829,14 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
     const uint32_t nvalid = (uint32_t)(ve - vs);
 
     R key[I][V];
+    VQS_PHASE(1);
     if (!(sg.flags & SEG_RUNS)) {
       TL::load(src_aligned, k, vs, ve, tmode, key);
     } else {
       // the runs the tile touches into LDS (from the first one, recorded by the
       // planning launch), then every key from its run
       const uint64_t j0 = vs - p.off - sg.b, j1 = j0 + nvalid;
-      const uint64_t u0 = p.frun[g];   // recorded by the planning launch
+      const uint64_t u0 = tr.frun;   // recorded by the planning launch
       uint32_t nr = 0;
       for (uint32_t r = 0;; r++) {
         const uint64_t u = u0 + (uint64_t)r * LEVEL_P + tid;
@@ -847,6 +856,7 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
         if (cnt < LEVEL_P) break;
       }
       S raw[I][V];
+      VQS_PHASE(2);
       if (nr <= (uint32_t)RMAX) {
         // a thread's slots increase with (j, q): walk the run list forward
         int i = 0;
@@ -913,7 +923,8 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
         }
       }
     }
-    // the pivot kernel gave every range of the level its pivot
+    VQS_PHASE(3);
+    // the planning launch gave every range of the level its pivot
     if (tid == 0) {
       sh.pivot = K::from_u64x2(sg.pv_lo, sg.pv_hi);
       if (!(sg.flags & SEG_PIVOT)) set_err(p, ERR_NO_PIVOT);
@@ -930,11 +941,14 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
                                              p.tilemin[g].hi = hi;
                                              cur[g].nl = cnt;
                                            });
+    VQS_PHASE(4);
     TL::write_out(stage, dst, nl, nvalid, vs - p.off, vs - p.off + nl, 0, p.n_total, p.off);
     tiles_done++;
+    VQS_PHASE(6);
     __syncthreads();
   }
   if (tid == 0 && tiles_done) atomicAdd(&p.stats->level_tiles, tiles_done);
+  VQS_PHASE_FLUSH();
 }
 
 // ---- run mode: planning ------------------------------------------------------------
@@ -1227,14 +1241,15 @@ __device__ void plan_second(const Params& p, int L, const Seg& sg, uint64_t g0, 
           // (kc0 + m) * T - off - cc.b
           const uint32_t u = side == 0 ? (uint32_t)t : (uint32_t)(nt - 1 - t);
           const uint64_t ctb = side == 0 ? tb_0 : tb_1;
+          const uint32_t cseg = (uint32_t)(side == 0 ? sl_.idx : sl_.idx + (r0.dest != RT_NONE ? 1 : 0));
           const uint64_t kc0 = (cc.b + off) / T;
           const uint64_t ntc = side == 0 ? st.nt0 : st.nt1;
           const uint64_t A = rs + cc.b + off, B = A + rl;
           uint64_t mlo = (A + T - 1) / T - kc0, mhi = (B + T - 1) / T - kc0;
           if (mlo < 1) mlo = 1;
           if (mhi > ntc) mhi = ntc;
-          if (rs == 0) p.frun[ctb] = u;
-          for (uint64_t m = mlo; m < mhi; m++) p.frun[ctb + m] = u;
+          if (rs == 0) p.tref[ctb] = TileRef{cseg, u};
+          for (uint64_t m = mlo; m < mhi; m++) p.tref[ctb + m] = TileRef{cseg, u};
         }
         for (uint32_t mm = cm; mm; mm &= mm - 1) {
           const int ch = __builtin_ctz(mm);

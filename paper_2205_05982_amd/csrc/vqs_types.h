@@ -58,6 +58,12 @@ struct Seg {
   uint32_t rt_b, rt_n;    // SEG_RUNS: the parent range's tiles in the previous level's table
 };
 
+// Run mode: a tile of a planned level: its range (index in the level's list) and the
+// first run it reads (run-held ranges)
+struct TileRef {
+  uint32_t seg, frun;
+};
+
 // Run mode: what a level tile left behind in its interval of the destination
 // (pos .. pos + nv: nl left keys in input order, then the right keys reversed), and
 // where its two parts start inside the left child (lp) and the right child (rp).
@@ -123,7 +129,7 @@ struct Params {
   int seed_level;        // level of the first partition (1: input ranges live in scratch)
   int run_mode;          // level partitions write tile-local runs (no look-back)
   TileRun* runs[2];      // run mode: per-tile table of the current and the previous level
-  uint32_t* frun;        // run mode: first run of each tile of the level being planned
+  TileRef* tref;         // run mode: range and first run of each tile of the level being planned
 };
 
 constexpr uint64_t FILL_CHUNK = 1ull << 16;
