@@ -280,6 +280,7 @@ int ensure_workspace(Workspace* ws, const Plan& pl) {
   const size_t o_run0 = take(cap_tiles * sizeof(TileRun));
   const size_t o_run1 = take(cap_tiles * sizeof(TileRun));
   const size_t o_tref = take(cap_tiles * sizeof(TileRef));
+  const size_t o_tnl = take(cap_tiles * sizeof(uint32_t));
   const size_t o_solo = take(cap_solo * sizeof(Seg));
   const size_t o_sctr = take(sizeof(SoloCtr));
   const size_t o_stats = take(sizeof(DevStats));
@@ -308,6 +309,7 @@ int ensure_workspace(Workspace* ws, const Plan& pl) {
   p.runs[0] = (TileRun*)(ws->mem + o_run0);
   p.runs[1] = (TileRun*)(ws->mem + o_run1);
   p.tref = (TileRef*)(ws->mem + o_tref);
+  p.tnl = (uint32_t*)(ws->mem + o_tnl);
   p.solo = (Seg*)(ws->mem + o_solo);
   p.solo_ctr = (SoloCtr*)(ws->mem + o_sctr);
   p.stats = (DevStats*)(ws->mem + o_stats);
@@ -858,7 +860,7 @@ uint64_t vqs_workspace_bytes(uint64_t n, uint64_t nseg, int key_type, const vqs_
   if (make_plan(n, nseg ? nseg : 1, key_type, 1, options, g, &pl) != VQS_OK) return 0;
   uint64_t b = (n + 32) * (uint64_t)pl.ks + 64;
   b += 2 * pl.cap_lvl * (sizeof(Seg) + 8) + (uint64_t)pl.max_levels * sizeof(LevelCtr);
-  b += pl.cap_tiles * (8 + sizeof(u128k) + 2 * sizeof(TileRun) + sizeof(TileRef)) + pl.cap_solo * sizeof(Seg) +
+  b += pl.cap_tiles * (8 + sizeof(u128k) + 2 * sizeof(TileRun) + sizeof(TileRef) + 4) + pl.cap_solo * sizeof(Seg) +
        4096;
   return b;
 }

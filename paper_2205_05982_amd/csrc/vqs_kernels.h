@@ -784,9 +784,7 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
   const S* src_aligned = src - p.off;
   const int tmode = (L == 0) ? p.mode : 0;   // only the first level reads untransformed keys
   const TileRun* prev = p.runs[(L + 1) & 1];
-  TileRun* cur = p.runs[L & 1];
   const int tid = threadIdx.x;
-  const int w = tid / WAVE;
   unsigned long long tiles_done = 0;
   VQS_PHASE_INIT();
 
@@ -939,7 +937,7 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
                                              to_words<K>(m, lo, hi);
                                              p.tilemin[g].lo = lo;
                                              p.tilemin[g].hi = hi;
-                                             cur[g].nl = cnt;
+                                             p.tnl[g] = cnt;
                                            });
     VQS_PHASE(4);
     TL::write_out(stage, dst, nl, nvalid, vs - p.off, vs - p.off + nl, 0, p.n_total, p.off);
@@ -1073,12 +1071,13 @@ __device__ PlanState plan_first(const Params& p, int L, const Seg& sg, uint64_t 
   const uint64_t per = (nt + G - 1) / G;
   const uint64_t ta = (uint64_t)gt * per < nt ? (uint64_t)gt * per : nt;
   const uint64_t tb = ta + per < nt ? ta + per : nt;
-  constexpr int QB = G == WAVE ? 4 : 16;   // counts read per batch, all in flight
+  constexpr int QB = G == WAVE ? 4 : 32;   // counts read per batch, all in flight
+  const uint32_t* tnl = p.tnl;
   uint64_t sl = 0;
   for (uint64_t a = ta; a < tb; a += QB) {
     uint32_t cv[QB];
 #pragma unroll
-    for (int q = 0; q < QB; q++) cv[q] = tab[g0 + ((a + q < tb) ? a + q : a)].nl;
+    for (int q = 0; q < QB; q++) cv[q] = tnl[g0 + ((a + q < tb) ? a + q : a)];
 #pragma unroll
     for (int q = 0; q < QB; q++) sl += (a + q < tb) ? cv[q] : 0u;
   }
@@ -1202,12 +1201,40 @@ __device__ void plan_second(const Params& p, int L, const Seg& sg, uint64_t g0, 
       if (st.piv1 && sm.o[1][ch] < rhi && sm.o[1][ch] + W > rlo) cm1 |= 1u << ch;
     }
   }
-  constexpr int QB = G == WAVE ? 4 : 16;
+  // first runs of the child tiles: a thread's left parts are contiguous in child 0 and
+  // its right parts in child 1 (in reverse tile order), so it walks the child tile
+  // starts forward through child 0 and backward through child 1.  Child tile m starts
+  // at 0 (m = 0) or at (kc + m) * T - off - b.
+  auto tile_start = [&](const Seg& cc, uint64_t m) -> uint64_t {
+    return m == 0 ? 0 : ((cc.b + off) / T + m) * T - off - cc.b;
+  };
+  const uint32_t cseg0 = (uint32_t)sl_.idx, cseg1 = (uint32_t)(sl_.idx + (r0.dest != RT_NONE ? 1 : 0));
+  uint64_t m0 = 0, s0 = 0;   // next child-0 tile and its start
+  int64_t m1 = -1;           // next child-1 tile (downward)
+  uint64_t s1 = 0;
+  if (have0 && st.lp0 > 0) {
+    m0 = (st.lp0 + r0.s.b + off + T - 1) / T - (r0.s.b + off) / T;
+    s0 = m0 < st.nt0 ? tile_start(r0.s, m0) : 0;
+  }
+  if (have1) {
+    const uint64_t kb = (sg.b + off) / T;
+    const uint64_t kbs = (kb + ta) * T > sg.b + off ? (kb + ta) * T : sg.b + off;
+    const uint64_t before = tb > ta ? kbs - (sg.b + off) : 0;
+    const uint64_t rhi = rtot - (before - st.lp0);   // end of my right parts in child 1
+    if (rhi > 0) {
+      int64_t m = (int64_t)((rhi + r1.s.b + off + T - 1) / T - (r1.s.b + off) / T) - 1;
+      if (m > (int64_t)st.nt1 - 1) m = (int64_t)st.nt1 - 1;
+      m1 = m;
+      s1 = m1 >= 0 ? tile_start(r1.s, (uint64_t)m1) : 0;
+    }
+  }
+  constexpr int QB = G == WAVE ? 4 : 8;
+  const uint32_t* tnl = p.tnl;
   uint64_t lp = st.lp0;
   for (uint64_t a = ta; a < tb; a += QB) {
     uint32_t cv[QB];
 #pragma unroll
-    for (int q = 0; q < QB; q++) cv[q] = tab[g0 + ((a + q < tb) ? a + q : a)].nl;
+    for (int q = 0; q < QB; q++) cv[q] = tnl[g0 + ((a + q < tb) ? a + q : a)];
 #pragma unroll
     for (int q = 0; q < QB; q++) {
       if (a + q >= tb) break;
@@ -1236,20 +1263,20 @@ __device__ void plan_second(const Params& p, int L, const Seg& sg, uint64_t g0, 
         const uint64_t rl = side == 0 ? tr.nl : nv - tr.nl;
         const uint64_t first = side == 0 ? tr.pos : tr.pos + tr.nl;
         if (rl == 0) continue;
-        if (have) {
-          // child tiles starting in the run: tile 0 starts at 0, tile m >= 1 at
-          // (kc0 + m) * T - off - cc.b
-          const uint32_t u = side == 0 ? (uint32_t)t : (uint32_t)(nt - 1 - t);
-          const uint64_t ctb = side == 0 ? tb_0 : tb_1;
-          const uint32_t cseg = (uint32_t)(side == 0 ? sl_.idx : sl_.idx + (r0.dest != RT_NONE ? 1 : 0));
-          const uint64_t kc0 = (cc.b + off) / T;
-          const uint64_t ntc = side == 0 ? st.nt0 : st.nt1;
-          const uint64_t A = rs + cc.b + off, B = A + rl;
-          uint64_t mlo = (A + T - 1) / T - kc0, mhi = (B + T - 1) / T - kc0;
-          if (mlo < 1) mlo = 1;
-          if (mhi > ntc) mhi = ntc;
-          if (rs == 0) p.tref[ctb] = TileRef{cseg, u};
-          for (uint64_t m = mlo; m < mhi; m++) p.tref[ctb + m] = TileRef{cseg, u};
+        if (side == 0 && have) {
+          // child-0 tiles starting in [rs, rs + rl)
+          while (m0 < st.nt0 && s0 < rs + rl) {
+            p.tref[tb_0 + m0] = TileRef{cseg0, (uint32_t)t};
+            m0++;
+            s0 = m0 == 1 ? tile_start(cc, 1) : s0 + T;
+          }
+        } else if (side == 1 && have) {
+          // child-1 tiles starting in [rs, rs + rl) (runs come downward)
+          while (m1 >= 0 && s1 >= rs) {
+            p.tref[tb_1 + (uint64_t)m1] = TileRef{cseg1, (uint32_t)(nt - 1 - t)};
+            m1--;
+            s1 = m1 <= 0 ? 0 : s1 - T;
+          }
         }
         for (uint32_t mm = cm; mm; mm &= mm - 1) {
           const int ch = __builtin_ctz(mm);

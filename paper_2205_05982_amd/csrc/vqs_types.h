@@ -130,6 +130,7 @@ struct Params {
   int run_mode;          // level partitions write tile-local runs (no look-back)
   TileRun* runs[2];      // run mode: per-tile table of the current and the previous level
   TileRef* tref;         // run mode: range and first run of each tile of the level being planned
+  uint32_t* tnl;         // run mode: left count of each tile of the level just partitioned
 };
 
 constexpr uint64_t FILL_CHUNK = 1ull << 16;
