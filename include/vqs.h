@@ -74,8 +74,10 @@ enum vqs_method {
  *    is then held as one run per tile of its parent.  The next level gathers it
  *    through a run table, and a range leaving for a single workgroup is first gathered
  *    into place by one copy pass.
- *  - AUTO: RUNS for 8- and 16-byte keys, LOOKBACK for 2- and 4-byte keys, whose
- *    one-key gathers cost more than the look-back saves. */
+ *  - AUTO: RUNS for one array of 8- or 16-byte keys.  LOOKBACK for 2- and 4-byte
+ *    keys, whose one-key gathers cost more than the look-back saves, and for many
+ *    ranges at once (segmented sorts, the learned splitter's buckets), whose short
+ *    look-back chains cost less than run mode's copy pass. */
 enum vqs_level_mode {
     VQS_LEVEL_AUTO = 0,
     VQS_LEVEL_LOOKBACK = 1,

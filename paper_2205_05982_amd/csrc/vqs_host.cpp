@@ -217,7 +217,10 @@ int make_plan(uint64_t n, uint64_t nseg, int kt, int asc, const vqs_options* o, 
   const bool has_lm = o && (o->struct_size == 0 || o->struct_size >= offsetof(vqs_options, level_mode) + 4);
   const uint32_t lm = has_lm ? o->level_mode : (uint32_t)VQS_LEVEL_AUTO;
   if (lm > VQS_LEVEL_RUNS) return VQS_EINVAL;
-  pl->run_mode = lm == VQS_LEVEL_RUNS || (lm == VQS_LEVEL_AUTO && bits >= 64);
+  // auto: runs for one array of 8- or 16-byte keys, whose top levels are a few long
+  // ranges (long look-back chains); the look-back for narrower keys and for many
+  // ranges at once (segments, learned buckets), where it measured faster
+  pl->run_mode = lm == VQS_LEVEL_RUNS || (lm == VQS_LEVEL_AUTO && bits >= 64 && nseg == 1);
   pl->depth_limit = -1;
   uint32_t lim = depth_limit_for(std::max<uint64_t>(n, 2));
   if (o && o->depth_limit != 0) {
