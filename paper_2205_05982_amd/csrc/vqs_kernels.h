@@ -2,15 +2,20 @@
 //
 // The paper's recursion (Alg. 1) is run breadth-first across the whole GPU:
 //
-//  * level_kernel: one launch per recursion level.  Every range longer than the
+//  * level partitions: one launch per recursion level.  Every range longer than the
 //    "solo" threshold is cut into 16-byte-aligned tiles; all tiles of all ranges of
 //    the level are partitioned in one persistent launch (atomic tile tickets).  Each
-//    tile recomputes its range's pivot (ChoosePivot, Sec. 2.2), classifies its keys
-//    against it, ranks them with wave ballots and prefix counts, stages them in LDS
-//    in compacted order (the compress-store of Sec. 2.1) and writes two coalesced
-//    runs.  A tile's offset inside its range comes from a decoupled look-back over
-//    the left counts of the preceding tiles.  The last tile of a range plans the
-//    children: small ones go to the solo list, large ones to the next level.
+//    tile classifies its keys against its range's pivot (ChoosePivot, Sec. 2.2),
+//    ranks them with wave ballots and prefix counts, stages them in LDS in compacted
+//    order (the compress-store of Sec. 2.1) and writes them coalesced.  Two
+//    placements of the output:
+//      - level_runs_kernel: each tile writes its own interval; a child range is then
+//        held as one run per tile of its parent, and runs_plan_kernel (before the
+//        next partition launch) plans the ranges and records the runs;
+//      - level_kernel: a tile's offset inside its range comes from a decoupled
+//        look-back over the left counts of the preceding tiles; the last tile of a
+//        range plans the children (pivots by pivot_kernel before each launch).
+//    Small children go to the solo list, large ones to the next level.
 //  * solo_kernel: one persistent launch; each workgroup takes whole ranges from the
 //    solo list and finishes them alone: partition passes through global memory while
 //    the range is larger than the LDS capacity, then the local sort in LDS
@@ -700,7 +705,8 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
 // per tile of its parent: the left child takes the tiles' left parts in tile order,
 // the right child their right parts in reverse tile order.  That is the key sequence
 // the contiguous partition writes, so pivots and the recursion are unchanged.  The
-// parent's last tile records every tile's run starts inside both children (TileRun).
+// planning launch after the partition records every tile's run starts inside both
+// children (TileRun) and, for each tile of the next level, its range and first run.
 
 // start (child-relative) of run u of a run-held range, and the source position of its
 // first key

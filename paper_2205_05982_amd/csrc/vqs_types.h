@@ -53,7 +53,7 @@ enum : uint32_t {
 struct Seg {
   uint64_t b, e;
   uint32_t depth, limit;
-  uint32_t flags, done;   // done: tiles of the range finished (run mode)
+  uint32_t flags, pad;
   uint64_t pv_lo, pv_hi;  // override pivot or fill value (internal form)
   uint32_t rt_b, rt_n;    // SEG_RUNS: the parent range's tiles in the previous level's table
 };
