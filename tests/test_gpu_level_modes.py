@@ -130,3 +130,23 @@ def test_level_mode_rejects_unknown(vqs):
     with pytest.raises(Exception):
         vqs.sort(t, key_type=U64, level_mode=7)
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("solo_max", [0, 4096])
+def test_runs_more_runs_than_the_tile_list(vqs, solo_max):
+    """A child range made of one-key runs: ones with a single zero in every 5120-key
+    tile.  The pivot sampled is 1, the partition is degenerate, the repeat with the
+    minimum as pivot sends exactly one key per tile left.  Above 2560 tiles, one tile
+    of that child touches more runs than its LDS list holds (its keys are then found
+    one by one); with the default threshold the child is gathered by a copy entry,
+    with a threshold of 4096 by a partition tile.  The tile boundaries are aligned, so
+    the array is allocated at a 16-byte boundary."""
+    import torch
+    tiles = 4300
+    n = tiles * 5120
+    keys = np.ones(n, dtype=np.uint64)
+    keys[np.arange(tiles) * 5120 + 1000] = 0
+    opts = {"solo_max": solo_max} if solo_max else {}
+    print(f"case: one-key runs, {tiles} tiles, solo_max={solo_max}", flush=True)
+    gst = _check(vqs, keys, U64, "runs", **opts)
+    assert gst["degenerate"] >= 1
