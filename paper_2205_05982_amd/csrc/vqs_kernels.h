@@ -773,7 +773,7 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
   constexpr int RMAX = (int)(T * sizeof(S) / sizeof(RunEnt));
   __shared__ __align__(16) S stage[T];
   __shared__ typename TL::Aux sh;
-  __shared__ unsigned long long sh_ticket;
+  __shared__ unsigned long long sh_tk[2];
   __shared__ int sh_seg;
   RunEnt* ent = reinterpret_cast<RunEnt*>(stage);
 
@@ -794,12 +794,16 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
   unsigned long long tiles_done = 0;
   VQS_PHASE_INIT();
 
-  for (;;) {
+  // tiles are independent: the next tile's ticket is drawn when a tile starts, and
+  // handed over through alternating LDS slots at its end
+  if (tid == 0) sh_tk[0] = atomicAdd(&p.lvl_ctr[L].ticket, 1u);
+  __syncthreads();
+  for (int it = 0;; it++) {
     VQS_PHASE(5);
-    if (tid == 0) sh_ticket = atomicAdd(&p.lvl_ctr[L].ticket, 1u);
-    __syncthreads();
-    const unsigned long long g = sh_ticket;
+    const unsigned long long g = sh_tk[it & 1];
     if (g >= ntiles) break;
+    unsigned int g_next = 0;
+    if (tid == 0) g_next = atomicAdd(&p.lvl_ctr[L].ticket, 1u);
     VQS_PHASE(0);
     // a planned level records each tile's range (and first run); the input ranges of
     // the first level are found by search
@@ -912,6 +916,7 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
           }
         }
         tiles_done++;
+        if (tid == 0) sh_tk[(it + 1) & 1] = g_next;
         __syncthreads();   // the LDS run list is read before the next tile rewrites it
         continue;
       }
@@ -949,6 +954,7 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
     TL::write_out(stage, dst, nl, nvalid, vs - p.off, vs - p.off + nl, 0, p.n_total, p.off);
     tiles_done++;
     VQS_PHASE(6);
+    if (tid == 0) sh_tk[(it + 1) & 1] = g_next;
     __syncthreads();
   }
   if (tid == 0 && tiles_done) atomicAdd(&p.stats->level_tiles, tiles_done);
