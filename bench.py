@@ -14,7 +14,9 @@ sorted by both methods (median of a few sorts each), the speedup of the learned
 Roofline: the dominant kernel is the device-wide partition (level kernel).  Its
 algorithmic traffic per launch is 2 * keys * key_size bytes (each key of the level
 read once and written once); HIP events around every launch on the library's
-stream give the durations.
+stream give the durations.  Besides the 8 TB/s peak, the bandwidth of a plain
+device-to-device copy of the input (measured the same way) is reported as a second
+denominator ("copy_gbs", "frac_of_copy").
 """
 from __future__ import annotations
 
@@ -319,6 +321,20 @@ def main():
         with open(args.profile_json, "w") as f:
             json.dump({"records": recs, "stats": stats}, f, indent=1)
 
+    # a second denominator: the device-to-device copy of the input (one read and one
+    # write of every key, like a partition pass), timed the same way
+    cp_ms = []
+    for r in range(4):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        bufs[0].copy_(src)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if r:
+            cp_ms.append(e0.elapsed_time(e1))
+    copy_gbs = 2 * n * ks / (min(cp_ms) * 1e-3) / 1e9
+
     # free the timed buffers before the larger comparison
     del bufs, out
     torch.cuda.empty_cache()
@@ -357,6 +373,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "copy_gbs": round(copy_gbs, 1),                  # measured device-to-device copy
+            "frac_of_copy": round(achieved / copy_gbs, 4),
             "traffic": measured_traffic() if (args.workload == "c2_uniform" and n == 100_000_000) else None,
             "launches_per_step": round(levels_per_step, 2),
             # every level launch of the timed steps, empty ones included (the
