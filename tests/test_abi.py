@@ -60,4 +60,23 @@ def test_options_layout_matches_binding():
     assert ctypes.sizeof(vqs.Options) == 104
     assert vqs.Options.model_seed.offset == 72
     assert vqs.Options.train_steps.offset == 48
+    assert vqs.Options.level_mode.offset == 88
     assert ctypes.sizeof(vqs.Stats) == 16 * 8
+
+
+def test_options_and_stats_layout_match_the_header(tmp_path):
+    """The binding's structures against the C header itself, compiled with gcc."""
+    import subprocess
+    from paper_2205_05982_amd import vqs
+    src = tmp_path / "layout.c"
+    src.write_text(
+        '#include <stddef.h>\n#include <stdio.h>\n#include "vqs.h"\n'
+        'int main(void) { printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(vqs_options),'
+        ' offsetof(vqs_options, train_steps), offsetof(vqs_options, model_seed),'
+        ' offsetof(vqs_options, level_mode), sizeof(vqs_stats), offsetof(vqs_stats, train_loss)); return 0; }\n')
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run(["gcc", "-I", inc, str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert got == [ctypes.sizeof(vqs.Options), vqs.Options.train_steps.offset, vqs.Options.model_seed.offset,
+                   vqs.Options.level_mode.offset, ctypes.sizeof(vqs.Stats), vqs.Stats.train_loss.offset]
