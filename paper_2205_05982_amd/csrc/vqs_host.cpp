@@ -69,7 +69,7 @@ struct Workspace {
   bool have_result = false;
   // learned splitter buffers
   char* lmem = nullptr;
-  uint64_t lcap_m = 0, lcap_tiles = 0;
+  uint64_t lcap_m = 0, lcap_chunks = 0;
   uint64_t* l_sample = nullptr;
   float* l_x = nullptr;
   float* l_t = nullptr;
@@ -584,15 +584,15 @@ int sort_impl(void* keys, const int64_t* offsets, uint64_t nseg, uint64_t n, int
 
 // ---- learned splitter ------------------------------------------------------------------
 
-int ensure_learned(Workspace* ws, uint64_t m, uint64_t ntiles) {
-  if (ws->lmem && m <= ws->lcap_m && ntiles <= ws->lcap_tiles) return VQS_OK;
+int ensure_learned(Workspace* ws, uint64_t m, uint64_t nchunks) {
+  if (ws->lmem && m <= ws->lcap_m && nchunks <= ws->lcap_chunks) return VQS_OK;
   if (ws->lmem) {
     (void)hipStreamSynchronize(ws->stream);
     (void)hipFree(ws->lmem);
     ws->lmem = nullptr;
   }
   m = std::max(m, ws->lcap_m);
-  ntiles = std::max(ntiles, ws->lcap_tiles);
+  nchunks = std::max(nchunks, ws->lcap_chunks);
   size_t off = 0;
   auto take = [&](size_t b) {
     size_t o = off;
@@ -601,7 +601,7 @@ int ensure_learned(Workspace* ws, uint64_t m, uint64_t ntiles) {
   };
   const size_t o_sample = take(m * 8), o_x = take(m * 4), o_t = take(m * 4), o_p = take(MLP_NBLOCK * 4),
                o_mom = take((2 * MLP_NPARAM + 1) * 4), o_thr = take(NBUCKET * 8), o_nv = take(16),
-               o_hist = take(ntiles * NBUCKET * 4), o_tot = take(NBUCKET * 8), o_off = take((NBUCKET + 1) * 8),
+               o_hist = take(nchunks * NBUCKET * 4), o_tot = take(NBUCKET * 8), o_off = take((NBUCKET + 1) * 8),
                o_sum = take(64);
   void* mem = nullptr;
   if (hipMalloc(&mem, off) != hipSuccess || !mem) {
@@ -611,7 +611,7 @@ int ensure_learned(Workspace* ws, uint64_t m, uint64_t ntiles) {
   char* b = (char*)mem;
   ws->lmem = b;
   ws->lcap_m = m;
-  ws->lcap_tiles = ntiles;
+  ws->lcap_chunks = nchunks;
   ws->l_sample = (uint64_t*)(b + o_sample);
   ws->l_x = (float*)(b + o_x);
   ws->l_t = (float*)(b + o_t);
@@ -652,7 +652,7 @@ int learned_locked(Workspace* ws, void* keys, uint64_t n, const vqs_options* o, 
   chunks = std::max<uint64_t>(chunks, 8);
   chunks = std::min<uint64_t>(chunks, n / 8);
   const uint64_t m = chunks * 8;
-  const uint64_t ntiles = (n + LEARN_TILE - 1) / LEARN_TILE;
+  const uint64_t nchunks = (n + (uint64_t)LEARN_TILE * CHUNK_TILES - 1) / ((uint64_t)LEARN_TILE * CHUNK_TILES);
   // the workspace for the final plain phase first: it owns the scatter target
   Plan pl;
   Params base;
@@ -665,7 +665,7 @@ int learned_locked(Workspace* ws, void* keys, uint64_t n, const vqs_options* o, 
     rc = prepare(ws, keys, n, NBUCKET, VQS_U64, 1, &plain, &pl, &base);
     if (rc != VQS_OK) return rc;
   }
-  rc = ensure_learned(ws, m, ntiles);
+  rc = ensure_learned(ws, m, nchunks);
   if (rc != VQS_OK) return rc;
   ws->have_result = false;
   ws->learned_ran = false;
@@ -698,11 +698,11 @@ int learned_locked(Workspace* ws, void* keys, uint64_t n, const vqs_options* o, 
   e = ws->timed(6, -1, [&] { return launch_thresholds(ws->l_params, ws->l_thr, ws->l_nvalid, stream); });
   if (e != hipSuccess) return VQS_EHIP;
   e = ws->timed(7, -1, [&] {
-    hipError_t r = launch_histogram((const uint64_t*)keys, n, ws->l_thr, ws->l_nvalid, ws->l_hist, ntiles, stream);
-    if (r == hipSuccess) r = launch_scan(ws->l_hist, ntiles, ws->l_totals, stream);
+    hipError_t r = launch_histogram((const uint64_t*)keys, n, ws->l_thr, ws->l_nvalid, ws->l_hist, nchunks, stream);
+    if (r == hipSuccess) r = launch_scan(ws->l_hist, nchunks, ws->l_totals, stream);
     if (r == hipSuccess) r = launch_offsets(ws->l_totals, n, over, ws->l_offsets, ws->l_summary, stream);
     if (r == hipSuccess)
-      r = launch_scatter((const uint64_t*)keys, n, ws->l_thr, ws->l_nvalid, ws->l_hist, ntiles, ws->l_offsets,
+      r = launch_scatter((const uint64_t*)keys, n, ws->l_thr, ws->l_nvalid, ws->l_hist, nchunks, ws->l_offsets,
                          (uint64_t*)base.scratch, stream);
     return r;
   });

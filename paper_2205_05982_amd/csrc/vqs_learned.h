@@ -22,6 +22,7 @@ constexpr int MLP_W1 = 0, MLP_B1 = 32, MLP_W2 = 64, MLP_B2 = 64 + 1024, MLP_W3 =
               MLP_B3 = MLP_W3 + 32, MLP_X0 = MLP_B3 + 1, MLP_XS = MLP_X0 + 1;
 constexpr int MLP_MAX_BATCH = 256;     // samples per optimiser step (one workgroup)
 constexpr int LEARN_TILE = 4096;       // keys per histogram / scatter tile
+constexpr int CHUNK_TILES = 16;        // consecutive tiles counted together and scattered by one workgroup
 constexpr int NBUCKET = 256;
 
 struct TrainArgs {
@@ -47,12 +48,12 @@ hipError_t launch_thresholds(const float* params, uint64_t* thr, uint32_t* nvali
 hipError_t launch_classify(const uint64_t* keys, uint64_t n, const uint64_t* thr, const uint32_t* nvalid,
                            int32_t* out, hipStream_t s);
 hipError_t launch_histogram(const uint64_t* keys, uint64_t n, const uint64_t* thr, const uint32_t* nvalid,
-                            uint32_t* hist, uint64_t ntiles, hipStream_t s);
-hipError_t launch_scan(uint32_t* hist, uint64_t ntiles, uint64_t* totals, hipStream_t s);
+                            uint32_t* hist, uint64_t nchunks, hipStream_t s);
+hipError_t launch_scan(uint32_t* hist, uint64_t nchunks, uint64_t* totals, hipStream_t s);
 hipError_t launch_offsets(const uint64_t* totals, uint64_t n, float overflow_factor, int64_t* offsets,
                           uint64_t* summary, hipStream_t s);
 hipError_t launch_scatter(const uint64_t* keys, uint64_t n, const uint64_t* thr, const uint32_t* nvalid,
-                          const uint32_t* hist, uint64_t ntiles, const int64_t* offsets, uint64_t* out,
+                          const uint32_t* hist, uint64_t nchunks, const int64_t* offsets, uint64_t* out,
                           hipStream_t s);
 
 }  // namespace vqs

@@ -59,13 +59,32 @@ __device__ inline uint64_t splitmix_at(uint64_t seed, uint64_t c) {
   return z ^ (z >> 31);
 }
 
-// number of the first nvalid thresholds that are <= k (thresholds non-decreasing)
-__device__ inline int classify(const uint64_t* thr, int nvalid, uint64_t k) {
+// The 255 thresholds of a classification sit in LDS in breadth-first order of the implicit
+// binary search tree: level L (0..7) holds slots 2^L - 1 .. 2^(L+1) - 2, slot 2^L - 1 + j
+// holding threshold (2j + 1) * 2^(7-L) - 1.  The nodes one search step can reach are then
+// adjacent words, not words 2^(8-L) apart that all fall into the same LDS bank.
+__device__ inline int tree_source(int slot) {
+  const int L = 31 - __clz(slot + 1);
+  const int j = slot + 1 - (1 << L);
+  return (2 * j + 1) * (128 >> L) - 1;
+}
+
+__device__ inline void tree_load(uint64_t* E, const uint64_t* thr) {
+  for (int i = threadIdx.x; i < NBUCKET - 1; i += blockDim.x) E[i] = thr[tree_source(i)];
+}
+
+// number of the first nvalid thresholds that are <= k (thresholds non-decreasing), by
+// binary search over the tree: at level L the search stands at b, a multiple of 2^(8-L),
+// and compares threshold b + 2^(7-L) - 1, the tree's node b >> (8-L) of that level.  Every
+// level loads its node and selects without a branch, so that the searches of several keys
+// of a thread interleave.
+__device__ inline int classify(const uint64_t* E, int nvalid, uint64_t k) {
   int b = 0;
 #pragma unroll
-  for (int step = 128; step >= 1; step >>= 1) {
-    const int c = b + step;
-    if (c <= nvalid && thr[c - 1] <= k) b = c;
+  for (int L = 0; L < 8; L++) {
+    const int c = b + (128 >> L);
+    const uint64_t e = E[(1 << L) - 1 + (b >> (8 - L))];
+    b = ((c <= nvalid) & (e <= k)) ? c : b;
   }
   return b;
 }
@@ -524,68 +543,96 @@ __global__ void __launch_bounds__(THR_P) thresholds_kernel(const float* params, 
 
 __global__ void classify_kernel(const uint64_t* keys, uint64_t n, const uint64_t* thr, const uint32_t* nvalid,
                                 int32_t* out) {
-  __shared__ uint64_t T[NBUCKET];
-  for (int i = threadIdx.x; i < NBUCKET - 1; i += blockDim.x) T[i] = thr[i];
+  __shared__ uint64_t E[NBUCKET];
+  tree_load(E, thr);
   __syncthreads();
   const int J = (int)*nvalid;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
-    out[i] = classify(T, J, keys[i]);
+    out[i] = classify(E, J, keys[i]);
 }
 
 // ---- 256-way partition ---------------------------------------------------------------------
+//
+// The input is cut into tiles of LEARN_TILE keys and the tiles into chunks of CHUNK_TILES
+// consecutive tiles.  histogram_kernel counts every chunk's keys per bucket (chunk-major
+// counts), scan_kernel turns each bucket's column into exclusive prefixes over the chunks,
+// and scatter_kernel walks the tiles of a chunk in order in one workgroup, so that each
+// bucket's keys of one chunk land as one contiguous stretch of the output, written from one
+// XCD (partial cache lines only where a stretch begins or ends).
 
 constexpr int LT_P = 256;
 constexpr int LT_PER = LEARN_TILE / LT_P;   // 16 keys per thread
+constexpr int LT_NW = LT_P / WAVE;
+static_assert(LT_P == NBUCKET, "thread b of a workgroup owns bucket b");
 
-// per-tile bucket counts, stored bucket-major: hist[b * ntiles + tile]
+// per-chunk bucket counts, chunk-major: hist[chunk * NBUCKET + b]
 __global__ void __launch_bounds__(LT_P) histogram_kernel(const uint64_t* keys, uint64_t n, const uint64_t* thr,
-                                                         const uint32_t* nvalid, uint32_t* hist, uint64_t ntiles) {
-  __shared__ uint64_t T[NBUCKET];
-  __shared__ uint32_t C[NBUCKET];
-  for (int i = threadIdx.x; i < NBUCKET - 1; i += LT_P) T[i] = thr[i];
+                                                         const uint32_t* nvalid, uint32_t* hist, uint64_t nchunks) {
+  __shared__ uint64_t E[NBUCKET];
+  __shared__ uint32_t C[LT_NW][NBUCKET];     // one row per wave: fewer colliding LDS atomics
+  tree_load(E, thr);
   const int J = (int)*nvalid;
-  for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    C[threadIdx.x] = 0;
+  const int w = threadIdx.x / WAVE;
+  for (uint64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+    for (int i = threadIdx.x; i < LT_NW * NBUCKET; i += LT_P) (&C[0][0])[i] = 0;
     __syncthreads();
-    const uint64_t base = tile * LEARN_TILE;
-#pragma unroll 4
-    for (int q = 0; q < LT_PER; q++) {
-      const uint64_t i = base + (uint64_t)q * LT_P + threadIdx.x;
-      if (i < n) atomicAdd(&C[classify(T, J, keys[i])], 1u);
+    for (uint64_t tile = ch * CHUNK_TILES; tile < (ch + 1) * CHUNK_TILES; tile++) {
+      const uint64_t base = tile * LEARN_TILE;
+      if (base >= n) break;
+      if (base + LEARN_TILE <= n) {
+        uint64_t k[LT_PER];
+#pragma unroll
+        for (int q = 0; q < LT_PER; q++) k[q] = keys[base + (uint64_t)q * LT_P + threadIdx.x];
+        int bb[LT_PER];
+#pragma unroll
+        for (int q = 0; q < LT_PER; q++) bb[q] = classify(E, J, k[q]);
+#pragma unroll
+        for (int q = 0; q < LT_PER; q++) atomicAdd(&C[w][bb[q]], 1u);
+      } else {
+        for (int q = 0; q < LT_PER; q++) {
+          const uint64_t i = base + (uint64_t)q * LT_P + threadIdx.x;
+          if (i < n) atomicAdd(&C[w][classify(E, J, keys[i])], 1u);
+        }
+      }
     }
     __syncthreads();
-    hist[(uint64_t)threadIdx.x * ntiles + tile] = C[threadIdx.x];
+    uint32_t s = 0;
+#pragma unroll
+    for (int r = 0; r < LT_NW; r++) s += C[r][threadIdx.x];
+    hist[ch * NBUCKET + threadIdx.x] = s;
     __syncthreads();
   }
 }
 
-// exclusive scan of each bucket's row over tiles, in place; totals[b] = row sum
-__global__ void __launch_bounds__(LT_P) scan_kernel(uint32_t* hist, uint64_t ntiles, uint64_t* totals) {
-  __shared__ uint64_t W[LT_P / WAVE];
+// bucket b = blockIdx.x: the column hist[* NBUCKET + b] becomes its exclusive prefix over
+// the chunks, in place; totals[b] = the column's sum.  Each thread takes a contiguous run
+// of chunks (independent loads), then one workgroup scan of the run sums.
+__global__ void __launch_bounds__(LT_P) scan_kernel(uint32_t* hist, uint64_t nchunks, uint64_t* totals) {
+  __shared__ uint64_t W[LT_NW];
   const uint64_t b = blockIdx.x;
-  uint32_t* row = hist + b * ntiles;
-  uint64_t carry = 0;
+  const uint64_t per = (nchunks + LT_P - 1) / LT_P;
+  const uint64_t c0 = min((uint64_t)threadIdx.x * per, nchunks), c1 = min(c0 + per, nchunks);
+  uint64_t v = 0;
+#pragma unroll 8
+  for (uint64_t c = c0; c < c1; c++) v += hist[c * NBUCKET + b];
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
-  for (uint64_t c0 = 0; c0 < ntiles; c0 += LT_P) {
-    const uint64_t i = c0 + threadIdx.x;
-    const uint64_t v = i < ntiles ? row[i] : 0;
-    uint64_t inc = v;
+  uint64_t inc = v;
 #pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-      const uint64_t o = (uint64_t)__shfl_up((long long)inc, d);
-      if (lane >= d) inc += o;
-    }
-    if (lane == WAVE - 1) W[w] = inc;
-    __syncthreads();
-    uint64_t before = carry;
-    for (int k = 0; k < w; k++) before += W[k];
-    uint64_t tot = 0;
-    for (int k = 0; k < LT_P / WAVE; k++) tot += W[k];
-    if (i < ntiles) row[i] = (uint32_t)(before + inc - v);
-    carry += tot;
-    __syncthreads();
+  for (int d = 1; d < WAVE; d <<= 1) {
+    const uint64_t o = (uint64_t)__shfl_up((long long)inc, d);
+    if (lane >= d) inc += o;
   }
-  if (threadIdx.x == 0) totals[b] = carry;
+  if (lane == WAVE - 1) W[w] = inc;
+  __syncthreads();
+  uint64_t run = inc - v;
+  for (int k = 0; k < w; k++) run += W[k];
+#pragma unroll 8
+  for (uint64_t c = c0; c < c1; c++) {
+    const uint32_t x = hist[c * NBUCKET + b];
+    hist[c * NBUCKET + b] = (uint32_t)run;
+    run += x;
+  }
+  if (threadIdx.x == LT_P - 1) totals[b] = run;
 }
 
 // bucket starts (offsets[0..256]) and a summary: [0] largest bucket, [1] buckets above
@@ -608,73 +655,102 @@ __global__ void offsets_kernel(const uint64_t* totals, uint64_t n, float overflo
   summary[2] = nonempty;
 }
 
-// one pass: classify, rank inside the tile per bucket, stage bucket-major in LDS, write
-// every bucket's run of the tile to offsets[b] + (keys of bucket b in earlier tiles)
+// One chunk per workgroup iteration, its tiles in order.  Per tile: classify, rank inside
+// the tile per bucket (LDS atomics), stage bucket-major in LDS, write each bucket's run of
+// the tile to the bucket's running destination (offsets[b] + its keys in earlier chunks +
+// its keys in earlier tiles of this chunk).  The next tile's loads are issued before the
+// current tile is written out.
 __global__ void __launch_bounds__(LT_P) scatter_kernel(const uint64_t* keys, uint64_t n, const uint64_t* thr,
                                                        const uint32_t* nvalid, const uint32_t* hist,
-                                                       uint64_t ntiles, const int64_t* offsets, uint64_t* out) {
-  __shared__ uint64_t T[NBUCKET];
-  __shared__ uint32_t C[NBUCKET];
-  __shared__ uint32_t LO[NBUCKET];
-  __shared__ uint64_t DST[NBUCKET];
+                                                       uint64_t nchunks, const int64_t* offsets, uint64_t* out) {
+  __shared__ uint64_t E[NBUCKET];
+  __shared__ uint32_t C[NBUCKET];            // the tile's bucket counts; zero between tiles
+  __shared__ uint32_t LO[NBUCKET];           // start of bucket b in the staged tile
+  __shared__ uint64_t DL[NBUCKET];           // destination of staged slot s of bucket b: DL[b] + s
   __shared__ uint64_t stage[LEARN_TILE];
   __shared__ uint8_t bid[LEARN_TILE];
-  __shared__ uint32_t W[LT_P / WAVE];
-  for (int i = threadIdx.x; i < NBUCKET - 1; i += LT_P) T[i] = thr[i];
+  __shared__ uint32_t W[LT_NW];
+  tree_load(E, thr);
+  C[threadIdx.x] = 0;
   const int J = (int)*nvalid;
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
-  for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    C[threadIdx.x] = 0;
-    DST[threadIdx.x] = (uint64_t)offsets[threadIdx.x] + hist[(uint64_t)threadIdx.x * ntiles + tile];
-    __syncthreads();
+  const uint64_t ntiles = (n + LEARN_TILE - 1) / LEARN_TILE;
+  uint64_t k[LT_PER];
+  auto load = [&](uint64_t tile) {
     const uint64_t base = tile * LEARN_TILE;
-    uint64_t k[LT_PER];
-    uint32_t r[LT_PER];
-    uint8_t bb[LT_PER];
+    if (base + LEARN_TILE <= n) {
 #pragma unroll
-    for (int q = 0; q < LT_PER; q++) {
-      const uint64_t i = base + (uint64_t)q * LT_P + threadIdx.x;
-      if (i < n) {
-        k[q] = keys[i];
-        const int b = classify(T, J, k[q]);
-        bb[q] = (uint8_t)b;
-        r[q] = atomicAdd(&C[b], 1u);
+      for (int q = 0; q < LT_PER; q++) k[q] = keys[base + (uint64_t)q * LT_P + threadIdx.x];
+    } else {
+#pragma unroll
+      for (int q = 0; q < LT_PER; q++) {
+        const uint64_t i = base + (uint64_t)q * LT_P + threadIdx.x;
+        k[q] = i < n ? keys[i] : 0;
       }
     }
+  };
+  for (uint64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+    // thread b alone reads and writes dst (its bucket's running destination)
+    uint64_t dst = (uint64_t)offsets[threadIdx.x] + hist[ch * NBUCKET + threadIdx.x];
+    const uint64_t t0 = ch * CHUNK_TILES, t1 = min(t0 + CHUNK_TILES, ntiles);
+    load(t0);
     __syncthreads();
-    // exclusive scan of the tile's bucket counts
-    {
-      const uint32_t v = C[threadIdx.x];
-      uint32_t inc = v;
+    for (uint64_t tile = t0; tile < t1; tile++) {
+      const uint32_t cnt = (uint32_t)min((uint64_t)LEARN_TILE, n - tile * LEARN_TILE);
+      int bb[LT_PER];
+      uint32_t r[LT_PER];
 #pragma unroll
-      for (int d = 1; d < WAVE; d <<= 1) {
-        const uint32_t o = (uint32_t)__shfl_up((int)inc, d);
-        if (lane >= d) inc += o;
+      for (int q = 0; q < LT_PER; q++) bb[q] = classify(E, J, k[q]);
+      if (cnt == LEARN_TILE) {
+#pragma unroll
+        for (int q = 0; q < LT_PER; q++) r[q] = atomicAdd(&C[bb[q]], 1u);
+      } else {
+#pragma unroll
+        for (int q = 0; q < LT_PER; q++)
+          r[q] = (uint32_t)(q * LT_P + threadIdx.x) < cnt ? atomicAdd(&C[bb[q]], 1u) : 0u;
       }
-      if (lane == WAVE - 1) W[w] = inc;
       __syncthreads();
-      uint32_t before = 0;
-      for (int kk = 0; kk < w; kk++) before += W[kk];
-      LO[threadIdx.x] = before + inc - v;
-    }
-    __syncthreads();
+      {  // exclusive scan of the tile's bucket counts; thread b owns C[b] from here on
+        const uint32_t v = C[threadIdx.x];
+        uint32_t inc = v;
 #pragma unroll
-    for (int q = 0; q < LT_PER; q++) {
-      const uint64_t i = base + (uint64_t)q * LT_P + threadIdx.x;
-      if (i < n) {
-        const uint32_t pos = LO[bb[q]] + r[q];
-        stage[pos] = k[q];
-        bid[pos] = bb[q];
+        for (int d = 1; d < WAVE; d <<= 1) {
+          const uint32_t o = (uint32_t)__shfl_up((int)inc, d);
+          if (lane >= d) inc += o;
+        }
+        if (lane == WAVE - 1) W[w] = inc;
+        __syncthreads();
+        uint32_t lo = inc - v;
+        for (int kk = 0; kk < w; kk++) lo += W[kk];
+        LO[threadIdx.x] = lo;
+        DL[threadIdx.x] = dst - lo;
+        dst += v;
+        C[threadIdx.x] = 0;
       }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < LT_PER; q++) {
+        if ((uint32_t)(q * LT_P + threadIdx.x) < cnt) {
+          const uint32_t pos = LO[bb[q]] + r[q];
+          stage[pos] = k[q];
+          bid[pos] = (uint8_t)bb[q];
+        }
+      }
+      __syncthreads();
+      if (tile + 1 < t1) load(tile + 1);
+      // destinations lie below n by construction (the histogram counted these very keys);
+      // the clamp keeps every store inside the output even for an input changed in between
+      if (cnt == LEARN_TILE) {
+#pragma unroll
+        for (int q = 0; q < LT_PER; q++) {
+          const uint32_t s = q * LT_P + threadIdx.x;
+          out[min(DL[bid[s]] + s, n - 1)] = stage[s];
+        }
+      } else {
+        for (uint32_t s = threadIdx.x; s < cnt; s += LT_P) out[min(DL[bid[s]] + s, n - 1)] = stage[s];
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    const uint32_t cnt = (uint32_t)((n - base) < (uint64_t)LEARN_TILE ? (n - base) : (uint64_t)LEARN_TILE);
-    for (uint32_t s = threadIdx.x; s < cnt; s += LT_P) {
-      const int b = bid[s];
-      const uint64_t d = DST[b] + (s - LO[b]);
-      if (d < n) out[d] = stage[s];
-    }
-    __syncthreads();
   }
 }
 
@@ -736,14 +812,14 @@ hipError_t launch_classify(const uint64_t* keys, uint64_t n, const uint64_t* thr
 }
 
 hipError_t launch_histogram(const uint64_t* keys, uint64_t n, const uint64_t* thr, const uint32_t* nvalid,
-                            uint32_t* hist, uint64_t ntiles, hipStream_t s) {
-  hipLaunchKernelGGL(histogram_kernel, dim3(grid_for(ntiles, 1, 4096)), dim3(LT_P), 0, s, keys, n, thr, nvalid, hist,
-                     ntiles);
+                            uint32_t* hist, uint64_t nchunks, hipStream_t s) {
+  hipLaunchKernelGGL(histogram_kernel, dim3(grid_for(nchunks, 1, 1 << 20)), dim3(LT_P), 0, s, keys, n, thr, nvalid,
+                     hist, nchunks);
   return hipGetLastError();
 }
 
-hipError_t launch_scan(uint32_t* hist, uint64_t ntiles, uint64_t* totals, hipStream_t s) {
-  hipLaunchKernelGGL(scan_kernel, dim3(NBUCKET), dim3(LT_P), 0, s, hist, ntiles, totals);
+hipError_t launch_scan(uint32_t* hist, uint64_t nchunks, uint64_t* totals, hipStream_t s) {
+  hipLaunchKernelGGL(scan_kernel, dim3(NBUCKET), dim3(LT_P), 0, s, hist, nchunks, totals);
   return hipGetLastError();
 }
 
@@ -754,10 +830,10 @@ hipError_t launch_offsets(const uint64_t* totals, uint64_t n, float overflow_fac
 }
 
 hipError_t launch_scatter(const uint64_t* keys, uint64_t n, const uint64_t* thr, const uint32_t* nvalid,
-                          const uint32_t* hist, uint64_t ntiles, const int64_t* offsets, uint64_t* out,
+                          const uint32_t* hist, uint64_t nchunks, const int64_t* offsets, uint64_t* out,
                           hipStream_t s) {
-  hipLaunchKernelGGL(scatter_kernel, dim3(grid_for(ntiles, 1, 2048)), dim3(LT_P), 0, s, keys, n, thr, nvalid, hist,
-                     ntiles, offsets, out);
+  hipLaunchKernelGGL(scatter_kernel, dim3(grid_for(nchunks, 1, 1 << 20)), dim3(LT_P), 0, s, keys, n, thr, nvalid,
+                     hist, nchunks, offsets, out);
   return hipGetLastError();
 }
 
