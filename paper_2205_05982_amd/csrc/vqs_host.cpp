@@ -280,6 +280,7 @@ int ensure_workspace(Workspace* ws, const Plan& pl) {
   const size_t o_ctr = take((size_t)cap_levels * sizeof(LevelCtr));
   const size_t o_flags = take(cap_tiles * 8);
   const size_t o_tmin = take(cap_tiles * sizeof(u128k));
+  const size_t o_trmin = take(cap_tiles * sizeof(u128k));
   const size_t o_run0 = take(cap_tiles * sizeof(TileRun));
   const size_t o_run1 = take(cap_tiles * sizeof(TileRun));
   const size_t o_tref = take(cap_tiles * sizeof(TileRef));
@@ -309,6 +310,7 @@ int ensure_workspace(Workspace* ws, const Plan& pl) {
   p.lvl_ctr = (LevelCtr*)(ws->mem + o_ctr);
   p.flags = (unsigned long long*)(ws->mem + o_flags);
   p.tilemin = (u128k*)(ws->mem + o_tmin);
+  p.tilermin = (u128k*)(ws->mem + o_trmin);
   p.runs[0] = (TileRun*)(ws->mem + o_run0);
   p.runs[1] = (TileRun*)(ws->mem + o_run1);
   p.tref = (TileRef*)(ws->mem + o_tref);
@@ -863,7 +865,7 @@ uint64_t vqs_workspace_bytes(uint64_t n, uint64_t nseg, int key_type, const vqs_
   if (make_plan(n, nseg ? nseg : 1, key_type, 1, options, g, &pl) != VQS_OK) return 0;
   uint64_t b = (n + 32) * (uint64_t)pl.ks + 64;
   b += 2 * pl.cap_lvl * (sizeof(Seg) + 8) + (uint64_t)pl.max_levels * sizeof(LevelCtr);
-  b += pl.cap_tiles * (8 + sizeof(u128k) + 2 * sizeof(TileRun) + sizeof(TileRef) + 4) + pl.cap_solo * sizeof(Seg) +
+  b += pl.cap_tiles * (8 + 2 * sizeof(u128k) + 2 * sizeof(TileRun) + sizeof(TileRef) + 4) + pl.cap_solo * sizeof(Seg) +
        4096;
   return b;
 }

@@ -99,6 +99,7 @@ struct Tile {
   struct Aux {
     uint32_t cnt[I][NW];
     R wmin[NW];
+    R wrmin[NW];
     R pivot;
   };
 
@@ -140,9 +141,10 @@ struct Tile {
   // Classify against the pivot (left: not after it; strict: before it), rank stably,
   // stage in LDS (left keys from 0 upward, right keys from nvalid-1 downward).  Returns
   // the tile's left count; *tmin gets the tile minimum (thread 0), and thread 0 calls
-  // publish(left count, minimum) as soon as both are known, before the keys are
-  // staged.  Ends with a barrier.
-  template <class Pub>
+  // publish(left count, minimum, minimum of the right keys) as soon as they are known,
+  // before the keys are staged (the last is the largest key value unless RMIN).  Ends
+  // with a barrier.
+  template <bool RMIN = false, class Pub>
   __device__ static uint32_t rank_and_stage(S* stage, Aux& sh, const R (&key)[I][V], uint64_t k,
                                             uint64_t vs, uint64_t ve, R pivot, bool strict, R* tmin,
                                             Pub&& publish) {
@@ -151,6 +153,7 @@ struct Tile {
     uint32_t pre[I];
     uint32_t flag[I];  // bit q: key (j, q) goes left
     R mn = K::maxv();
+    R rmn = K::maxv();
 #pragma unroll
     for (int j = 0; j < I; j++) {
       const uint64_t v0 = (k * TC + (uint64_t)j * P + tid) * V;
@@ -160,6 +163,7 @@ struct Tile {
         const bool valid = (v0 + q >= vs) && (v0 + q < ve);
         const bool left = valid && (strict ? K::lt(key[j][q], pivot) : !K::lt(pivot, key[j][q]));
         if (valid) mn = K::kmin(mn, key[j][q]);
+        if (RMIN && valid && !left) rmn = K::kmin(rmn, key[j][q]);
         const uint64_t m = ballot(left);
         lanepre += mbcnt(m);
         tot += __popcll(m);
@@ -171,6 +175,10 @@ struct Tile {
     }
     mn = wave_min<K>(mn);
     if ((tid & (WAVE - 1)) == 0) sh.wmin[w] = mn;
+    if constexpr (RMIN) {
+      rmn = wave_min<K>(rmn);
+      if ((tid & (WAVE - 1)) == 0) sh.wrmin[w] = rmn;
+    }
     __syncthreads();
     uint32_t total = 0, mybase[I];
 #pragma unroll
@@ -187,8 +195,13 @@ struct Tile {
       R m2 = sh.wmin[0];
 #pragma unroll
       for (int ww = 1; ww < NW; ww++) m2 = K::kmin(m2, sh.wmin[ww]);
+      R r2 = K::maxv();
+      if constexpr (RMIN) {
+#pragma unroll
+        for (int ww = 0; ww < NW; ww++) r2 = K::kmin(r2, sh.wrmin[ww]);
+      }
       *tmin = m2;
-      publish(total, m2);
+      publish(total, m2, r2);
     }
     const uint32_t nvalid = (uint32_t)(ve - vs);
 #pragma unroll
@@ -363,6 +376,7 @@ __device__ inline Routed route_decide(const Params& p, Seg s) {
     r.dest = RT_NONE;
   } else if (len <= p.solo_max) {
     r.dest = RT_SOLO;
+    r.s.flags &= ~(SEG_MAXK | SEG_MINR);
   } else if (s.depth > s.limit) {
     if (!(s.flags & SEG_FALLBACK)) {
       r.fb_enter = true;
@@ -403,6 +417,12 @@ __device__ inline Seg make_seg(uint64_t b, uint64_t e, uint32_t depth, uint32_t 
   s.flags = flags;
   to_words<K>(pv, s.pv_lo, s.pv_hi);
   return s;
+}
+
+// Whether look-back levels foresee degenerate partitions (see pivot_kernel) for K.
+template <class K>
+constexpr bool foresee_degenerate() {
+  return K::SIZE == 4 || K::SIZE == 8;
 }
 
 // ---- level kernel ------------------------------------------------------------------------
@@ -478,6 +498,10 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
     __syncthreads();
     const int si = sh_seg;
     const Seg sg = segs[si];
+    if (sg.flags & SEG_SKIP) {   // finished by the planning before this launch
+      __syncthreads();
+      continue;
+    }
     const unsigned long long g0 = tbase[si];
     const uint64_t ntile_seg = tiles_of(sg.b, sg.e, p.off, T);
     const uint64_t k = (sg.b + p.off) / T + (g - g0);
@@ -506,14 +530,20 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
     R tmin;
     // publish the tile minimum, then the left count (the minimum is made visible
     // before the count by waiting for its stores to complete)
-    const uint32_t nl = TL::rank_and_stage(stage, sh, key, k, vs, ve, pivot, (sg.flags & SEG_STRICT) != 0, &tmin,
-                                           [&](uint32_t cnt, R m) {
+    const uint32_t nl = TL::template rank_and_stage<foresee_degenerate<K>()>(
+        stage, sh, key, k, vs, ve, pivot, (sg.flags & SEG_STRICT) != 0, &tmin, [&](uint32_t cnt, R m, R rm) {
                                              uint64_t lo, hi;
                                              to_words<K>(m, lo, hi);
                                              __hip_atomic_store(&p.tilemin[g].lo, lo, __ATOMIC_RELAXED,
                                                                 __HIP_MEMORY_SCOPE_AGENT);
                                              __hip_atomic_store(&p.tilemin[g].hi, hi, __ATOMIC_RELAXED,
                                                                 __HIP_MEMORY_SCOPE_AGENT);
+                                             if constexpr (foresee_degenerate<K>()) {
+                                               // for the next level's planning only (no order needed)
+                                               to_words<K>(rm, lo, hi);
+                                               p.tilermin[g].lo = lo;
+                                               p.tilermin[g].hi = hi;
+                                             }
                                              __atomic_signal_fence(__ATOMIC_SEQ_CST);
                                              __builtin_amdgcn_s_waitcnt(0);
                                              __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -668,7 +698,10 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
           if (tid == 0) atomicAdd(&p.stats->all_equal, 1ull);
           retire_equal(sg.b, sg.e, false);
         } else if (tid == 0) {
-          route<K, T>(p, make_seg<K>(sg.b, sg.e, sg.depth + 1, sg.limit, cf | SEG_OVERRIDE | SEG_PIVOT, mn), L + 1);
+          // the range's largest key is the pivot (every key went left)
+          Seg r = make_seg<K>(sg.b, sg.e, sg.depth + 1, sg.limit, cf | SEG_OVERRIDE | SEG_PIVOT | SEG_MAXK, mn);
+          to_words<K>(pivot, r.mx_lo, r.mx_hi);
+          route<K, T>(p, r, L + 1);
         }
       } else if (bound == sg.e) {
         // fallback mode, degenerate: split off the keys equal to the pivot (the maximum)
@@ -676,8 +709,22 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
           route<K, T>(p, make_seg<K>(sg.b, sg.e, sg.depth + 1, sg.limit, cf | SEG_OVERRIDE | SEG_PIVOT | SEG_STRICT, pivot),
                       L + 1);
       } else if (tid == 0) {
-        route<K, T>(p, make_seg<K>(sg.b, bound, sg.depth + 1, sg.limit, cf, pivot), L + 1);
-        route<K, T>(p, make_seg<K>(bound, sg.e, sg.depth + 1, sg.limit, cf, pivot), L + 1);
+        Seg lc = make_seg<K>(sg.b, bound, sg.depth + 1, sg.limit, cf, pivot);
+        Seg rc = make_seg<K>(bound, sg.e, sg.depth + 1, sg.limit, cf, pivot);
+        if (!fb) {
+          // for the next level's planning: the left part's largest key is the pivot (a key
+          // of the range, and keys equal to it go left), the right part's is the range's
+          // when that is known; their minima are those this level gathers for range si
+          lc.flags |= SEG_MAXK;
+          to_words<K>(pivot, lc.mx_lo, lc.mx_hi);
+          rc.flags |= SEG_MINR | (sg.flags & SEG_MAXK);
+          rc.mx_lo = sg.mx_lo;
+          rc.mx_hi = sg.mx_hi;
+          lc.rt_b = rc.rt_b = (uint32_t)g0;
+          lc.rt_n = rc.rt_n = (uint32_t)ntile_seg;
+        }
+        route<K, T>(p, lc, L + 1);
+        route<K, T>(p, rc, L + 1);
       }
     }
     tiles_done++;
@@ -943,7 +990,7 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
     R tmin;
     // the tile's left count and minimum, for the planning launch after this one
     const uint32_t nl = TL::rank_and_stage(stage, sh, key, k, vs, ve, pivot, (sg.flags & SEG_STRICT) != 0, &tmin,
-                                           [&](uint32_t cnt, R m) {
+                                           [&](uint32_t cnt, R m, R) {
                                              uint64_t lo, hi;
                                              to_words<K>(m, lo, hi);
                                              p.tilemin[g].lo = lo;
@@ -1536,6 +1583,20 @@ __global__ void __launch_bounds__(LEVEL_P) runs_plan_kernel(Params p) {
 
 // ChoosePivot for every range of a level, one wave per range, before the level's
 // partition launch: the tiles then read the pivot with the range record.
+//
+// Degenerate partitions are foreseen here.  With pivot pv, a range's partition is
+// degenerate exactly when pv is its largest key, which the range record carries when
+// it is known (a left part's largest key is its parent's pivot, a right part inherits
+// its parent's).  Alg. 1 then finds the range's minimum and stops if it equals pv (all
+// keys equal), else partitions again with the minimum as pivot, one level deeper.
+// Since a partition that sends every key left leaves the keys where and as they were,
+// neither step needs this level's pass: the minimum is reduced from what the previous
+// level recorded per tile of the range's parent (the tile minima for a left part, the
+// minima of the tiles' right keys for a right part), the partition is counted as the
+// oracle counts it, and the range either leaves the level (filled with its one value)
+// or becomes that second partition.  Keys of 2 and 16 bytes (whose level kernels would
+// lose occupancy to the extra minimum), and a second partition past the depth limit,
+// take the level pass.
 constexpr int PIVOT_P = 256;
 
 template <class K>
@@ -1563,6 +1624,71 @@ __global__ void __launch_bounds__(PIVOT_P) pivot_kernel(Params p) {
           return tmode ? K::load_t(sv, tmode) : r;
         },
         sg.b, sg.e, p.seed);
+    if constexpr (foresee_degenerate<K>()) {
+      if (L > 0 && (sg.flags & SEG_MAXK) && !(sg.flags & SEG_FALLBACK) &&
+          K::eq(pv, K::from_u64x2(sg.mx_lo, sg.mx_hi))) {
+        const u128k* tm = (sg.flags & SEG_MINR) ? p.tilermin : p.tilemin;
+        R m0 = K::maxv(), m1 = K::maxv();
+#pragma unroll 4
+        for (uint32_t t = lane_id(); t < sg.rt_n; t += 2 * WAVE) {
+          m0 = K::kmin(m0, K::from_u64x2(tm[sg.rt_b + t].lo, tm[sg.rt_b + t].hi));
+          if (t + WAVE < sg.rt_n) m1 = K::kmin(m1, K::from_u64x2(tm[sg.rt_b + t + WAVE].lo, tm[sg.rt_b + t + WAVE].hi));
+        }
+        const R mn = wave_min<K>(K::kmin(m0, m1));
+        const uint64_t len = sg.e - sg.b;
+        if (K::eq(mn, pv)) {
+          // all keys equal: the caller's array holds them already unless the level reads
+          // scratch or the keys are transformed
+          if (lane_id() == 0) {
+            atomicAdd(&p.stats->partitions, 1ull);
+            atomicAdd(&p.stats->keys_partitioned, (unsigned long long)len);
+            atomicMax(&p.stats->max_depth, (unsigned long long)sg.depth);
+            atomicAdd(&p.stats->degenerate, 1ull);
+            atomicAdd(&p.stats->all_equal, 1ull);
+            atomicAdd(&p.lvl_ctr[L].keys, 0ull - (unsigned long long)len);   // keys the pass moves
+            segs[si].flags = sg.flags | SEG_SKIP;
+          }
+          if ((L & 1) != 0 || p.mode != 0) {
+            const uint64_t nch = (len + FILL_CHUNK - 1) / FILL_CHUNK;
+            unsigned long long f0 = 0;
+            if (lane_id() == 0) {
+              f0 = atomicAdd(&p.solo_ctr->count, (unsigned long long)nch);
+              atomicAdd(&p.stats->solo_items, (unsigned long long)nch);
+            }
+            f0 = __shfl(f0, 0);
+            for (uint64_t c = lane_id(); c < nch; c += WAVE) {
+              const unsigned long long i = f0 + c;
+              if (i >= p.cap_solo) {
+                set_err(p, ERR_SOLO_OVERFLOW);
+                continue;
+              }
+              Seg f{};
+              f.b = sg.b + c * FILL_CHUNK;
+              f.e = (f.b + FILL_CHUNK < sg.e) ? f.b + FILL_CHUNK : sg.e;
+              f.flags = SEG_FILL;
+              to_words<K>(pv, f.pv_lo, f.pv_hi);
+              p.solo[i] = f;
+            }
+          }
+          continue;
+        }
+        if (sg.depth + 1 <= sg.limit) {
+          if (lane_id() == 0) {
+            atomicAdd(&p.stats->partitions, 1ull);
+            atomicAdd(&p.stats->keys_partitioned, (unsigned long long)len);
+            atomicMax(&p.stats->max_depth, (unsigned long long)sg.depth);
+            atomicAdd(&p.stats->degenerate, 1ull);
+            uint64_t lo, hi;
+            to_words<K>(mn, lo, hi);
+            segs[si].pv_lo = lo;
+            segs[si].pv_hi = hi;
+            segs[si].depth = sg.depth + 1;
+            segs[si].flags = sg.flags | SEG_OVERRIDE | SEG_PIVOT;
+          }
+          continue;
+        }
+      }
+    }
     if (lane_id() == 0) {
       uint64_t lo, hi;
       to_words<K>(pv, lo, hi);
@@ -2367,7 +2493,7 @@ __global__ void __launch_bounds__(SOLO_P) __attribute__((amdgpu_waves_per_eu(sol
         R key[SI][K::V];
         TL::load(src_aligned, k, vs, ve, raw ? p.mode : 0, key);
         R tmin;
-        const uint32_t nl = TL::rank_and_stage(bufA, aux, key, k, vs, ve, pivot, strict, &tmin, [](uint32_t, R) {});
+        const uint32_t nl = TL::rank_and_stage(bufA, aux, key, k, vs, ve, pivot, strict, &tmin, [](uint32_t, R, R) {});
         const uint32_t nvalid = (uint32_t)(ve - vs);
         const uint32_t nr = nvalid - nl;
         TL::write_out_keys(bufA, dst, nl, nvalid, cur.b + excl_l, cur.e - excl_r - nr, 0, p.n_total);

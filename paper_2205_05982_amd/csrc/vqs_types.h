@@ -48,6 +48,10 @@ enum : uint32_t {
   SEG_RUNS = 256u,     // keys held as runs of the previous level's tiles (run mode)
   SEG_RIGHT = 512u,    // with SEG_RUNS: the right parts of those tiles, in reverse tile order
   SEG_COPY = 1024u,    // level entry that only gathers the runs into [b, e) (then solo)
+  SEG_MAXK = 2048u,    // mx holds the range's largest key (internal form)
+  SEG_MINR = 4096u,    // the range is the right part of the range whose tiles were
+                       // [rt_b, rt_b + rt_n) in the level that made it (else the left part)
+  SEG_SKIP = 8192u,    // finished while planning its level: the level's tiles of it do nothing
 };
 
 struct Seg {
@@ -55,7 +59,8 @@ struct Seg {
   uint32_t depth, limit;
   uint32_t flags, pad;
   uint64_t pv_lo, pv_hi;  // override pivot or fill value (internal form)
-  uint32_t rt_b, rt_n;    // SEG_RUNS: the parent range's tiles in the previous level's table
+  uint32_t rt_b, rt_n;    // the parent range's tiles in the previous level (its run table in run mode)
+  uint64_t mx_lo, mx_hi;  // SEG_MAXK: the range's largest key (internal form)
 };
 
 // Run mode: a tile of a planned level: its range (index in the level's list) and the
@@ -117,6 +122,7 @@ struct Params {
   LevelCtr* lvl_ctr;
   unsigned long long* flags;  // look-back words, one per tile
   u128k* tilemin;        // per-tile minimum (internal form)
+  u128k* tilermin;       // look-back levels: per-tile minimum of the keys that went right
   Seg* solo;
   SoloCtr* solo_ctr;
   DevStats* stats;

@@ -150,3 +150,55 @@ def test_runs_more_runs_than_the_tile_list(vqs, solo_max):
     print(f"case: one-key runs, {tiles} tiles, solo_max={solo_max}", flush=True)
     gst = _check(vqs, keys, U64, "runs", **opts)
     assert gst["degenerate"] >= 1
+
+
+def _heavy(n, kt, frac, top, seed):
+    """n keys: a fraction frac of them copies of one value, the others spread values
+    below it (top) or above it; shuffled."""
+    rng = np.random.default_rng(seed)
+    nh = int(n * frac)
+    spread = rng.integers(0, 1 << 20, n - nh)
+    heavy = np.full(nh, 1 << 20 if top else 0)
+    if not top:
+        spread = spread + 1
+    k = np.concatenate([heavy, spread])
+    rng.shuffle(k)
+    if kt in (F32, F64):
+        return (k.astype(np.float64) * 0.25 - 1000.0).astype(np.float32 if kt == F32 else np.float64)
+    return k.astype(np.uint32 if kt == U32 else np.uint64)
+
+
+@pytest.mark.parametrize("kt", [U32, U64, F32, F64])
+@pytest.mark.parametrize("asc", [True, False])
+@pytest.mark.parametrize("top", [True, False])
+def test_lookback_foreseen_degenerate_partitions(vqs, kt, asc, top):
+    """Look-back levels foresee a degenerate partition (pivot = the range's known largest
+    key) and take it, and the all-equal finding or the repeat with the minimum, without
+    a pass over the keys.  A heavy value above spread keys (top) gives long chains of
+    them, each peeling the smallest value off, until the depth limit; a heavy value
+    below them gives all-equal left parts.  Keys, order and every counter must match the
+    oracle, which makes the passes the Alg. 1 way."""
+    n = 1_500_000
+    keys = _heavy(n, kt, 0.7, top, 41 + kt)
+    print(f"case: foreseen degenerate kt={kt} asc={asc} top={top}", flush=True)
+    gst = _check(vqs, keys, kt, "lookback", asc, seed=5, solo_max=8192)
+    assert gst["degenerate"] >= 1
+
+
+@pytest.mark.parametrize("use_graph", [0, 1])
+def test_lookback_foreseen_degenerate_segmented(vqs, use_graph):
+    import torch
+    off = W.segment_offsets(40, seed=8, lo=1 << 14, hi=1 << 17)
+    parts = [_heavy(int(off[i + 1] - off[i]), U64, 0.6, i % 2 == 0, 100 + i) for i in range(len(off) - 1)]
+    keys = np.concatenate(parts)
+    want = keys.copy()
+    ost = oracle.sort_segmented(want, off, U64, seed=4, stats=True)
+    t = to_gpu(keys)
+    o = to_gpu(off)
+    print(f"case: foreseen degenerate segmented graph={use_graph}", flush=True)
+    vqs.sort_segmented(t, o, key_type=U64, seed=4, solo_max=4096, use_graph=use_graph, level_mode=1)
+    torch.cuda.synchronize()
+    assert vqs.last_error_bits() == 0
+    np.testing.assert_array_equal(to_host(t), want)
+    if not use_graph:
+        assert_stats_equal(ost, vqs.get_stats())
