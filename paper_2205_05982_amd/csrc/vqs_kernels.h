@@ -99,7 +99,6 @@ struct Tile {
   struct Aux {
     uint32_t cnt[I][NW];
     R wmin[NW];
-    R wrmin[NW];
     R pivot;
   };
 
@@ -141,10 +140,9 @@ struct Tile {
   // Classify against the pivot (left: not after it; strict: before it), rank stably,
   // stage in LDS (left keys from 0 upward, right keys from nvalid-1 downward).  Returns
   // the tile's left count; *tmin gets the tile minimum (thread 0), and thread 0 calls
-  // publish(left count, minimum, minimum of the right keys) as soon as they are known,
-  // before the keys are staged (the last is the largest key value unless RMIN).  Ends
-  // with a barrier.
-  template <bool RMIN = false, class Pub>
+  // publish(left count, minimum) as soon as both are known, before the keys are
+  // staged.  Ends with a barrier.
+  template <class Pub>
   __device__ static uint32_t rank_and_stage(S* stage, Aux& sh, const R (&key)[I][V], uint64_t k,
                                             uint64_t vs, uint64_t ve, R pivot, bool strict, R* tmin,
                                             Pub&& publish) {
@@ -153,7 +151,6 @@ struct Tile {
     uint32_t pre[I];
     uint32_t flag[I];  // bit q: key (j, q) goes left
     R mn = K::maxv();
-    R rmn = K::maxv();
 #pragma unroll
     for (int j = 0; j < I; j++) {
       const uint64_t v0 = (k * TC + (uint64_t)j * P + tid) * V;
@@ -163,7 +160,6 @@ struct Tile {
         const bool valid = (v0 + q >= vs) && (v0 + q < ve);
         const bool left = valid && (strict ? K::lt(key[j][q], pivot) : !K::lt(pivot, key[j][q]));
         if (valid) mn = K::kmin(mn, key[j][q]);
-        if (RMIN && valid && !left) rmn = K::kmin(rmn, key[j][q]);
         const uint64_t m = ballot(left);
         lanepre += mbcnt(m);
         tot += __popcll(m);
@@ -175,10 +171,6 @@ struct Tile {
     }
     mn = wave_min<K>(mn);
     if ((tid & (WAVE - 1)) == 0) sh.wmin[w] = mn;
-    if constexpr (RMIN) {
-      rmn = wave_min<K>(rmn);
-      if ((tid & (WAVE - 1)) == 0) sh.wrmin[w] = rmn;
-    }
     __syncthreads();
     uint32_t total = 0, mybase[I];
 #pragma unroll
@@ -195,13 +187,8 @@ struct Tile {
       R m2 = sh.wmin[0];
 #pragma unroll
       for (int ww = 1; ww < NW; ww++) m2 = K::kmin(m2, sh.wmin[ww]);
-      R r2 = K::maxv();
-      if constexpr (RMIN) {
-#pragma unroll
-        for (int ww = 0; ww < NW; ww++) r2 = K::kmin(r2, sh.wrmin[ww]);
-      }
       *tmin = m2;
-      publish(total, m2, r2);
+      publish(total, m2);
     }
     const uint32_t nvalid = (uint32_t)(ve - vs);
 #pragma unroll
@@ -266,9 +253,13 @@ struct Tile {
     return K::store_t(r, tmode);
   }
 
-  __device__ static void write_run(const S* stage, S* dst, uint32_t s0, uint32_t len, uint64_t rb, int tmode,
-                                   uint64_t n_total, int off) {
-    if (len == 0) return;
+  // (With MIN, also the smallest of the staged keys this thread wrote; keys of 4 and 8
+  // bytes, whose staged form is their register form.)
+  template <bool MIN = false>
+  __device__ static R write_run(const S* stage, S* dst, uint32_t s0, uint32_t len, uint64_t rb, int tmode,
+                                uint64_t n_total, int off) {
+    R mn = K::maxv();
+    if (len == 0) return mn;
     const uint64_t vb = rb + (uint64_t)off, ve = vb + len;
     const uint64_t c0 = vb / V, c1 = (ve + V - 1) / V;
     char* dbase = reinterpret_cast<char*>(dst - off);   // 16-byte aligned
@@ -278,7 +269,10 @@ struct Tile {
         const S* from = stage + s0 + (v - vb);
         S tmp[V];
 #pragma unroll
-        for (int q = 0; q < V; q++) tmp[q] = out_t(from[q], tmode);
+        for (int q = 0; q < V; q++) {
+          if constexpr (MIN) mn = K::kmin(mn, (R)from[q]);
+          tmp[q] = out_t(from[q], tmode);
+        }
         uint4 u;
         __builtin_memcpy(&u, tmp, 16);
         *reinterpret_cast<uint4*>(dbase + c * 16) = u;
@@ -286,12 +280,42 @@ struct Tile {
 #pragma unroll
         for (int q = 0; q < V; q++) {
           const uint64_t vv = v + q;
-          if (vv >= vb && vv < ve && vv - off < n_total) dst[vv - off] = out_t(stage[s0 + (vv - vb)], tmode);
+          if (vv >= vb && vv < ve) {
+            const S x = stage[s0 + (vv - vb)];
+            if constexpr (MIN) mn = K::kmin(mn, (R)x);
+            if (vv - off < n_total) dst[vv - off] = out_t(x, tmode);
+          }
         }
       }
     }
+    return mn;
+  }
+
+  // write_out that also leaves, per wave, the smallest key written to the right run
+  // (K::maxv() for a wave that wrote none) in wrm[w] (LDS), for the next level's
+  // planning; visible to the workgroup after its next barrier.
+  __device__ static void write_out_rmin(const S* stage, S* dst, uint32_t nleft, uint32_t nvalid,
+                                        uint64_t left_base, uint64_t right_base, int tmode, uint64_t n_total,
+                                        int off, R* wrm) {
+    write_run(stage, dst, 0, nleft, left_base, tmode, n_total, off);
+    R m = write_run<true>(stage, dst, nleft, nvalid - nleft, right_base, tmode, n_total, off);
+    m = wave_min<K>(m);
+    if ((threadIdx.x & (WAVE - 1)) == 0) wrm[threadIdx.x / WAVE] = m;
   }
 };
+
+// The tile's smallest right key from the waves' minima (thread 0, after the barrier
+// that followed write_out_rmin): stored for the next level's planning.
+template <class K>
+__device__ inline void store_tile_rmin(const Params& p, unsigned long long g, const typename K::R* wrm) {
+  typename K::R m = wrm[0];
+#pragma unroll
+  for (int w = 1; w < LEVEL_NW; w++) m = K::kmin(m, wrm[w]);
+  uint64_t lo, hi;
+  K::to_u64x2(m, lo, hi);
+  p.tilermin[g].lo = lo;
+  p.tilermin[g].hi = hi;
+}
 
 // ---- segment bookkeeping --------------------------------------------------------------
 
@@ -419,10 +443,46 @@ __device__ inline Seg make_seg(uint64_t b, uint64_t e, uint32_t depth, uint32_t 
   return s;
 }
 
-// Whether look-back levels foresee degenerate partitions (see pivot_kernel) for K.
+static_assert(LEVEL_NW == LEVEL_P / WAVE, "waves of a level workgroup");
+
+// Whether the levels foresee degenerate partitions (see pivot_kernel) for K.
 template <class K>
 constexpr bool foresee_degenerate() {
   return K::SIZE == 4 || K::SIZE == 8;
+}
+
+// The smallest key of a range routed by the previous level, by a group of G threads
+// (gt its index; wsum: G / WAVE words of LDS when G > WAVE): from that level's records
+// of the parent's tiles [rt_b, rt_b + rt_n), the tile minima for a left part, the
+// tiles' smallest right keys for a right part.
+template <class K, int G>
+__device__ inline typename K::R range_min(const Params& p, const Seg& sg, int gt, typename K::R* wsum) {
+  using R = typename K::R;
+  const u128k* tm = ((sg.flags & SEG_MINR) ? p.tilermin : p.tilemin) + sg.rt_b;
+  const uint64_t cnt = sg.rt_n;
+  constexpr int U = 4;   // loads in flight per thread
+  R m[U];
+#pragma unroll
+  for (int u = 0; u < U; u++) m[u] = K::maxv();
+  for (uint64_t t0 = gt; t0 < cnt; t0 += (uint64_t)U * G) {
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const uint64_t t = t0 + (uint64_t)u * G;
+      if (t < cnt) m[u] = K::kmin(m[u], K::from_u64x2(tm[t].lo, tm[t].hi));
+    }
+  }
+#pragma unroll
+  for (int u = 1; u < U; u++) m[0] = K::kmin(m[0], m[u]);
+  R r = wave_min<K>(m[0]);
+  if constexpr (G > WAVE) {
+    if ((gt & (WAVE - 1)) == 0) wsum[gt / WAVE] = r;
+    __syncthreads();
+    r = wsum[0];
+#pragma unroll
+    for (int w = 1; w < G / WAVE; w++) r = K::kmin(r, wsum[w]);
+    __syncthreads();
+  }
+  return r;
 }
 
 // ---- level kernel ------------------------------------------------------------------------
@@ -445,6 +505,7 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
   __shared__ unsigned long long sh_ticket;
   __shared__ unsigned long long sh_excl;
   __shared__ R sh_segmin;
+  __shared__ R sh_wrm[LEVEL_NW];
   __shared__ int sh_seg;
   __shared__ unsigned long long sh_fill0;
 
@@ -470,8 +531,13 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
   unsigned long long lb_n = 0, lb_it = 0, lb_sp = 0, lb_sp0 = 0, lb_lat = 0;
 #endif
 
+  unsigned long long rmin_tile = ~0ull;   // thread 0: tile whose right minimum is pending
   for (;;) {
     VQS_PHASE(5);
+    if (foresee_degenerate<K>() && tid == 0 && rmin_tile != ~0ull) {
+      store_tile_rmin<K>(p, rmin_tile, sh_wrm);
+      rmin_tile = ~0ull;
+    }
     if (tid == 0) sh_ticket = atomicAdd(&p.lvl_ctr[L].ticket, 1u);
     __syncthreads();
     const unsigned long long g = sh_ticket;
@@ -530,20 +596,14 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
     R tmin;
     // publish the tile minimum, then the left count (the minimum is made visible
     // before the count by waiting for its stores to complete)
-    const uint32_t nl = TL::template rank_and_stage<foresee_degenerate<K>()>(
-        stage, sh, key, k, vs, ve, pivot, (sg.flags & SEG_STRICT) != 0, &tmin, [&](uint32_t cnt, R m, R rm) {
+    const uint32_t nl = TL::rank_and_stage(stage, sh, key, k, vs, ve, pivot, (sg.flags & SEG_STRICT) != 0, &tmin,
+                                           [&](uint32_t cnt, R m) {
                                              uint64_t lo, hi;
                                              to_words<K>(m, lo, hi);
                                              __hip_atomic_store(&p.tilemin[g].lo, lo, __ATOMIC_RELAXED,
                                                                 __HIP_MEMORY_SCOPE_AGENT);
                                              __hip_atomic_store(&p.tilemin[g].hi, hi, __ATOMIC_RELAXED,
                                                                 __HIP_MEMORY_SCOPE_AGENT);
-                                             if constexpr (foresee_degenerate<K>()) {
-                                               // for the next level's planning only (no order needed)
-                                               to_words<K>(rm, lo, hi);
-                                               p.tilermin[g].lo = lo;
-                                               p.tilermin[g].hi = hi;
-                                             }
                                              __atomic_signal_fence(__ATOMIC_SEQ_CST);
                                              __builtin_amdgcn_s_waitcnt(0);
                                              __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -623,7 +683,11 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
     const uint64_t excl_r = before - excl_l;
     const uint32_t nr = nvalid - nl;
     VQS_PHASE(3);
-    TL::write_out(stage, dst, nl, nvalid, sg.b + excl_l, sg.e - excl_r - nr, 0, p.n_total, p.off);
+    if constexpr (foresee_degenerate<K>()) {
+      TL::write_out_rmin(stage, dst, nl, nvalid, sg.b + excl_l, sg.e - excl_r - nr, 0, p.n_total, p.off, sh_wrm);
+      rmin_tile = g;
+    } else
+      TL::write_out(stage, dst, nl, nvalid, sg.b + excl_l, sg.e - excl_r - nr, 0, p.n_total, p.off);
 
     if (g == g0 + ntile_seg - 1) {
       // last tile of the range: the range is partitioned; plan what follows
@@ -821,6 +885,7 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
   __shared__ __align__(16) S stage[T];
   __shared__ typename TL::Aux sh;
   __shared__ unsigned long long sh_tk[2];
+  __shared__ R sh_wrm[LEVEL_NW];
   __shared__ int sh_seg;
   RunEnt* ent = reinterpret_cast<RunEnt*>(stage);
 
@@ -845,8 +910,13 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
   // handed over through alternating LDS slots at its end
   if (tid == 0) sh_tk[0] = atomicAdd(&p.lvl_ctr[L].ticket, 1u);
   __syncthreads();
+  unsigned long long rmin_tile = ~0ull;   // thread 0: tile whose right minimum is pending
   for (int it = 0;; it++) {
     VQS_PHASE(5);
+    if (foresee_degenerate<K>() && tid == 0 && rmin_tile != ~0ull) {
+      store_tile_rmin<K>(p, rmin_tile, sh_wrm);
+      rmin_tile = ~0ull;
+    }
     const unsigned long long g = sh_tk[it & 1];
     if (g >= ntiles) break;
     unsigned int g_next = 0;
@@ -876,6 +946,11 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
     if (!planned) __syncthreads();
     const int si = planned ? (int)tr.seg : sh_seg;
     const Seg sg = segs[si];
+    if (sg.flags & SEG_SKIP) {   // finished by the planning launch: no keys to move
+      if (tid == 0) sh_tk[(it + 1) & 1] = g_next;
+      __syncthreads();
+      continue;
+    }
     const unsigned long long g0 = tbase[si];
     const uint64_t nt = tiles_of(sg.b, sg.e, p.off, T);
     const uint64_t k = (sg.b + p.off) / T + (g - g0);
@@ -990,7 +1065,7 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
     R tmin;
     // the tile's left count and minimum, for the planning launch after this one
     const uint32_t nl = TL::rank_and_stage(stage, sh, key, k, vs, ve, pivot, (sg.flags & SEG_STRICT) != 0, &tmin,
-                                           [&](uint32_t cnt, R m, R) {
+                                           [&](uint32_t cnt, R m) {
                                              uint64_t lo, hi;
                                              to_words<K>(m, lo, hi);
                                              p.tilemin[g].lo = lo;
@@ -998,7 +1073,11 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
                                              p.tnl[g] = cnt;
                                            });
     VQS_PHASE(4);
-    TL::write_out(stage, dst, nl, nvalid, vs - p.off, vs - p.off + nl, 0, p.n_total, p.off);
+    if constexpr (foresee_degenerate<K>()) {
+      TL::write_out_rmin(stage, dst, nl, nvalid, vs - p.off, vs - p.off + nl, 0, p.n_total, p.off, sh_wrm);
+      rmin_tile = g;
+    } else
+      TL::write_out(stage, dst, nl, nvalid, vs - p.off, vs - p.off + nl, 0, p.n_total, p.off);
     tiles_done++;
     VQS_PHASE(6);
     if (tid == 0) sh_tk[(it + 1) & 1] = g_next;
@@ -1018,6 +1097,7 @@ struct PlanShared {
   uint64_t spos[2][9 * W];                // source positions of their sampled keys
   typename K::R wmin[LEVEL_P / WAVE];
   typename K::R pv[2];
+  typename K::R mn[2];                    // minima of children with a foreseen degenerate partition
   typename K::R samp[2][9 * W];           // the sampled keys
 };
 
@@ -1164,24 +1244,18 @@ __device__ PlanState plan_first(const Params& p, int L, const Seg& sg, uint64_t 
   } else if (bound == sg.e && !fb) {
     // degenerate: the minimum of the range decides (Alg. 1, ScanMinMax)
     st.degenerate = true;
-    R m = K::maxv();
-    for (uint64_t t = g0 + gt; t < g0 + nt; t += G) m = K::kmin(m, K::from_u64x2(p.tilemin[t].lo, p.tilemin[t].hi));
-    m = wave_min<K>(m);
-    R mn = m;
-    if constexpr (G != WAVE) {
-      if ((gt & (WAVE - 1)) == 0) sm.wmin[gt / WAVE] = m;
-      __syncthreads();
-      mn = sm.wmin[0];
-#pragma unroll
-      for (int ww = 1; ww < G / WAVE; ww++) mn = K::kmin(mn, sm.wmin[ww]);
-      __syncthreads();
-    }
+    Seg whole{};   // the range's own tiles of level L-1
+    whole.rt_b = (uint32_t)g0;
+    whole.rt_n = (uint32_t)nt;
+    const R mn = range_min<K, G>(p, whole, gt, sm.wmin);
     if (K::eq(mn, pivot)) {
       st.all_equal = true;
       st.fill_b = sg.b;
       st.fill_e = sg.e;
     } else {
-      c0 = child(sg.b, sg.e, cf | SEG_OVERRIDE | SEG_PIVOT, mn, false);
+      // the range's largest key is the pivot (every key went left)
+      c0 = child(sg.b, sg.e, cf | SEG_OVERRIDE | SEG_PIVOT | SEG_MAXK, mn, false);
+      to_words<K>(pivot, c0.mx_lo, c0.mx_hi);
       nc = 1;
     }
   } else if (bound == sg.e) {
@@ -1191,6 +1265,14 @@ __device__ PlanState plan_first(const Params& p, int L, const Seg& sg, uint64_t 
   } else {
     c0 = child(sg.b, bound, cf, pivot, false);
     c1 = child(bound, sg.e, cf, pivot, true);
+    if (!fb) {
+      // largest keys, for foreseeing degenerate partitions (as in level_kernel)
+      c0.flags |= SEG_MAXK;
+      to_words<K>(pivot, c0.mx_lo, c0.mx_hi);
+      c1.flags |= SEG_MINR | (sg.flags & SEG_MAXK);
+      c1.mx_lo = sg.mx_lo;
+      c1.mx_hi = sg.mx_hi;
+    }
     nc = 2;
   }
   st.r0 = route_decide(p, c0);
@@ -1382,6 +1464,27 @@ __device__ void plan_second(const Params& p, int L, const Seg& sg, uint64_t g0, 
     }
     gsync<G>();
   }
+  // degenerate partitions foreseen (see pivot_kernel): a child whose pivot is its known
+  // largest key; its minimum, by the group
+  bool fd[2] = {false, false};
+  if constexpr (foresee_degenerate<K>()) {
+#pragma unroll
+    for (int side = 0; side < 2; side++) {
+      const Routed& r = side == 0 ? r0 : r1;
+      fd[side] = (side == 0 ? st.piv0 : st.piv1) && ok && (r.s.flags & SEG_MAXK) && !(r.s.flags & SEG_FALLBACK) &&
+                 K::eq(sm.pv[side], K::from_u64x2(r.s.mx_lo, r.s.mx_hi));
+    }
+    if (fd[0] || fd[1]) {
+#pragma unroll
+      for (int side = 0; side < 2; side++) {
+        if (fd[side]) {
+          const R m = range_min<K, G>(p, side == 0 ? r0.s : r1.s, gt, sm.wmin);
+          if (gt == 0) sm.mn[side] = m;
+        }
+      }
+      gsync<G>();
+    }
+  }
   if (gt == 0) {
     if (!fb) {
       pc.part++;
@@ -1406,13 +1509,50 @@ __device__ void plan_second(const Params& p, int L, const Seg& sg, uint64_t g0, 
         to_words<K>(sm.pv[side], r.s.pv_lo, r.s.pv_hi);
         r.s.flags |= SEG_PIVOT;
       }
+      bool skip = false;
+      if (fd[side]) {
+        // the foreseen degenerate partition, counted as the oracle counts it; then the
+        // range is all one value (filled, its level entry skipped) or is partitioned
+        // again with its minimum as pivot, one level deeper (unless past the limit)
+        const R pv = sm.pv[side], mn = sm.mn[side];
+        if (K::eq(mn, pv) || r.s.depth + 1 <= r.s.limit) {
+          pc.part++;
+          pc.pkeys += r.s.e - r.s.b;
+          pc.maxd = r.s.depth > pc.maxd ? r.s.depth : pc.maxd;
+          pc.deg++;
+        }
+        if (K::eq(mn, pv)) {
+          pc.alleq++;
+          skip = true;
+          const uint64_t nch = (r.s.e - r.s.b + FILL_CHUNK - 1) / FILL_CHUNK;
+          const unsigned long long f0 = atomicAdd(&p.solo_ctr->count, (unsigned long long)nch);
+          pc.solo += nch;
+          for (uint64_t c = 0; c < nch; c++) {
+            if (f0 + c >= p.cap_solo) {
+              set_err(p, ERR_SOLO_OVERFLOW);
+              break;
+            }
+            Seg f{};
+            f.b = r.s.b + c * FILL_CHUNK;
+            f.e = (f.b + FILL_CHUNK < r.s.e) ? f.b + FILL_CHUNK : r.s.e;
+            f.flags = SEG_FILL;
+            to_words<K>(pv, f.pv_lo, f.pv_hi);
+            p.solo[f0 + c] = f;
+          }
+        } else if (r.s.depth + 1 <= r.s.limit) {
+          to_words<K>(mn, r.s.pv_lo, r.s.pv_hi);
+          r.s.depth += 1;
+          r.s.flags |= SEG_OVERRIDE;
+        }
+      }
       if (ok) {
         // the range itself, or the copy entry that gathers it for the solo list
         Seg e = r.s;
         if (r.dest == RT_SOLO) e.flags = (r.s.flags & (SEG_RUNS | SEG_RIGHT)) | SEG_COPY;
+        if (skip) e.flags |= SEG_SKIP;
         p.lvl_segs[L & 1][li] = e;
         p.lvl_tbase[L & 1][li] = side == 0 ? tb_0 : tb_1;
-        pc.lvlkeys += e.e - e.b;
+        if (!skip) pc.lvlkeys += e.e - e.b;
         li++;
       }
       if (r.dest == RT_SOLO) {
@@ -1511,7 +1651,7 @@ __global__ void __launch_bounds__(LEVEL_P) runs_plan_kernel(Params p) {
   for (uint32_t si = blockIdx.x; si < nseg; si += gridDim.x) {
     const Seg sg = uniform_seg(segs[si]);
     const uint64_t nt = tiles_of(sg.b, sg.e, p.off, T);
-    if ((sg.flags & SEG_COPY) || nt <= SMALL) continue;
+    if ((sg.flags & (SEG_COPY | SEG_SKIP)) || nt <= SMALL) continue;   // gathers and finished ranges: no plan
     const uint64_t g0 = uniform64(tbase[si]);
     const PlanState st = plan_first<K, LEVEL_P>(p, L, sg, g0, nt, smg, tid);
     if (tid == 0) slots[0] = plan_reserve(p, L, st.ne, st.nt0 + st.nt1, st.nsolo);
@@ -1527,7 +1667,7 @@ __global__ void __launch_bounds__(LEVEL_P) runs_plan_kernel(Params p) {
     if (si < nseg) {
       sg = uniform_seg(segs[si]);
       nt = tiles_of(sg.b, sg.e, p.off, T);
-      mine = !(sg.flags & SEG_COPY) && nt <= SMALL;
+      mine = !(sg.flags & (SEG_COPY | SEG_SKIP)) && nt <= SMALL;
       g0 = uniform64(tbase[si]);
     }
     PlanState st{};
@@ -1591,12 +1731,10 @@ __global__ void __launch_bounds__(LEVEL_P) runs_plan_kernel(Params p) {
 // keys equal), else partitions again with the minimum as pivot, one level deeper.
 // Since a partition that sends every key left leaves the keys where and as they were,
 // neither step needs this level's pass: the minimum is reduced from what the previous
-// level recorded per tile of the range's parent (the tile minima for a left part, the
-// minima of the tiles' right keys for a right part), the partition is counted as the
+// level recorded for the range's parent (range_min), the partition is counted as the
 // oracle counts it, and the range either leaves the level (filled with its one value)
-// or becomes that second partition.  Keys of 2 and 16 bytes (whose level kernels would
-// lose occupancy to the extra minimum), and a second partition past the depth limit,
-// take the level pass.
+// or becomes that second partition.  Keys of 2 and 16 bytes, and a second partition
+// past the depth limit, take the level pass.
 constexpr int PIVOT_P = 256;
 
 template <class K>
@@ -1627,14 +1765,7 @@ __global__ void __launch_bounds__(PIVOT_P) pivot_kernel(Params p) {
     if constexpr (foresee_degenerate<K>()) {
       if (L > 0 && (sg.flags & SEG_MAXK) && !(sg.flags & SEG_FALLBACK) &&
           K::eq(pv, K::from_u64x2(sg.mx_lo, sg.mx_hi))) {
-        const u128k* tm = (sg.flags & SEG_MINR) ? p.tilermin : p.tilemin;
-        R m0 = K::maxv(), m1 = K::maxv();
-#pragma unroll 4
-        for (uint32_t t = lane_id(); t < sg.rt_n; t += 2 * WAVE) {
-          m0 = K::kmin(m0, K::from_u64x2(tm[sg.rt_b + t].lo, tm[sg.rt_b + t].hi));
-          if (t + WAVE < sg.rt_n) m1 = K::kmin(m1, K::from_u64x2(tm[sg.rt_b + t + WAVE].lo, tm[sg.rt_b + t + WAVE].hi));
-        }
-        const R mn = wave_min<K>(K::kmin(m0, m1));
+        const R mn = range_min<K, WAVE>(p, sg, lane_id(), nullptr);
         const uint64_t len = sg.e - sg.b;
         if (K::eq(mn, pv)) {
           // all keys equal: the caller's array holds them already unless the level reads
@@ -2493,7 +2624,7 @@ __global__ void __launch_bounds__(SOLO_P) __attribute__((amdgpu_waves_per_eu(sol
         R key[SI][K::V];
         TL::load(src_aligned, k, vs, ve, raw ? p.mode : 0, key);
         R tmin;
-        const uint32_t nl = TL::rank_and_stage(bufA, aux, key, k, vs, ve, pivot, strict, &tmin, [](uint32_t, R, R) {});
+        const uint32_t nl = TL::rank_and_stage(bufA, aux, key, k, vs, ve, pivot, strict, &tmin, [](uint32_t, R) {});
         const uint32_t nvalid = (uint32_t)(ve - vs);
         const uint32_t nr = nvalid - nl;
         TL::write_out_keys(bufA, dst, nl, nvalid, cur.b + excl_l, cur.e - excl_r - nr, 0, p.n_total);

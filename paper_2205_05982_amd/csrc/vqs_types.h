@@ -16,6 +16,7 @@ constexpr int MODE_DESC = 2;
 #define VQS_LEVEL_P 256
 #endif
 constexpr int LEVEL_P = VQS_LEVEL_P;  // threads per level-kernel workgroup
+constexpr int LEVEL_NW = LEVEL_P / 64;  // its waves
 // 16-byte chunks per thread of a level tile, by key width (measured): 16 KB tiles for
 // u16 (its keys take one register each), 32 KB for u32, 40 KB for u64, 32 KB for u128
 // (three or four workgroups per CU)
@@ -122,7 +123,7 @@ struct Params {
   LevelCtr* lvl_ctr;
   unsigned long long* flags;  // look-back words, one per tile
   u128k* tilemin;        // per-tile minimum (internal form)
-  u128k* tilermin;       // look-back levels: per-tile minimum of the keys that went right
+  u128k* tilermin;       // per tile of a level: its smallest right key (keys of 4 and 8 bytes)
   Seg* solo;
   SoloCtr* solo_ctr;
   DevStats* stats;

@@ -168,20 +168,21 @@ def _heavy(n, kt, frac, top, seed):
     return k.astype(np.uint32 if kt == U32 else np.uint64)
 
 
+@pytest.mark.parametrize("mode", list(MODES))
 @pytest.mark.parametrize("kt", [U32, U64, F32, F64])
 @pytest.mark.parametrize("asc", [True, False])
 @pytest.mark.parametrize("top", [True, False])
-def test_lookback_foreseen_degenerate_partitions(vqs, kt, asc, top):
-    """Look-back levels foresee a degenerate partition (pivot = the range's known largest
-    key) and take it, and the all-equal finding or the repeat with the minimum, without
-    a pass over the keys.  A heavy value above spread keys (top) gives long chains of
+def test_foreseen_degenerate_partitions(vqs, mode, kt, asc, top):
+    """The levels foresee a degenerate partition (pivot = the range's known largest key)
+    and take it, and the all-equal finding or the repeat with the minimum, without a
+    pass over the keys.  A heavy value above spread keys (top) gives long chains of
     them, each peeling the smallest value off, until the depth limit; a heavy value
     below them gives all-equal left parts.  Keys, order and every counter must match the
     oracle, which makes the passes the Alg. 1 way."""
     n = 1_500_000
     keys = _heavy(n, kt, 0.7, top, 41 + kt)
-    print(f"case: foreseen degenerate kt={kt} asc={asc} top={top}", flush=True)
-    gst = _check(vqs, keys, kt, "lookback", asc, seed=5, solo_max=8192)
+    print(f"case: foreseen degenerate mode={mode} kt={kt} asc={asc} top={top}", flush=True)
+    gst = _check(vqs, keys, kt, mode, asc, seed=5, solo_max=8192)
     assert gst["degenerate"] >= 1
 
 
