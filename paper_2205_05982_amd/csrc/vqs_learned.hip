@@ -93,35 +93,52 @@ __device__ inline int classify(const uint64_t* E, int nvalid, uint64_t k) {
 
 // chunk c: 8 keys (64 bytes) at chunk offset (u * chunks) >> 32, u the high half of
 // SplitMix64 output c of the seed; chunks are counted from the array start
+// (one thread per sampled key: eight neighbouring threads read and write a chunk's 64
+// contiguous bytes)
 __global__ void sample_kernel(const uint64_t* keys, uint64_t n, uint64_t* sample, uint64_t nsample_chunks,
                               uint64_t seed) {
   const uint64_t nch = n / 8;
-  for (uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nsample_chunks;
-       c += (uint64_t)gridDim.x * blockDim.x) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nsample_chunks * 8;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t c = i / 8;
     const uint32_t u = (uint32_t)(splitmix_at(seed, c) >> 32);
     const uint64_t off = (((uint64_t)u * nch) >> 32) * 8;
-#pragma unroll
-    for (int j = 0; j < 8; j++) sample[c * 8 + j] = keys[off + j];
+    sample[i] = keys[off + (i & 7)];
   }
 }
 
-// x(k) of each sorted sample and its mid-rank CDF target (first + last + 1) / 2 / m
+// x(k) of each sorted sample and its mid-rank CDF target (first + last + 1) / 2 / m.
+// The run of keys equal to s[i] is found by galloping outward from i (one load each
+// way for a key without copies), then a binary search inside the last step.
 __global__ void targets_kernel(const uint64_t* s, uint64_t m, float* x, float* t) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += (uint64_t)gridDim.x * blockDim.x) {
     const uint64_t k = s[i];
-    uint64_t lo = 0, hi = i;          // first index with s[idx] == k
+    // first: s[f] == k, then steps 1, 2, 4, ... down while the key is still k
+    uint64_t f = i, step = 1;
+    while (f >= step && s[f - step] == k) {
+      f -= step;
+      step <<= 1;
+    }
+    uint64_t lo = f >= step ? f - step + 1 : 0, hi = f;   // first index with s == k is in [lo, hi]
     while (lo < hi) {
       const uint64_t mid = (lo + hi) / 2;
       if (s[mid] < k) lo = mid + 1; else hi = mid;
     }
     const uint64_t first = lo;
-    lo = i;
-    hi = m;                           // first index with s[idx] > k
-    while (lo < hi) {
-      const uint64_t mid = (lo + hi) / 2;
-      if (s[mid] <= k) lo = mid + 1; else hi = mid;
+    // last: the same upward
+    uint64_t e = i;
+    step = 1;
+    while (e + step < m && s[e + step] == k) {
+      e += step;
+      step <<= 1;
     }
-    const uint64_t last = lo - 1;
+    lo = e;
+    hi = e + step < m ? e + step - 1 : m - 1;   // last index with s == k is in [lo, hi]
+    while (lo < hi) {
+      const uint64_t mid = (lo + hi + 1) / 2;
+      if (s[mid] == k) lo = mid; else hi = mid - 1;
+    }
+    const uint64_t last = lo;
     x[i] = key_to_x(k);
     t[i] = (float)(((double)first + (double)last + 1.0) * 0.5 / (double)m);
   }
@@ -636,23 +653,45 @@ __global__ void __launch_bounds__(LT_P) scan_kernel(uint32_t* hist, uint64_t nch
 }
 
 // bucket starts (offsets[0..256]) and a summary: [0] largest bucket, [1] buckets above
-// overflow_factor * n / 256, [2] non-empty buckets
-__global__ void offsets_kernel(const uint64_t* totals, uint64_t n, float overflow_factor, int64_t* offsets,
-                               uint64_t* summary) {
-  if (threadIdx.x != 0) return;
-  uint64_t acc = 0, mx = 0, over = 0, nonempty = 0;
+// overflow_factor * n / 256, [2] non-empty buckets; thread b takes bucket b
+__global__ void __launch_bounds__(LT_P) offsets_kernel(const uint64_t* totals, uint64_t n, float overflow_factor,
+                                                       int64_t* offsets, uint64_t* summary) {
+  __shared__ uint64_t W[4][LT_NW];
+  const int b = threadIdx.x, lane = b & (WAVE - 1), w = b / WAVE;
+  const uint64_t v = totals[b];
   const double bound = (double)overflow_factor * (double)n / (double)NBUCKET;
-  for (int b = 0; b < NBUCKET; b++) {
-    offsets[b] = (int64_t)acc;
-    acc += totals[b];
-    mx = totals[b] > mx ? totals[b] : mx;
-    over += (double)totals[b] > bound ? 1 : 0;
-    nonempty += totals[b] ? 1 : 0;
+  uint64_t inc = v, mx = v, over = (double)v > bound ? 1 : 0, nonempty = v ? 1 : 0;
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+    const uint64_t o = (uint64_t)__shfl_up((long long)inc, d);
+    if (lane >= d) inc += o;
+    const uint64_t om = (uint64_t)__shfl_xor((long long)mx, d);
+    mx = om > mx ? om : mx;
+    over += (uint64_t)__shfl_xor((long long)over, d);
+    nonempty += (uint64_t)__shfl_xor((long long)nonempty, d);
   }
-  offsets[NBUCKET] = (int64_t)acc;
-  summary[0] = mx;
-  summary[1] = over;
-  summary[2] = nonempty;
+  if (lane == WAVE - 1) {
+    W[0][w] = inc;
+    W[1][w] = mx;
+    W[2][w] = over;
+    W[3][w] = nonempty;
+  }
+  __syncthreads();
+  uint64_t before = 0;
+  for (int k = 0; k < w; k++) before += W[0][k];
+  offsets[b] = (int64_t)(before + inc - v);
+  if (b == NBUCKET - 1) offsets[NBUCKET] = (int64_t)(before + inc);
+  if (b == 0) {
+    uint64_t m = 0, o = 0, ne = 0;
+    for (int k = 0; k < LT_NW; k++) {
+      m = W[1][k] > m ? W[1][k] : m;
+      o += W[2][k];
+      ne += W[3][k];
+    }
+    summary[0] = m;
+    summary[1] = o;
+    summary[2] = ne;
+  }
 }
 
 // One chunk per workgroup iteration, its tiles in order.  Per tile: classify, rank inside
@@ -765,7 +804,7 @@ int grid_for(uint64_t work, int per, int cap) {
 
 hipError_t launch_sample(const uint64_t* keys, uint64_t n, uint64_t* sample, uint64_t chunks, uint64_t seed,
                          hipStream_t s) {
-  hipLaunchKernelGGL(sample_kernel, dim3(grid_for(chunks, 256, 4096)), dim3(256), 0, s, keys, n, sample, chunks, seed);
+  hipLaunchKernelGGL(sample_kernel, dim3(grid_for(chunks * 8, 256, 8192)), dim3(256), 0, s, keys, n, sample, chunks, seed);
   return hipGetLastError();
 }
 
@@ -825,7 +864,7 @@ hipError_t launch_scan(uint32_t* hist, uint64_t nchunks, uint64_t* totals, hipSt
 
 hipError_t launch_offsets(const uint64_t* totals, uint64_t n, float overflow_factor, int64_t* offsets,
                           uint64_t* summary, hipStream_t s) {
-  hipLaunchKernelGGL(offsets_kernel, dim3(1), dim3(64), 0, s, totals, n, overflow_factor, offsets, summary);
+  hipLaunchKernelGGL(offsets_kernel, dim3(1), dim3(LT_P), 0, s, totals, n, overflow_factor, offsets, summary);
   return hipGetLastError();
 }
 

@@ -154,3 +154,36 @@ def test_trained_model_balances_better_than_untrained(vqs):
     assert bt.max() < bu.max()
     # no bucket of the trained model beyond what plain sampling's worst range holds
     assert bt.max() <= plain.max()
+
+
+def test_fit_sample_targets_and_first_step_match_reference(vqs):
+    """learned_fit with one Adam step against the same steps on the CPU: the sampled
+    64-byte chunks (SplitMix64 outputs of the sample seed), their sort, x(k) and the
+    mid-rank targets (runs of equal keys included: the mixture has Zipf duplicates),
+    the untrained model, the minibatch draw and the step."""
+    n, seed_s, seed_m, batch, lr = 3_000_000, 17, 16, 256, 0.003
+    keys = W.lognormal_mixture_u64(n, 15)
+    params = to_host(vqs.learned_fit(to_gpu(keys), train_steps=1, batch=batch))
+    # sample: chunks = floor(frac * n / 8) with the FP32 default fraction 0.01
+    chunks = int(float(np.float32(0.01)) * n / 8.0)
+    chunks = min(max(chunks, 8), n // 8)
+    m, nch = chunks * 8, n // 8
+    u = np.array(oracle.splitmix64(seed_s, chunks), dtype=np.uint64) >> np.uint64(32)
+    off = np.array([(int(v) * nch) >> 32 for v in u], dtype=np.int64) * 8
+    s = np.sort(keys[off[:, None] + np.arange(8)].ravel())
+    x = mlp.key_to_x(s).astype(np.float32)
+    t = mlp.mid_rank_targets(s).astype(np.float32)
+    assert np.unique(s).size < m                      # equal keys occur in the sample
+    x0 = np.float32(x[0])
+    xs = np.float32(1.0) / (np.float32(x[-1]) - x0)
+    p0 = mlp.init_params(seed_m, x0, xs).astype(np.float32)
+    np.testing.assert_array_equal(params[mlp.X0:], p0[mlp.X0:])
+    draws = np.array(oracle.splitmix64(seed_s, batch), dtype=np.uint64) >> np.uint64(32)
+    idx = np.array([(int(d) * m) >> 32 for d in draws])
+    _, g = mlp.loss_and_grad(p0.astype(np.float64), x[idx].astype(np.float64), t[idx].astype(np.float64))
+    want, _, _ = mlp.adam_step(p0.astype(np.float64), g, np.zeros(mlp.NBLOCK), np.zeros(mlp.NBLOCK), 1,
+                               mlp.lr_at(1, 1, lr))
+    sel = np.abs(g[:mlp.NPARAM]) > 1e-5
+    assert sel.sum() > 100
+    np.testing.assert_allclose(params[:mlp.NPARAM][sel].astype(np.float64), want[:mlp.NPARAM][sel],
+                               rtol=1e-5, atol=1e-6)
