@@ -344,6 +344,18 @@ Workspace* workspace_for(hipStream_t s) {
   return r;
 }
 
+// Levels launched before the host reads whether work is left: a read stalls the GPU
+// for a round trip (about 35 us), a level launched without work costs two launches
+// that return at once (a few us).  First batch: log2(n / solo threshold), the
+// halvings a range takes to reach the solo list, plus room for uneven pivots;
+// afterwards LEVEL_BATCH_NEXT at a time.
+constexpr int LEVEL_BATCH_NEXT = 4;
+int level_batch(const Plan& pl) {
+  int batch = 6;
+  for (uint64_t x = pl.n / std::max<uint64_t>(pl.solo, 1); x > 1; x >>= 1) batch++;
+  return batch;
+}
+
 template <int B>
 hipError_t launch_all(Workspace* ws, const Params& base, const Plan& pl, const Geometry& g,
                       const int64_t* offsets, uint64_t nseg, bool capture, int* levels_out) {
@@ -373,14 +385,7 @@ hipError_t launch_all(Workspace* ws, const Params& base, const Plan& pl, const G
       e = step(L, false);
       if (e != hipSuccess) return e;
     } else {
-      int batch = 2;
-      {
-        uint64_t x = pl.n / std::max<uint64_t>(pl.solo, 1);
-        while (x > 1) {
-          batch++;
-          x >>= 1;
-        }
-      }
+      int batch = level_batch(pl);
       for (;;) {
         const int upto = std::min(L + batch, pl.max_levels - 1);
         for (; L < upto; L++) {
@@ -398,7 +403,7 @@ hipError_t launch_all(Workspace* ws, const Params& base, const Plan& pl, const G
           if (e != hipSuccess) return e;
           break;
         }
-        batch = 2;
+        batch = LEVEL_BATCH_NEXT;
       }
     }
   } else if (pl.n > pl.solo) {
@@ -412,14 +417,7 @@ hipError_t launch_all(Workspace* ws, const Params& base, const Plan& pl, const G
         if (e != hipSuccess) return e;
       }
     } else {
-      int batch = 2;
-      {
-        uint64_t x = pl.n / std::max<uint64_t>(pl.solo, 1);
-        while (x > 1) {
-          batch++;
-          x >>= 1;
-        }
-      }
+      int batch = level_batch(pl);
       for (;;) {
         const int upto = std::min(L + batch, pl.max_levels - 1);
         for (; L < upto; L++) {
@@ -436,7 +434,7 @@ hipError_t launch_all(Workspace* ws, const Params& base, const Plan& pl, const G
         e = hipStreamSynchronize(s);
         if (e != hipSuccess) return e;
         if (ws->host_pinned[0] == 0) break;
-        batch = 2;
+        batch = LEVEL_BATCH_NEXT;
       }
     }
   }

@@ -186,8 +186,9 @@ def test_foreseen_degenerate_partitions(vqs, mode, kt, asc, top):
     assert gst["degenerate"] >= 1
 
 
+@pytest.mark.parametrize("mode", list(MODES))
 @pytest.mark.parametrize("use_graph", [0, 1])
-def test_lookback_foreseen_degenerate_segmented(vqs, use_graph):
+def test_foreseen_degenerate_segmented(vqs, mode, use_graph):
     import torch
     off = W.segment_offsets(40, seed=8, lo=1 << 14, hi=1 << 17)
     parts = [_heavy(int(off[i + 1] - off[i]), U64, 0.6, i % 2 == 0, 100 + i) for i in range(len(off) - 1)]
@@ -196,8 +197,8 @@ def test_lookback_foreseen_degenerate_segmented(vqs, use_graph):
     ost = oracle.sort_segmented(want, off, U64, seed=4, stats=True)
     t = to_gpu(keys)
     o = to_gpu(off)
-    print(f"case: foreseen degenerate segmented graph={use_graph}", flush=True)
-    vqs.sort_segmented(t, o, key_type=U64, seed=4, solo_max=4096, use_graph=use_graph, level_mode=1)
+    print(f"case: foreseen degenerate segmented mode={mode} graph={use_graph}", flush=True)
+    vqs.sort_segmented(t, o, key_type=U64, seed=4, solo_max=4096, use_graph=use_graph, level_mode=MODES[mode])
     torch.cuda.synchronize()
     assert vqs.last_error_bits() == 0
     np.testing.assert_array_equal(to_host(t), want)
