@@ -364,15 +364,18 @@ __device__ float* batch_gradient(TrainShared& S, float xv, float tv, int B, floa
 #pragma unroll
       for (int b = 0; b < 4; b++) g[a][b] = fmaf(dv[a], hv[b], g[a][b]);
   }
-  const int o = tid & 127, qq = tid >> 7;
+  // vector gradient o (0..31 w1, 32..63 b1, 64..95 b2, 96..127 w3) over quarter qq of
+  // the samples, in sample order: each wave takes one kind (its 64 lanes: 32 outputs
+  // times 2 quarters), so the loop has no divergent branch; x * 1 + sm is sm + x
+  const int kind = w & 3;
+  const int o = kind * 32 + (lane & 31), qq = (lane >> 5) + 2 * (w >> 2);
+  const float* A = kind < 2 ? S.DA1 : (kind == 2 ? S.DA2 : S.H2);
   float sm = 0.0f;
-#pragma unroll 4
+#pragma unroll 8
   for (int q = 0; q < TB / 4; q++) {
     const int s2 = qq * (TB / 4) + q;
-    if (o < 32) sm = fmaf(telem(S.DA1, s2, o), S.XN[s2], sm);
-    else if (o < 64) sm += telem(S.DA1, s2, o - 32);
-    else if (o < 96) sm += telem(S.DA2, s2, o - 64);
-    else sm = fmaf(S.D3[s2], telem(S.H2, s2, o - 96), sm);
+    const float mult = kind == 0 ? S.XN[s2] : (kind == 3 ? S.D3[s2] : 1.0f);
+    sm = fmaf(telem(A, s2, o & 31), mult, sm);
   }
   lds_sync();
 
