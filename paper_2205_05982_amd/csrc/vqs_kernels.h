@@ -253,8 +253,7 @@ struct Tile {
     return K::store_t(r, tmode);
   }
 
-  // (With MIN, also the smallest of the staged keys this thread wrote; keys of 4 and 8
-  // bytes, whose staged form is their register form.)
+  // (With MIN, also the smallest of the staged keys this thread wrote.)
   template <bool MIN = false>
   __device__ static R write_run(const S* stage, S* dst, uint32_t s0, uint32_t len, uint64_t rb, int tmode,
                                 uint64_t n_total, int off) {
@@ -445,12 +444,6 @@ __device__ inline Seg make_seg(uint64_t b, uint64_t e, uint32_t depth, uint32_t 
 
 static_assert(LEVEL_NW == LEVEL_P / WAVE, "waves of a level workgroup");
 
-// Whether the levels foresee degenerate partitions (see pivot_kernel) for K.
-template <class K>
-constexpr bool foresee_degenerate() {
-  return K::SIZE == 4 || K::SIZE == 8;
-}
-
 // The smallest key of a range routed by the previous level, by a group of G threads
 // (gt its index; wsum: G / WAVE words of LDS when G > WAVE): from that level's records
 // of the parent's tiles [rt_b, rt_b + rt_n), the tile minima for a left part, the
@@ -534,7 +527,7 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
   unsigned long long rmin_tile = ~0ull;   // thread 0: tile whose right minimum is pending
   for (;;) {
     VQS_PHASE(5);
-    if (foresee_degenerate<K>() && tid == 0 && rmin_tile != ~0ull) {
+    if (tid == 0 && rmin_tile != ~0ull) {
       store_tile_rmin<K>(p, rmin_tile, sh_wrm);
       rmin_tile = ~0ull;
     }
@@ -683,11 +676,8 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
     const uint64_t excl_r = before - excl_l;
     const uint32_t nr = nvalid - nl;
     VQS_PHASE(3);
-    if constexpr (foresee_degenerate<K>()) {
-      TL::write_out_rmin(stage, dst, nl, nvalid, sg.b + excl_l, sg.e - excl_r - nr, 0, p.n_total, p.off, sh_wrm);
-      rmin_tile = g;
-    } else
-      TL::write_out(stage, dst, nl, nvalid, sg.b + excl_l, sg.e - excl_r - nr, 0, p.n_total, p.off);
+    TL::write_out_rmin(stage, dst, nl, nvalid, sg.b + excl_l, sg.e - excl_r - nr, 0, p.n_total, p.off, sh_wrm);
+    rmin_tile = g;
 
     if (g == g0 + ntile_seg - 1) {
       // last tile of the range: the range is partitioned; plan what follows
@@ -913,7 +903,7 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
   unsigned long long rmin_tile = ~0ull;   // thread 0: tile whose right minimum is pending
   for (int it = 0;; it++) {
     VQS_PHASE(5);
-    if (foresee_degenerate<K>() && tid == 0 && rmin_tile != ~0ull) {
+    if (tid == 0 && rmin_tile != ~0ull) {
       store_tile_rmin<K>(p, rmin_tile, sh_wrm);
       rmin_tile = ~0ull;
     }
@@ -1073,11 +1063,8 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
                                              p.tnl[g] = cnt;
                                            });
     VQS_PHASE(4);
-    if constexpr (foresee_degenerate<K>()) {
-      TL::write_out_rmin(stage, dst, nl, nvalid, vs - p.off, vs - p.off + nl, 0, p.n_total, p.off, sh_wrm);
-      rmin_tile = g;
-    } else
-      TL::write_out(stage, dst, nl, nvalid, vs - p.off, vs - p.off + nl, 0, p.n_total, p.off);
+    TL::write_out_rmin(stage, dst, nl, nvalid, vs - p.off, vs - p.off + nl, 0, p.n_total, p.off, sh_wrm);
+    rmin_tile = g;
     tiles_done++;
     VQS_PHASE(6);
     if (tid == 0) sh_tk[(it + 1) & 1] = g_next;
@@ -1467,7 +1454,7 @@ __device__ void plan_second(const Params& p, int L, const Seg& sg, uint64_t g0, 
   // degenerate partitions foreseen (see pivot_kernel): a child whose pivot is its known
   // largest key; its minimum, by the group
   bool fd[2] = {false, false};
-  if constexpr (foresee_degenerate<K>()) {
+  {
 #pragma unroll
     for (int side = 0; side < 2; side++) {
       const Routed& r = side == 0 ? r0 : r1;
@@ -1733,8 +1720,8 @@ __global__ void __launch_bounds__(LEVEL_P) runs_plan_kernel(Params p) {
 // neither step needs this level's pass: the minimum is reduced from what the previous
 // level recorded for the range's parent (range_min), the partition is counted as the
 // oracle counts it, and the range either leaves the level (filled with its one value)
-// or becomes that second partition.  Keys of 2 and 16 bytes, and a second partition
-// past the depth limit, take the level pass.
+// or becomes that second partition.  A second partition past the depth limit takes the
+// level pass.
 constexpr int PIVOT_P = 256;
 
 template <class K>
@@ -1762,7 +1749,7 @@ __global__ void __launch_bounds__(PIVOT_P) pivot_kernel(Params p) {
           return tmode ? K::load_t(sv, tmode) : r;
         },
         sg.b, sg.e, p.seed);
-    if constexpr (foresee_degenerate<K>()) {
+    {
       if (L > 0 && (sg.flags & SEG_MAXK) && !(sg.flags & SEG_FALLBACK) &&
           K::eq(pv, K::from_u64x2(sg.mx_lo, sg.mx_hi))) {
         const R mn = range_min<K, WAVE>(p, sg, lane_id(), nullptr);

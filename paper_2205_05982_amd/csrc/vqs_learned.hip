@@ -352,7 +352,7 @@ __device__ float* batch_gradient(TrainShared& S, float xv, float tv, int B, floa
   for (int a = 0; a < 4; a++)
 #pragma unroll
     for (int b = 0; b < 4; b++) g[a][b] = 0.0f;
-#pragma unroll 2
+#pragma unroll 8
   for (int q = 0; q < SG; q++) {
     const int s2 = w * SG + q;
     const float4 d = *tchunk(S.DA2, s2, jb);
@@ -371,7 +371,7 @@ __device__ float* batch_gradient(TrainShared& S, float xv, float tv, int B, floa
   const int o = kind * 32 + (lane & 31), qq = (lane >> 5) + 2 * (w >> 2);
   const float* A = kind < 2 ? S.DA1 : (kind == 2 ? S.DA2 : S.H2);
   float sm = 0.0f;
-#pragma unroll 8
+#pragma unroll 16
   for (int q = 0; q < TB / 4; q++) {
     const int s2 = qq * (TB / 4) + q;
     const float mult = kind == 0 ? S.XN[s2] : (kind == 3 ? S.D3[s2] : 1.0f);

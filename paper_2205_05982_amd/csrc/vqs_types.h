@@ -123,7 +123,7 @@ struct Params {
   LevelCtr* lvl_ctr;
   unsigned long long* flags;  // look-back words, one per tile
   u128k* tilemin;        // per-tile minimum (internal form)
-  u128k* tilermin;       // per tile of a level: its smallest right key (keys of 4 and 8 bytes)
+  u128k* tilermin;       // per tile of a level: its smallest right key
   Seg* solo;
   SoloCtr* solo_ctr;
   DevStats* stats;

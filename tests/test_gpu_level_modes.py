@@ -154,22 +154,29 @@ def test_runs_more_runs_than_the_tile_list(vqs, solo_max):
 
 def _heavy(n, kt, frac, top, seed):
     """n keys: a fraction frac of them copies of one value, the others spread values
-    below it (top) or above it; shuffled."""
+    below it (top) or above it; shuffled.  u128 keys spread their high word (the low
+    word is random below the heavy key's)."""
     rng = np.random.default_rng(seed)
     nh = int(n * frac)
-    spread = rng.integers(0, 1 << 20, n - nh)
-    heavy = np.full(nh, 1 << 20 if top else 0)
+    span = (1 << 15) if kt == U16 else (1 << 20)
+    spread = rng.integers(0, span, n - nh)
+    heavy = np.full(nh, span if top else 0)
     if not top:
         spread = spread + 1
     k = np.concatenate([heavy, spread])
-    rng.shuffle(k)
+    perm = rng.permutation(n)
+    k = k[perm]
     if kt in (F32, F64):
         return (k.astype(np.float64) * 0.25 - 1000.0).astype(np.float32 if kt == F32 else np.float64)
-    return k.astype(np.uint32 if kt == U32 else np.uint64)
+    if kt == U128:
+        lo = rng.integers(0, 1 << 62, n, dtype=np.uint64)
+        lo[np.concatenate([np.ones(nh, bool), np.zeros(n - nh, bool)])[perm]] = 7
+        return np.stack([lo, k.astype(np.uint64)], axis=1)
+    return k.astype({U16: np.uint16, U32: np.uint32}.get(kt, np.uint64))
 
 
 @pytest.mark.parametrize("mode", list(MODES))
-@pytest.mark.parametrize("kt", [U32, U64, F32, F64])
+@pytest.mark.parametrize("kt", [U16, U32, U64, U128, F32, F64])
 @pytest.mark.parametrize("asc", [True, False])
 @pytest.mark.parametrize("top", [True, False])
 def test_foreseen_degenerate_partitions(vqs, mode, kt, asc, top):
@@ -179,10 +186,10 @@ def test_foreseen_degenerate_partitions(vqs, mode, kt, asc, top):
     them, each peeling the smallest value off, until the depth limit; a heavy value
     below them gives all-equal left parts.  Keys, order and every counter must match the
     oracle, which makes the passes the Alg. 1 way."""
-    n = 1_500_000
+    n = 1_500_000 if kt != U128 else 600_000
     keys = _heavy(n, kt, 0.7, top, 41 + kt)
     print(f"case: foreseen degenerate mode={mode} kt={kt} asc={asc} top={top}", flush=True)
-    gst = _check(vqs, keys, kt, mode, asc, seed=5, solo_max=8192)
+    gst = _check(vqs, keys, kt, mode, asc, seed=5, solo_max=16384)
     assert gst["degenerate"] >= 1
 
 
