@@ -13,10 +13,12 @@ sorted by both methods (median of a few sorts each), the speedup of the learned
 
 Roofline: the dominant kernel is the device-wide partition (level kernel).  Its
 algorithmic traffic per launch is 2 * keys * key_size bytes (each key of the level
-read once and written once); HIP events around every launch on the library's
-stream give the durations.  Besides the 8 TB/s peak, the bandwidth of a plain
-device-to-device copy of the input (measured the same way) is reported as a second
-denominator ("copy_gbs", "frac_of_copy").
+read once and written once); HIP events around each level launch of the timed
+steps, on the library's stream, give the durations (only those launches are
+recorded there, which costs the timed steps little; two more sorts after them, with
+every launch recorded, give the solo and total kernel times).  Besides the 8 TB/s
+peak, the bandwidth of a plain device-to-device copy of the input (measured the same
+way) is reported as a second denominator ("copy_gbs", "frac_of_copy").
 """
 from __future__ import annotations
 
@@ -278,7 +280,7 @@ def main():
         raise RuntimeError(f"device error bits {err:#x}")
     print(f"# warmup done", file=sys.stderr, flush=True)
 
-    vqs.profile(True)
+    vqs.profile(2)                # events around the level launches only
     vqs.profile_read()            # drop records of the warmup
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
@@ -305,21 +307,35 @@ def main():
     if not (sorted_ok and sum_ok):
         raise RuntimeError(f"bench output check failed: sorted={sorted_ok} multiset={sum_ok}")
 
-    # roofline of the dominant kernel: the level (device-wide partition) kernel
+    # roofline of the dominant kernel: the level (device-wide partition) kernel, from
+    # the events around its launches in the timed steps
     lv_all = [r for r in recs if r["kind"] == "level_partition"]
     lv = [r for r in lv_all if r["keys"] > 0]
-    solo = [r for r in recs if r["kind"] == "solo"]
     lv_bytes = sum(2 * r["keys"] * ks for r in lv)
     lv_ms = sum(r["ms"] for r in lv)
     achieved = lv_bytes / (lv_ms * 1e-3) / 1e9 if lv_ms > 0 else 0.0
     levels_per_step = len(lv) / args.steps
-    solo_ms = sum(r["ms"] for r in solo) / max(args.steps, 1)
-    all_ms = sum(r["ms"] for r in recs) / max(args.steps, 1)
+
+    # the other kernels' times: two more sorts (after the timed steps) with every launch
+    # recorded
+    ndiag = min(2, len(bufs))
+    for i in range(ndiag):
+        bufs[i].copy_(src)
+    torch.cuda.synchronize()
+    vqs.profile(1)
+    vqs.profile_read()
+    for i in range(ndiag):
+        vqs.sort(bufs[i], key_type=kt)
+    torch.cuda.synchronize()
+    diag = vqs.profile_read()
+    vqs.profile(0)
+    solo_ms = sum(r["ms"] for r in diag if r["kind"] == "solo") / ndiag
+    all_ms = sum(r["ms"] for r in diag) / ndiag
     passes = stats["keys_partitioned"] / n + 1.0     # partitions + the final local-sort pass
     e2e_frac = (passes * 2 * n * ks / (ms_step * 1e-3) / 1e9) / HBM_PEAK_GBS
     if args.profile_json:
         with open(args.profile_json, "w") as f:
-            json.dump({"records": recs, "stats": stats}, f, indent=1)
+            json.dump({"records": recs, "diagnostic_records": diag, "stats": stats}, f, indent=1)
 
     # a second denominator: the device-to-device copy of the input (one read and one
     # write of every key, like a partition pass), timed the same way
@@ -382,6 +398,7 @@ def main():
             "launch_avg_us_all": round(1e3 * sum(r["ms"] for r in lv_all) / max(len(lv_all), 1), 1),
             "bytes_per_launch_all": int(lv_bytes / max(len(lv_all), 1)),
             "level_ms_per_step": round(lv_ms / args.steps, 4),
+            # from two more sorts with every launch recorded
             "solo_ms_per_step": round(solo_ms, 4),
             "kernels_ms_per_step": round(all_ms, 4),
             "passes": round(passes, 3),

@@ -231,7 +231,9 @@ typedef struct vqs_kernel_time {
     double ms;                  /* event-measured duration */
 } vqs_kernel_time;
 
-/* Enable (1) or disable (0) event recording around every launch of later calls. */
+/* Event recording around the launches of later calls: 0 none, 1 every launch,
+ * 2 only the device-wide partition launches (kind 2; the others run unrecorded, so
+ * a timing of the whole call is barely disturbed).  Other values: VQS_EINVAL. */
 int vqs_profile(int enable);
 
 /* Copy up to max records of the calls on `stream` since the last read to out and

@@ -52,7 +52,7 @@ struct ProfRec {
   hipEvent_t a, b;
 };
 
-bool g_profile = false;
+int g_profile = 0;   // vqs_profile: 0 off, 1 every launch, 2 level partitions only
 unsigned long long* g_dbg = nullptr;  // per-phase cycle totals (instrumented builds)
 
 struct Workspace {
@@ -101,7 +101,7 @@ struct Workspace {
   // record an event pair around a launch when profiling
   template <class F>
   hipError_t timed(int kind, int level, F&& launch) {
-    if (!g_profile || capturing) return launch();
+    if (!g_profile || (g_profile == 2 && kind != 2) || capturing) return launch();
     hipEvent_t a = next_event(), b = next_event();
     if (a) (void)hipEventRecord(a, stream);
     hipError_t e = launch();
@@ -983,8 +983,9 @@ int vqs_last_error_bits(void* stream, uint32_t* out) {
 }
 
 int vqs_profile(int enable) {
+  if (enable < 0 || enable > 2) return VQS_EINVAL;
   std::lock_guard<std::mutex> lock(g_mu);
-  g_profile = enable != 0;
+  g_profile = enable;
   return VQS_OK;
 }
 

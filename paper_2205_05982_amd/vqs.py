@@ -235,9 +235,10 @@ def version() -> int:
     return int(lib().vqs_version())
 
 
-def profile(enable: bool) -> None:
-    """Record HIP events around every kernel launch of later calls."""
-    lib().vqs_profile(int(bool(enable)))
+def profile(enable) -> None:
+    """Record HIP events around kernel launches of later calls: False/0 none, True/1
+    every launch, 2 only the device-wide partition launches."""
+    _rc(lib().vqs_profile(int(enable)), "vqs_profile")
 
 
 def profile_read(stream=None, max_records: int = 4096) -> list:

@@ -44,6 +44,15 @@ def test_strerror_and_version(lib):
     assert lib.vqs_version() >= 10000
 
 
+def test_profile_modes(lib):
+    """vqs_profile: 0 off, 1 every launch, 2 level partitions only; other values
+    rejected (setting the mode touches no device)."""
+    for mode in (1, 2, 0):
+        assert lib.vqs_profile(mode) == 0
+    assert lib.vqs_profile(3) == -1
+    assert lib.vqs_profile(-1) == -1
+
+
 def test_argument_errors_return_before_any_device_call(lib):
     vp, u64, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int
     lib.vqs_sort_ex.argtypes = [vp, u64, i32, i32, vp, vp]

@@ -211,3 +211,24 @@ def test_foreseen_degenerate_segmented(vqs, mode, use_graph):
     np.testing.assert_array_equal(to_host(t), want)
     if not use_graph:
         assert_stats_equal(ost, vqs.get_stats())
+
+
+def test_profile_level_launches_only(vqs):
+    """vqs_profile(2) records the device-wide partition launches and nothing else;
+    vqs_profile(1) records the other kinds too (planning, solo)."""
+    import torch
+    keys = to_gpu(W.uniform_u64(2_000_000, 5))
+    kinds = {}
+    for mode in (2, 1):
+        t = keys.clone()
+        torch.cuda.synchronize()
+        vqs.profile(mode)
+        vqs.profile_read()
+        vqs.sort(t, key_type=U64, solo_max=20_000)
+        torch.cuda.synchronize()
+        recs = vqs.profile_read()
+        vqs.profile(0)
+        kinds[mode] = {r["kind"] for r in recs}
+        assert all(r["ms"] >= 0 for r in recs)
+    assert kinds[2] == {"level_partition"}
+    assert "level_partition" in kinds[1] and "solo" in kinds[1] and len(kinds[1]) >= 3
