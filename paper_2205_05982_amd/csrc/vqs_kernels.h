@@ -2004,24 +2004,21 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
 #define VQS_LPH(i)
 #endif
 
-  // 1. load into bufA[0, n) (16-byte aligned chunks in v-space)
-  {
-    const S* src_aligned = src - p.off;
-    const uint64_t vb = b + p.off, ve = e + p.off;
-    const uint64_t c0 = vb / V, c1 = (ve + V - 1) / V;
-    for (uint64_t c = c0 + tid; c < c1; c += SOLO_P) {
-      const uint4 rawc = *reinterpret_cast<const uint4*>(reinterpret_cast<const char*>(src_aligned) + c * 16);
-      R tmp[V];
-      K::unpack(rawc, tmp);
+  // 1. load into bufA[0, n) (16-byte aligned chunks in v-space).  A thread's chunks
+  // are all requested before any is used (a chunk past the range reads the range's
+  // last one, a safe address, and is dropped), and the first pivot's chunk starts are
+  // drawn meanwhile.
+  const S* src_aligned = src - p.off;
+  const uint64_t vb = b + p.off, ve = e + p.off;
+  const uint64_t c0 = vb / V, c1 = (ve + V - 1) / V;
+  constexpr int LC = (LOCAL_BYTES / 16 + 1 + SOLO_P - 1) / SOLO_P;   // chunks per thread at most
+  uint4 rawc[LC];
+  if (c1 > c0) {
 #pragma unroll
-      for (int q = 0; q < V; q++) {
-        const uint64_t v = c * V + q;
-        if (v >= vb && v < ve) {
-          R r = tmp[q];
-          if (tmode) r = K::load_t((S)r, tmode);
-          bufA[v - vb] = (S)r;
-        }
-      }
+    for (int j = 0; j < LC; j++) {
+      uint64_t c = c0 + tid + (uint64_t)j * SOLO_P;
+      c = c < c1 ? c : c1 - 1;
+      rawc[j] = *reinterpret_cast<const uint4*>(reinterpret_cast<const char*>(src_aligned) + c * 16);
     }
   }
   if (tid == 0) {
@@ -2049,6 +2046,25 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
         pivot_chunk_starts<K>(b, e, p.seed, o);
 #pragma unroll
         for (int i = 0; i < 9; i++) ls.pvoff[0][0][i] = (uint32_t)o[i];
+      }
+    }
+  }
+  if (c1 > c0) {
+#pragma unroll
+    for (int j = 0; j < LC; j++) {
+      const uint64_t c = c0 + tid + (uint64_t)j * SOLO_P;
+      if (c < c1) {
+        R tmp[V];
+        K::unpack(rawc[j], tmp);
+#pragma unroll
+        for (int q = 0; q < V; q++) {
+          const uint64_t v = c * V + q;
+          if (v >= vb && v < ve) {
+            R r = tmp[q];
+            if (tmode) r = K::load_t((S)r, tmode);
+            bufA[v - vb] = (S)r;
+          }
+        }
       }
     }
   }
