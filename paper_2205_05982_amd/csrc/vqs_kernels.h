@@ -768,7 +768,8 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
         if (!fb) {
           // for the next level's planning: the left part's largest key is the pivot (a key
           // of the range, and keys equal to it go left), the right part's is the range's
-          // when that is known; their minima are those this level gathers for range si
+          // when that is known; their minima come from this level's records of the
+          // range's tiles [g0, g0 + ntile_seg) (range_min)
           lc.flags |= SEG_MAXK;
           to_words<K>(pivot, lc.mx_lo, lc.mx_hi);
           rc.flags |= SEG_MINR | (sg.flags & SEG_MAXK);
@@ -1197,7 +1198,7 @@ __device__ PlanState plan_first(const Params& p, int L, const Seg& sg, uint64_t 
   const uint64_t per = (nt + G - 1) / G;
   const uint64_t ta = (uint64_t)gt * per < nt ? (uint64_t)gt * per : nt;
   const uint64_t tb = ta + per < nt ? ta + per : nt;
-  constexpr int QB = G == WAVE ? 4 : 32;   // counts read per batch, all in flight
+  constexpr int QB = G == WAVE ? 4 : 16;   // counts read per batch, all in flight
   const uint32_t* tnl = p.tnl;
   uint64_t sl = 0;
   for (uint64_t a = ta; a < tb; a += QB) {
@@ -1356,7 +1357,7 @@ __device__ void plan_second(const Params& p, int L, const Seg& sg, uint64_t g0, 
       s1 = m1 >= 0 ? tile_start(r1.s, (uint64_t)m1) : 0;
     }
   }
-  constexpr int QB = G == WAVE ? 4 : 8;
+  constexpr int QB = G == WAVE ? 4 : 16;
   const uint32_t* tnl = p.tnl;
   uint64_t lp = st.lp0;
   for (uint64_t a = ta; a < tb; a += QB) {
