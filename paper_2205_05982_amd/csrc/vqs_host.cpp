@@ -287,6 +287,7 @@ int ensure_workspace(Workspace* ws, const Plan& pl) {
   const size_t o_tnl = take(cap_tiles * sizeof(uint32_t));
   const size_t o_solo = take(cap_solo * sizeof(Seg));
   const size_t o_sctr = take(sizeof(SoloCtr));
+  const size_t o_sord = take(cap_solo * 4);
   const size_t o_stats = take(sizeof(DevStats));
   const size_t o_err = take(16);
   void* mem = nullptr;
@@ -317,6 +318,7 @@ int ensure_workspace(Workspace* ws, const Plan& pl) {
   p.tnl = (uint32_t*)(ws->mem + o_tnl);
   p.solo = (Seg*)(ws->mem + o_solo);
   p.solo_ctr = (SoloCtr*)(ws->mem + o_sctr);
+  p.solo_order = (uint32_t*)(ws->mem + o_sord);
   p.stats = (DevStats*)(ws->mem + o_stats);
   p.err = (unsigned int*)(ws->mem + o_err);
   p.cap_lvl = cap_lvl;
@@ -863,7 +865,7 @@ uint64_t vqs_workspace_bytes(uint64_t n, uint64_t nseg, int key_type, const vqs_
   if (make_plan(n, nseg ? nseg : 1, key_type, 1, options, g, &pl) != VQS_OK) return 0;
   uint64_t b = (n + 32) * (uint64_t)pl.ks + 64;
   b += 2 * pl.cap_lvl * (sizeof(Seg) + 8) + (uint64_t)pl.max_levels * sizeof(LevelCtr);
-  b += pl.cap_tiles * (8 + 2 * sizeof(u128k) + 2 * sizeof(TileRun) + sizeof(TileRef) + 4) + pl.cap_solo * sizeof(Seg) +
+  b += pl.cap_tiles * (8 + 2 * sizeof(u128k) + 2 * sizeof(TileRun) + sizeof(TileRef) + 4) + pl.cap_solo * (sizeof(Seg) + 4) +
        4096;
   return b;
 }

@@ -2547,7 +2547,7 @@ __global__ void __launch_bounds__(SOLO_P) __attribute__((amdgpu_waves_per_eu(sol
     __syncthreads();
     const unsigned long long ii = sh_item;
     if (ii >= nitems) break;
-    const Seg item = p.solo[ii];
+    const Seg item = p.solo[p.solo_order[ii]];
     if (item.flags & SEG_FILL) {
       fill_range<K>(p, item.b, item.e, K::from_u64x2(item.pv_lo, item.pv_hi));
       __syncthreads();
@@ -2697,6 +2697,41 @@ __global__ void __launch_bounds__(SOLO_P) __attribute__((amdgpu_waves_per_eu(sol
   VQS_PHASE_FLUSH_AT(8);
 }
 
+// The solo list's order of service, before the solo launch: ranges longer than half
+// the solo threshold first, then the shorter ones and the fills.  Workgroups take items
+// one by one, so the last items taken should be short: a long range taken last holds
+// its workgroup while the others have nothing left.  (Order within each class: that of
+// the wave-aggregated reservations.)
+constexpr int ORDER_P = 256;
+template <class K>
+__global__ void __launch_bounds__(ORDER_P) solo_order_kernel(Params p) {
+  const unsigned long long count = p.solo_ctr->count;
+  const uint64_t nitems = count < p.cap_solo ? count : p.cap_solo;
+  const int lane = lane_id();
+  for (uint64_t base = (uint64_t)blockIdx.x * ORDER_P + (threadIdx.x & ~(WAVE - 1)); base < nitems;
+       base += (uint64_t)gridDim.x * ORDER_P) {
+    const uint64_t i = base + lane;
+    const bool valid = i < nitems;
+    bool big = false;
+    if (valid) {
+      const Seg& s = p.solo[i];
+      big = !(s.flags & SEG_FILL) && (s.e - s.b) > p.solo_max / 2;
+    }
+    const uint64_t mb = ballot(valid && big), ms = ballot(valid && !big);
+    unsigned long long b0 = 0, s0 = 0;
+    if (lane == 0) {
+      if (mb) b0 = atomicAdd(&p.solo_ctr->big, (unsigned long long)__popcll(mb));
+      if (ms) s0 = atomicAdd(&p.solo_ctr->small, (unsigned long long)__popcll(ms));
+    }
+    b0 = __shfl(b0, 0);
+    s0 = __shfl(s0, 0);
+    if (valid) {
+      const uint64_t pos = big ? b0 + mbcnt(mb) : nitems - 1 - (s0 + mbcnt(ms));
+      p.solo_order[pos] = (uint32_t)i;
+    }
+  }
+}
+
 // ---- setup ----------------------------------------------------------------------------------
 
 // Clear counters, statistics and look-back words.
@@ -2715,6 +2750,8 @@ __global__ void clear_kernel(Params p) {
   if (gid == 0) {
     p.solo_ctr->count = 0;
     p.solo_ctr->ticket = 0;
+    p.solo_ctr->big = 0;
+    p.solo_ctr->small = 0;
     *p.err = 0;
     unsigned long long* st = (unsigned long long*)p.stats;
     for (size_t i = 0; i < sizeof(DevStats) / 8; i++) st[i] = 0;

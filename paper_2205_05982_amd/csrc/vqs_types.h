@@ -89,6 +89,7 @@ struct LevelCtr {
 struct SoloCtr {
   unsigned long long count;
   unsigned long long ticket;
+  unsigned long long big, small;   // the order of service: long ranges first (solo_order_kernel)
 };
 
 // Counters of the recursion, comparable one to one with the oracle's.
@@ -125,6 +126,7 @@ struct Params {
   u128k* tilemin;        // per-tile minimum (internal form)
   u128k* tilermin;       // per tile of a level: its smallest right key
   Seg* solo;
+  uint32_t* solo_order;  // the solo list's order of service (indices into solo)
   SoloCtr* solo_ctr;
   DevStats* stats;
   unsigned int* err;
