@@ -169,7 +169,7 @@ def plain_split_sizes(keys: np.ndarray, kt: int, levels: int = 8, seed: int = 0,
     partitioning keys[0, n) (a copy): every range longer than the base-case size is
     split at ChoosePivot; a degenerate split repeats with the first key in sort order
     as pivot within the same round, and an all-equal range stays whole.  Ranges that
-    stop splitting early keep their size.  Judges a 2^levels-way splitter: these are
+    stop splitting early keep their size.  Yardstick for a 2^levels-way splitter: these are
     the buckets plain pivot sampling makes."""
     a = np.ascontiguousarray(keys).copy()
     n = nkeys(a, kt)

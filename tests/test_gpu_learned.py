@@ -135,7 +135,7 @@ def test_learned_sort_overflow_rule_and_degenerate_inputs(vqs):
 
 def test_trained_model_balances_better_than_untrained(vqs):
     """Bucket balance on the mixture workload (4e6 keys) of (A) the model trained with
-    the default settings, (B) the untrained model, and, as the judge, (C) the 256
+    the default settings, (B) the untrained model, and, as the yardstick, (C) the 256
     ranges that 8 levels of the paper's plain pivot sampling make."""
     import torch
     n = 4_000_000

@@ -459,7 +459,7 @@ def test_median3_killer_drives_textbook_quicksort_linear():
     assert (got == np.arange(1, 200_001, dtype=np.uint64)).all()
 
 
-# ---- the plain splitter that judges the learned bucket map ---------------------------------
+# ---- the plain splitter the learned bucket map is measured against --------------------------
 
 U64 = W.U64
 
