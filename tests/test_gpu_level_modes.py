@@ -232,3 +232,28 @@ def test_profile_level_launches_only(vqs):
         assert all(r["ms"] >= 0 for r in recs)
     assert kinds[2] == {"level_partition"}
     assert "level_partition" in kinds[1] and "solo" in kinds[1] and len(kinds[1]) >= 3
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+@pytest.mark.parametrize("shift", [1, 3])
+@pytest.mark.parametrize("asc", [True, False])
+def test_foreseen_degenerate_unaligned_view(vqs, mode, shift, asc):
+    """Peeling chains and all-equal fills on a view that starts off a 16-byte boundary:
+    the keys around the view stay untouched, the view matches the oracle."""
+    import torch
+    n = 1_200_000
+    for top in (True, False):
+        inner = _heavy(n, U32, 0.7, top, 77 + shift)
+        base = np.concatenate([np.full(shift, 123, np.uint32), inner, np.full(5, 456, np.uint32)])
+        t = to_gpu(base)
+        want = inner.copy()
+        ost = oracle.sort(want, U32, ascending=asc, seed=5, stats=True)
+        print(f"case: foreseen degenerate unaligned mode={mode} shift={shift} asc={asc} top={top}", flush=True)
+        vqs.sort(t[shift:shift + n], key_type=U32, ascending=asc, seed=5, solo_max=16384, level_mode=MODES[mode])
+        torch.cuda.synchronize()
+        assert vqs.last_error_bits() == 0
+        got = to_host(t)
+        np.testing.assert_array_equal(got[shift:shift + n], want)
+        np.testing.assert_array_equal(got[:shift], base[:shift])
+        np.testing.assert_array_equal(got[shift + n:], base[shift + n:])
+        assert_stats_equal(ost, vqs.get_stats())
