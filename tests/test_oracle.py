@@ -358,6 +358,31 @@ def test_partition_bound_and_sides(kt):
         np.testing.assert_array_equal(k[e:], keys[e:])
 
 
+@pytest.mark.parametrize("kt", TYPES)
+def test_partition_at_the_largest_key_leaves_the_range_unchanged(kt):
+    """What lets the GPU take a degenerate partition without a pass over the keys:
+    with the range's largest key (in sort order) as pivot every key goes left, in
+    input order, so the range is exactly as before; and the two parts of any
+    partition have as their largest keys the pivot (left) and the range's own
+    (right), which is how a range's largest key is known before its partition."""
+    keys = _random_keys(kt, 3000, seed=11 + kt)
+    for asc in (True, False):
+        b, e = 17, 2900
+        first, last = oracle.minmax(keys, b, e, kt, asc)
+        k = keys.copy()
+        assert oracle.partition(k, b, e, last, kt, asc) == e
+        np.testing.assert_array_equal(k, keys)
+        # a partition at an inner key: the parts' largest keys
+        k = keys.copy()
+        piv = keys[1000]
+        bound = oracle.partition(k, b, e, piv, kt, asc)
+        assert b < bound < e
+        _, lmax = oracle.minmax(k, b, bound, kt, asc)
+        _, rmax = oracle.minmax(k, bound, e, kt, asc)
+        np.testing.assert_array_equal(np.asarray(lmax), np.asarray(piv))
+        np.testing.assert_array_equal(np.asarray(rmax), np.asarray(last))
+
+
 def test_all_equal_input_takes_degenerate_path_once():
     keys = np.full(100_000, 7, dtype=np.uint64)
     st = oracle.sort(keys, oracle.U64, stats=True)
