@@ -53,6 +53,16 @@ def test_profile_modes(lib):
     assert lib.vqs_profile(-1) == -1
 
 
+def test_binding_profile_modes():
+    """The binding passes the mode through and raises on a rejected one."""
+    from paper_2205_05982_amd import vqs
+    vqs.profile(2)
+    vqs.profile(True)
+    vqs.profile(False)
+    with pytest.raises(vqs.VqsError):
+        vqs.profile(7)
+
+
 def test_argument_errors_return_before_any_device_call(lib):
     vp, u64, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int
     lib.vqs_sort_ex.argtypes = [vp, u64, i32, i32, vp, vp]
