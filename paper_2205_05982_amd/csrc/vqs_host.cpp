@@ -681,10 +681,8 @@ int learned_locked(Workspace* ws, void* keys, uint64_t n, const vqs_options* o, 
   vqs_options sopt{};
   sopt.struct_size = sizeof(vqs_options);
   sopt.seed = o ? o->seed : 0;
-  // the sample (1 % of the keys) is small: with solo ranges of the LDS capacity the
-  // solo kernel gets many short ranges rather than a few 32K-key ones that leave most
-  // of its workgroups idle (5e8-key learned sort: -0.65 ms against the default rule)
-  sopt.solo_max = (uint64_t)LOCAL_BYTES / 8;
+  // (the sample is small: the solo threshold rule gives its sort solo ranges of the
+  // LDS capacity, which keep the solo kernel's workgroups busy)
   rc = sort_locked(in, ws->l_sample, nullptr, 1, m, VQS_U64, 1, &sopt, stream);
   if (rc != VQS_OK) return rc;
   e = ws->timed(5, -1, [&] {
