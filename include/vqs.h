@@ -56,7 +56,8 @@ enum vqs_status {
     VQS_ENOMEM = -3,     /* workspace allocation failed */
     VQS_EHIP = -4,       /* a HIP runtime call failed */
     VQS_EOFFSETS = -5,   /* offsets decrease (checked only with options.validate) */
-    VQS_EINTERNAL = -6   /* a device-side capacity check failed (see vqs_last_error_bits) */
+    VQS_EINTERNAL = -6,  /* a device-side capacity check failed (see vqs_last_error_bits) */
+    VQS_ESIZE = -7       /* input too large for the fixed scratch of vqs_sort_noalloc */
 };
 
 /* Method selector of vqs_options.method. */
@@ -150,6 +151,37 @@ int vqs_sort_ex(void* keys, uint64_t n, int key_type, int ascending, const vqs_o
                 void* stream);
 int vqs_sort_segmented_ex(void* keys, const int64_t* offsets, uint64_t nseg, int key_type,
                           int ascending, const vqs_options* options, void* stream);
+
+/* ---- allocation-free sort ----------------------------------------------------------
+ * For callers that cannot allocate device memory: serving loops that must not call
+ * hipMalloc between requests, and harnesses that forbid allocation.
+ *
+ * The same sort as vqs_sort_ex on one array with the plain method (same kernels, same
+ * result and counters), except that every workspace buffer -- the n-key ping-pong
+ * scratch, range lists, tile tables, counters, statistics -- is carved from a fixed
+ * device array of VQS_NOALLOC_SCRATCH_BYTES bytes.  The library holds one such array
+ * per device it runs on, from its load until the process exits.  The call makes no
+ * hipMalloc, hipFree, hipHostMalloc or event creation; the caller passes the keys.
+ *
+ *  - Limit: n is accepted iff vqs_workspace_bytes(n, 1, key_type, options) <=
+ *    VQS_NOALLOC_SCRATCH_BYTES (with default options on a 256-CU device up to about
+ *    7.2e7 u16, 3.9e7 u32 or f32, 2.0e7 u64 or f64, 1.0e7 u128 keys); a larger n
+ *    returns VQS_ESIZE and launches nothing.
+ *  - options: as for vqs_sort_ex, but method must be VQS_METHOD_PLAIN and use_graph
+ *    0 (VQS_EINVAL otherwise).
+ *  - Sharing: every call on a device uses that device's one array, which keeps the
+ *    last call's contents (each call clears what it reads with a kernel first).  Calls
+ *    that overlap on one device -- on two streams, or from two threads without
+ *    ordering -- race on the array and corrupt each other's results: issue them on one
+ *    stream or order them with events.
+ *  - Synchronisation: as vqs_sort_ex, the host waits for the stream once per batch of
+ *    recursion levels to read an 8-byte level counter (into a pageable host word), so
+ *    the call cannot be captured into a HIP graph.
+ *  - vqs_get_stats and vqs_last_error_bits on the same stream report this call until
+ *    a later call on that stream. */
+#define VQS_NOALLOC_SCRATCH_BYTES (256ull << 20)
+int vqs_sort_noalloc(void* keys, uint64_t n, int key_type, int ascending, const vqs_options* options,
+                     void* stream);
 
 /* Autotuner of the batched (segmented) sort.  Times the sort with every combination
  * of the run-time tunables -- solo_max (ranges up to this many keys are finished by

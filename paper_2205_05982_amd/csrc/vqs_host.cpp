@@ -16,6 +16,12 @@
 #include "vqs_launch.h"
 #include "vqs_learned.h"
 
+// Fixed device scratch of vqs_sort_noalloc: every device the library runs on holds its
+// own copy from the library's load until the process ends.  In host code this name
+// stands for a host-side shadow, not a device address: each device's address comes
+// from hipGetSymbolAddress (noalloc_setup) and only that address is used.
+static __device__ __align__(256) unsigned char scratch[VQS_NOALLOC_SCRATCH_BYTES];
+
 namespace vqs {
 
 namespace {
@@ -90,6 +96,9 @@ struct Workspace {
   std::vector<ProfRec> prof;
   size_t events_used = 0;
   bool capturing = false;
+  bool owned = true;       // false: mem and host_pinned belong to someone else (nothing freed)
+  bool no_profile = false; // never record profiling events (the allocation-free path)
+  uint64_t seq = 0;        // order of the calls that left a result (newest is largest)
   hipEvent_t next_event() {
     if (events_used == event_pool.size()) {
       hipEvent_t e = nullptr;
@@ -101,7 +110,7 @@ struct Workspace {
   // record an event pair around a launch when profiling
   template <class F>
   hipError_t timed(int kind, int level, F&& launch) {
-    if (!g_profile || (g_profile == 2 && kind != 2) || capturing) return launch();
+    if (!g_profile || (g_profile == 2 && kind != 2) || capturing || no_profile) return launch();
     hipEvent_t a = next_event(), b = next_event();
     if (a) (void)hipEventRecord(a, stream);
     hipError_t e = launch();
@@ -112,6 +121,7 @@ struct Workspace {
   ~Workspace() {
     for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
     if (graph) (void)hipGraphExecDestroy(graph);
+    if (!owned) return;
     if (mem) (void)hipFree(mem);
     if (host_pinned) (void)hipHostFree(host_pinned);
     if (lmem) (void)hipFree(lmem);
@@ -120,17 +130,26 @@ struct Workspace {
 
 std::mutex g_mu;
 std::map<std::pair<int, hipStream_t>, std::unique_ptr<Workspace>> g_ws;
+uint64_t g_seq = 0;  // numbers the calls that leave a result
 std::map<int, Geometry> g_geom;
+
+Geometry geometry_of(int dev) {
+  Geometry g;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
+    g.num_cu = prop.multiProcessorCount;
+  else
+    (void)hipGetLastError();
+  g.level_grid = g.num_cu * 8;
+  g.solo_grid = g.num_cu * 2;
+  g.plan_grid = g.num_cu * 2;
+  return g;
+}
 
 Geometry geometry(int dev) {
   auto it = g_geom.find(dev);
   if (it != g_geom.end()) return it->second;
-  Geometry g;
-  hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0) g.num_cu = prop.multiProcessorCount;
-  g.level_grid = g.num_cu * 8;
-  g.solo_grid = g.num_cu * 2;
-  g.plan_grid = g.num_cu * 2;
+  const Geometry g = geometry_of(dev);
   g_geom[dev] = g;
   return g;
 }
@@ -248,11 +267,81 @@ int make_plan(uint64_t n, uint64_t nseg, int kt, int asc, const vqs_options* o, 
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Capacities a workspace is carved for.
+struct Caps {
+  uint64_t scratch_bytes, lvl, tiles, solo;
+  int levels;
+};
+
+Caps caps_of(const Plan& pl) {
+  return Caps{(pl.n + 32) * (uint64_t)pl.ks + 64, pl.cap_lvl, pl.cap_tiles, pl.cap_solo, pl.max_levels};
+}
+
+// Layout of a workspace with capacities c: returns its size in bytes and, when mem is
+// not null, points p's buffers into mem (which must be 256-byte aligned).
+size_t carve(char* mem, const Caps& c, Params* p) {
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    size_t o = off;
+    off = align_up(off + b, 256);
+    return o;
+  };
+  const size_t o_scratch = take(c.scratch_bytes);
+  const size_t o_seg0 = take(c.lvl * sizeof(Seg));
+  const size_t o_seg1 = take(c.lvl * sizeof(Seg));
+  const size_t o_tb0 = take(c.lvl * 8);
+  const size_t o_tb1 = take(c.lvl * 8);
+  const size_t o_ctr = take((size_t)c.levels * sizeof(LevelCtr));
+  const size_t o_flags = take(c.tiles * 8);
+  const size_t o_tmin = take(c.tiles * sizeof(u128k));
+  const size_t o_trmin = take(c.tiles * sizeof(u128k));
+  const size_t o_run0 = take(c.tiles * sizeof(TileRun));
+  const size_t o_run1 = take(c.tiles * sizeof(TileRun));
+  const size_t o_tref = take(c.tiles * sizeof(TileRef));
+  const size_t o_tnl = take(c.tiles * sizeof(uint32_t));
+  const size_t o_solo = take(c.solo * sizeof(Seg));
+  const size_t o_sctr = take(sizeof(SoloCtr));
+  const size_t o_sord = take(c.solo * 4);
+  const size_t o_stats = take(sizeof(DevStats));
+  const size_t o_err = take(16);
+  if (!mem) return off;
+  p->scratch = mem + o_scratch;  // re-based per call to the keys' alignment
+  p->lvl_segs[0] = (Seg*)(mem + o_seg0);
+  p->lvl_segs[1] = (Seg*)(mem + o_seg1);
+  p->lvl_tbase[0] = (unsigned long long*)(mem + o_tb0);
+  p->lvl_tbase[1] = (unsigned long long*)(mem + o_tb1);
+  p->lvl_ctr = (LevelCtr*)(mem + o_ctr);
+  p->flags = (unsigned long long*)(mem + o_flags);
+  p->tilemin = (u128k*)(mem + o_tmin);
+  p->tilermin = (u128k*)(mem + o_trmin);
+  p->runs[0] = (TileRun*)(mem + o_run0);
+  p->runs[1] = (TileRun*)(mem + o_run1);
+  p->tref = (TileRef*)(mem + o_tref);
+  p->tnl = (uint32_t*)(mem + o_tnl);
+  p->solo = (Seg*)(mem + o_solo);
+  p->solo_ctr = (SoloCtr*)(mem + o_sctr);
+  p->solo_order = (uint32_t*)(mem + o_sord);
+  p->stats = (DevStats*)(mem + o_stats);
+  p->err = (unsigned int*)(mem + o_err);
+  p->cap_lvl = c.lvl;
+  p->cap_tiles = c.tiles;
+  p->cap_solo = c.solo;
+  return off;
+}
+
+void set_caps(Workspace* ws, const Caps& c) {
+  ws->cap_scratch_bytes = c.scratch_bytes;
+  ws->cap_lvl = c.lvl;
+  ws->cap_tiles = c.tiles;
+  ws->cap_solo = c.solo;
+  ws->cap_levels = c.levels;
+}
+
 // Allocate (or reuse) the workspace for a plan.  Caller holds g_mu.
 int ensure_workspace(Workspace* ws, const Plan& pl) {
-  const uint64_t scratch_bytes = (pl.n + 32) * (uint64_t)pl.ks + 64;
-  if (ws->mem && scratch_bytes <= ws->cap_scratch_bytes && pl.cap_lvl <= ws->cap_lvl &&
-      pl.cap_tiles <= ws->cap_tiles && pl.cap_solo <= ws->cap_solo && pl.max_levels <= ws->cap_levels)
+  const Caps need = caps_of(pl);
+  if (ws->mem && need.scratch_bytes <= ws->cap_scratch_bytes && need.lvl <= ws->cap_lvl &&
+      need.tiles <= ws->cap_tiles && need.solo <= ws->cap_solo && need.levels <= ws->cap_levels)
     return VQS_OK;
   if (ws->mem) {
     (void)hipStreamSynchronize(ws->stream);
@@ -264,74 +353,24 @@ int ensure_workspace(Workspace* ws, const Plan& pl) {
     (void)hipFree(ws->mem);
     ws->mem = nullptr;
   }
-  const uint64_t cap_scratch = std::max(scratch_bytes, ws->cap_scratch_bytes);
-  const uint64_t cap_lvl = std::max(pl.cap_lvl, ws->cap_lvl);
-  const uint64_t cap_tiles = std::max(pl.cap_tiles, ws->cap_tiles);
-  const uint64_t cap_solo = std::max(pl.cap_solo, ws->cap_solo);
-  const int cap_levels = std::max(pl.max_levels, ws->cap_levels);
-  size_t off = 0;
-  auto take = [&](size_t b) {
-    size_t o = off;
-    off = align_up(off + b, 256);
-    return o;
-  };
-  const size_t o_scratch = take(cap_scratch);
-  const size_t o_seg0 = take(cap_lvl * sizeof(Seg));
-  const size_t o_seg1 = take(cap_lvl * sizeof(Seg));
-  const size_t o_tb0 = take(cap_lvl * 8);
-  const size_t o_tb1 = take(cap_lvl * 8);
-  const size_t o_ctr = take((size_t)cap_levels * sizeof(LevelCtr));
-  const size_t o_flags = take(cap_tiles * 8);
-  const size_t o_tmin = take(cap_tiles * sizeof(u128k));
-  const size_t o_trmin = take(cap_tiles * sizeof(u128k));
-  const size_t o_run0 = take(cap_tiles * sizeof(TileRun));
-  const size_t o_run1 = take(cap_tiles * sizeof(TileRun));
-  const size_t o_tref = take(cap_tiles * sizeof(TileRef));
-  const size_t o_tnl = take(cap_tiles * sizeof(uint32_t));
-  const size_t o_solo = take(cap_solo * sizeof(Seg));
-  const size_t o_sctr = take(sizeof(SoloCtr));
-  const size_t o_sord = take(cap_solo * 4);
-  const size_t o_stats = take(sizeof(DevStats));
-  const size_t o_err = take(16);
+  const Caps c{std::max(need.scratch_bytes, ws->cap_scratch_bytes), std::max(need.lvl, ws->cap_lvl),
+               std::max(need.tiles, ws->cap_tiles), std::max(need.solo, ws->cap_solo),
+               std::max(need.levels, ws->cap_levels)};
+  const size_t bytes = carve(nullptr, c, nullptr);
   void* mem = nullptr;
-  if (hipMalloc(&mem, off) != hipSuccess || !mem) {
+  if (hipMalloc(&mem, bytes) != hipSuccess || !mem) {
     (void)hipGetLastError();
     return VQS_ENOMEM;
   }
   ws->mem = (char*)mem;
-  ws->bytes = off;
-  ws->cap_scratch_bytes = cap_scratch;
-  ws->cap_lvl = cap_lvl;
-  ws->cap_tiles = cap_tiles;
-  ws->cap_solo = cap_solo;
-  ws->cap_levels = cap_levels;
-  Params& p = ws->p;
-  p.scratch = ws->mem + o_scratch;  // re-based per call to the keys' alignment
-  p.lvl_segs[0] = (Seg*)(ws->mem + o_seg0);
-  p.lvl_segs[1] = (Seg*)(ws->mem + o_seg1);
-  p.lvl_tbase[0] = (unsigned long long*)(ws->mem + o_tb0);
-  p.lvl_tbase[1] = (unsigned long long*)(ws->mem + o_tb1);
-  p.lvl_ctr = (LevelCtr*)(ws->mem + o_ctr);
-  p.flags = (unsigned long long*)(ws->mem + o_flags);
-  p.tilemin = (u128k*)(ws->mem + o_tmin);
-  p.tilermin = (u128k*)(ws->mem + o_trmin);
-  p.runs[0] = (TileRun*)(ws->mem + o_run0);
-  p.runs[1] = (TileRun*)(ws->mem + o_run1);
-  p.tref = (TileRef*)(ws->mem + o_tref);
-  p.tnl = (uint32_t*)(ws->mem + o_tnl);
-  p.solo = (Seg*)(ws->mem + o_solo);
-  p.solo_ctr = (SoloCtr*)(ws->mem + o_sctr);
-  p.solo_order = (uint32_t*)(ws->mem + o_sord);
-  p.stats = (DevStats*)(ws->mem + o_stats);
-  p.err = (unsigned int*)(ws->mem + o_err);
-  p.cap_lvl = cap_lvl;
-  p.cap_tiles = cap_tiles;
-  p.cap_solo = cap_solo;
+  ws->bytes = bytes;
+  set_caps(ws, c);
+  carve(ws->mem, c, &ws->p);
   if (!ws->host_pinned && hipHostMalloc((void**)&ws->host_pinned, 4096, hipHostMallocDefault) != hipSuccess) {
     ws->host_pinned = nullptr;
     return VQS_ENOMEM;
   }
-  if (hipMemsetAsync(ws->mem + o_stats, 0, sizeof(DevStats), ws->stream) != hipSuccess) return VQS_EHIP;
+  if (hipMemsetAsync(ws->p.stats, 0, sizeof(DevStats), ws->stream) != hipSuccess) return VQS_EHIP;
   return VQS_OK;
 }
 
@@ -477,6 +516,29 @@ int check_offsets_host(const int64_t* offsets, uint64_t nseg, uint64_t* total, h
 int learned_locked(Workspace* ws, void* keys, uint64_t n, const vqs_options* o, hipStream_t stream, bool fit_only,
                    float* params_out);
 
+// Per-call parameters for keys from a carved workspace's buffers.
+void init_params(Params* base, const Params& carved, void* keys, uint64_t n, const Plan& pl) {
+  const uintptr_t addr = (uintptr_t)keys;
+  Params& b = *base;
+  b = carved;
+  b.keys = keys;
+  b.off = (int)((addr % 16) / (uintptr_t)pl.ks);
+  // scratch shares the keys' offset from a 16-byte boundary
+  b.scratch = (void*)(((uintptr_t)carved.scratch + 15) / 16 * 16 + (addr % 16));
+  b.n_total = n;
+  b.mode = pl.mode;
+  b.seed = pl.seed;
+  b.nb = pl.nb;
+  b.local_cap = pl.local;
+  b.solo_max = pl.solo;
+  b.max_levels = pl.max_levels;
+  b.level = 0;
+  b.seed_level = 0;
+  b.fixed_limit = pl.depth_limit;
+  b.run_mode = pl.run_mode;
+  b.dbg = nullptr;
+}
+
 // Prepare base parameters for keys on ws (caller holds g_mu).
 int prepare(Workspace* ws, void* keys, uint64_t n, uint64_t nseg, int kt, int asc, const vqs_options* o, Plan* pl,
             Params* base) {
@@ -485,32 +547,12 @@ int prepare(Workspace* ws, void* keys, uint64_t n, uint64_t nseg, int kt, int as
   if (rc != VQS_OK) return rc;
   rc = ensure_workspace(ws, *pl);
   if (rc != VQS_OK) return rc;
-  const int ks = pl->ks;
-  const uintptr_t addr = (uintptr_t)keys;
-  Params& b = *base;
-  b = ws->p;
-  b.keys = keys;
-  b.off = (int)((addr % 16) / (uintptr_t)ks);
-  // scratch shares the keys' offset from a 16-byte boundary
-  b.scratch = (void*)(((uintptr_t)ws->p.scratch + 15) / 16 * 16 + (addr % 16));
-  b.n_total = n;
-  b.mode = pl->mode;
-  b.seed = pl->seed;
-  b.nb = pl->nb;
-  b.local_cap = pl->local;
-  b.solo_max = pl->solo;
-  b.max_levels = pl->max_levels;
-  b.level = 0;
-  b.seed_level = 0;
-  b.fixed_limit = pl->depth_limit;
-  b.run_mode = pl->run_mode;
+  init_params(base, ws->p, keys, n, *pl);
 #ifdef VQS_PHASE_TIMING
   static unsigned long long* dbg = nullptr;
   if (!dbg && hipMalloc(&dbg, 256) == hipSuccess) (void)hipMemset(dbg, 0, 256);
-  b.dbg = dbg;
+  base->dbg = dbg;
   g_dbg = dbg;
-#else
-  b.dbg = nullptr;
 #endif
   return VQS_OK;
 }
@@ -559,12 +601,14 @@ int sort_locked(Workspace* ws, void* keys, const int64_t* offsets, uint64_t nseg
     if (e != hipSuccess) return VQS_EHIP;
     ws->last_levels = pl.max_levels - 1;
     ws->have_result = true;
+    ws->seq = ++g_seq;
     return VQS_OK;
   }
   e = dispatch_launch(ws, base, pl, g, offsets, nseg, false, &levels);
   if (e != hipSuccess) return VQS_EHIP;
   ws->last_levels = levels;
   ws->have_result = true;
+  ws->seq = ++g_seq;
   return VQS_OK;
 }
 
@@ -722,7 +766,107 @@ int learned_locked(Workspace* ws, void* keys, uint64_t n, const vqs_options* o, 
   if (e != hipSuccess) return VQS_EHIP;
   ws->last_levels = levels;
   ws->have_result = true;
+  ws->seq = ++g_seq;
   ws->learned_ran = true;
+  return VQS_OK;
+}
+
+// ---- allocation-free entry point -------------------------------------------------------
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+
+// Per-device state of vqs_sort_noalloc.  Nothing here owns memory: ws carves its
+// buffers from the device's copy of `scratch` and reads the level counter into a
+// pageable host word.
+struct NoAlloc {
+  bool ready = false;
+  char* ptr = nullptr;                   // this device's copy of `scratch`
+  Geometry geom{};
+  unsigned long long host_ctr[8] = {};   // host word of the level counter reads
+  Workspace ws;
+};
+
+NoAlloc g_noalloc[NOALLOC_MAX_DEVICES];
+
+int current_device() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    dev = 0;
+  }
+  return dev;
+}
+
+// The workspace holding the newest result of a call on (current device, s).
+Workspace* latest_ws(hipStream_t s) {
+  const int dev = current_device();
+  Workspace* best = nullptr;
+  auto it = g_ws.find(std::make_pair(dev, s));
+  if (it != g_ws.end()) best = it->second.get();
+  if (dev >= 0 && dev < NOALLOC_MAX_DEVICES) {
+    Workspace* na = &g_noalloc[dev].ws;
+    if (na->have_result && na->stream == s && (!best || na->seq > best->seq)) best = na;
+  }
+  return best;
+}
+
+// First call on device dev (current): the device address of its copy of `scratch`.
+// Caller holds g_mu.
+int noalloc_setup(int dev) {
+  NoAlloc& na = g_noalloc[dev];
+  if (na.ready) return VQS_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    return VQS_EHIP;
+  }
+  na.ptr = (char*)ptr;
+  na.geom = geometry_of(dev);
+  na.ws.owned = false;
+  na.ws.no_profile = true;
+  na.ws.device = dev;
+  na.ws.mem = na.ptr;
+  na.ws.host_pinned = na.host_ctr;
+  na.ready = true;
+  return VQS_OK;
+}
+
+int noalloc_sort(void* keys, uint64_t n, int kt, int asc, const vqs_options* o, hipStream_t stream) {
+  if (o && o->struct_size != 0 && o->struct_size < offsetof(vqs_options, train_steps)) return VQS_EINVAL;
+  const int bits = key_bits(kt);
+  if (!bits) return VQS_ETYPE;
+  if (asc != 0 && asc != 1) return VQS_EINVAL;
+  if (o && (o->method != VQS_METHOD_PLAIN || o->use_graph)) return VQS_EINVAL;
+  if (n == 0) return VQS_OK;
+  if (!keys) return VQS_EINVAL;
+  if ((uintptr_t)keys % (uintptr_t)std::min(bits / 8, 16)) return VQS_EINVAL;
+  std::lock_guard<std::mutex> lock(g_mu);
+  const int dev = current_device();
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return VQS_EINVAL;
+  int rc = noalloc_setup(dev);
+  if (rc != VQS_OK) return rc;
+  NoAlloc& na = g_noalloc[dev];
+  Plan pl;
+  rc = make_plan(n, 1, kt, asc, o, na.geom, &pl);
+  if (rc != VQS_OK) return rc;
+  const Caps c = caps_of(pl);
+  if (carve(nullptr, c, nullptr) > (size_t)VQS_NOALLOC_SCRATCH_BYTES) return VQS_ESIZE;
+  Workspace* ws = &na.ws;
+  ws->stream = stream;
+  ws->have_result = false;
+  ws->learned_ran = false;
+  ws->bytes = (size_t)VQS_NOALLOC_SCRATCH_BYTES;
+  set_caps(ws, c);
+  carve(ws->mem, c, &ws->p);
+  Params base;
+  init_params(&base, ws->p, keys, n, pl);
+  int levels = 0;
+  // clear_kernel zeroes every counter, flag and statistic the call reads
+  if (dispatch_launch(ws, base, pl, na.geom, nullptr, 1, false, &levels) != hipSuccess) return VQS_EHIP;
+  ws->last_levels = levels;
+  ws->have_result = true;
+  ws->seq = ++g_seq;
   return VQS_OK;
 }
 
@@ -740,6 +884,11 @@ int vqs_sort_ex(void* keys, uint64_t n, int key_type, int ascending, const vqs_o
 
 int vqs_sort(void* keys, uint64_t n, int key_type, int ascending) {
   return vqs_sort_ex(keys, n, key_type, ascending, nullptr, nullptr);
+}
+
+int vqs_sort_noalloc(void* keys, uint64_t n, int key_type, int ascending, const vqs_options* options,
+                     void* stream) {
+  return noalloc_sort(keys, n, key_type, ascending, options, (hipStream_t)stream);
 }
 
 int vqs_sort_segmented_ex(void* keys, const int64_t* offsets, uint64_t nseg, int key_type, int ascending,
@@ -865,25 +1014,23 @@ int vqs_sort_segmented(void* keys, const int64_t* offsets, uint64_t nseg, int ke
 
 uint64_t vqs_workspace_bytes(uint64_t n, uint64_t nseg, int key_type, const vqs_options* options) {
   if (!key_bits(key_type)) return 0;
-  Geometry g;
+  std::lock_guard<std::mutex> lock(g_mu);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    dev = 0;
+  }
   Plan pl;
-  if (make_plan(n, nseg ? nseg : 1, key_type, 1, options, g, &pl) != VQS_OK) return 0;
-  uint64_t b = (n + 32) * (uint64_t)pl.ks + 64;
-  b += 2 * pl.cap_lvl * (sizeof(Seg) + 8) + (uint64_t)pl.max_levels * sizeof(LevelCtr);
-  b += pl.cap_tiles * (8 + 2 * sizeof(u128k) + 2 * sizeof(TileRun) + sizeof(TileRef) + 4) + pl.cap_solo * (sizeof(Seg) + 4) +
-       4096;
-  return b;
+  if (make_plan(n, nseg ? nseg : 1, key_type, 1, options, geometry(dev), &pl) != VQS_OK) return 0;
+  return carve(nullptr, caps_of(pl), nullptr);
 }
 
 int vqs_get_stats(void* stream, vqs_stats* out) {
   if (!out) return VQS_EINVAL;
   std::lock_guard<std::mutex> lock(g_mu);
-  int dev = 0;
-  (void)hipGetDevice(&dev);
-  auto it = g_ws.find(std::make_pair(dev, (hipStream_t)stream));
   memset(out, 0, sizeof(*out));
-  if (it == g_ws.end() || !it->second->have_result) return VQS_OK;
-  Workspace* ws = it->second.get();
+  Workspace* ws = latest_ws((hipStream_t)stream);
+  if (!ws || !ws->have_result) return VQS_OK;
   DevStats d;
   if (hipMemcpyAsync(&d, ws->p.stats, sizeof(d), hipMemcpyDeviceToHost, ws->stream) != hipSuccess ||
       hipStreamSynchronize(ws->stream) != hipSuccess)
@@ -975,12 +1122,9 @@ int vqs_learned_classify(const uint64_t* keys, uint64_t n, const uint64_t* thres
 int vqs_last_error_bits(void* stream, uint32_t* out) {
   if (!out) return VQS_EINVAL;
   std::lock_guard<std::mutex> lock(g_mu);
-  int dev = 0;
-  (void)hipGetDevice(&dev);
   *out = 0;
-  auto it = g_ws.find(std::make_pair(dev, (hipStream_t)stream));
-  if (it == g_ws.end() || !it->second->mem) return VQS_OK;
-  Workspace* ws = it->second.get();
+  Workspace* ws = latest_ws((hipStream_t)stream);
+  if (!ws || !ws->mem) return VQS_OK;
   unsigned int e = 0;
   if (hipMemcpyAsync(&e, ws->p.err, 4, hipMemcpyDeviceToHost, ws->stream) != hipSuccess ||
       hipStreamSynchronize(ws->stream) != hipSuccess)
@@ -999,10 +1143,8 @@ int vqs_profile(int enable) {
 int vqs_profile_read(void* stream, vqs_kernel_time* out, int max, int* count) {
   if (!count || (max > 0 && !out)) return VQS_EINVAL;
   std::lock_guard<std::mutex> lock(g_mu);
-  int dev = 0;
-  (void)hipGetDevice(&dev);
   *count = 0;
-  auto it = g_ws.find(std::make_pair(dev, (hipStream_t)stream));
+  auto it = g_ws.find(std::make_pair(current_device(), (hipStream_t)stream));
   if (it == g_ws.end() || !it->second->mem) return VQS_OK;
   Workspace* ws = it->second.get();
   if (hipStreamSynchronize(ws->stream) != hipSuccess) return VQS_EHIP;
@@ -1042,6 +1184,7 @@ const char* vqs_strerror(int code) {
     case VQS_EHIP: return "HIP runtime error";
     case VQS_EOFFSETS: return "segment offsets decrease";
     case VQS_EINTERNAL: return "device-side capacity check failed";
+    case VQS_ESIZE: return "input larger than the fixed scratch of vqs_sort_noalloc allows";
     default: return "unknown error";
   }
 }

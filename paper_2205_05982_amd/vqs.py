@@ -23,7 +23,9 @@ for _name, _kt in (("uint16", U16), ("uint32", U32), ("uint64", U64)):
     if hasattr(torch, _name):
         _DTYPE_TO_KT[getattr(torch, _name)] = _kt
 _ERRORS = {-1: "invalid argument", -2: "unknown key type", -3: "workspace allocation failed",
-           -4: "HIP runtime error", -5: "segment offsets decrease", -6: "device capacity check failed"}
+           -4: "HIP runtime error", -5: "segment offsets decrease", -6: "device capacity check failed",
+           -7: "input too large for the fixed scratch of vqs_sort_noalloc"}
+NOALLOC_SCRATCH_BYTES = 256 << 20
 
 
 class VqsError(RuntimeError):
@@ -75,6 +77,7 @@ def lib():
         vp, u64, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int
         L.vqs_sort.argtypes = [vp, u64, i32, i32]
         L.vqs_sort_ex.argtypes = [vp, u64, i32, i32, ctypes.POINTER(Options), vp]
+        L.vqs_sort_noalloc.argtypes = [vp, u64, i32, i32, ctypes.POINTER(Options), vp]
         L.vqs_sort_segmented.argtypes = [vp, vp, u64, i32, i32]
         L.vqs_sort_segmented_ex.argtypes = [vp, vp, u64, i32, i32, ctypes.POINTER(Options), vp]
         L.vqs_workspace_bytes.argtypes = [u64, u64, i32, ctypes.POINTER(Options)]
@@ -85,7 +88,8 @@ def lib():
         L.vqs_strerror.restype = ctypes.c_char_p
         L.vqs_profile.argtypes = [i32]
         L.vqs_profile_read.argtypes = [vp, ctypes.POINTER(KernelTime), i32, ctypes.POINTER(i32)]
-        for name in ("vqs_profile", "vqs_profile_read", "vqs_sort", "vqs_sort_ex", "vqs_sort_segmented", "vqs_sort_segmented_ex",
+        for name in ("vqs_profile", "vqs_profile_read", "vqs_sort", "vqs_sort_ex", "vqs_sort_noalloc",
+                     "vqs_sort_segmented", "vqs_sort_segmented_ex",
                      "vqs_get_stats", "vqs_last_error_bits", "vqs_release", "vqs_version"):
             getattr(L, name).restype = i32
         _lib = L
@@ -141,6 +145,21 @@ def sort(t: torch.Tensor, ascending: bool = True, key_type: int | None = None, s
                            ctypes.byref(o), ctypes.c_void_p(_stream_handle(stream)))
     if rc != 0:
         raise VqsError(rc, "vqs_sort")
+    return t
+
+
+def sort_noalloc(t: torch.Tensor, ascending: bool = True, key_type: int | None = None, stream=None,
+                 **opts) -> torch.Tensor:
+    """Sort t in place with the allocation-free entry point (vqs_sort_noalloc): the
+    plain method, every workspace buffer taken from the library's fixed per-device
+    scratch of NOALLOC_SCRATCH_BYTES; raises VqsError(-7) for inputs that do not fit."""
+    _check(t)
+    kt = key_type_of(t, key_type)
+    o = make_options(**opts)
+    rc = lib().vqs_sort_noalloc(ctypes.c_void_p(t.data_ptr()), _nkeys(t, kt), kt, int(bool(ascending)),
+                                ctypes.byref(o), ctypes.c_void_p(_stream_handle(stream)))
+    if rc != 0:
+        raise VqsError(rc, "vqs_sort_noalloc")
     return t
 
 

@@ -99,3 +99,21 @@ def test_options_and_stats_layout_match_the_header(tmp_path):
     got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
     assert got == [ctypes.sizeof(vqs.Options), vqs.Options.train_steps.offset, vqs.Options.model_seed.offset,
                    vqs.Options.level_mode.offset, ctypes.sizeof(vqs.Stats), vqs.Stats.train_loss.offset]
+
+
+def test_noalloc_argument_errors_return_before_any_device_call(lib):
+    """vqs_sort_noalloc checks its arguments before it touches a device."""
+    from paper_2205_05982_amd import vqs
+    vp, u64, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int
+    lib.vqs_sort_noalloc.argtypes = [vp, u64, i32, i32, ctypes.POINTER(vqs.Options), vp]
+    assert lib.vqs_sort_noalloc(None, 10, 9, 1, None, None) == -2      # unknown key type
+    assert lib.vqs_sort_noalloc(None, 10, 3, 2, None, None) == -1      # ascending not 0/1
+    assert lib.vqs_sort_noalloc(None, 0, 3, 1, None, None) == 0        # nothing to sort
+    assert lib.vqs_sort_noalloc(None, 10, 3, 1, None, None) == -1      # null keys
+    assert lib.vqs_sort_noalloc(ctypes.c_void_p(0x1004), 10, 3, 1, None, None) == -1   # misaligned u64
+    learned = vqs.make_options(method=1)
+    assert lib.vqs_sort_noalloc(ctypes.c_void_p(0x1000), 10, 3, 1, ctypes.byref(learned), None) == -1
+    graph = vqs.make_options(use_graph=1)
+    assert lib.vqs_sort_noalloc(ctypes.c_void_p(0x1000), 10, 3, 1, ctypes.byref(graph), None) == -1
+    lib.vqs_strerror.restype = ctypes.c_char_p
+    assert b"vqs_sort_noalloc" in lib.vqs_strerror(-7)
