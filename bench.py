@@ -18,7 +18,14 @@ steps, on the library's stream, give the durations (only those launches are
 recorded there, which costs the timed steps little; two more sorts after them, with
 every launch recorded, give the solo and total kernel times).  Besides the 8 TB/s
 peak, the bandwidth of a plain device-to-device copy of the input (measured the same
-way) is reported as a second denominator ("copy_gbs", "frac_of_copy").
+way) is reported as a second denominator ("copy_gbs", "frac_of_copy").  "passes" is
+the number of full read+write sweeps over the keys the sort made, from the library's
+key-traffic counters (level partitions and copy passes, single-workgroup partitions,
+the load and store of every in-LDS sort; partitions inside LDS move no device
+memory), and "end_to_end_frac" is passes x 2 x n x key size / step time / peak.
+
+"cpu_baseline" is the CPU oracle on the host's cores (one thread and all threads, on
+a sample of the same input), with np.sort and std::sort of that sample as context.
 """
 from __future__ import annotations
 
@@ -62,7 +69,8 @@ def parse():
     ap.add_argument("--workload", default="c2_uniform", choices=sorted(WORKLOADS))
     ap.add_argument("--n", type=int, default=0, help="override the key count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=100_000_000)
+    ap.add_argument("--cpu-sample", type=int, default=30_000_000,
+                    help="keys of the CPU baseline's sample (the first keys of the same input)")
     ap.add_argument("--profile-json", default="", help="write per-launch kernel times here")
     ap.add_argument("--learned-n", type=int, default=500_000_000,
                     help="keys of the learned-splitter vs plain comparison (0: skip it)")
@@ -244,6 +252,69 @@ def make_input(name: str, n: int) -> np.ndarray:
     return W.c2(dist, n)
 
 
+def cpu_threads() -> int:
+    """Host threads for the all-core oracle timing: the cores this process may run on,
+    capped by OMP_NUM_THREADS where the machine sets it (the process's CPU share)."""
+    t = len(os.sched_getaffinity(0))
+    cap = os.environ.get("OMP_NUM_THREADS")
+    if cap and cap.isdigit() and int(cap) > 0:
+        t = min(t, int(cap))
+    return t
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(host, kt: int, m: int) -> dict:
+    """The oracle timed on the host's cores on the first m keys of the input (median of
+    three runs each): one thread, and all threads (the oracle's top recursion levels as
+    parallel tasks, then its sort of the remaining ranges across the threads); np.sort
+    and std::sort of the same keys as context."""
+    import oracle
+    oracle.build()
+    threads = cpu_threads()
+    src = host[:m]
+    want = None
+
+    def timed(fn):
+        ts = []
+        for _ in range(3):
+            a = src.copy()
+            t0 = time.perf_counter()
+            fn(a)
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts)), a
+
+    t1, a1 = timed(lambda a: oracle.sort(a, kt))
+    tp, ap = timed(lambda a: oracle.parallel_sort(a, kt, threads))
+    if not np.array_equal(a1, ap):
+        raise RuntimeError("the parallel oracle run differs from the one-threaded oracle")
+    if kt == 4:
+        tnp = None
+    else:
+        tnp, _ = timed(lambda a: a.sort(kind="quicksort"))
+    tstd, astd = timed(lambda a: oracle.context_std_sort(a, kt))
+    if not np.array_equal(a1, astd):
+        raise RuntimeError("std::sort differs from the oracle")
+    g = lambda t: round(m / t / 1e9, 5) if t else None
+    return {"value": g(tp), "unit": "Gkeys/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {m} keys of the same input; scalar C oracle; median of 3 runs; "
+                      f"{threads} threads: top recursion levels as parallel tasks, then the oracle on "
+                      f"each remaining range ({tp:.2f} s)",
+            "one_thread": {"value": g(t1), "seconds": round(t1, 3)},
+            "cpu_model": cpu_model(),
+            "context": {"np_sort_one_thread": g(tnp), "std_sort_one_thread": g(tstd),
+                        "numpy": np.__version__}}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -331,7 +402,9 @@ def main():
     vqs.profile(0)
     solo_ms = sum(r["ms"] for r in diag if r["kind"] == "solo") / ndiag
     all_ms = sum(r["ms"] for r in diag) / ndiag
-    passes = stats["keys_partitioned"] / n + 1.0     # partitions + the final local-sort pass
+    # full read+write sweeps over the keys: every key each level partition, copy pass,
+    # single-workgroup partition and in-LDS sort reads and writes, counted by the library
+    passes = (stats["hbm_read_keys"] + stats["hbm_write_keys"]) / (2.0 * n)
     e2e_frac = (passes * 2 * n * ks / (ms_step * 1e-3) / 1e9) / HBM_PEAK_GBS
     if args.profile_json:
         with open(args.profile_json, "w") as f:
@@ -356,16 +429,7 @@ def main():
     torch.cuda.empty_cache()
     lvp = learned_vs_plain(args.learned_n, args.learned_reps) if args.learned_n else None
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-        m = min(args.cpu_sample, n)
-        sample = host[:m].copy()
-        t0 = time.perf_counter()
-        oracle.sort(sample, kt)
-        dt = time.perf_counter() - t0
-        cpu = {"value": m / dt / 1e9, "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
-               "sample": f"first {m} keys of the same input, scalar C oracle, one thread, {dt:.1f} s"}
+    cpu = None if args.no_cpu_baseline else cpu_baseline(host, kt, min(args.cpu_sample, n))
 
     line = {
         "metric": METRIC,
@@ -405,7 +469,7 @@ def main():
             "end_to_end_frac": round(e2e_frac, 4),
         },
         "stats": {k: stats[k] for k in ("partitions", "degenerate", "basecases", "fallbacks", "max_depth",
-                                       "levels", "solo_items")},
+                                       "levels", "solo_items", "hbm_read_keys", "hbm_write_keys")},
         "cpu_baseline": cpu,
         "learned_vs_plain": lvp,
     }

@@ -20,14 +20,36 @@
  *  - Floating-point keys are ordered by the total order of their bit patterns:
  *    -NaN < -inf < ... < -0.0 < +0.0 < ... < +inf < +NaN.  For inputs without NaN
  *    and without -0.0 this is the IEEE order, and the result is unique.
- *  - Calls are asynchronous on `stream` (a hipStream_t; NULL is the default
- *    stream).  Argument errors return at once without launching anything.  The
- *    library keeps a scratch workspace of n keys plus bookkeeping per stream,
- *    allocated on first use and reused; calls on distinct streams are thread safe.
- *    If the workspace cannot be allocated, VQS_ENOMEM is returned and keys is
- *    untouched.
  *  - Sorting is not stable (Sec. 5): equal keys are bit-identical here, so the
  *    output is the unique sorted rearrangement of the input.
+ *  - Workspace: unless options.workspace supplies one, the library keeps a device
+ *    workspace (a scratch array of n keys for the out-of-place partitions, plus range
+ *    lists, tile tables and counters; vqs_workspace_bytes gives its size) per
+ *    (device, stream), allocated on first use, grown when needed and reused.  If it
+ *    cannot be allocated, VQS_ENOMEM is returned and keys is untouched.  Calls on
+ *    distinct streams are thread safe.
+ *  - Argument errors return at once without launching anything.  A failing HIP call
+ *    returns VQS_EHIP.
+ *
+ * Synchronisation.  Work is issued on `stream` (a hipStream_t; NULL is the default
+ * stream) and a call returns while its last kernels still run, except where the host
+ * waits for the stream:
+ *  - the level loop (vqs_sort, vqs_sort_ex, vqs_sort_noalloc, and the segmented
+ *    forms without use_graph): when the input holds ranges longer than solo_max,
+ *    the device-wide recursion levels are issued in batches (first
+ *    floor(log2(n / solo_max)) + 6 levels, then 4 at a time) and after each batch
+ *    the host waits for the stream and reads one 8-byte counter to see whether a
+ *    level is left.  The per-workgroup finish (the last kernel) is in flight on
+ *    return.  An input with no range longer than solo_max is issued without waiting;
+ *  - segmented sorts read offsets[nseg] (the total key count) before issuing anything,
+ *    unless options.total_keys supplies it; with options.validate every offset is read;
+ *  - with options.use_graph, a segmented call replays one captured graph holding every
+ *    level's launches, so with options.total_keys it does not wait at all (capture,
+ *    on the first call with given arguments, does not wait either);
+ *  - the learned method waits in the level loops of its sample's sort and of the
+ *    buckets' sort;
+ *  - vqs_autotune_segmented, vqs_get_stats, vqs_last_error_bits, vqs_profile_read and
+ *    vqs_release wait for the stream (or all streams) before returning.
  */
 #ifndef VQS_H
 #define VQS_H
@@ -38,7 +60,9 @@
 extern "C" {
 #endif
 
-/* Key types. */
+/* Key types: the 16/32/64-bit unsigned integers, 32/64-bit floating point and pairs of
+ * 64-bit halves forming a 128-bit key that the paper's method handles (Sec. 2.4,
+ * Sec. 5).  Every type sorts ascending or descending (Sec. 2.4's order tag). */
 enum vqs_key_type {
     VQS_U16 = 1,
     VQS_U32 = 2,
@@ -55,19 +79,25 @@ enum vqs_status {
     VQS_ETYPE = -2,      /* unknown key type */
     VQS_ENOMEM = -3,     /* workspace allocation failed */
     VQS_EHIP = -4,       /* a HIP runtime call failed */
-    VQS_EOFFSETS = -5,   /* offsets decrease (checked only with options.validate) */
+    VQS_EOFFSETS = -5,   /* offsets decrease (checked only with options.validate), or
+                            options.total_keys differs from offsets[nseg] (validate) */
     VQS_EINTERNAL = -6,  /* a device-side capacity check failed (see vqs_last_error_bits) */
-    VQS_ESIZE = -7       /* input too large for the fixed scratch of vqs_sort_noalloc */
+    VQS_ESIZE = -7       /* input too large for the supplied workspace
+                            (options.workspace_bytes) or for the fixed scratch of
+                            vqs_sort_noalloc */
 };
 
 /* Method selector of vqs_options.method. */
 enum vqs_method {
-    VQS_METHOD_PLAIN = 0,    /* the paper's Quicksort */
-    VQS_METHOD_LEARNED = 1   /* learned 256-bucket splitter first, then the plain method */
+    VQS_METHOD_PLAIN = 0,    /* the paper's Quicksort (Alg. 1) */
+    VQS_METHOD_LEARNED = 1   /* a 256-way split first, then the Quicksort on every bucket:
+                                the samplesort-then-Quicksort hybrid of Sec. 4.2, with
+                                the splitters given by a learned monotone CDF model */
 };
 
 /* How the device-wide partition levels place a tile's output (vqs_options.level_mode).
- * Both give identical results and recursion counts.
+ * Both give identical results and recursion counts (the key sequence of Sec. 2.1's
+ * partition is the same; only its placement in memory differs).
  *  - LOOKBACK: each tile finds its offsets inside its range from the left counts of
  *    the range's earlier tiles (a decoupled look-back), and the partition is written
  *    contiguously.
@@ -86,15 +116,17 @@ enum vqs_level_mode {
 };
 
 /* Options of the extended entry points.  Zero-initialise and set struct_size;
- * every zero field selects the default. */
+ * every zero field selects the default.  A field is read only when struct_size
+ * covers it (struct_size 0 is taken as the full structure). */
 typedef struct vqs_options {
     uint32_t struct_size;       /* sizeof(vqs_options) */
     uint32_t method;            /* enum vqs_method */
-    uint64_t seed;              /* seed of the pivot sampler (Sec. 2.2); default 0 */
-    int64_t depth_limit;        /* 0: 2*floor(log2 n)+4 per range; > 0: that limit;
-                                   < 0: limit 0 (every range above the base case
-                                   takes the bounded-time fallback) */
-    uint32_t base_case;         /* NBaseCase in keys, 32..256; default 256 */
+    uint64_t seed;              /* seed of the pivot sampler's generator (Sec. 2.2);
+                                   default 0 */
+    int64_t depth_limit;        /* recursion depth limit (Sec. 2.2): 0: 2*floor(log2 n)+4
+                                   per range; > 0: that limit; < 0: limit 0 (every range
+                                   above the base case takes the fallback) */
+    uint32_t base_case;         /* NBaseCase in keys (Sec. 2.3), 32..256; default 256 */
     uint32_t local_keys;        /* LDS local-sort capacity in keys; default: tuned */
     uint64_t solo_max;          /* ranges up to this many keys are finished by one
                                    workgroup; default: tuned */
@@ -113,11 +145,30 @@ typedef struct vqs_options {
     uint64_t sample_seed;       /* seed of the 1 % chunk sample and of the minibatches;
                                    default 17 */
     uint32_t level_mode;        /* enum vqs_level_mode; default VQS_LEVEL_AUTO */
-    uint32_t reserved[2];
+    uint32_t fallback_limit;    /* depth limit of the fallback mode itself: a range past
+                                   the paper's limit (Sec. 2.2) keeps being partitioned
+                                   until this depth, then takes the bounded-time sort.
+                                   0: 2*floor(log2 len)+4 of the range;
+                                   VQS_FALLBACK_LIMIT_ZERO: 0, so such a range goes
+                                   straight to the bounded-time sort */
+    uint32_t reserved;
+    uint64_t total_keys;        /* segmented sorts: offsets[nseg], if the caller knows it
+                                   (then it is not read from the device); 0: read it */
+    void* workspace;            /* optional caller-owned device workspace (256-byte
+                                   aligned) used instead of the library's, so the call
+                                   allocates no device memory.  Its contents are
+                                   scratch; keep it until the call has finished and its
+                                   statistics or error bits have been read.  Not with
+                                   the learned method (VQS_EINVAL). */
+    uint64_t workspace_bytes;   /* its size; below vqs_workspace_bytes(...): VQS_ESIZE */
 } vqs_options;
 
+#define VQS_FALLBACK_LIMIT_ZERO 0xFFFFFFFFu
+
 /* Counters of the last call on a stream (copied with synchronisation).  The first
- * eight count the recursion exactly like the CPU oracle does. */
+ * eight count the recursion of Alg. 1 exactly as the CPU oracle does: one Partition
+ * per Recurse call that partitions, the degenerate re-partition with the first key
+ * included; BaseCase calls; ranges past the depth limit (the oracle's HeapSort calls). */
 typedef struct vqs_stats {
     uint64_t partitions;        /* Partition calls (all ranges, all levels) */
     uint64_t keys_partitioned;  /* sum of partitioned range lengths */
@@ -136,17 +187,32 @@ typedef struct vqs_stats {
     uint64_t overflow_buckets;  /* buckets above the overflow bound */
     uint64_t max_bucket;        /* largest bucket */
     double train_loss;          /* final minibatch loss */
+    /* traffic and the bounded-time fallback */
+    uint64_t hbm_read_keys;     /* keys read from device memory by whole-key sweeps: the
+                                   level partitions and copy passes, the per-workgroup
+                                   partitions, the load of every in-LDS sort, the
+                                   bounded-time sorts' passes (partitions inside LDS,
+                                   pivot samples, tile minima and the learned splitter's
+                                   own passes are not counted) */
+    uint64_t hbm_write_keys;    /* keys written by the same sweeps, fills included */
+    uint64_t bounded_lds;       /* ranges sorted by the bounded-time network in LDS */
+    uint64_t bounded_global;    /* ranges sorted by the bounded-time chunk sort and
+                                   merge through device memory */
 } vqs_stats;
 
-/* Sort keys[0, n) in place on the default stream with default options. */
+/* Sort keys[0, n) in place, ascending (ascending = 1) or descending (0), on the
+ * default stream with default options: Sec. 2.4's Sort(keys, n, order tag). */
 int vqs_sort(void* keys, uint64_t n, int key_type, int ascending);
 
 /* Sort each segment [offsets[i], offsets[i+1]) of keys independently, for
- * i < nseg.  offsets is a device array of nseg + 1 non-decreasing int64 values;
- * empty segments are allowed. */
+ * i < nseg, each as vqs_sort would (the same pivots, recursion and result per
+ * segment), all in one sequence of launches.  offsets is a device array of nseg + 1
+ * non-decreasing int64 values; empty segments are allowed.  Not in the paper: the
+ * batched analogue of many independent Sort calls. */
 int vqs_sort_segmented(void* keys, const int64_t* offsets, uint64_t nseg, int key_type, int ascending);
 
-/* Extended forms: options may be NULL (defaults); stream is a hipStream_t or NULL. */
+/* Extended forms of the two calls above: options may be NULL (defaults); stream is a
+ * hipStream_t or NULL. */
 int vqs_sort_ex(void* keys, uint64_t n, int key_type, int ascending, const vqs_options* options,
                 void* stream);
 int vqs_sort_segmented_ex(void* keys, const int64_t* offsets, uint64_t nseg, int key_type,
@@ -167,8 +233,8 @@ int vqs_sort_segmented_ex(void* keys, const int64_t* offsets, uint64_t nseg, int
  *    VQS_NOALLOC_SCRATCH_BYTES (with default options on a 256-CU device up to about
  *    7.2e7 u16, 3.9e7 u32 or f32, 2.0e7 u64 or f64, 1.0e7 u128 keys); a larger n
  *    returns VQS_ESIZE and launches nothing.
- *  - options: as for vqs_sort_ex, but method must be VQS_METHOD_PLAIN and use_graph
- *    0 (VQS_EINVAL otherwise).
+ *  - options: as for vqs_sort_ex, but method must be VQS_METHOD_PLAIN, use_graph 0
+ *    and workspace NULL (VQS_EINVAL otherwise).
  *  - Sharing: every call on a device uses that device's one array, which keeps the
  *    last call's contents (each call clears what it reads with a kernel first).  Calls
  *    that overlap on one device -- on two streams, or from two threads without
@@ -187,41 +253,48 @@ int vqs_sort_noalloc(void* keys, uint64_t n, int key_type, int ascending, const 
  * of the run-time tunables -- solo_max (ranges up to this many keys are finished by
  * one workgroup each, longer ones are partitioned by the device-wide level kernel) in
  * {0 = the library's size rule, 2^14, 2^16, 2^18, 2^20}, local_keys (size of the
- * in-LDS sort) in {full buffer, half}, base_case in {256, 128} -- on a copy of the
- * segments (all of them when max_keys is 0, else the longest prefix with at most
- * max_keys keys, at least one segment), best of two timed runs after a warm-up each,
- * and writes the fastest combination into options->solo_max, local_keys and base_case
- * (the other fields are kept and used for the runs; method is plain).  keys and
- * offsets are device pointers as for vqs_sort_segmented; the caller's keys are not
- * modified.  Allocates the copy (hipMalloc, freed before return) and synchronises the
- * stream.  *best_ms (if not NULL) receives the best time.  Errors: VQS_EINVAL for
- * null pointers, nseg == 0 or a short options struct, VQS_EOFFSETS, VQS_ENOMEM,
- * VQS_EHIP.  A prefix represents the batch only when the segment order carries no
- * size trend, and the best solo_max depends on how many ranges run at once, so a
- * prefix may prefer a smaller one than the whole batch. */
+ * in-LDS sort) in {full buffer, half}, base_case in {256, 128}, and level_mode in
+ * {LOOKBACK, RUNS} -- on a copy of the segments (all of them when max_keys is 0, else
+ * the longest prefix with at most max_keys keys, at least one segment), best of two
+ * timed runs after a warm-up each, and writes the fastest combination into
+ * options->solo_max, local_keys, base_case and level_mode (the other fields are kept
+ * and used for the runs; method is plain).  keys and offsets are device pointers as
+ * for vqs_sort_segmented; the caller's keys are not modified.  Allocates the copy
+ * (hipMalloc, freed before return) and synchronises the stream.  *best_ms (if not
+ * NULL) receives the best time.  Errors: VQS_EINVAL for null pointers, nseg == 0 or a
+ * short options struct, VQS_EOFFSETS, VQS_ENOMEM, VQS_EHIP.  A prefix represents the
+ * batch only when the segment order carries no size trend, and the best solo_max
+ * depends on how many ranges run at once, so a prefix may prefer a smaller one than
+ * the whole batch.  Not in the paper. */
 int vqs_autotune_segmented(const void* keys, const int64_t* offsets, uint64_t nseg, int key_type, int ascending,
                            uint64_t max_keys, vqs_options* options, float* best_ms, void* stream);
 
-/* Device bytes of the workspace a sort of n keys (in nseg segments) needs. */
+/* Device bytes of the workspace a plain sort of n keys in nseg segments (nseg 0 is
+ * taken as 1) needs with these options (NULL: defaults) on the current device: the
+ * size options.workspace must have, and the measure of vqs_sort_noalloc's limit.
+ * 0 for an unknown key type or rejected options. */
 uint64_t vqs_workspace_bytes(uint64_t n, uint64_t nseg, int key_type, const vqs_options* options);
 
-/* Statistics of the last call issued on `stream`; waits for that call to finish. */
+/* Statistics of the last call issued on `stream` (the counters above); waits for
+ * that call to finish.  All zero if no call has run on the stream. */
 int vqs_get_stats(void* stream, vqs_stats* out);
 
 /* Device error bits of the last call on `stream` (0 if none); waits for it. */
 int vqs_last_error_bits(void* stream, uint32_t* out);
 
 /* ---- learned splitter pieces (method VQS_METHOD_LEARNED runs all of them) --------
+ * Not in the paper, which names the 256-way samplesort split as the bandwidth-friendly
+ * generalisation of the partition (Sec. 4.2); here its splitters come from a CDF model.
  * The model is a 1 -> 32 -> 32 -> 1 perceptron with clamp-to-[0,1] activations and
  * non-negative weight matrices: its parameter block is 1155 floats on the device,
  * w1[32] b1[32] W2[32][32] (row j = second-layer unit j) b2[32] w3[32] b3 x0 xs.
  * Input of a key k: x(k) = float(bits(float(k))) * 2^-31; xn = (x - x0) * xs;
  * bucket(k) = min(255, floor(256 * y)).  All pointers are device pointers. */
 
-/* Sample sample_fraction of the u64 keys in random 64-byte chunks, sort the sample,
- * compute mid-rank CDF targets and train (train_steps Adam steps, 0 meaning the
- * default; vqs_mlp_init gives the untrained model).  Writes the parameter block to
- * params (1155 floats). */
+/* Sample sample_fraction of the u64 keys in random 64-byte chunks (the unit of
+ * Sec. 2.2's pivot sampling), sort the sample, compute mid-rank CDF targets and train
+ * (train_steps Adam steps, 0 meaning the default; vqs_mlp_init gives the untrained
+ * model).  Writes the parameter block to params (1155 floats). */
 int vqs_learned_fit(const void* keys, uint64_t n, const vqs_options* options, float* params, void* stream);
 
 /* y = model(x) for m inputs. */
@@ -265,14 +338,16 @@ typedef struct vqs_kernel_time {
 
 /* Event recording around the launches of later calls: 0 none, 1 every launch,
  * 2 only the device-wide partition launches (kind 2; the others run unrecorded, so
- * a timing of the whole call is barely disturbed).  Other values: VQS_EINVAL. */
+ * a timing of the whole call is barely disturbed).  Other values: VQS_EINVAL.
+ * Calls through vqs_sort_noalloc record nothing. */
 int vqs_profile(int enable);
 
 /* Copy up to max records of the calls on `stream` since the last read to out and
  * clear them; *count receives the number copied.  Waits for the stream. */
 int vqs_profile_read(void* stream, vqs_kernel_time* out, int max, int* count);
 
-/* Free every workspace held by the library (waits for pending work). */
+/* Free every workspace held by the library (waits for pending work).  The fixed
+ * scratch of vqs_sort_noalloc is not freed. */
 int vqs_release(void);
 
 /* Human-readable text of a return code. */

@@ -24,8 +24,11 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "vqs_oracle.c")
+_CTX_SRC = os.path.join(_HERE, "context_sort.cpp")
+_CTX_PATH = os.path.join(_HERE, "libcontext_sort.so")
 _lock = threading.Lock()
 _lib = None
+_ctx = None
 
 U16, U32, U64, U128, F32, F64 = 1, 2, 3, 4, 5, 6
 _DTYPES = {U16: np.uint16, U32: np.uint32, U64: np.uint64, U128: np.uint64,
@@ -55,6 +58,10 @@ def build(force: bool = False) -> str:
                                    "-fno-fast-math", "-Wall", "-Wno-unused-function",
                                    "-o", tmp, _SRC, os.path.join(_HERE, "mlp_oracle.c"), "-lm"])
             os.replace(tmp, _LIB_PATH)
+        if force or not os.path.exists(_CTX_PATH) or os.path.getmtime(_CTX_PATH) < os.path.getmtime(_CTX_SRC):
+            tmp = _CTX_PATH + ".tmp%d" % os.getpid()
+            subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-o", tmp, _CTX_SRC])
+            os.replace(tmp, _CTX_PATH)
     return _LIB_PATH
 
 
@@ -250,3 +257,63 @@ def merge_network(length: int):
 
 def med3_u64(a: int, b: int, c: int, ascending: bool = True) -> int:
     return int(lib().vqo_med3_u64(a, b, c, int(bool(ascending))))
+
+
+def parallel_sort(keys: np.ndarray, kt: int, threads: int, ascending: bool = True, seed: int = 0,
+                  nb: int = NB_DEFAULT) -> None:
+    """Sort keys in place with the oracle on `threads` host threads (timing only).
+
+    The top levels of Alg. 1's recursion run as tasks: every range longer than
+    n / (2 * threads) keys is split by ChoosePivot and Partition, the ranges of a
+    level concurrently (a degenerate split leaves its range whole).  The remaining
+    ranges are then sorted by the oracle's sort, handed to the threads longest first.
+    The output is the sorted keys.  Below the top levels the recursion restarts per
+    range (its pivots drawn for it as an array of its own, its depth limit from its
+    length), so the recursion counters are not those of the one-threaded oracle."""
+    import concurrent.futures as cf
+    _check_keys(keys, kt)
+    n = nkeys(keys, kt)
+    ks = KEY_SIZE[kt]
+    L = lib()
+    asc = int(bool(ascending))
+    big = max(n // (2 * max(threads, 1)), 64 // ks + 1, nb + 1)
+
+    def split(r):
+        b, e = r
+        p = choose_pivot(keys, b, e, kt, ascending, seed)
+        bound = partition(keys, b, e, p, kt, ascending)
+        if bound in (b, e):
+            return [(b, e, True)]
+        return [(b, bound, False), (bound, e, False)]
+
+    def leaf(r):
+        b, e = r
+        st = Stats()
+        L.vqo_sort(_ptr(keys) + b * ks, e - b, kt, asc, seed, nb, -1, ctypes.byref(st))
+
+    with cf.ThreadPoolExecutor(max_workers=max(threads, 1)) as ex:
+        todo, leaves = [(0, n)], []
+        while todo:
+            nxt = []
+            for parts in ex.map(split, todo):
+                for b, e, whole in parts:
+                    if whole or e - b <= big:
+                        leaves.append((b, e))
+                    else:
+                        nxt.append((b, e))
+            todo = nxt
+        leaves.sort(key=lambda r: r[0] - r[1])
+        list(ex.map(leaf, leaves))
+
+
+def context_std_sort(keys: np.ndarray, kt: int, ascending: bool = True) -> None:
+    """std::sort of the same keys (context timing next to the oracle; not a reference)."""
+    global _ctx
+    _check_keys(keys, kt)
+    if _ctx is None:
+        build()
+        c = ctypes.CDLL(_CTX_PATH)
+        c.ctx_std_sort.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_int]
+        _ctx = c
+    if _ctx.ctx_std_sort(_ptr(keys), nkeys(keys, kt), kt, int(bool(ascending))) != 0:
+        raise ValueError("unknown key type")

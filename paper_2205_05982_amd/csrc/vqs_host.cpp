@@ -37,19 +37,20 @@ struct Geometry {
 };
 
 struct GraphKey {
+  const void* ws_base;   // workspace the graph's launches use
   void* keys;
   const int64_t* offsets;
   uint64_t nseg, n;
   int kt, asc;
   uint64_t seed;
-  int64_t depth_limit;
+  int64_t depth_limit, fb_limit;
   uint32_t nb, local;
   uint64_t solo;
   int run_mode;
   bool operator<(const GraphKey& o) const {
-    return std::tie(keys, offsets, nseg, n, kt, asc, seed, depth_limit, nb, local, solo, run_mode) <
-           std::tie(o.keys, o.offsets, o.nseg, o.n, o.kt, o.asc, o.seed, o.depth_limit, o.nb, o.local, o.solo,
-                    o.run_mode);
+    return std::tie(ws_base, keys, offsets, nseg, n, kt, asc, seed, depth_limit, fb_limit, nb, local, solo,
+                    run_mode) < std::tie(o.ws_base, o.keys, o.offsets, o.nseg, o.n, o.kt, o.asc, o.seed,
+                                         o.depth_limit, o.fb_limit, o.nb, o.local, o.solo, o.run_mode);
   }
 };
 
@@ -59,7 +60,6 @@ struct ProfRec {
 };
 
 int g_profile = 0;   // vqs_profile: 0 off, 1 every launch, 2 level partitions only
-unsigned long long* g_dbg = nullptr;  // per-phase cycle totals (instrumented builds)
 
 struct Workspace {
   int device = 0;
@@ -71,6 +71,10 @@ struct Workspace {
   int cap_levels = 0;
   Params p{};  // carved pointers
   unsigned long long* host_pinned = nullptr;
+  unsigned long long host_word[8] = {};   // pageable stand-in when host_pinned is absent
+  unsigned long long* ctr_word() { return host_pinned ? host_pinned : host_word; }
+  int p_levels = 0;          // level counters p.lvl_ctr holds
+  bool p_external = false;   // p points into a caller's workspace, not into mem
   int last_levels = 0;
   bool have_result = false;
   // learned splitter buffers
@@ -96,7 +100,7 @@ struct Workspace {
   std::vector<ProfRec> prof;
   size_t events_used = 0;
   bool capturing = false;
-  bool owned = true;       // false: mem and host_pinned belong to someone else (nothing freed)
+  bool owned = true;       // false: mem belongs to someone else (nothing freed)
   bool no_profile = false; // never record profiling events (the allocation-free path)
   uint64_t seq = 0;        // order of the calls that left a result (newest is largest)
   hipEvent_t next_event() {
@@ -188,6 +192,11 @@ uint32_t depth_limit_for(uint64_t n) {
   return 2 * lg + 4;
 }
 
+// True when the caller's options structure holds the field ending at byte `end`
+// (struct_size 0 is taken as the full structure).
+bool has_field(const vqs_options* o, size_t end) { return o && (o->struct_size == 0 || o->struct_size >= end); }
+#define VQS_HAS(o, f) has_field((o), offsetof(vqs_options, f) + sizeof(((vqs_options*)0)->f))
+
 struct Plan {
   int bits, ks, mode;
   uint64_t n, nseg;
@@ -197,6 +206,7 @@ struct Plan {
   uint64_t cap_lvl, cap_tiles, cap_solo;
   uint64_t seed;
   int64_t depth_limit;  // < 0: default per range, else this limit for every range
+  int64_t fb_limit;     // < 0: default per range, else the fallback mode's own limit
   int run_mode;         // level partitions write tile-local runs
 };
 
@@ -236,8 +246,7 @@ int make_plan(uint64_t n, uint64_t nseg, int kt, int asc, const vqs_options* o, 
     pl->solo = std::max<uint64_t>(s, pl->local);
   }
   // (level_mode is read only from a struct that holds it)
-  const bool has_lm = o && (o->struct_size == 0 || o->struct_size >= offsetof(vqs_options, level_mode) + 4);
-  const uint32_t lm = has_lm ? o->level_mode : (uint32_t)VQS_LEVEL_AUTO;
+  const uint32_t lm = VQS_HAS(o, level_mode) ? o->level_mode : (uint32_t)VQS_LEVEL_AUTO;
   if (lm > VQS_LEVEL_RUNS) return VQS_EINVAL;
   // auto: runs for one array of 8- or 16-byte keys, whose top levels are a few long
   // ranges (long look-back chains); the look-back for narrower keys and for many
@@ -250,12 +259,19 @@ int make_plan(uint64_t n, uint64_t nseg, int kt, int asc, const vqs_options* o, 
     if (pl->depth_limit > 200) return VQS_EINVAL;
     lim = (uint32_t)pl->depth_limit;
   }
+  pl->fb_limit = -1;
+  uint32_t fb_lim = depth_limit_for(std::max<uint64_t>(n, 2));
+  if (VQS_HAS(o, fallback_limit) && o->fallback_limit != 0) {
+    pl->fb_limit = o->fallback_limit == VQS_FALLBACK_LIMIT_ZERO ? 0 : (int64_t)o->fallback_limit;
+    if (pl->fb_limit > 200) return VQS_EINVAL;
+    fb_lim = std::max<uint32_t>(fb_lim, (uint32_t)pl->fb_limit);
+  }
   // A range reaches the paper's depth limit by level lim (one more when the ranges are
-  // seeded at level 1); past it, fallback mode may take depth_limit_for(n) more levels.
+  // seeded at level 1); past it, fallback mode may take fb_lim more levels.
   // Levels 0 .. max_levels - 2 are launched.
   // (one more: in run mode a range leaving for the solo list is gathered by a copy
   // entry of the next level)
-  pl->max_levels = (int)lim + (int)depth_limit_for(std::max<uint64_t>(n, 2)) + 5;
+  pl->max_levels = (int)lim + (int)fb_lim + 5;
   const uint64_t T = level_tile_keys(bits);
   // a level holds at most n / (solo + 1) ranges longer than solo, and up to twice as
   // many copy entries
@@ -341,8 +357,15 @@ void set_caps(Workspace* ws, const Caps& c) {
 int ensure_workspace(Workspace* ws, const Plan& pl) {
   const Caps need = caps_of(pl);
   if (ws->mem && need.scratch_bytes <= ws->cap_scratch_bytes && need.lvl <= ws->cap_lvl &&
-      need.tiles <= ws->cap_tiles && need.solo <= ws->cap_solo && need.levels <= ws->cap_levels)
+      need.tiles <= ws->cap_tiles && need.solo <= ws->cap_solo && need.levels <= ws->cap_levels) {
+    if (ws->p_external) {   // the last call used a caller's workspace
+      const Caps c{ws->cap_scratch_bytes, ws->cap_lvl, ws->cap_tiles, ws->cap_solo, ws->cap_levels};
+      carve(ws->mem, c, &ws->p);
+      ws->p_levels = c.levels;
+      ws->p_external = false;
+    }
     return VQS_OK;
+  }
   if (ws->mem) {
     (void)hipStreamSynchronize(ws->stream);
     if (ws->graph) {
@@ -366,6 +389,8 @@ int ensure_workspace(Workspace* ws, const Plan& pl) {
   ws->bytes = bytes;
   set_caps(ws, c);
   carve(ws->mem, c, &ws->p);
+  ws->p_levels = c.levels;
+  ws->p_external = false;
   if (!ws->host_pinned && hipHostMalloc((void**)&ws->host_pinned, 4096, hipHostMallocDefault) != hipSuccess) {
     ws->host_pinned = nullptr;
     return VQS_ENOMEM;
@@ -437,11 +462,11 @@ hipError_t launch_all(Workspace* ws, const Params& base, const Plan& pl, const G
           if (e != hipSuccess) return e;
         }
         // the last launched level had no work: nothing is left to plan
-        e = hipMemcpyAsync(ws->host_pinned, &base.lvl_ctr[L - 1].packed, 8, hipMemcpyDeviceToHost, s);
+        e = hipMemcpyAsync(ws->ctr_word(), &base.lvl_ctr[L - 1].packed, 8, hipMemcpyDeviceToHost, s);
         if (e != hipSuccess) return e;
         e = hipStreamSynchronize(s);
         if (e != hipSuccess) return e;
-        if (ws->host_pinned[0] == 0) break;
+        if (ws->ctr_word()[0] == 0) break;
         if (L >= pl.max_levels - 1) {
           e = step(L, false);
           if (e != hipSuccess) return e;
@@ -473,11 +498,11 @@ hipError_t launch_all(Workspace* ws, const Params& base, const Plan& pl, const G
           if (e != hipSuccess) return e;
         }
         if (L >= pl.max_levels - 1) break;
-        e = hipMemcpyAsync(ws->host_pinned, &base.lvl_ctr[L].packed, 8, hipMemcpyDeviceToHost, s);
+        e = hipMemcpyAsync(ws->ctr_word(), &base.lvl_ctr[L].packed, 8, hipMemcpyDeviceToHost, s);
         if (e != hipSuccess) return e;
         e = hipStreamSynchronize(s);
         if (e != hipSuccess) return e;
-        if (ws->host_pinned[0] == 0) break;
+        if (ws->ctr_word()[0] == 0) break;
         batch = LEVEL_BATCH_NEXT;
       }
     }
@@ -535,8 +560,8 @@ void init_params(Params* base, const Params& carved, void* keys, uint64_t n, con
   b.level = 0;
   b.seed_level = 0;
   b.fixed_limit = pl.depth_limit;
+  b.fb_limit = pl.fb_limit;
   b.run_mode = pl.run_mode;
-  b.dbg = nullptr;
 }
 
 // Prepare base parameters for keys on ws (caller holds g_mu).
@@ -545,15 +570,18 @@ int prepare(Workspace* ws, void* keys, uint64_t n, uint64_t nseg, int kt, int as
   const Geometry g = geometry(ws->device);
   int rc = make_plan(n, nseg, kt, asc, o, g, pl);
   if (rc != VQS_OK) return rc;
-  rc = ensure_workspace(ws, *pl);
-  if (rc != VQS_OK) return rc;
+  if (VQS_HAS(o, workspace_bytes) && o->workspace) {
+    // the caller's workspace: carved for this call, nothing allocated
+    const Caps c = caps_of(*pl);
+    if (carve(nullptr, c, nullptr) > o->workspace_bytes) return VQS_ESIZE;
+    carve((char*)o->workspace, c, &ws->p);
+    ws->p_levels = c.levels;
+    ws->p_external = true;
+  } else {
+    rc = ensure_workspace(ws, *pl);
+    if (rc != VQS_OK) return rc;
+  }
   init_params(base, ws->p, keys, n, *pl);
-#ifdef VQS_PHASE_TIMING
-  static unsigned long long* dbg = nullptr;
-  if (!dbg && hipMalloc(&dbg, 256) == hipSuccess) (void)hipMemset(dbg, 0, 256);
-  base->dbg = dbg;
-  g_dbg = dbg;
-#endif
   return VQS_OK;
 }
 
@@ -571,7 +599,8 @@ int sort_locked(Workspace* ws, void* keys, const int64_t* offsets, uint64_t nseg
   hipError_t e;
   const bool use_graph = o && o->use_graph && offsets;
   if (use_graph) {
-    GraphKey gk{keys, offsets, nseg, n, kt, asc, pl.seed, pl.depth_limit, pl.nb, pl.local, pl.solo, pl.run_mode};
+    GraphKey gk{base.stats, keys, offsets, nseg, n, kt, asc, pl.seed, pl.depth_limit, pl.fb_limit, pl.nb, pl.local,
+                pl.solo, pl.run_mode};
     if (!(ws->graph_valid && !(gk < ws->graph_key) && !(ws->graph_key < gk))) {
       if (ws->graph) {
         (void)hipGraphExecDestroy(ws->graph);
@@ -621,6 +650,7 @@ int sort_impl(void* keys, const int64_t* offsets, uint64_t nseg, uint64_t n, int
   if (o && o->method > VQS_METHOD_LEARNED) return VQS_EINVAL;
   const bool learned = o && o->method == VQS_METHOD_LEARNED;
   if (learned && (kt != VQS_U64 || offsets || !asc)) return VQS_EINVAL;
+  if (VQS_HAS(o, workspace_bytes) && o->workspace && (learned || (uintptr_t)o->workspace % 256)) return VQS_EINVAL;
   if (n == 0) return VQS_OK;
   if (!keys) return VQS_EINVAL;
   const int ks = bits / 8;
@@ -776,14 +806,13 @@ int learned_locked(Workspace* ws, void* keys, uint64_t n, const vqs_options* o, 
 constexpr int NOALLOC_MAX_DEVICES = 64;
 
 // Per-device state of vqs_sort_noalloc.  Nothing here owns memory: ws carves its
-// buffers from the device's copy of `scratch` and reads the level counter into a
+// buffers from the device's copy of `scratch` and reads the level counter into its
 // pageable host word.
 struct NoAlloc {
   bool ready = false;
   char* ptr = nullptr;                   // this device's copy of `scratch`
   Geometry geom{};
-  unsigned long long host_ctr[8] = {};   // host word of the level counter reads
-  Workspace ws;
+  Workspace ws;   // no pinned host word: level counters are read into ws.host_word
 };
 
 NoAlloc g_noalloc[NOALLOC_MAX_DEVICES];
@@ -827,7 +856,6 @@ int noalloc_setup(int dev) {
   na.ws.no_profile = true;
   na.ws.device = dev;
   na.ws.mem = na.ptr;
-  na.ws.host_pinned = na.host_ctr;
   na.ready = true;
   return VQS_OK;
 }
@@ -838,6 +866,7 @@ int noalloc_sort(void* keys, uint64_t n, int kt, int asc, const vqs_options* o, 
   if (!bits) return VQS_ETYPE;
   if (asc != 0 && asc != 1) return VQS_EINVAL;
   if (o && (o->method != VQS_METHOD_PLAIN || o->use_graph)) return VQS_EINVAL;
+  if (VQS_HAS(o, workspace_bytes) && o->workspace) return VQS_EINVAL;
   if (n == 0) return VQS_OK;
   if (!keys) return VQS_EINVAL;
   if ((uintptr_t)keys % (uintptr_t)std::min(bits / 8, 16)) return VQS_EINVAL;
@@ -859,6 +888,7 @@ int noalloc_sort(void* keys, uint64_t n, int kt, int asc, const vqs_options* o, 
   ws->bytes = (size_t)VQS_NOALLOC_SCRATCH_BYTES;
   set_caps(ws, c);
   carve(ws->mem, c, &ws->p);
+  ws->p_levels = c.levels;
   Params base;
   init_params(&base, ws->p, keys, n, pl);
   int levels = 0;
@@ -897,11 +927,18 @@ int vqs_sort_segmented_ex(void* keys, const int64_t* offsets, uint64_t nseg, int
   if (nseg == 0) return VQS_OK;
   if (!offsets) return VQS_EINVAL;
   hipStream_t s = (hipStream_t)stream;
-  // total key count = offsets[nseg] (and the scratch size): read it once
+  if (options && options->struct_size != 0 && options->struct_size < offsetof(vqs_options, train_steps))
+    return VQS_EINVAL;
+  // total key count = offsets[nseg] (and the scratch size): given by the caller, or
+  // read once
+  const uint64_t given = VQS_HAS(options, total_keys) ? options->total_keys : 0;
   uint64_t total = 0;
   if (options && options->validate) {
     int rc = check_offsets_host(offsets, nseg, &total, s);
     if (rc != VQS_OK) return rc;
+    if (given && given != total) return VQS_EOFFSETS;
+  } else if (given) {
+    total = given;
   } else {
     int64_t last = 0;
     if (hipMemcpyAsync(&last, offsets + nseg, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -954,6 +991,7 @@ int vqs_autotune_segmented(const void* keys, const int64_t* offsets, uint64_t ns
   const uint64_t solos[] = {0, 1ull << 14, 1ull << 16, 1ull << 18, 1ull << 20};   // 0: the size rule
   const uint32_t locals[] = {full, full / 2};
   const uint32_t bases[] = {256, 128};
+  const uint32_t modes[] = {VQS_LEVEL_LOOKBACK, VQS_LEVEL_RUNS};
   float best = -1.0f;
   vqs_options base{};
   std::memcpy(&base, options, sizeof(vqs_options));
@@ -963,38 +1001,40 @@ int vqs_autotune_segmented(const void* keys, const int64_t* offsets, uint64_t ns
   vqs_options chosen = base;
   for (uint64_t sm : solos)
     for (uint32_t lk : locals)
-      for (uint32_t nb : bases) {
-        if (rc != VQS_OK) break;
-        vqs_options c = base;
-        c.solo_max = sm;
-        c.local_keys = lk;
-        c.base_case = nb;
-        float t_min = -1.0f;
-        for (int rep = 0; rep < 3 && rc == VQS_OK; rep++) {   // the first run warms up
-          if (hipMemcpyAsync(tk, src, sub * ks, hipMemcpyDeviceToDevice, s) != hipSuccess ||
-              hipEventRecord(e0, s) != hipSuccess) {
-            rc = VQS_EHIP;
-            break;
+      for (uint32_t nb : bases)
+        for (uint32_t lm : modes) {
+          if (rc != VQS_OK) break;
+          vqs_options c = base;
+          c.solo_max = sm;
+          c.local_keys = lk;
+          c.base_case = nb;
+          c.level_mode = lm;
+          float t_min = -1.0f;
+          for (int rep = 0; rep < 3 && rc == VQS_OK; rep++) {   // the first run warms up
+            if (hipMemcpyAsync(tk, src, sub * ks, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+                hipEventRecord(e0, s) != hipSuccess) {
+              rc = VQS_EHIP;
+              break;
+            }
+            const int r = sort_impl(tk, to, k, sub, key_type, ascending, &c, s);
+            if (r == VQS_EINVAL) break;          // a combination the library rejects
+            if (r != VQS_OK) {
+              rc = r;
+              break;
+            }
+            float ms = 0.0f;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+              rc = VQS_EHIP;
+              break;
+            }
+            if (rep > 0 && (t_min < 0.0f || ms < t_min)) t_min = ms;
           }
-          const int r = sort_impl(tk, to, k, sub, key_type, ascending, &c, s);
-          if (r == VQS_EINVAL) break;          // a combination the library rejects
-          if (r != VQS_OK) {
-            rc = r;
-            break;
+          if (rc == VQS_OK && t_min >= 0.0f && (best < 0.0f || t_min < best)) {
+            best = t_min;
+            chosen = c;
           }
-          float ms = 0.0f;
-          if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-              hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-            rc = VQS_EHIP;
-            break;
-          }
-          if (rep > 0 && (t_min < 0.0f || ms < t_min)) t_min = ms;
         }
-        if (rc == VQS_OK && t_min >= 0.0f && (best < 0.0f || t_min < best)) {
-          best = t_min;
-          chosen = c;
-        }
-      }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   (void)hipStreamSynchronize(s);
@@ -1004,6 +1044,7 @@ int vqs_autotune_segmented(const void* keys, const int64_t* offsets, uint64_t ns
   options->solo_max = chosen.solo_max;
   options->local_keys = chosen.local_keys;
   options->base_case = chosen.base_case;
+  options->level_mode = chosen.level_mode;
   if (best_ms) *best_ms = best;
   return VQS_OK;
 }
@@ -1046,8 +1087,12 @@ int vqs_get_stats(void* stream, vqs_stats* out) {
   out->level_tiles = d.level_tiles;
   out->solo_items = d.solo_items;
   out->lds_partitions = d.lds_partitions;
+  out->hbm_read_keys = d.hbm_read_keys;
+  out->hbm_write_keys = d.hbm_write_keys;
+  out->bounded_lds = d.bounded_lds;
+  out->bounded_global = d.bounded_global;
   // levels that had work
-  const int nl = std::min(ws->last_levels + 1, ws->cap_levels);
+  const int nl = std::min(ws->last_levels + 1, ws->p_levels);
   LevelCtr* h = (LevelCtr*)malloc(sizeof(LevelCtr) * (size_t)std::max(nl, 1));
   if (h && nl > 0 && hipMemcpy(h, ws->p.lvl_ctr, sizeof(LevelCtr) * nl, hipMemcpyDeviceToHost) == hipSuccess) {
     for (int i = 0; i < nl; i++)
@@ -1124,7 +1169,7 @@ int vqs_last_error_bits(void* stream, uint32_t* out) {
   std::lock_guard<std::mutex> lock(g_mu);
   *out = 0;
   Workspace* ws = latest_ws((hipStream_t)stream);
-  if (!ws || !ws->mem) return VQS_OK;
+  if (!ws || !ws->p.err) return VQS_OK;
   unsigned int e = 0;
   if (hipMemcpyAsync(&e, ws->p.err, 4, hipMemcpyDeviceToHost, ws->stream) != hipSuccess ||
       hipStreamSynchronize(ws->stream) != hipSuccess)
@@ -1145,10 +1190,10 @@ int vqs_profile_read(void* stream, vqs_kernel_time* out, int max, int* count) {
   std::lock_guard<std::mutex> lock(g_mu);
   *count = 0;
   auto it = g_ws.find(std::make_pair(current_device(), (hipStream_t)stream));
-  if (it == g_ws.end() || !it->second->mem) return VQS_OK;
+  if (it == g_ws.end() || !it->second->p.lvl_ctr) return VQS_OK;
   Workspace* ws = it->second.get();
   if (hipStreamSynchronize(ws->stream) != hipSuccess) return VQS_EHIP;
-  std::vector<LevelCtr> ctr((size_t)ws->cap_levels);
+  std::vector<LevelCtr> ctr((size_t)ws->p_levels);
   if (hipMemcpy(ctr.data(), ws->p.lvl_ctr, sizeof(LevelCtr) * ctr.size(), hipMemcpyDeviceToHost) != hipSuccess)
     return VQS_EHIP;
   int n = 0;
@@ -1191,15 +1236,5 @@ const char* vqs_strerror(int code) {
 
 int vqs_version(void) { return VERSION; }
 
-#ifdef VQS_PHASE_TIMING
-// Instrumented builds only: per-phase cycle totals of the level kernel, then reset.
-int vqs_debug_phase_read(uint64_t out[32]) {
-  if (!g_dbg) return VQS_EINVAL;
-  if (hipDeviceSynchronize() != hipSuccess || hipMemcpy(out, g_dbg, 256, hipMemcpyDeviceToHost) != hipSuccess)
-    return VQS_EHIP;
-  (void)hipMemset(g_dbg, 0, 256);
-  return VQS_OK;
-}
-#endif
 
 }  // extern "C"

@@ -37,32 +37,6 @@ namespace vqs {
 
 __device__ inline void set_err(const Params& p, uint32_t e) { atomicOr(p.err, e); }
 
-// Optional per-phase cycle accounting of the level kernel (thread 0 of each
-// workgroup), enabled only in instrumented builds with a debug buffer in Params.
-#ifdef VQS_PHASE_TIMING
-#define VQS_PHASE_INIT()            \
-  unsigned long long ph_t = wall_clock64(); \
-  unsigned long long ph_acc[8] = {0, 0, 0, 0, 0, 0, 0, 0}; \
-  int ph_cur = 7;
-#define VQS_PHASE(n)                                     \
-  {                                                      \
-    const unsigned long long ph_now = wall_clock64();    \
-    ph_acc[ph_cur] += ph_now - ph_t;                     \
-    ph_t = ph_now;                                       \
-    ph_cur = (n);                                        \
-  }
-#define VQS_PHASE_FLUSH_AT(base)                                                  \
-  if (threadIdx.x == 0 && p.dbg) {                                                \
-    for (int ph_i = 0; ph_i < 8; ph_i++) atomicAdd(&p.dbg[(base) + ph_i], ph_acc[ph_i]); \
-  }
-#define VQS_PHASE_FLUSH() VQS_PHASE_FLUSH_AT(0)
-#else
-#define VQS_PHASE_FLUSH_AT(base)
-#define VQS_PHASE_INIT()
-#define VQS_PHASE(n)
-#define VQS_PHASE_FLUSH()
-#endif
-
 template <class K>
 __device__ inline void to_words(typename K::R r, uint64_t& lo, uint64_t& hi) {
   K::to_u64x2(r, lo, hi);
@@ -83,6 +57,11 @@ __device__ inline uint64_t tiles_of(uint64_t b, uint64_t e, int off, uint64_t T)
 __device__ inline uint32_t depth_limit_of(uint64_t n) {
   uint32_t lg = 63 - __clzll(n | 1);
   return 2 * lg + 4;
+}
+
+// depth limit of the fallback mode itself for a range of len keys
+__device__ inline uint32_t fb_limit_of(const Params& p, uint64_t len) {
+  return p.fb_limit >= 0 ? (uint32_t)p.fb_limit : depth_limit_of(len);
 }
 
 // ---- tile partition (workgroup) -------------------------------------------------------
@@ -405,9 +384,11 @@ __device__ inline Routed route_decide(const Params& p, Seg s) {
       r.fb_enter = true;
       r.s.flags = (s.flags & (SEG_SCRATCH | RUNBITS)) | SEG_FALLBACK;
       r.s.depth = 1;
-      r.s.limit = depth_limit_of(len);
-    } else {
-      r.s.flags = (s.flags & (SEG_SCRATCH | RUNBITS)) | SEG_FALLBACK | SEG_BOUNDED;
+      r.s.limit = fb_limit_of(p, len);
+    }
+    if (r.s.depth > r.s.limit) {   // past the fallback mode's own limit
+      // (an input range can get here untransformed, with a fallback-mode limit of 0)
+      r.s.flags = (s.flags & (SEG_SCRATCH | SEG_RAW | RUNBITS)) | SEG_FALLBACK | SEG_BOUNDED;
       r.dest = RT_SOLO;
     }
   }
@@ -518,15 +499,10 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
   constexpr unsigned long long ST_AGG = 1ull << 46, ST_INC = 2ull << 46;
   constexpr unsigned long long VAL_MASK = (1ull << 46) - 1;
   const int tid = threadIdx.x;
-  unsigned long long tiles_done = 0;
-  VQS_PHASE_INIT();
-#ifdef VQS_PHASE_TIMING
-  unsigned long long lb_n = 0, lb_it = 0, lb_sp = 0, lb_sp0 = 0, lb_lat = 0;
-#endif
+  unsigned long long tiles_done = 0, keys_done = 0;
 
   unsigned long long rmin_tile = ~0ull;   // thread 0: tile whose right minimum is pending
   for (;;) {
-    VQS_PHASE(5);
     if (tid == 0 && rmin_tile != ~0ull) {
       store_tile_rmin<K>(p, rmin_tile, sh_wrm);
       rmin_tile = ~0ull;
@@ -537,7 +513,6 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
     if (g >= ntiles) break;
     // segment of tile g: last s with tbase[s] <= g; one wave narrows the interval
     // 64-fold per step
-    VQS_PHASE(0);
     if (tid < WAVE) {
       uint32_t lo = 0, hi = nseg;  // invariant: tbase[lo] <= g, and g < tbase[hi] if hi < nseg
       while (hi - lo > 1) {
@@ -566,8 +541,6 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
     const uint64_t k = (sg.b + p.off) / T + (g - g0);
     const uint64_t vs = (k * T > sg.b + p.off) ? k * T : sg.b + p.off;
     const uint64_t ve = ((k + 1) * T < sg.e + p.off) ? (k + 1) * T : sg.e + p.off;
-
-    VQS_PHASE(1);
     R key[I][K::V];
     TL::load(src_aligned, k, vs, ve, tmode, key);
     if (sg.flags & SEG_PIVOT) {
@@ -607,7 +580,6 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
 
     // decoupled look-back on the left counts of the range's earlier tiles, one wave
     // reading 64 predecessors per step
-    VQS_PHASE(2);
     if (tid < WAVE) {
       const int lane = tid;
       // Only device-coherent single-word accesses are used here (relaxed agent-scope
@@ -617,36 +589,18 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
       if (g != g0) {
         unsigned long long top = g - 1;   // highest predecessor not yet summed
         uint32_t spins = 0;
-#ifdef VQS_PHASE_TIMING
-        bool lb_first = true;
-        lb_n++;
-#endif
         for (;;) {
-#ifdef VQS_PHASE_TIMING
-          const unsigned long long lb_t0 = wall_clock64();
-          lb_it++;
-#endif
           const bool inr = top >= g0 + (unsigned long long)lane;   // lane reads tile top - lane
           unsigned long long f = 0;
           if (inr) f = __hip_atomic_load(&p.flags[top - lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           const bool ready = inr && (f & ~((1ull << 48) - 1)) == epoch && (f & (3ull << 46)) != 0;
           const bool inc = ready && (f & ST_INC);
           const uint64_t incm = ballot(inc), readym = ballot(ready), inrm = ballot(inr);
-#ifdef VQS_PHASE_TIMING
-          if (lb_first) {
-            lb_lat += wall_clock64() - lb_t0;
-            lb_first = false;
-          }
-#endif
           // lanes up to the nearest inclusive tile must all be ready
           const int first_inc = incm ? __builtin_ctzll(incm) : WAVE;
           const uint64_t need = (first_inc >= WAVE - 1) ? inrm : (((2ull << first_inc) - 1) & inrm);
           if ((need & ~readym) != 0) {
             ++spins;
-#ifdef VQS_PHASE_TIMING
-            lb_sp++;
-            if (!(readym & 1ull)) lb_sp0++;   // the nearest predecessor has no count yet
-#endif
             if ((spins & 255u) == 0 &&
                 (spins > (1u << 20) || __hip_atomic_load(p.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
               if (lane == 0) set_err(p, ERR_SPIN);
@@ -675,7 +629,6 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
     const uint64_t before = vs - (sg.b + p.off);             // keys of the range before this tile
     const uint64_t excl_r = before - excl_l;
     const uint32_t nr = nvalid - nl;
-    VQS_PHASE(3);
     TL::write_out_rmin(stage, dst, nl, nvalid, sg.b + excl_l, sg.e - excl_r - nr, 0, p.n_total, p.off, sh_wrm);
     rmin_tile = g;
 
@@ -783,20 +736,14 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
       }
     }
     tiles_done++;
-    VQS_PHASE(4);
+    keys_done += nvalid;
     __syncthreads();
   }
-  if (tid == 0 && tiles_done) atomicAdd(&p.stats->level_tiles, tiles_done);
-  VQS_PHASE_FLUSH();
-#ifdef VQS_PHASE_TIMING
-  if (tid == 0 && p.dbg) {
-    atomicAdd(&p.dbg[20], lb_n);
-    atomicAdd(&p.dbg[21], lb_it);
-    atomicAdd(&p.dbg[22], lb_sp);
-    atomicAdd(&p.dbg[23], lb_lat);
-    atomicAdd(&p.dbg[28], lb_sp0);
+  if (tid == 0 && tiles_done) {
+    atomicAdd(&p.stats->level_tiles, tiles_done);
+    atomicAdd(&p.stats->hbm_read_keys, keys_done);
+    atomicAdd(&p.stats->hbm_write_keys, keys_done);
   }
-#endif
 }
 
 // ---- run mode: ranges held as runs of the previous level's tiles --------------------
@@ -894,8 +841,7 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
   const int tmode = (L == 0) ? p.mode : 0;   // only the first level reads untransformed keys
   const TileRun* prev = p.runs[(L + 1) & 1];
   const int tid = threadIdx.x;
-  unsigned long long tiles_done = 0;
-  VQS_PHASE_INIT();
+  unsigned long long tiles_done = 0, keys_done = 0;
 
   // tiles are independent: the next tile's ticket is drawn when a tile starts, and
   // handed over through alternating LDS slots at its end
@@ -903,7 +849,6 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
   __syncthreads();
   unsigned long long rmin_tile = ~0ull;   // thread 0: tile whose right minimum is pending
   for (int it = 0;; it++) {
-    VQS_PHASE(5);
     if (tid == 0 && rmin_tile != ~0ull) {
       store_tile_rmin<K>(p, rmin_tile, sh_wrm);
       rmin_tile = ~0ull;
@@ -912,7 +857,6 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
     if (g >= ntiles) break;
     unsigned int g_next = 0;
     if (tid == 0) g_next = atomicAdd(&p.lvl_ctr[L].ticket, 1u);
-    VQS_PHASE(0);
     // a planned level records each tile's range (and first run); the input ranges of
     // the first level are found by search
     const bool planned = L != p.seed_level;
@@ -950,7 +894,6 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
     const uint32_t nvalid = (uint32_t)(ve - vs);
 
     R key[I][V];
-    VQS_PHASE(1);
     if (!(sg.flags & SEG_RUNS)) {
       TL::load(src_aligned, k, vs, ve, tmode, key);
     } else {
@@ -977,7 +920,6 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
         if (cnt < LEVEL_P) break;
       }
       S raw[I][V];
-      VQS_PHASE(2);
       if (nr <= (uint32_t)RMAX) {
         // a thread's slots increase with (j, q): walk the run list forward
         int i = 0;
@@ -1029,6 +971,7 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
           }
         }
         tiles_done++;
+        keys_done += nvalid;
         if (tid == 0) sh_tk[(it + 1) & 1] = g_next;
         __syncthreads();   // the LDS run list is read before the next tile rewrites it
         continue;
@@ -1045,7 +988,6 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
         }
       }
     }
-    VQS_PHASE(3);
     // the planning launch gave every range of the level its pivot
     if (tid == 0) {
       sh.pivot = K::from_u64x2(sg.pv_lo, sg.pv_hi);
@@ -1063,16 +1005,18 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
                                              p.tilemin[g].hi = hi;
                                              p.tnl[g] = cnt;
                                            });
-    VQS_PHASE(4);
     TL::write_out_rmin(stage, dst, nl, nvalid, vs - p.off, vs - p.off + nl, 0, p.n_total, p.off, sh_wrm);
     rmin_tile = g;
     tiles_done++;
-    VQS_PHASE(6);
+    keys_done += nvalid;
     if (tid == 0) sh_tk[(it + 1) & 1] = g_next;
     __syncthreads();
   }
-  if (tid == 0 && tiles_done) atomicAdd(&p.stats->level_tiles, tiles_done);
-  VQS_PHASE_FLUSH();
+  if (tid == 0 && tiles_done) {
+    atomicAdd(&p.stats->level_tiles, tiles_done);
+    atomicAdd(&p.stats->hbm_read_keys, keys_done);
+    atomicAdd(&p.stats->hbm_write_keys, keys_done);
+  }
 }
 
 // ---- run mode: planning ------------------------------------------------------------
@@ -1993,17 +1937,6 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
   const int wave = tid / WAVE;
   const uint32_t n = (uint32_t)(e - b);
   const int tmode = raw ? p.mode : 0;
-#ifdef VQS_PHASE_TIMING
-  unsigned long long lt0 = wall_clock64(), lacc[4] = {0, 0, 0, 0}, lst[6] = {0, 0, 0, 0, 0, 0};
-#define VQS_LPH(i)                                   \
-  {                                                  \
-    const unsigned long long lt1 = wall_clock64();   \
-    lacc[i] += lt1 - lt0;                            \
-    lt0 = lt1;                                       \
-  }
-#else
-#define VQS_LPH(i)
-#endif
 
   // 1. load into bufA[0, n) (16-byte aligned chunks in v-space).  A thread's chunks
   // are all requested before any is used (a chunk past the range reads the range's
@@ -2070,7 +2003,6 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
     }
   }
   __syncthreads();
-  VQS_LPH(0);
 
   // this wave's recursion counts (wave-uniform), added to the workgroup's at the end
   uint32_t w_part = 0, w_pkeys = 0, w_maxd = 0, w_deg = 0, w_eq = 0;
@@ -2096,8 +2028,8 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
         }
         it.flags = (it.flags & LI_INB) | LI_FB;
         it.depth = 1;
-        it.limit = depth_limit_of(le - lb);
-        return true;
+        it.limit = fb_limit_of(p, le - lb);
+        if (it.depth <= it.limit) return true;
       }
       if (report && lane == 0) {
         const uint32_t f = atomicAdd(&ls.nbounded, 1u);
@@ -2220,27 +2152,10 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
         const bool strict = (it.flags & LI_STRICT) != 0;
         S* s_buf = (it.flags & LI_INB) ? bufB : bufA;
         S* d_buf = (it.flags & LI_INB) ? bufA : bufB;
-#ifdef VQS_PHASE_TIMING
-        const unsigned long long q0 = wall_clock64();
-#endif
         const R pivot = pick_pivot(it, it_i, s_buf);
-#ifdef VQS_PHASE_TIMING
-        const unsigned long long q1 = wall_clock64();
-#endif
         R mn = K::maxv();
         const uint32_t bound = scatter(s_buf, d_buf, it.lb, it.le, it.lb, it.le, pivot, strict, mn);
-#ifdef VQS_PHASE_TIMING
-        const unsigned long long q2 = wall_clock64();
-#endif
         plan(it, bound, wave_min<K>(mn), pivot);
-#ifdef VQS_PHASE_TIMING
-        if (tid == 0) {
-          lst[2] += q1 - q0;
-          lst[3] += q2 - q1;
-          lst[4] += wall_clock64() - q2;
-          lst[5]++;
-        }
-#endif
       }
     } else {
       // wave group: wave sw of item wave / G takes the sw-th part of the range; a
@@ -2305,7 +2220,6 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
       if (go && sw == 0) plan(it, it.lb + ltot, gm, pivot);
     }
     __syncthreads();
-    VQS_LPH(1);
     // the next level's ranges are known: one wave computes their ChoosePivot chunk
     // starts, one range per lane (the random-number chain is serial per range, so
     // this takes the time of one range instead of one per range)
@@ -2352,8 +2266,8 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
     }
     // 4. bounded-time sorts of this level (whole workgroup, one range at a time)
     __syncthreads();
-    VQS_LPH(2);
     const uint32_t nbd = ls.nbounded < LIST_CAP ? ls.nbounded : LIST_CAP;
+    if (tid == 0 && nbd) atomicAdd(&p.stats->bounded_lds, (unsigned long long)nbd);
     for (uint32_t f = 0; f < nbd; f++) {
       const LocalItem<K> it = ls.bounded[f];
       S* a = (it.flags & LI_INB) ? bufB : bufA;
@@ -2382,28 +2296,12 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
     if (w_eq) atomicAdd(&ls.stat_eq, w_eq);
   }
   __syncthreads();
-  VQS_LPH(1);
   // 5. write out
   for (uint32_t i = tid; i < n; i += SOLO_P) {
     S val = bufA[i];
     if (!out_internal && p.mode) val = K::store_t((R)val, p.mode);
     out[b + i] = val;
   }
-  VQS_LPH(3);
-#ifdef VQS_PHASE_TIMING
-  if (tid == 0 && p.dbg)
-    for (int i = 0; i < 4; i++) atomicAdd(&p.dbg[16 + i], lacc[i]);
-  if (tid == 0 && p.dbg) {
-    atomicAdd(&p.dbg[24], lst[0]);
-    atomicAdd(&p.dbg[25], lst[1]);
-    atomicAdd(&p.dbg[26], lst[2]);
-    atomicAdd(&p.dbg[27], lst[3]);
-    atomicAdd(&p.dbg[29], lst[4]);
-    atomicAdd(&p.dbg[30], lst[5]);
-    atomicAdd(&p.dbg[31], 1ull);
-  }
-#endif
-#undef VQS_LPH
   if (tid == 0) {
     if (ls.stat_part) {
       atomicAdd(&p.stats->partitions, (unsigned long long)ls.stat_part);
@@ -2472,12 +2370,19 @@ __device__ void wg_merge(const typename K::S* a, uint64_t na, const typename K::
 // Bounded-time sort for a range past the fallback mode's own depth limit: sort
 // LDS-sized chunks with the bitonic network, then merge runs pairwise through the two
 // global buffers; the result goes to the caller's array.  O(n log^2 n) work at most.
-// Not counted: the range was counted when it entered fallback mode.
+// Not counted in the recursion counters: the range was counted when it entered
+// fallback mode.  Thread 0 adds the keys its passes read and write to rd and wr.
 template <class K>
-__device__ void fallback_global(const Params& p, typename K::S* bufA, const Seg& it) {
+__device__ void fallback_global(const Params& p, typename K::S* bufA, const Seg& it, unsigned long long& rd,
+                                unsigned long long& wr) {
   using R = typename K::R;
   using S = typename K::S;
   const uint64_t b = it.b, e = it.e, n = e - b;
+  if (threadIdx.x == 0) {
+    atomicAdd(&p.stats->bounded_global, 1ull);
+    rd += n;   // chunks in, sorted, out
+    wr += n;
+  }
   S* X = (S*)((it.flags & SEG_SCRATCH) ? p.scratch : p.keys);
   S* Y = (S*)((it.flags & SEG_SCRATCH) ? p.keys : p.scratch);
   const int tmode = (it.flags & SEG_RAW) ? p.mode : 0;
@@ -2498,6 +2403,10 @@ __device__ void fallback_global(const Params& p, typename K::S* bufA, const Seg&
   S* from = X;
   S* to = Y;
   for (uint64_t w = C; w < n; w *= 2) {
+    if (threadIdx.x == 0) {
+      rd += n;
+      wr += n;
+    }
     for (uint64_t s = 0; s < n; s += 2 * w) {
       const uint64_t na = (s + w < n) ? w : n - s;
       const uint64_t nc = (s + 2 * w < n) ? w : (s + w < n ? n - s - w : 0);
@@ -2511,6 +2420,10 @@ __device__ void fallback_global(const Params& p, typename K::S* bufA, const Seg&
   // 3. output transform into the caller's array
   S* out = (S*)p.keys;
   if (from != out || p.mode != 0) {
+    if (threadIdx.x == 0) {
+      rd += n;
+      wr += n;
+    }
     for (uint64_t i = b + threadIdx.x; i < e; i += blockDim.x) {
       S v = from[i];
       out[i] = p.mode ? K::store_t((R)v, p.mode) : v;
@@ -2539,10 +2452,8 @@ __global__ void __launch_bounds__(SOLO_P) __attribute__((amdgpu_waves_per_eu(sol
   const int tid = threadIdx.x;
   const unsigned long long count = p.solo_ctr->count;
   const unsigned long long nitems = count < p.cap_solo ? count : p.cap_solo;
-
-  VQS_PHASE_INIT();
+  unsigned long long hrd = 0, hwr = 0;   // thread 0: keys read / written by whole-key sweeps
   for (;;) {
-    VQS_PHASE(0);
     if (tid == 0) sh_item = atomicAdd(&p.solo_ctr->ticket, 1ull);
     __syncthreads();
     const unsigned long long ii = sh_item;
@@ -2550,6 +2461,7 @@ __global__ void __launch_bounds__(SOLO_P) __attribute__((amdgpu_waves_per_eu(sol
     const Seg item = p.solo[p.solo_order[ii]];
     if (item.flags & SEG_FILL) {
       fill_range<K>(p, item.b, item.e, K::from_u64x2(item.pv_lo, item.pv_hi));
+      if (tid == 0) hwr += item.e - item.b;
       __syncthreads();
       continue;
     }
@@ -2568,23 +2480,24 @@ __global__ void __launch_bounds__(SOLO_P) __attribute__((amdgpu_waves_per_eu(sol
       S* dst = (S*)(in_scratch ? p.keys : p.scratch);
       const bool raw = (cur.flags & SEG_RAW) != 0;
       if (cur.flags & SEG_BOUNDED) {
-        fallback_global<K>(p, bufA, cur);
+        fallback_global<K>(p, bufA, cur, hrd, hwr);
         __syncthreads();
         continue;
       }
       if (n <= p.local_cap) {
-        VQS_PHASE(2);
         const uint32_t lf = ((cur.flags & SEG_OVERRIDE) ? LI_OVERRIDE : 0u) |
                             ((cur.flags & SEG_FALLBACK) ? LI_FB : 0u) | ((cur.flags & SEG_STRICT) ? LI_STRICT : 0u);
         local_sort<K>(p, ls, bufA, bufB, src, raw, cur.b, cur.e, cur.depth, cur.limit, lf,
                       K::from_u64x2(cur.pv_lo, cur.pv_hi), (S*)p.keys, false);
-        VQS_PHASE(0);
+        if (tid == 0) {
+          hrd += n;
+          hwr += n;
+        }
         continue;
       }
-      VQS_PHASE(1);
       if (cur.depth > cur.limit) {
         if (cur.flags & SEG_FALLBACK) {
-          fallback_global<K>(p, bufA, cur);
+          fallback_global<K>(p, bufA, cur, hrd, hwr);
           __syncthreads();
           continue;
         }
@@ -2595,7 +2508,12 @@ __global__ void __launch_bounds__(SOLO_P) __attribute__((amdgpu_waves_per_eu(sol
         }
         cur.flags = (cur.flags & (SEG_SCRATCH | SEG_RAW)) | SEG_FALLBACK;
         cur.depth = 1;
-        cur.limit = depth_limit_of(n);
+        cur.limit = fb_limit_of(p, n);
+        if (cur.depth > cur.limit) {   // a fallback-mode limit of 0
+          fallback_global<K>(p, bufA, cur, hrd, hwr);
+          __syncthreads();
+          continue;
+        }
       }
       const bool fb = (cur.flags & SEG_FALLBACK) != 0;
       const bool strict = (cur.flags & SEG_STRICT) != 0;
@@ -2640,6 +2558,8 @@ __global__ void __launch_bounds__(SOLO_P) __attribute__((amdgpu_waves_per_eu(sol
       const uint64_t bound = cur.b + excl_l;
       if (tid == 0) {
         sh_min = mn;
+        hrd += n;
+        hwr += n;
         if (!fb) {
           atomicAdd(&p.stats->partitions, 1ull);
           atomicAdd(&p.stats->global_solo_partitions, 1ull);
@@ -2657,7 +2577,10 @@ __global__ void __launch_bounds__(SOLO_P) __attribute__((amdgpu_waves_per_eu(sol
       // caller's array untransformed, it holds other keys there
       auto retire_equal = [&](uint64_t fb_, uint64_t fe_, bool part) {
         const bool need = part ? (!in_scratch || p.mode != 0) : (p.mode != 0 && !raw);
-        if (need && fe_ > fb_) fill_range<K>(p, fb_, fe_, pivot);
+        if (need && fe_ > fb_) {
+          fill_range<K>(p, fb_, fe_, pivot);
+          if (tid == 0) hwr += fe_ - fb_;
+        }
       };
       auto push = [&](const Seg& sgn) {
         if (sgn.e <= sgn.b) return;
@@ -2694,7 +2617,10 @@ __global__ void __launch_bounds__(SOLO_P) __attribute__((amdgpu_waves_per_eu(sol
       __syncthreads();
     }
   }
-  VQS_PHASE_FLUSH_AT(8);
+  if (tid == 0 && (hrd | hwr)) {
+    atomicAdd(&p.stats->hbm_read_keys, hrd);
+    atomicAdd(&p.stats->hbm_write_keys, hwr);
+  }
 }
 
 // The solo list's order of service, before the solo launch: ranges longer than half

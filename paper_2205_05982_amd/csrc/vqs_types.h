@@ -98,6 +98,8 @@ struct DevStats {
       fallback_keys, max_depth;
   unsigned long long level_tiles, solo_items, lds_partitions, global_solo_partitions;
   unsigned long long fallback_partitions;
+  unsigned long long hbm_read_keys, hbm_write_keys;   // keys moved by whole-key sweeps
+  unsigned long long bounded_lds, bounded_global;     // ranges sorted by the bounded-time sorts
 };
 
 enum : uint32_t {
@@ -134,7 +136,7 @@ struct Params {
   int level;
   int max_levels;
   int64_t fixed_limit;   // < 0: 2*floor(log2 len)+4 per input range; else this limit
-  unsigned long long* dbg;  // instrumented builds only (null otherwise)
+  int64_t fb_limit;      // fallback mode's own limit: < 0: 2*floor(log2 len)+4 of the range; else this
   int seed_level;        // level of the first partition (1: input ranges live in scratch)
   int run_mode;          // level partitions write tile-local runs (no look-back)
   TileRun* runs[2];      // run mode: per-tile table of the current and the previous level

@@ -43,14 +43,20 @@ class Options(ctypes.Structure):
                 ("batch", ctypes.c_uint32), ("sample_fraction", ctypes.c_float),
                 ("overflow_factor", ctypes.c_float), ("learning_rate", ctypes.c_float),
                 ("model_seed", ctypes.c_uint64), ("sample_seed", ctypes.c_uint64),
-                ("level_mode", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 2)]
+                ("level_mode", ctypes.c_uint32), ("fallback_limit", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("total_keys", ctypes.c_uint64),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64)]
+
+
+FALLBACK_LIMIT_ZERO = 0xFFFFFFFF
 
 
 class Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in (
         "partitions", "keys_partitioned", "degenerate", "all_equal", "basecases", "fallbacks",
         "fallback_keys", "max_depth", "levels", "level_tiles", "solo_items", "lds_partitions",
-        "learned_buckets", "overflow_buckets", "max_bucket")] + [("train_loss", ctypes.c_double)]
+        "learned_buckets", "overflow_buckets", "max_bucket")] + [("train_loss", ctypes.c_double)] + [
+        (n, ctypes.c_uint64) for n in ("hbm_read_keys", "hbm_write_keys", "bounded_lds", "bounded_global")]
 
     def as_dict(self):
         return {n: (float(getattr(self, n)) if n == "train_loss" else int(getattr(self, n)))
@@ -179,7 +185,7 @@ def sort_segmented(t: torch.Tensor, offsets: torch.Tensor, ascending: bool = Tru
     return t
 
 
-TUNED_FIELDS = ("solo_max", "local_keys", "base_case")
+TUNED_FIELDS = ("solo_max", "local_keys", "base_case", "level_mode")
 
 
 def autotune_segmented(t: torch.Tensor, offsets: torch.Tensor, ascending: bool = True,

@@ -1,0 +1,253 @@
+"""The C interface itself, on the GPU: the two named entry points called directly
+(vqs_sort, vqs_sort_segmented on the default stream), a caller-supplied workspace,
+a caller-supplied total key count for segmented sorts (with hipGraph replay), the
+bounded-time fallback sorts forced through the fallback mode's own depth limit, and
+the key-traffic counters.  Every sort is compared with the CPU oracle element by
+element, and its recursion counters with the oracle's."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2205_05982_amd import workloads as W
+from tests.helpers import (F32, F64, U16, U32, U64, U128, assert_stats_equal, random_keys, to_gpu,
+                           to_host)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vqs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a visible GPU")
+    from paper_2205_05982_amd import vqs as v
+    return v
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _oracle_sorted(keys, kt, asc=True, depth_limit=-1):
+    want = keys.copy()
+    st = oracle.sort(want, kt, ascending=asc, depth_limit=depth_limit, stats=True)
+    return want, st
+
+
+# ---- vqs_sort and vqs_sort_segmented, as declared ---------------------------------------
+
+@pytest.mark.parametrize("kt,asc,n", [(U64, 1, 700_001), (F32, 0, 300_000), (U128, 1, 90_000), (U16, 0, 1000)])
+def test_vqs_sort_direct_on_the_default_stream(vqs, kt, asc, n):
+    import torch
+    print(f"case: vqs_sort kt={kt} asc={asc} n={n}", flush=True)
+    assert torch.cuda.current_stream().cuda_stream == 0        # torch's default stream is the null stream
+    keys = random_keys(kt, n, 40 + kt)
+    want, ost = _oracle_sorted(keys, kt, bool(asc))
+    t = to_gpu(keys)
+    L = vqs.lib()
+    assert L.vqs_sort(_ptr(t), n, kt, asc) == 0
+    torch.cuda.synchronize()
+    assert vqs.last_error_bits() == 0
+    np.testing.assert_array_equal(to_host(t), want)
+    assert_stats_equal(ost, vqs.get_stats())
+
+
+def test_vqs_sort_segmented_direct_on_the_default_stream(vqs):
+    import torch
+    print("case: vqs_sort_segmented", flush=True)
+    off = W.segment_offsets(400, seed=31, lo=1, hi=1 << 16)
+    keys = W.segmented_keys(off, U64, 32)
+    want = keys.copy()
+    ost = oracle.sort_segmented(want, off, U64, ascending=False, stats=True)
+    t, o = to_gpu(keys), to_gpu(off)
+    assert vqs.lib().vqs_sort_segmented(_ptr(t), _ptr(o), off.size - 1, U64, 0) == 0
+    torch.cuda.synchronize()
+    assert vqs.last_error_bits() == 0
+    np.testing.assert_array_equal(to_host(t), want)
+    assert_stats_equal(ost, vqs.get_stats())
+
+
+# ---- caller workspace --------------------------------------------------------------------
+
+def test_caller_workspace(vqs):
+    """A workspace of vqs_workspace_bytes bytes sorts like the library's own; one byte
+    less is VQS_ESIZE with the keys untouched; the learned method refuses one; a
+    library-owned call on the same stream afterwards is unaffected."""
+    import torch
+    print("case: caller workspace", flush=True)
+    n = 1_200_000
+    keys = random_keys(U64, n, 51)
+    want, ost = _oracle_sorted(keys, U64)
+    need = vqs.workspace_bytes(n, U64)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    t = to_gpu(keys)
+    vqs.sort(t, key_type=U64, workspace=ws.data_ptr(), workspace_bytes=need)
+    torch.cuda.synchronize()
+    assert vqs.last_error_bits() == 0
+    np.testing.assert_array_equal(to_host(t), want)
+    assert_stats_equal(ost, vqs.get_stats())
+    t2 = to_gpu(keys)
+    with pytest.raises(vqs.VqsError) as e:
+        vqs.sort(t2, key_type=U64, workspace=ws.data_ptr(), workspace_bytes=need - 1)
+    assert e.value.code == -7
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(to_host(t2), keys)
+    with pytest.raises(vqs.VqsError) as e:
+        vqs.sort(t2, key_type=U64, method=1, workspace=ws.data_ptr(), workspace_bytes=need)
+    assert e.value.code == -1
+    # the library's own workspace again on this stream
+    k3 = random_keys(U32, 500_000, 52)
+    w3, o3 = _oracle_sorted(k3, U32, False)
+    t3 = to_gpu(k3)
+    vqs.sort(t3, ascending=False, key_type=U32)
+    torch.cuda.synchronize()
+    assert vqs.last_error_bits() == 0
+    np.testing.assert_array_equal(to_host(t3), w3)
+    assert_stats_equal(o3, vqs.get_stats())
+
+
+def test_caller_workspace_segmented_graph_and_total_keys(vqs):
+    """Segments with a caller workspace and the total key count given: the hipGraph is
+    captured once and replayed, every replay equals the oracle; a wrong total with
+    validate is VQS_EOFFSETS."""
+    import torch
+    print("case: workspace + total_keys + graph", flush=True)
+    off = W.segment_offsets(600, seed=33, lo=16, hi=1 << 15)
+    n = int(off[-1])
+    keys = W.segmented_keys(off, U32, 34)
+    want = keys.copy()
+    ost = oracle.sort_segmented(want, off, U32, stats=True)
+    need = vqs.workspace_bytes(n, U32, nseg=off.size - 1)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    src = to_gpu(keys)
+    t, o = torch.empty_like(src), to_gpu(off)
+    for rep in range(3):
+        t.copy_(src)
+        torch.cuda.synchronize()
+        vqs.sort_segmented(t, o, key_type=U32, use_graph=1, total_keys=n, workspace=ws.data_ptr(),
+                           workspace_bytes=need)
+        torch.cuda.synchronize()
+        assert vqs.last_error_bits() == 0
+        np.testing.assert_array_equal(to_host(t), want)
+        st = vqs.get_stats()
+        assert {k: st[k] for k in ("partitions", "keys_partitioned", "basecases", "max_depth")} == \
+            {k: ost[k] for k in ("partitions", "keys_partitioned", "basecases", "max_depth")}
+    # the total given, no graph, library workspace
+    t.copy_(src)
+    vqs.sort_segmented(t, o, key_type=U32, total_keys=n)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(to_host(t), want)
+    assert_stats_equal(ost, vqs.get_stats())
+    with pytest.raises(vqs.VqsError) as e:
+        vqs.sort_segmented(t, o, key_type=U32, total_keys=n + 1, validate=1)
+    assert e.value.code == -5
+
+
+# ---- the bounded-time fallback sorts -------------------------------------------------------
+
+@pytest.mark.parametrize("kt,asc", [(U64, True), (U32, False), (F32, True), (U128, False), (U16, True), (F64, False)])
+@pytest.mark.parametrize("where", ["lds", "solo_global", "level"])
+def test_bounded_time_sorts_forced(vqs, kt, asc, where):
+    """A fallback-mode limit of 0 sends every range past the paper's depth limit
+    straight to a bounded-time sort: the network in LDS for a range that fits one
+    local sort, the chunk sort and merge through device memory otherwise.  The output
+    equals the oracle's (whose fallback is Heapsort at the same depth), the paper's
+    counters agree, and the bounded sort ran."""
+    import torch
+    ks = {U16: 2, U32: 4, F32: 4, U64: 8, F64: 8, U128: 16}[kt]
+    cap = 32768 // ks                      # keys of one LDS local sort
+    if where == "lds":
+        n, opts = cap - 5, {}
+    elif where == "solo_global":
+        n, opts = 6 * cap + 17, {"solo_max": 8 * cap}
+    else:
+        n, opts = 40 * cap + 3, {"solo_max": 4 * cap}
+    print(f"case: bounded kt={kt} asc={asc} where={where} n={n}", flush=True)
+    keys = random_keys(kt, n, 60 + kt)
+    want, ost = _oracle_sorted(keys, kt, asc, depth_limit=0)
+    t = to_gpu(keys)
+    vqs.sort(t, ascending=asc, key_type=kt, depth_limit=-1, fallback_limit=vqs.FALLBACK_LIMIT_ZERO, **opts)
+    torch.cuda.synchronize()
+    assert vqs.last_error_bits() == 0
+    np.testing.assert_array_equal(to_host(t), want)
+    gst = vqs.get_stats()
+    assert_stats_equal(ost, gst)
+    assert gst["fallbacks"] == 1
+    if where == "lds":
+        assert gst["bounded_lds"] == 1 and gst["bounded_global"] == 0
+    else:
+        assert gst["bounded_global"] == 1 and gst["bounded_lds"] == 0
+
+
+@pytest.mark.parametrize("fb", [0, 1, 2])
+@pytest.mark.parametrize("kt", [U64, U32])
+def test_bounded_time_sorts_below_the_paper_limit(vqs, kt, fb):
+    """Ranges reach the paper's depth limit 2 in every placement; the fallback mode
+    then partitions fb more times before the bounded-time sorts (fb = 0: none)."""
+    import torch
+    print(f"case: bounded deep kt={kt} fb={fb}", flush=True)
+    n = 400_000
+    keys = random_keys(kt, n, 70 + fb)
+    want, ost = _oracle_sorted(keys, kt, depth_limit=2)
+    t = to_gpu(keys)
+    lim = vqs.FALLBACK_LIMIT_ZERO if fb == 0 else fb
+    vqs.sort(t, key_type=kt, depth_limit=2, fallback_limit=lim, solo_max=30_000)
+    torch.cuda.synchronize()
+    assert vqs.last_error_bits() == 0
+    np.testing.assert_array_equal(to_host(t), want)
+    gst = vqs.get_stats()
+    assert_stats_equal(ost, gst)
+    assert gst["fallbacks"] >= 4
+    assert gst["bounded_lds"] + gst["bounded_global"] >= 1
+
+
+def test_bounded_time_sorts_on_heavy_duplicates(vqs):
+    """Zipf keys drive ranges past the depth limit by peeling; with a fallback-mode
+    limit of 0 they are finished by the bounded-time sorts."""
+    import torch
+    print("case: bounded zipf", flush=True)
+    keys = W.zipf_u64(600_000, 3)
+    want, ost = _oracle_sorted(keys, U64)
+    t = to_gpu(keys)
+    vqs.sort(t, key_type=U64, fallback_limit=vqs.FALLBACK_LIMIT_ZERO, solo_max=20_000)
+    torch.cuda.synchronize()
+    assert vqs.last_error_bits() == 0
+    np.testing.assert_array_equal(to_host(t), want)
+    gst = vqs.get_stats()
+    assert_stats_equal(ost, gst)
+    assert gst["fallbacks"] > 0 and gst["bounded_lds"] + gst["bounded_global"] > 0
+
+
+# ---- key-traffic counters ----------------------------------------------------------------
+
+def test_traffic_counters(vqs):
+    """One local sort moves every key once each way; a multi-level sort of distinct keys
+    reads and writes the same number of keys, between two sweeps and one sweep more
+    than the keys partitioned."""
+    import torch
+    print("case: traffic counters", flush=True)
+    for kt, n in ((U64, 3000), (U32, 8000), (U16, 16000)):
+        t = to_gpu(random_keys(kt, n, 80))
+        vqs.sort(t, key_type=kt)
+        torch.cuda.synchronize()
+        st = vqs.get_stats()
+        assert st["hbm_read_keys"] == n and st["hbm_write_keys"] == n, (kt, st)
+    n = 2_000_000
+    keys = np.random.default_rng(81).permutation(n).astype(np.uint64)
+    t = to_gpu(keys)
+    vqs.sort(t, key_type=U64, level_mode=1)
+    torch.cuda.synchronize()
+    st = vqs.get_stats()
+    # distinct keys, look-back placement (no copy passes), no fallback: every key is
+    # read and written by the first level and by its final in-LDS sort, and beyond
+    # that only by partitions outside LDS, which keys_partitioned includes
+    assert st["fallbacks"] == 0 and st["levels"] >= 2
+    assert st["hbm_read_keys"] == st["hbm_write_keys"]
+    assert 2 * n <= st["hbm_read_keys"] <= st["keys_partitioned"] + n
