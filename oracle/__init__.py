@@ -90,6 +90,7 @@ def lib():
         L.vqo_default_depth_limit.restype = u64
         L.vqo_green16.argtypes = [vp]
         L.vqo_merge_network.argtypes = [u64, vp]
+        L.vqo_basecase_network.argtypes = [u64, vp, vp, vp]
         L.vqo_med3_u64.argtypes = [u64, u64, u64, i32]
         L.vqo_med3_u64.restype = u64
         L.vqo_key_size.argtypes = [i32]
@@ -253,6 +254,19 @@ def merge_network(length: int):
     out = np.zeros(length * 32, dtype=np.uint32)
     n = lib().vqo_merge_network(length, _ptr(out))
     return [tuple(map(int, out[2 * i:2 * i + 2])) for i in range(n)]
+
+
+def basecase_network(n: int):
+    """The module list BaseCase applies to n keys: (pairs as an (m, 2) array of cells,
+    output order (the cell of the k-th key in sort order), cell count 16c)."""
+    pairs = np.zeros(2 * 32768, dtype=np.uint32)
+    order = np.zeros(1024, dtype=np.uint32)
+    cells = np.zeros(1, dtype=np.uint32)
+    m = lib().vqo_basecase_network(n, _ptr(pairs), _ptr(order), _ptr(cells))
+    if m < 0:
+        raise ValueError("BaseCase holds at most 1024 keys")
+    c = int(cells[0])
+    return pairs[:2 * m].reshape(m, 2).copy(), order[:c].copy(), c
 
 
 def med3_u64(a: int, b: int, c: int, ascending: bool = True) -> int:

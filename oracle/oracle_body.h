@@ -135,42 +135,22 @@ static void SFX(heapsort)(KT* a, uint64_t n, int asc) {
 /* BaseCase (Sec. 2.3 and Sec. 3).  The n <= 16*c keys are copied into a buffer
  * viewed as a row-major matrix of 16 rows and c columns (c the smallest power of
  * two with 16*c >= n), padded with the last value in sort order so the padding
- * stays in place.  Each column is sorted with Green's 60-module network; then
- * adjacent sorted groups of w columns are merged into groups of 2w columns with
- * the bitonic merge network (flip stage, then half-cleaners) until one group
- * remains.  A group's sorted sequence is its elements in row-major order, so the
- * final group is the whole buffer in order. */
+ * stays in place.  Then the network of basecase_network runs on the cells: each
+ * column is sorted with Green's 60-module network, then adjacent sorted groups of w
+ * columns are merged into groups of 2w columns with the bitonic merge network (flip
+ * stage, then half-cleaners) until one group remains; a group's sorted sequence is
+ * its elements in row-major order.  The keys leave in the network's output order. */
 static void SFX(basecase)(KT* keys, uint64_t n, int asc) {
     if (n < 2) return;
-    uint64_t c = 1;
-    while (16 * c < n) c *= 2;
-    const uint64_t cells = 16 * c;
-    KT* buf = (KT*)malloc(cells * sizeof(KT));
-    KT* seq = (KT*)malloc(cells * sizeof(KT));
+    int lc = 0;
+    while ((16ull << lc) < n) lc++;
+    const bc_net* net = &BC_NET[lc];
+    KT buf[BC_MAX_CELLS];
     memcpy(buf, keys, n * sizeof(KT));
     const KT last = asc ? KMAXV : KMINV;
-    for (uint64_t i = n; i < cells; i++) buf[i] = last;
-
-    for (uint64_t j = 0; j < c; j++)
-        for (int m = 0; m < GREEN16_MODULES; m++)
-            SFX(cex)(&buf[(uint64_t)GREEN16[m][0] * c + j], &buf[(uint64_t)GREEN16[m][1] * c + j], asc);
-
-    for (uint64_t w = 1; w < c; w *= 2) {
-        const uint64_t L = 16 * w;                 /* keys per input group */
-        int npairs = 0;
-        const uint32_t(*net)[2] = merge_network(2 * L, &npairs);
-        for (uint64_t g0 = 0; g0 < c; g0 += 2 * w) {
-            for (uint64_t k = 0; k < L; k++) {
-                seq[k] = buf[(k / w) * c + g0 + k % w];
-                seq[L + k] = buf[(k / w) * c + g0 + w + k % w];
-            }
-            for (int m = 0; m < npairs; m++) SFX(cex)(&seq[net[m][0]], &seq[net[m][1]], asc);
-            for (uint64_t k = 0; k < 2 * L; k++) buf[(k / (2 * w)) * c + g0 + k % (2 * w)] = seq[k];
-        }
-    }
-    memcpy(keys, buf, n * sizeof(KT));
-    free(buf);
-    free(seq);
+    for (uint64_t i = n; i < net->cells; i++) buf[i] = last;
+    for (int m = 0; m < net->nmod; m++) SFX(cex)(&buf[net->pairs[m][0]], &buf[net->pairs[m][1]], asc);
+    for (uint64_t k = 0; k < n; k++) keys[k] = buf[net->order[k]];
 }
 
 /* Recurse (Alg. 1).  depth counts nested Recurse calls (the first call is 1); a

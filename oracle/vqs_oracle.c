@@ -205,6 +205,83 @@ int vqo_merge_network(uint64_t len, uint32_t* out_pairs) {
     return n;
 }
 
+/* The whole BaseCase network for 16*c cells (Sec. 2.3, Sec. 3), as one list of
+ * compare-and-exchange modules on the cells of the row-major 16 x c matrix: Green's
+ * 60 modules down each of the c columns, then for w = 1, 2, ... < c the bitonic merge
+ * of every pair of adjacent sorted w-column groups, applied to each group's elements
+ * in row-major order.  A merge reads its group's row-major sequence from the cells
+ * where the previous stage left it (where[q] is the cell holding matrix position q),
+ * so no data moves between stages; afterwards order[k] = where[k] is the cell holding
+ * the k-th key in sort order.  The same list drives the base case below and the 0-1
+ * checker of the tests.  Built for c = 1, 2, ..., 64 when the library loads. */
+#define BC_LOG2_MAX_C 6
+#define BC_MAX_CELLS (16u << BC_LOG2_MAX_C)
+#define BC_MAX_MODULES 32768
+typedef struct {
+    int nmod;
+    uint32_t cells;
+    uint32_t pairs[BC_MAX_MODULES][2];
+    uint32_t order[BC_MAX_CELLS];
+} bc_net;
+static bc_net BC_NET[BC_LOG2_MAX_C + 1];
+
+static void build_basecase_network(uint64_t c, bc_net* out) {
+    static uint32_t where[BC_MAX_CELLS], nw[BC_MAX_CELLS];
+    const uint64_t cells = 16 * c;
+    int m = 0;
+    for (uint64_t q = 0; q < cells; q++) where[q] = (uint32_t)q;
+    for (uint64_t j = 0; j < c; j++)
+        for (int g = 0; g < GREEN16_MODULES; g++) {
+            out->pairs[m][0] = (uint32_t)(GREEN16[g][0] * c + j);
+            out->pairs[m][1] = (uint32_t)(GREEN16[g][1] * c + j);
+            m++;
+        }
+    for (uint64_t w = 1; w < c; w *= 2) {
+        const uint64_t L = 16 * w;                 /* keys per input group */
+        int npairs = 0;
+        const uint32_t(*net)[2] = merge_network(2 * L, &npairs);
+        memcpy(nw, where, sizeof(uint32_t) * cells);
+        for (uint64_t g0 = 0; g0 < c; g0 += 2 * w) {
+            uint32_t in[BC_MAX_CELLS];             /* matrix position of sequence element k */
+            for (uint64_t k = 0; k < L; k++) {
+                in[k] = (uint32_t)((k / w) * c + g0 + k % w);
+                in[L + k] = (uint32_t)((k / w) * c + g0 + w + k % w);
+            }
+            for (int t = 0; t < npairs; t++) {
+                out->pairs[m][0] = where[in[net[t][0]]];
+                out->pairs[m][1] = where[in[net[t][1]]];
+                m++;
+            }
+            for (uint64_t k = 0; k < 2 * L; k++) nw[(k / (2 * w)) * c + g0 + k % (2 * w)] = where[in[k]];
+        }
+        memcpy(where, nw, sizeof(uint32_t) * cells);
+    }
+    out->nmod = m;
+    out->cells = (uint32_t)cells;
+    memcpy(out->order, where, sizeof(uint32_t) * cells);
+}
+
+__attribute__((constructor)) static void build_networks(void) {
+    for (int lc = 0; lc <= BC_LOG2_MAX_C; lc++) build_basecase_network(1ull << lc, &BC_NET[lc]);
+}
+
+/* The network BaseCase applies to n keys (c the smallest power of two with 16c >= n):
+ * modules to pairs (2 per module), the output order to order, the cell count to
+ * *cells; returns the number of modules, or -1 for n > 1024. */
+int vqo_basecase_network(uint64_t n, uint32_t* pairs, uint32_t* order, uint32_t* cells) {
+    int lc = 0;
+    while ((16ull << lc) < n) lc++;
+    if (lc > BC_LOG2_MAX_C) return -1;
+    const bc_net* net = &BC_NET[lc];
+    for (int m = 0; m < net->nmod; m++) {
+        pairs[2 * m] = net->pairs[m][0];
+        pairs[2 * m + 1] = net->pairs[m][1];
+    }
+    memcpy(order, net->order, sizeof(uint32_t) * net->cells);
+    *cells = net->cells;
+    return net->nmod;
+}
+
 /* ---- per-type instantiation ---------------------------------------------------- */
 
 #define CAT2(a, b) a##_##b
