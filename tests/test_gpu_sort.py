@@ -190,7 +190,7 @@ def test_autotune_segmented(vqs, tmp_path):
     assert again == res
 
 
-@pytest.mark.parametrize("n", [4, 9, 16, 20])
+@pytest.mark.parametrize("n", [4, 9, 16, 20, 24])
 def test_base_case_every_zero_one_input(vqs, n):
     import torch
     m = 1 << n

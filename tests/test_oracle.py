@@ -192,6 +192,109 @@ def test_basecase_all_zero_one_inputs(n):
     assert st["partitions"] == 0 and st["basecases"] == m
 
 
+def _bitsliced_inputs(ncells, nfree, word0, nwords):
+    """Wires of 64 * nwords 0-1 inputs, bitsliced: input number i = 64 * (word0 + w) + b
+    sits in bit b of word w, and wire k carries bit k of i (k < nfree); the other wires
+    are the padding, all ones."""
+    lanes = np.arange(64, dtype=np.uint64)
+    wires = []
+    words = np.arange(word0, word0 + nwords, dtype=np.uint64)
+    for k in range(ncells):
+        if k >= nfree:
+            wires.append(np.full(nwords, ~np.uint64(0)))
+        elif k < 6:
+            pat = np.uint64(0)
+            for b in lanes[((lanes >> np.uint64(k)) & np.uint64(1)) == 1]:
+                pat |= np.uint64(1) << b
+            wires.append(np.full(nwords, pat))
+        else:
+            wires.append(np.where((words >> np.uint64(k - 6)) & np.uint64(1), ~np.uint64(0), np.uint64(0)))
+    return wires
+
+
+def _run_network_bitsliced(pairs, wires):
+    for a, b in pairs:
+        lo = wires[a] & wires[b]
+        wires[b] = wires[a] | wires[b]
+        wires[a] = lo
+    return wires
+
+
+@pytest.fixture(scope="module")
+def zero_one(tmp_path_factory):
+    """The bitsliced exhaustive checker (tests/zero_one_check.c), built with gcc."""
+    import ctypes
+    import subprocess
+    out = tmp_path_factory.mktemp("zo") / "libzo.so"
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "zero_one_check.c")
+    subprocess.run(["gcc", "-O3", "-march=native", "-shared", "-fPIC", "-o", str(out), src], check=True)
+    L = ctypes.CDLL(str(out))
+    L.zero_one_check.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
+    L.zero_one_check.restype = ctypes.c_int64
+
+    def check(pairs, order, cells, nfree):
+        p = np.ascontiguousarray(pairs, dtype=np.uint32)
+        o = np.ascontiguousarray(order, dtype=np.uint32)
+        return int(L.zero_one_check(p.ctypes.data, p.shape[0], o.ctypes.data, cells, nfree))
+    return check
+
+
+@pytest.mark.parametrize("n", [16, 32])
+def test_basecase_network_sorts_every_zero_one_input(zero_one, n):
+    """0-1 principle, exhaustively: the module list BaseCase applies (one column for
+    n <= 16, two columns and one merge for n <= 32) sorts all 2^n 0-1 inputs of its
+    cells, so every input of up to n keys (the rest padded with the last value) is
+    sorted.  Bitsliced, 64 inputs per word: 2^32 inputs for the two-column network."""
+    pairs, order, cells = oracle.basecase_network(n)
+    assert cells == n
+    assert zero_one(pairs, order, cells, n) == -1
+
+
+def test_zero_one_checker_finds_a_dropped_module(zero_one):
+    """The checker is not vacuous: the two-column network without one of its merge
+    modules, or with two output positions swapped, fails it."""
+    pairs, order, cells = oracle.basecase_network(32)
+    assert zero_one(np.delete(pairs, 150, axis=0), order, cells, 32) >= 0
+    bad = order.copy()
+    bad[[3, 20]] = bad[[20, 3]]
+    assert zero_one(pairs, bad, cells, 20) >= 0
+
+
+@pytest.mark.parametrize("n", [33, 64, 100, 128, 256, 1000])
+def test_basecase_network_random_zero_one_inputs(n):
+    """Wider base cases on 2^20 random 0-1 inputs each (bitsliced); every merge stage
+    they are built from is exhaustively checked above by the 0-1 principle for merging
+    networks, and the columns by Green-16's."""
+    pairs, order, cells = oracle.basecase_network(n)
+    rng = np.random.default_rng(n)
+    nwords = 1 << 14
+    wires = [rng.integers(0, 2**64, nwords, dtype=np.uint64) if k < n else np.full(nwords, ~np.uint64(0))
+             for k in range(cells)]
+    ones = sum(np.array([bin(int(x)).count("1") for x in w[:64]]) for w in wires)
+    wires = _run_network_bitsliced(pairs, wires)
+    out = [wires[int(c)] for c in order]
+    for k in range(cells - 1):
+        assert not (out[k] & ~out[k + 1]).any(), (n, k)
+    assert (sum(np.array([bin(int(x)).count("1") for x in w[:64]]) for w in out) == ones).all()
+
+
+def test_basecase_uses_its_network():
+    """BaseCase on random keys equals its module list applied to the padded buffer."""
+    rng = np.random.default_rng(3)
+    for n in (2, 15, 16, 17, 31, 32, 33, 200, 256, 1000):
+        keys = rng.integers(0, 1000, n).astype(np.uint32)
+        got = keys.copy()
+        oracle.basecase(got, oracle.U32)
+        pairs, order, cells = oracle.basecase_network(n)
+        buf = np.full(cells, 0xFFFFFFFF, dtype=np.uint32)
+        buf[:n] = keys
+        for a, b in pairs:
+            x, y = buf[a], buf[b]
+            buf[a], buf[b] = min(x, y), max(x, y)
+        np.testing.assert_array_equal(got, buf[order[:n]])
+        np.testing.assert_array_equal(got, np.sort(keys))
+
+
 @pytest.mark.parametrize("n", [2, 3, 5, 8, 9])
 def test_basecase_all_permutations(n):
     perms = np.array(list(itertools.permutations(range(n))), dtype=np.uint64)
@@ -294,20 +397,58 @@ def test_choose_pivot_matches_independent_recomputation(kt, w):
             assert p in keys[b:e]
 
 
-def test_pivot_median_counts_per_type():
-    # 3W medians, then W, then scalar triples: u64 24 -> 8 -> 2, u32 48 -> 16 -> 5 -> 1,
-    # u16 96 -> 32 -> 10 -> 3 -> 1, u128 12 -> 4 -> 1 (reduction rule of Sec. 2.2).
-    def rounds(w):
-        m, seq = 3 * w, [3 * w]
-        while m >= 3:
-            nv = m // (3 * w)
-            m = nv * w + (m - nv * 3 * w) // 3
-            seq.append(m)
-        return seq
-    assert rounds(8) == [24, 8, 2]
-    assert rounds(16) == [48, 16, 5, 1]
-    assert rounds(32) == [96, 32, 10, 3, 1]
-    assert rounds(4) == [12, 4, 1]
+# Chunk i of the nine sampled chunks holds BASE[i] + pi(j) in lane j.  The paper's
+# grouping takes lanewise medians of chunks (0,1,2), (3,4,5), (6,7,8): bases
+# med(100,200,900) = 200, med(300,800,400) = 400, med(700,600,500) = 600, then
+# the first reduction round's lanewise median of those three gives 400 + pi(j) in
+# lane j.  (Grouping chunks (0,3,6), (1,4,7), (2,5,8) instead would give 500 + pi(j).)
+# The remaining rounds take consecutive triples of the W values 400 + pi(0..W-1),
+# dropping 0..2 leftovers, until fewer than three remain; worked by hand for the
+# identity lane order and for the reversed one (pi(j) = W - 1 - j):
+#   W = 8  (u64, f64):  identity 400..407 -> 401, 404 -> 401;
+#                       reversed 407..400 -> 406, 403 -> 406
+#   W = 16 (u32, f32):  identity -> 401, 404, 407, 410, 413 -> 404;
+#                       reversed -> 414, 411, 408, 405, 402 -> 411
+#   W = 32 (u16):       identity -> 401, 404, ..., 428 -> 404, 413, 422 -> 413;
+#                       reversed -> 430, 427, ..., 403 -> 427, 418, 409 -> 418
+#   W = 4  (u128):      identity 400..403 -> 401; reversed 403..400 -> 402
+BASE = [100, 200, 900, 300, 800, 400, 700, 600, 500]
+PIVOT_BY_HAND = {8: (401, 406), 16: (404, 411), 32: (413, 418), 4: (401, 402)}
+
+
+@pytest.mark.parametrize("kt,w", [(oracle.U16, 32), (oracle.U32, 16), (oracle.U64, 8), (oracle.U128, 4),
+                                  (oracle.F32, 16), (oracle.F64, 8)])
+@pytest.mark.parametrize("reverse", [False, True])
+def test_pivot_reduction_grouping_on_structured_chunks(kt, w, reverse):
+    """ChoosePivot (Sec. 2.2) on keys whose nine sampled chunks are filled so that the
+    chunk grouping, the lanewise reduction and the leftover rule each decide the
+    pivot; the expected pivots are worked out by hand above.  The chunk positions come
+    from the offset generator pinned against NumPy's SFC64."""
+    n = 200 * w
+    b, e = 37 * w, n - 5          # a range not starting at 0, with a ragged tail
+    seed = next(s for s in range(1000)
+                if len(set(oracle.pivot_offsets(s, b, e, w).tolist())) == 9)
+    offs = oracle.pivot_offsets(seed, b, e, w)
+    lane = np.arange(w)[::-1] if reverse else np.arange(w)
+    dt = {oracle.U16: np.uint16, oracle.U32: np.uint32, oracle.U64: np.uint64,
+          oracle.F32: np.float32, oracle.F64: np.float64}.get(kt, np.uint64)
+    if kt == oracle.U128:
+        keys = np.zeros((n, 2), np.uint64)
+        keys[:, 0] = np.random.default_rng(5).integers(0, 2**64, n, dtype=np.uint64)   # low words vary
+        keys[:, 1] = 50
+        for i in range(9):
+            c0 = b + int(offs[i]) * w
+            keys[c0:c0 + w, 1] = BASE[i] + lane
+    else:
+        keys = np.full(n, 50, dtype=dt)
+        for i in range(9):
+            c0 = b + int(offs[i]) * w
+            keys[c0:c0 + w] = (BASE[i] + lane).astype(dt)
+    want = PIVOT_BY_HAND[w][1 if reverse else 0]
+    for asc in (True, False):
+        p = oracle.choose_pivot(keys, b, e, kt, asc, seed)
+        got = int(p[1]) if kt == oracle.U128 else int(p)
+        assert got == want, (kt, reverse, asc, got, want)
 
 
 def test_pivot_is_central_on_uniform_data():
