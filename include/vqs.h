@@ -20,8 +20,10 @@
  *  - Floating-point keys are ordered by the total order of their bit patterns:
  *    -NaN < -inf < ... < -0.0 < +0.0 < ... < +inf < +NaN.  For inputs without NaN
  *    and without -0.0 this is the IEEE order, and the result is unique.
- *  - Sorting is not stable (Sec. 5): equal keys are bit-identical here, so the
- *    output is the unique sorted rearrangement of the input.
+ *  - Sorting is not stable (Sec. 5): equal keys are bit-identical here (for
+ *    VQS_K64V64 equal keys are ordered by their data), so the output is the unique
+ *    sorted rearrangement of the input.  vqs_sort_stable keeps equal keys in input
+ *    order and returns the permutation.
  *  - Workspace: unless options.workspace supplies one, the library keeps a device
  *    workspace (a scratch array of n keys for the out-of-place partitions, plus range
  *    lists, tile tables and counters; vqs_workspace_bytes gives its size) per
@@ -60,16 +62,24 @@
 extern "C" {
 #endif
 
-/* Key types: the 16/32/64-bit unsigned integers, 32/64-bit floating point and pairs of
- * 64-bit halves forming a 128-bit key that the paper's method handles (Sec. 2.4,
- * Sec. 5).  Every type sorts ascending or descending (Sec. 2.4's order tag). */
+/* Key types: the 16/32/64-bit integers, 32/64-bit floating point and pairs of 64-bit
+ * halves forming a 128-bit key that the paper's method handles (Sec. 2.4, Sec. 5; its
+ * measurements use signed i16/i32/i64 keys).  Every type sorts ascending or
+ * descending (Sec. 2.4's order tag). */
 enum vqs_key_type {
     VQS_U16 = 1,
     VQS_U32 = 2,
     VQS_U64 = 3,
     VQS_U128 = 4,
     VQS_F32 = 5,
-    VQS_F64 = 6
+    VQS_F64 = 6,
+    VQS_I16 = 7,     /* two's-complement integers, signed order */
+    VQS_I32 = 8,
+    VQS_I64 = 9,
+    VQS_K64V64 = 10  /* a 64-bit key with 64-bit associated data, 16 bytes: the data at
+                        byte 0, the key at byte 8.  Sorted as the 128-bit key (key,
+                        data), as Sec. 2.4 treats such pairs: keys in order, equal keys
+                        ordered by their data, so the result is unique. */
 };
 
 /* Return codes: 0 on success, negative on failure. */
@@ -217,6 +227,22 @@ int vqs_sort_ex(void* keys, uint64_t n, int key_type, int ascending, const vqs_o
                 void* stream);
 int vqs_sort_segmented_ex(void* keys, const int64_t* offsets, uint64_t nseg, int key_type,
                           int ascending, const vqs_options* options, void* stream);
+
+/* Stable sort (Sec. 5: Quicksort is not stable, but becomes so when a unique row
+ * identifier is appended to the least-significant bits of each key).  Sorts keys[0, n)
+ * in place so that equal keys keep their input order and, if rows is not NULL, writes
+ * rows[i] = the input position of the key now at position i (device array of n
+ * uint64, 8-byte aligned) -- the permutation to apply to any associated data.  Each
+ * key's order-preserving unsigned form is joined with its row number into a
+ * composite key, (key << 32) | row as a u64 for keys of up to 32 bits and n <= 2^32,
+ * otherwise a 128-bit key (key, row); the composites (all distinct) are sorted by the
+ * plain method and split again.  Key types of up to 64 bits (VQS_U128 and VQS_K64V64:
+ * VQS_ETYPE).  options as for vqs_sort_ex, method plain, no caller workspace
+ * (VQS_EINVAL otherwise); the composite array (n * 8 or n * 16 bytes) is a library
+ * workspace per stream.  vqs_get_stats reports the composite sort.  Synchronisation as
+ * vqs_sort_ex. */
+int vqs_sort_stable(void* keys, uint64_t n, int key_type, int ascending, uint64_t* rows,
+                    const vqs_options* options, void* stream);
 
 /* ---- allocation-free sort ----------------------------------------------------------
  * For callers that cannot allocate device memory: serving loops that must not call

@@ -10,7 +10,8 @@ The learned-splitter model oracle is in oracle/mlp.py.
 
 Key types use the interface numbering: 1 u16, 2 u32, 3 u64, 4 u128 (numpy
 uint64 array of shape (n, 2): column 0 the low word, column 1 the high word),
-5 f32, 6 f64.
+5 f32, 6 f64, 7 i16, 8 i32, 9 i64, 10 k64v64 (a 64-bit key with 64-bit data as
+a 128-bit key: column 1 the key, column 0 the data).
 """
 from __future__ import annotations
 
@@ -31,9 +32,12 @@ _lib = None
 _ctx = None
 
 U16, U32, U64, U128, F32, F64 = 1, 2, 3, 4, 5, 6
+I16, I32, I64, K64V64 = 7, 8, 9, 10
 _DTYPES = {U16: np.uint16, U32: np.uint32, U64: np.uint64, U128: np.uint64,
-           F32: np.float32, F64: np.float64}
-KEY_SIZE = {U16: 2, U32: 4, U64: 8, U128: 16, F32: 4, F64: 8}
+           F32: np.float32, F64: np.float64, I16: np.int16, I32: np.int32, I64: np.int64,
+           K64V64: np.uint64}
+KEY_SIZE = {U16: 2, U32: 4, U64: 8, U128: 16, F32: 4, F64: 8, I16: 2, I32: 4, I64: 8, K64V64: 16}
+PAIR_TYPES = (U128, K64V64)   # (n, 2) uint64 arrays: column 0 the low word, column 1 the high
 NB_DEFAULT = 256
 
 
@@ -115,12 +119,12 @@ def _check_keys(keys: np.ndarray, kt: int) -> None:
         raise ValueError("keys must be C-contiguous")
     if keys.dtype != _DTYPES[kt]:
         raise TypeError(f"key type {kt} needs dtype {_DTYPES[kt]}, got {keys.dtype}")
-    if kt == U128 and (keys.ndim != 2 or keys.shape[1] != 2):
-        raise ValueError("u128 keys are an (n, 2) uint64 array [lo, hi]")
+    if kt in PAIR_TYPES and (keys.ndim != 2 or keys.shape[1] != 2):
+        raise ValueError("u128 / k64v64 keys are an (n, 2) uint64 array [lo, hi]")
 
 
 def nkeys(keys: np.ndarray, kt: int) -> int:
-    return keys.shape[0] if kt == U128 else keys.size
+    return keys.shape[0] if kt in PAIR_TYPES else keys.size
 
 
 def sort(keys: np.ndarray, kt: int, ascending: bool = True, seed: int = 0,
@@ -149,11 +153,11 @@ def sort_segmented(keys: np.ndarray, offsets: np.ndarray, kt: int, ascending: bo
 
 def choose_pivot(keys: np.ndarray, b: int, e: int, kt: int, ascending: bool = True, seed: int = 0):
     _check_keys(keys, kt)
-    out = np.zeros(2 if kt == U128 else 1, dtype=_DTYPES[kt])
+    out = np.zeros(2 if kt in PAIR_TYPES else 1, dtype=_DTYPES[kt])
     rc = lib().vqo_choose_pivot(_ptr(keys), b, e, kt, int(bool(ascending)), seed, _ptr(out))
     if rc != 0:
         raise RuntimeError(f"vqo_choose_pivot failed: {rc}")
-    return out if kt == U128 else out[0]
+    return out if kt in PAIR_TYPES else out[0]
 
 
 def partition(keys: np.ndarray, b: int, e: int, pivot, kt: int, ascending: bool = True) -> int:
@@ -164,11 +168,11 @@ def partition(keys: np.ndarray, b: int, e: int, pivot, kt: int, ascending: bool 
 
 def minmax(keys: np.ndarray, b: int, e: int, kt: int, ascending: bool = True):
     _check_keys(keys, kt)
-    f = np.zeros(2 if kt == U128 else 1, dtype=_DTYPES[kt])
+    f = np.zeros(2 if kt in PAIR_TYPES else 1, dtype=_DTYPES[kt])
     l = np.zeros_like(f)
     if lib().vqo_minmax(_ptr(keys), b, e, kt, int(bool(ascending)), _ptr(f), _ptr(l)) != 0:
         raise ValueError("empty range")
-    return (f, l) if kt == U128 else (f[0], l[0])
+    return (f, l) if kt in PAIR_TYPES else (f[0], l[0])
 
 
 def plain_split_sizes(keys: np.ndarray, kt: int, levels: int = 8, seed: int = 0,

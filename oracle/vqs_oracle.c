@@ -28,6 +28,10 @@
  *    Heapsorts its range; the degenerate re-partition counts as a recursion.
  *  - degenerate pivot: the first key in sort order (minimum ascending, maximum
  *    descending); padding: the last value in sort order.
+ *  - key types: unsigned 16/32/64/128-bit, float, double (Sec. 2.4), and the signed
+ *    16/32/64-bit integers of the paper's measurements; a 64-bit key with 64-bit
+ *    associated data is a 128-bit key with the key in the upper half (Sec. 2.4), so
+ *    equal keys are ordered by their data and the result stays unique.
  */
 #include <math.h>
 #include <stdint.h>
@@ -40,6 +44,10 @@
 #define VQO_U128 4
 #define VQO_F32 5
 #define VQO_F64 6
+#define VQO_I16 7
+#define VQO_I32 8
+#define VQO_I64 9
+#define VQO_K64V64 10   /* 64-bit key in the upper half, 64-bit value in the lower: a 128-bit key */
 
 typedef struct {
     uint64_t partitions;        /* Partition calls */
@@ -374,14 +382,58 @@ typedef unsigned __int128 u128_t;
 #undef KMINV
 #undef KW
 
+/* Signed integers (the i16 / i32 / i64 keys of the paper's measurements): the
+ * natural signed order. */
+#define KT int16_t
+#define SFX(n) CAT(n, i16)
+#define KLESS(a, b) ((a) < (b))
+#define KMAXV ((int16_t)INT16_MAX)
+#define KMINV ((int16_t)INT16_MIN)
+#define KW 32
+#include "oracle_body.h"
+#undef KT
+#undef SFX
+#undef KLESS
+#undef KMAXV
+#undef KMINV
+#undef KW
+
+#define KT int32_t
+#define SFX(n) CAT(n, i32)
+#define KLESS(a, b) ((a) < (b))
+#define KMAXV ((int32_t)INT32_MAX)
+#define KMINV ((int32_t)INT32_MIN)
+#define KW 16
+#include "oracle_body.h"
+#undef KT
+#undef SFX
+#undef KLESS
+#undef KMAXV
+#undef KMINV
+#undef KW
+
+#define KT int64_t
+#define SFX(n) CAT(n, i64)
+#define KLESS(a, b) ((a) < (b))
+#define KMAXV ((int64_t)INT64_MAX)
+#define KMINV ((int64_t)INT64_MIN)
+#define KW 8
+#include "oracle_body.h"
+#undef KT
+#undef SFX
+#undef KLESS
+#undef KMAXV
+#undef KMINV
+#undef KW
+
 /* ---- exported API ---------------------------------------------------------------- */
 
 static int key_size(int kt) {
     switch (kt) {
-        case VQO_U16: return 2;
-        case VQO_U32: case VQO_F32: return 4;
-        case VQO_U64: case VQO_F64: return 8;
-        case VQO_U128: return 16;
+        case VQO_U16: case VQO_I16: return 2;
+        case VQO_U32: case VQO_F32: case VQO_I32: return 4;
+        case VQO_U64: case VQO_F64: case VQO_I64: return 8;
+        case VQO_U128: case VQO_K64V64: return 16;
         default: return 0;
     }
 }
@@ -394,8 +446,12 @@ int vqo_key_size(int kt) { return key_size(kt); }
         case VQO_U32: { call(u32, uint32_t); break; }        \
         case VQO_U64: { call(u64, uint64_t); break; }        \
         case VQO_U128: { call(u128, u128_t); break; }        \
+        case VQO_K64V64: { call(u128, u128_t); break; }      \
         case VQO_F32: { call(f32, float); break; }           \
         case VQO_F64: { call(f64, double); break; }          \
+        case VQO_I16: { call(i16, int16_t); break; }         \
+        case VQO_I32: { call(i32, int32_t); break; }         \
+        case VQO_I64: { call(i64, int64_t); break; }         \
         default: return -2;                                  \
     }
 
@@ -425,9 +481,12 @@ int vqo_sort_segmented(void* keys, const int64_t* offsets, uint64_t nseg, int kt
         case VQO_U16: SORT_SEGS(u16, uint16_t); break;
         case VQO_U32: SORT_SEGS(u32, uint32_t); break;
         case VQO_U64: SORT_SEGS(u64, uint64_t); break;
-        case VQO_U128: SORT_SEGS(u128, u128_t); break;
+        case VQO_U128: case VQO_K64V64: SORT_SEGS(u128, u128_t); break;
         case VQO_F32: SORT_SEGS(f32, float); break;
         case VQO_F64: SORT_SEGS(f64, double); break;
+        case VQO_I16: SORT_SEGS(i16, int16_t); break;
+        case VQO_I32: SORT_SEGS(i32, int32_t); break;
+        case VQO_I64: SORT_SEGS(i64, int64_t); break;
         default: free(tmp); return -2;
     }
 #undef SORT_SEGS
@@ -474,9 +533,12 @@ int64_t vqo_partition(void* keys, uint64_t b, uint64_t e, int kt, int ascending,
         case VQO_U16: PART(u16, uint16_t); break;
         case VQO_U32: PART(u32, uint32_t); break;
         case VQO_U64: PART(u64, uint64_t); break;
-        case VQO_U128: PART(u128, u128_t); break;
+        case VQO_U128: case VQO_K64V64: PART(u128, u128_t); break;
         case VQO_F32: PART(f32, float); break;
         case VQO_F64: PART(f64, double); break;
+        case VQO_I16: PART(i16, int16_t); break;
+        case VQO_I32: PART(i32, int32_t); break;
+        case VQO_I64: PART(i64, int64_t); break;
         default: break;
     }
 #undef PART

@@ -2,9 +2,9 @@
 //
 // Key traits: every key type is sorted internally as an unsigned integer in
 // ascending order.  Floats are mapped to unsigned integers by the order-preserving
-// bit transform (flip all bits of negatives, set the sign bit of non-negatives), and
-// descending order is the bitwise complement, so one comparison serves the six key
-// types and both orders of Sec. 2.4.  The transform is applied when keys are first
+// bit transform (flip all bits of negatives, set the sign bit of non-negatives),
+// signed integers by flipping the sign bit, and descending order is the bitwise
+// complement, so one comparison serves every key type and both orders of Sec. 2.4.  The transform is applied when keys are first
 // read from the caller's array and inverted when results are written back.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -27,11 +27,13 @@ struct Key<16> {
   static constexpr int V = 8;  // keys per 16-byte chunk
   __device__ static R load_t(S s, int mode) {
     R r = s;
+    if (mode & MODE_SIGNED) r ^= 0x8000u;
     if (mode & MODE_DESC) r = (~r) & 0xFFFFu;
     return r;
   }
   __device__ static S store_t(R r, int mode) {
     if (mode & MODE_DESC) r = (~r) & 0xFFFFu;
+    if (mode & MODE_SIGNED) r ^= 0x8000u;
     return (S)r;
   }
   __device__ static bool lt(R a, R b) { return a < b; }
@@ -63,11 +65,13 @@ struct Key<32> {
   __device__ static R load_t(S s, int mode) {
     R r = s;
     if (mode & MODE_FLOAT) r = (r & 0x80000000u) ? ~r : (r | 0x80000000u);
+    if (mode & MODE_SIGNED) r ^= 0x80000000u;
     if (mode & MODE_DESC) r = ~r;
     return r;
   }
   __device__ static S store_t(R r, int mode) {
     if (mode & MODE_DESC) r = ~r;
+    if (mode & MODE_SIGNED) r ^= 0x80000000u;
     if (mode & MODE_FLOAT) r = (r & 0x80000000u) ? (r & 0x7FFFFFFFu) : ~r;
     return r;
   }
@@ -98,11 +102,13 @@ struct Key<64> {
   __device__ static R load_t(S s, int mode) {
     R r = s;
     if (mode & MODE_FLOAT) r = (r >> 63) ? ~r : (r | 0x8000000000000000ull);
+    if (mode & MODE_SIGNED) r ^= 0x8000000000000000ull;
     if (mode & MODE_DESC) r = ~r;
     return r;
   }
   __device__ static S store_t(R r, int mode) {
     if (mode & MODE_DESC) r = ~r;
+    if (mode & MODE_SIGNED) r ^= 0x8000000000000000ull;
     if (mode & MODE_FLOAT) r = (r >> 63) ? (r & 0x7FFFFFFFFFFFFFFFull) : ~r;
     return r;
   }

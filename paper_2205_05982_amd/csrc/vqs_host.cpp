@@ -15,6 +15,7 @@
 #include "../../include/vqs.h"
 #include "vqs_launch.h"
 #include "vqs_learned.h"
+#include "vqs_stable.h"
 
 // Fixed device scratch of vqs_sort_noalloc: every device the library runs on holds its
 // own copy from the library's load until the process ends.  In host code this name
@@ -92,6 +93,8 @@ struct Workspace {
   int64_t* l_offsets = nullptr;
   uint64_t* l_summary = nullptr;
   bool learned_ran = false;
+  char* smem = nullptr;   // stable sort: the composite keys
+  size_t scap = 0;
   std::unique_ptr<Workspace> inner;  // for sorting the sample
   hipGraphExec_t graph = nullptr;
   GraphKey graph_key{};
@@ -129,6 +132,7 @@ struct Workspace {
     if (mem) (void)hipFree(mem);
     if (host_pinned) (void)hipHostFree(host_pinned);
     if (lmem) (void)hipFree(lmem);
+    if (smem) (void)hipFree(smem);
   }
 };
 
@@ -160,10 +164,10 @@ Geometry geometry(int dev) {
 
 int key_bits(int kt) {
   switch (kt) {
-    case VQS_U16: return 16;
-    case VQS_U32: case VQS_F32: return 32;
-    case VQS_U64: case VQS_F64: return 64;
-    case VQS_U128: return 128;
+    case VQS_U16: case VQS_I16: return 16;
+    case VQS_U32: case VQS_F32: case VQS_I32: return 32;
+    case VQS_U64: case VQS_F64: case VQS_I64: return 64;
+    case VQS_U128: case VQS_K64V64: return 128;
     default: return 0;
   }
 }
@@ -197,6 +201,12 @@ uint32_t depth_limit_for(uint64_t n) {
 bool has_field(const vqs_options* o, size_t end) { return o && (o->struct_size == 0 || o->struct_size >= end); }
 #define VQS_HAS(o, f) has_field((o), offsetof(vqs_options, f) + sizeof(((vqs_options*)0)->f))
 
+// Transform of the caller's keys into the internal ascending unsigned form.
+int mode_of(int kt, int asc) {
+  return ((kt == VQS_F32 || kt == VQS_F64) ? MODE_FLOAT : 0) |
+         ((kt == VQS_I16 || kt == VQS_I32 || kt == VQS_I64) ? MODE_SIGNED : 0) | (asc ? 0 : MODE_DESC);
+}
+
 struct Plan {
   int bits, ks, mode;
   uint64_t n, nseg;
@@ -215,7 +225,7 @@ int make_plan(uint64_t n, uint64_t nseg, int kt, int asc, const vqs_options* o, 
   if (!bits) return VQS_ETYPE;
   pl->bits = bits;
   pl->ks = bits / 8;
-  pl->mode = ((kt == VQS_F32 || kt == VQS_F64) ? MODE_FLOAT : 0) | (asc ? 0 : MODE_DESC);
+  pl->mode = mode_of(kt, asc);
   pl->n = n;
   pl->nseg = nseg;
   pl->seed = o ? o->seed : 0;
@@ -801,6 +811,55 @@ int learned_locked(Workspace* ws, void* keys, uint64_t n, const vqs_options* o, 
   return VQS_OK;
 }
 
+// ---- stable sort ---------------------------------------------------------------------------
+
+int stable_sort(void* keys, uint64_t n, int kt, int asc, uint64_t* rows, const vqs_options* o, hipStream_t stream) {
+  if (o && o->struct_size != 0 && o->struct_size < offsetof(vqs_options, train_steps)) return VQS_EINVAL;
+  const int bits = key_bits(kt);
+  if (!bits || bits > 64) return VQS_ETYPE;
+  if (asc != 0 && asc != 1) return VQS_EINVAL;
+  if (o && o->method != VQS_METHOD_PLAIN) return VQS_EINVAL;
+  if (VQS_HAS(o, workspace_bytes) && o->workspace) return VQS_EINVAL;
+  if (n == 0) return VQS_OK;
+  if (!keys) return VQS_EINVAL;
+  if ((uintptr_t)keys % (uintptr_t)(bits / 8) || (rows && (uintptr_t)rows % 8)) return VQS_EINVAL;
+  // (key << 32 | row) fits a u64 for keys of up to 32 bits and rows below 2^32
+  const int comp = (bits <= 32 && n <= (1ull << 32)) ? COMP64 : COMP128;
+  const size_t cbytes = (size_t)n * (comp == COMP64 ? 8 : 16);
+  std::lock_guard<std::mutex> lock(g_mu);
+  Workspace* ws = workspace_for(stream);
+  if (cbytes > ws->scap) {
+    if (ws->smem) {
+      (void)hipStreamSynchronize(ws->stream);
+      (void)hipFree(ws->smem);
+      ws->smem = nullptr;
+      ws->scap = 0;
+    }
+    void* m = nullptr;
+    if (hipMalloc(&m, cbytes) != hipSuccess || !m) {
+      (void)hipGetLastError();
+      return VQS_ENOMEM;
+    }
+    ws->smem = (char*)m;
+    ws->scap = cbytes;
+  }
+  ws->stream = stream;
+  const int mode = mode_of(kt, asc);
+  if (launch_stable_pack(keys, n, bits, mode, comp, ws->smem, stream) != hipSuccess) return VQS_EHIP;
+  vqs_options plain{};
+  if (o) std::memcpy(&plain, o, std::min<size_t>(o->struct_size ? o->struct_size : sizeof(vqs_options),
+                                                sizeof(vqs_options)));
+  plain.struct_size = sizeof(vqs_options);
+  plain.method = VQS_METHOD_PLAIN;
+  plain.use_graph = 0;
+  plain.workspace = nullptr;
+  plain.workspace_bytes = 0;
+  const int rc = sort_locked(ws, ws->smem, nullptr, 1, n, comp == COMP64 ? VQS_U64 : VQS_U128, 1, &plain, stream);
+  if (rc != VQS_OK) return rc;
+  if (launch_stable_unpack(ws->smem, n, bits, mode, comp, keys, rows, stream) != hipSuccess) return VQS_EHIP;
+  return VQS_OK;
+}
+
 // ---- allocation-free entry point -------------------------------------------------------
 
 constexpr int NOALLOC_MAX_DEVICES = 64;
@@ -919,6 +978,11 @@ int vqs_sort(void* keys, uint64_t n, int key_type, int ascending) {
 int vqs_sort_noalloc(void* keys, uint64_t n, int key_type, int ascending, const vqs_options* options,
                      void* stream) {
   return noalloc_sort(keys, n, key_type, ascending, options, (hipStream_t)stream);
+}
+
+int vqs_sort_stable(void* keys, uint64_t n, int key_type, int ascending, uint64_t* rows,
+                    const vqs_options* options, void* stream) {
+  return stable_sort(keys, n, key_type, ascending, rows, options, (hipStream_t)stream);
 }
 
 int vqs_sort_segmented_ex(void* keys, const int64_t* offsets, uint64_t nseg, int key_type, int ascending,

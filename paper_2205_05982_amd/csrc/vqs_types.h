@@ -11,6 +11,7 @@ struct u128k {
 // transform mode bits of the caller's keys
 constexpr int MODE_FLOAT = 1;
 constexpr int MODE_DESC = 2;
+constexpr int MODE_SIGNED = 4;   // two's-complement integers: the sign bit flipped
 
 #ifndef VQS_LEVEL_P
 #define VQS_LEVEL_P 256

@@ -15,10 +15,12 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libvqs.so")
 
 U16, U32, U64, U128, F32, F64 = 1, 2, 3, 4, 5, 6
+I16, I32, I64, K64V64 = 7, 8, 9, 10
 PLAIN, LEARNED = 0, 1
-KEY_SIZE = {U16: 2, U32: 4, U64: 8, U128: 16, F32: 4, F64: 8}
+KEY_SIZE = {U16: 2, U32: 4, U64: 8, U128: 16, F32: 4, F64: 8, I16: 2, I32: 4, I64: 8, K64V64: 16}
 
-_DTYPE_TO_KT = {torch.float32: F32, torch.float64: F64}
+_DTYPE_TO_KT = {torch.float32: F32, torch.float64: F64, torch.int16: I16, torch.int32: I32,
+                torch.int64: I64}
 for _name, _kt in (("uint16", U16), ("uint32", U32), ("uint64", U64)):
     if hasattr(torch, _name):
         _DTYPE_TO_KT[getattr(torch, _name)] = _kt
@@ -118,7 +120,7 @@ def key_type_of(t: torch.Tensor, key_type: int | None = None) -> int:
     if key_type is not None:
         return key_type
     if t.dim() == 2 and t.shape[1] == 2 and t.element_size() == 8:
-        raise ValueError("pass key_type=U128 (or U64) explicitly for a 2-column tensor")
+        raise ValueError("pass key_type=U128, K64V64 (or U64, I64) explicitly for a 2-column tensor")
     kt = _DTYPE_TO_KT.get(t.dtype)
     if kt is None:
         raise TypeError(f"no key type for dtype {t.dtype}; pass key_type")
@@ -167,6 +169,27 @@ def sort_noalloc(t: torch.Tensor, ascending: bool = True, key_type: int | None =
     if rc != 0:
         raise VqsError(rc, "vqs_sort_noalloc")
     return t
+
+
+def sort_stable(t: torch.Tensor, ascending: bool = True, key_type: int | None = None, rows: bool = True,
+                stream=None, **opts):
+    """Stable sort of t in place (vqs_sort_stable); returns (t, rows) where rows[i] is
+    the input position of the key now at i (int64 tensor), or (t, None)."""
+    _check(t)
+    kt = key_type_of(t, key_type)
+    n = _nkeys(t, kt)
+    r = torch.empty(n, dtype=torch.int64, device=t.device) if rows else None
+    o = make_options(**opts)
+    L = lib()
+    L.vqs_sort_stable.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                  ctypes.POINTER(Options), ctypes.c_void_p]
+    L.vqs_sort_stable.restype = ctypes.c_int
+    rc = L.vqs_sort_stable(ctypes.c_void_p(t.data_ptr()), n, kt, int(bool(ascending)),
+                           ctypes.c_void_p(r.data_ptr() if r is not None else 0), ctypes.byref(o),
+                           ctypes.c_void_p(_stream_handle(stream)))
+    if rc != 0:
+        raise VqsError(rc, "vqs_sort_stable")
+    return t, r
 
 
 def sort_segmented(t: torch.Tensor, offsets: torch.Tensor, ascending: bool = True,

@@ -66,7 +66,7 @@ def test_binding_profile_modes():
 def test_argument_errors_return_before_any_device_call(lib):
     vp, u64, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int
     lib.vqs_sort_ex.argtypes = [vp, u64, i32, i32, vp, vp]
-    assert lib.vqs_sort_ex(None, 10, 9, 1, None, None) == -2      # unknown key type
+    assert lib.vqs_sort_ex(None, 10, 11, 1, None, None) == -2     # unknown key type
     assert lib.vqs_sort_ex(None, 10, 3, 2, None, None) == -1      # ascending not 0/1
     assert lib.vqs_sort_ex(None, 0, 3, 1, None, None) == 0        # nothing to sort
     assert lib.vqs_sort_ex(None, 10, 3, 1, None, None) == -1      # null keys
@@ -115,7 +115,7 @@ def test_noalloc_argument_errors_return_before_any_device_call(lib):
     from paper_2205_05982_amd import vqs
     vp, u64, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int
     lib.vqs_sort_noalloc.argtypes = [vp, u64, i32, i32, ctypes.POINTER(vqs.Options), vp]
-    assert lib.vqs_sort_noalloc(None, 10, 9, 1, None, None) == -2      # unknown key type
+    assert lib.vqs_sort_noalloc(None, 10, 11, 1, None, None) == -2     # unknown key type
     assert lib.vqs_sort_noalloc(None, 10, 3, 2, None, None) == -1      # ascending not 0/1
     assert lib.vqs_sort_noalloc(None, 0, 3, 1, None, None) == 0        # nothing to sort
     assert lib.vqs_sort_noalloc(None, 10, 3, 1, None, None) == -1      # null keys
@@ -126,3 +126,24 @@ def test_noalloc_argument_errors_return_before_any_device_call(lib):
     assert lib.vqs_sort_noalloc(ctypes.c_void_p(0x1000), 10, 3, 1, ctypes.byref(graph), None) == -1
     lib.vqs_strerror.restype = ctypes.c_char_p
     assert b"vqs_sort_noalloc" in lib.vqs_strerror(-7)
+
+
+def test_stable_and_new_key_types_argument_errors(lib):
+    """vqs_sort_stable rejects 128-bit key types and bad arguments before any device
+    call; the signed and key+data types are known to every entry point."""
+    vp, u64, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int
+    lib.vqs_sort_stable.argtypes = [vp, u64, i32, i32, vp, vp, vp]
+    assert lib.vqs_sort_stable(None, 10, 4, 1, None, None, None) == -2     # u128
+    assert lib.vqs_sort_stable(None, 10, 10, 1, None, None, None) == -2    # k64v64
+    assert lib.vqs_sort_stable(None, 10, 11, 1, None, None, None) == -2    # unknown
+    assert lib.vqs_sort_stable(None, 10, 8, 2, None, None, None) == -1     # ascending not 0/1
+    assert lib.vqs_sort_stable(None, 0, 8, 1, None, None, None) == 0
+    assert lib.vqs_sort_stable(ctypes.c_void_p(0x1000), 10, 8, 1, ctypes.c_void_p(0x1004), None, None) == -1
+    lib.vqs_sort_ex.argtypes = [vp, u64, i32, i32, vp, vp]
+    for kt in (7, 8, 9, 10):
+        assert lib.vqs_sort_ex(None, 10, kt, 1, None, None) == -1          # known type, null keys
+    assert lib.vqs_sort_ex(ctypes.c_void_p(0x1008), 10, 10, 1, None, None) == -1   # k64v64 needs 16-byte alignment
+    lib.vqs_workspace_bytes.restype = ctypes.c_uint64
+    lib.vqs_workspace_bytes.argtypes = [u64, u64, i32, vp]
+    assert lib.vqs_workspace_bytes(1000, 1, 9, None) == lib.vqs_workspace_bytes(1000, 1, 3, None)
+    assert lib.vqs_workspace_bytes(1000, 1, 10, None) == lib.vqs_workspace_bytes(1000, 1, 4, None)
