@@ -9,7 +9,9 @@ timed region starts and nothing but sorting is timed.  Prints one JSON line.
 
 The line also carries "learned_vs_plain": the 5e8-key lognormal-mixture workload
 sorted by both methods (median of a few sorts each), the speedup of the learned
-256-bucket splitter and whether both outputs are identical.
+256-bucket splitter and whether both outputs are identical; and "batched": the
+65,536-segment u32 batch sorted by one hipGraph replay (library defaults and the
+autotuner's choice) against one vqs_sort call per segment.
 
 Roofline: the dominant kernel is the device-wide partition (level kernel).  Its
 algorithmic traffic per launch is 2 * keys * key_size bytes (each key of the level
@@ -77,12 +79,16 @@ def parse():
     ap.add_argument("--learned-reps", type=int, default=3)
     ap.add_argument("--per-array", action="store_true",
                     help="batched workloads: also time one vqs_sort call per segment")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 65,536-segment batch record of the default line")
     return ap.parse_args()
 
 
 def bench_batched(args, kt: int, desc: str) -> None:
     """The 65,536-segment batch: keys generated on the GPU (SplitMix64 by index), the
-    whole batch sorted by one vqs_sort_segmented call captured in a hipGraph."""
+    autotuner's settings chosen on a prefix of about 2e8 keys, then the whole batch
+    sorted by one vqs_sort_segmented call replaying a hipGraph (total key count
+    given, so a replay never waits on the host)."""
     import torch
     from paper_2205_05982_amd import vqs
     from paper_2205_05982_amd import workloads as W
@@ -94,13 +100,17 @@ def bench_batched(args, kt: int, desc: str) -> None:
     work = torch.empty_like(src)
     o = torch.from_numpy(off).to(dev)
     stream = torch.cuda.current_stream()
+    work.copy_(src)
+    tuned = vqs.autotune_segmented(work, o, key_type=kt, max_keys=200_000_000)
+    settings = {k: tuned[k] for k in vqs.TUNED_FIELDS}
+    print(f"# tuned on a prefix: {settings}", file=sys.stderr, flush=True)
     times = []
     for r in range(args.warmup + args.steps):
         work.copy_(src)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        vqs.sort_segmented(work, o, key_type=kt, use_graph=1)
+        vqs.sort_segmented(work, o, key_type=kt, use_graph=1, total_keys=n, **settings)
         e1.record(stream)
         torch.cuda.synchronize()
         if vqs.last_error_bits():
@@ -125,10 +135,83 @@ def bench_batched(args, kt: int, desc: str) -> None:
         "metric": METRIC, "value": round(n / ms / 1e6, 4), "unit": "Gkeys/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": {2: "u32", 3: "u64"}[kt], "data": "synthetic",
-        "config": {"workload": desc, "n": n, "segments": 65536, "method": "plain, one hipGraph", "key_bytes": ks},
+        "config": {"workload": desc, "n": n, "segments": 65536, "method": "plain, one hipGraph", "key_bytes": ks,
+                   "tuned": settings},
         "per_array_calls": per_array,
     }
     print(json.dumps(line), flush=True)
+
+
+def batched_record(reps: int = 3, tune_keys: int = 200_000_000) -> dict:
+    """The 65,536-segment u32 batch (lengths log-uniform in [16, 2^20], 6.1e9 keys):
+    the autotuner's choice on a prefix of about tune_keys keys, then the whole batch
+    sorted by one hipGraph replay (total key count given, so a replay never waits on
+    the host) with the library defaults and with the tuned settings, median of reps
+    each, against one vqs_sort call per segment (once)."""
+    import torch
+    from paper_2205_05982_amd import vqs
+    from paper_2205_05982_amd import workloads as W
+    off = W.segment_offsets(65536, 12)
+    n = int(off[-1])
+    dev = torch.device("cuda", 0)
+    src = W.counter_torch(13, 0, n, 32, dev)
+    work = torch.empty_like(src)
+    o = torch.from_numpy(off).to(dev)
+    stream = torch.cuda.current_stream()
+    work.copy_(src)
+    t0 = time.time()
+    tuned = vqs.autotune_segmented(work, o, key_type=2, max_keys=tune_keys)
+    tune_s = time.time() - t0
+    settings = {k: tuned[k] for k in vqs.TUNED_FIELDS}
+
+    def timed(opts):
+        ts = []
+        for r in range(reps + 1):             # the first call captures the graph
+            work.copy_(src)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            vqs.sort_segmented(work, o, key_type=2, use_graph=1, total_keys=n, **opts)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            if vqs.last_error_bits():
+                raise RuntimeError(f"device error bits {vqs.last_error_bits():#x}")
+            if r:
+                ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    ms_default = timed({})
+    ms_tuned = timed(settings)
+    # the last output: every segment non-decreasing, same multiset
+    a = work.view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+    bad = a[1:] < a[:-1]
+    bad[o[1:-1] - 1] = False
+    ok = not bool(bad.any().item())
+    b = src.view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+    ok = ok and bool((a.sum() == b.sum()).item())
+    del a, b, bad
+    work.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(65536):
+        vqs.sort(work[int(off[i]):int(off[i + 1])], key_type=2)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_per_array = e0.elapsed_time(e1)
+    best = min(ms_default, ms_tuned)
+    gbs = lambda ms: round(n * 4 / (ms * 1e-3) / 1e9, 1)
+    del src, work
+    torch.cuda.empty_cache()
+    return {
+        "workload": "65,536 u32 segments, lengths log-uniform [16, 2^20] (seed 12), keys seed 13",
+        "n": n, "segments": 65536,
+        "graph_ms_default": round(ms_default, 2), "graph_ms_tuned": round(ms_tuned, 2),
+        "tuned": settings, "tune_prefix_keys": tune_keys, "tune_s": round(tune_s, 1),
+        "gkeys": round(n / best / 1e6, 2), "gbs": gbs(best),
+        "per_array_ms": round(ms_per_array, 1), "per_array_gbs": gbs(ms_per_array),
+        "speedup_vs_per_array": round(ms_per_array / best, 1), "sorted": ok,
+    }
 
 
 def learned_vs_plain(n: int, reps: int) -> dict:
@@ -428,6 +511,7 @@ def main():
     del bufs, out
     torch.cuda.empty_cache()
     lvp = learned_vs_plain(args.learned_n, args.learned_reps) if args.learned_n else None
+    batched = None if args.no_batched else batched_record()
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(host, kt, min(args.cpu_sample, n))
 
@@ -472,6 +556,7 @@ def main():
                                        "levels", "solo_items", "hbm_read_keys", "hbm_write_keys")},
         "cpu_baseline": cpu,
         "learned_vs_plain": lvp,
+        "batched": batched,
     }
     print(json.dumps(line), flush=True)
 

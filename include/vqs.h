@@ -161,7 +161,10 @@ typedef struct vqs_options {
                                    0: 2*floor(log2 len)+4 of the range;
                                    VQS_FALLBACK_LIMIT_ZERO: 0, so such a range goes
                                    straight to the bounded-time sort */
-    uint32_t reserved;
+    uint32_t tile_variant;      /* level partition tile size: 0 the default per key width
+                                   (16 KB u16, 32 KB u32, 40 KB u64, 32 KB u128), 1 half
+                                   of it (for batches of many short ranges); other values:
+                                   VQS_EINVAL */
     uint64_t total_keys;        /* segmented sorts: offsets[nseg], if the caller knows it
                                    (then it is not read from the device); 0: read it */
     void* workspace;            /* optional caller-owned device workspace (256-byte
@@ -279,11 +282,12 @@ int vqs_sort_noalloc(void* keys, uint64_t n, int key_type, int ascending, const 
  * of the run-time tunables -- solo_max (ranges up to this many keys are finished by
  * one workgroup each, longer ones are partitioned by the device-wide level kernel) in
  * {0 = the library's size rule, 2^14, 2^16, 2^18, 2^20}, local_keys (size of the
- * in-LDS sort) in {full buffer, half}, base_case in {256, 128}, and level_mode in
- * {LOOKBACK, RUNS} -- on a copy of the segments (all of them when max_keys is 0, else
- * the longest prefix with at most max_keys keys, at least one segment), best of two
- * timed runs after a warm-up each, and writes the fastest combination into
- * options->solo_max, local_keys, base_case and level_mode (the other fields are kept
+ * in-LDS sort) in {full buffer, half}, base_case in {256, 128}, level_mode in
+ * {LOOKBACK, RUNS} and tile_variant (compiled level tile sizes) in {0, 1} -- on a copy
+ * of the segments (all of them when max_keys is 0, else the longest prefix with at
+ * most max_keys keys, at least one segment), best of two timed runs after a warm-up
+ * each, and writes the fastest combination into options->solo_max, local_keys,
+ * base_case, level_mode and tile_variant (the other fields are kept
  * and used for the runs; method is plain).  keys and offsets are device pointers as
  * for vqs_sort_segmented; the caller's keys are not modified.  Allocates the copy
  * (hipMalloc, freed before return) and synchronises the stream.  *best_ms (if not

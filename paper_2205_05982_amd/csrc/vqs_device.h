@@ -134,6 +134,10 @@ struct Key<64> {
   __device__ static R from_u64x2(uint64_t lo, uint64_t) { return lo; }
 };
 
+// A key width together with the level kernels' tile size: LI 16-byte chunks per thread.
+template <int BITS, int LI_>
+struct KeyL;
+
 // 128-bit keys: two 64-bit words, low word first in memory; compared as (hi, lo)
 // lexicographically (Sec. 2.4, Alg. 2).
 template <>
@@ -173,6 +177,11 @@ struct Key<128> {
   __device__ static R from_u64x2(uint64_t lo, uint64_t hi) { return R{lo, hi}; }
 };
 
+template <int BITS, int LI_>
+struct KeyL : Key<BITS> {
+  static constexpr int LI = LI_;
+};
+
 // ---- wave utilities ---------------------------------------------------------------
 
 __device__ inline int lane_id() { return __lane_id(); }
@@ -196,7 +205,8 @@ __device__ inline uint32_t xor_lanes32(uint32_t v) {
   if constexpr (M == 3) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x1B, 0xF, 0xF, true);
   if constexpr (M == 7) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, true);
   if constexpr (M == 15) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xF, 0xF, true);
-  if constexpr (M == 4) return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x101F);
+  // xor 4 = xor 7 (row_half_mirror) then xor 3 (quad_perm): two DPP moves, no LDS trip
+  if constexpr (M == 4) return xor_lanes32<3>(xor_lanes32<7>(v));
   return v;
 }
 

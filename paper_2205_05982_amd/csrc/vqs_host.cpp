@@ -47,11 +47,12 @@ struct GraphKey {
   int64_t depth_limit, fb_limit;
   uint32_t nb, local;
   uint64_t solo;
-  int run_mode;
+  int run_mode, tile;
   bool operator<(const GraphKey& o) const {
     return std::tie(ws_base, keys, offsets, nseg, n, kt, asc, seed, depth_limit, fb_limit, nb, local, solo,
-                    run_mode) < std::tie(o.ws_base, o.keys, o.offsets, o.nseg, o.n, o.kt, o.asc, o.seed,
-                                         o.depth_limit, o.fb_limit, o.nb, o.local, o.solo, o.run_mode);
+                    run_mode, tile) < std::tie(o.ws_base, o.keys, o.offsets, o.nseg, o.n, o.kt, o.asc, o.seed,
+                                               o.depth_limit, o.fb_limit, o.nb, o.local, o.solo, o.run_mode,
+                                               o.tile);
   }
 };
 
@@ -172,12 +173,16 @@ int key_bits(int kt) {
   }
 }
 
-uint64_t level_tile_keys(int bits) {
+uint64_t level_tile_keys(int bits, int tile) {
   switch (bits) {
-    case 16: return Launch<16>::level_tile_keys();
-    case 32: return Launch<32>::level_tile_keys();
-    case 64: return Launch<64>::level_tile_keys();
-    default: return Launch<128>::level_tile_keys();
+    case 16: return tile ? LaunchLevel<16, level_chunks_half(16)>::level_tile_keys()
+                         : LaunchLevel<16, level_chunks(16)>::level_tile_keys();
+    case 32: return tile ? LaunchLevel<32, level_chunks_half(32)>::level_tile_keys()
+                         : LaunchLevel<32, level_chunks(32)>::level_tile_keys();
+    case 64: return tile ? LaunchLevel<64, level_chunks_half(64)>::level_tile_keys()
+                         : LaunchLevel<64, level_chunks(64)>::level_tile_keys();
+    default: return tile ? LaunchLevel<128, level_chunks_half(128)>::level_tile_keys()
+                         : LaunchLevel<128, level_chunks(128)>::level_tile_keys();
   }
 }
 
@@ -218,6 +223,7 @@ struct Plan {
   int64_t depth_limit;  // < 0: default per range, else this limit for every range
   int64_t fb_limit;     // < 0: default per range, else the fallback mode's own limit
   int run_mode;         // level partitions write tile-local runs
+  int tile;             // level tile size: 0 default, 1 half
 };
 
 int make_plan(uint64_t n, uint64_t nseg, int kt, int asc, const vqs_options* o, const Geometry& g, Plan* pl) {
@@ -282,7 +288,9 @@ int make_plan(uint64_t n, uint64_t nseg, int kt, int asc, const vqs_options* o, 
   // (one more: in run mode a range leaving for the solo list is gathered by a copy
   // entry of the next level)
   pl->max_levels = (int)lim + (int)fb_lim + 5;
-  const uint64_t T = level_tile_keys(bits);
+  pl->tile = VQS_HAS(o, tile_variant) ? (int)o->tile_variant : 0;
+  if (pl->tile < 0 || pl->tile > 1) return VQS_EINVAL;
+  const uint64_t T = level_tile_keys(bits, pl->tile);
   // a level holds at most n / (solo + 1) ranges longer than solo, and up to twice as
   // many copy entries
   pl->cap_lvl = 3 * (n / (pl->solo + 1)) + 4;
@@ -435,13 +443,13 @@ int level_batch(const Plan& pl) {
   return batch;
 }
 
-template <int B>
+template <int B, int LI>
 hipError_t launch_all(Workspace* ws, const Params& base, const Plan& pl, const Geometry& g,
                       const int64_t* offsets, uint64_t nseg, bool capture, int* levels_out) {
   hipStream_t s = ws->stream;
   hipError_t e = ws->timed(0, -1, [&] { return Launch<B>::clear(base, s); });
   if (e != hipSuccess) return e;
-  e = ws->timed(1, -1, [&] { return Launch<B>::seed(base, offsets, nseg, s); });
+  e = ws->timed(1, -1, [&] { return LaunchLevel<B, LI>::seed(base, offsets, nseg, s); });
   if (e != hipSuccess) return e;
   // the level loop: launch levels in batches, then read the next level's counter
   int L = base.seed_level;
@@ -452,9 +460,9 @@ hipError_t launch_all(Workspace* ws, const Params& base, const Plan& pl, const G
     auto step = [&](int lv, bool part) -> hipError_t {
       Params p = base;
       p.level = lv;
-      hipError_t e2 = ws->timed(8, lv, [&] { return Launch<B>::plan(p, g.plan_grid, s); });
+      hipError_t e2 = ws->timed(8, lv, [&] { return LaunchLevel<B, LI>::plan(p, g.plan_grid, s); });
       if (e2 != hipSuccess || !part) return e2;
-      return ws->timed(2, lv, [&] { return Launch<B>::level(p, g.level_grid, s); });
+      return ws->timed(2, lv, [&] { return LaunchLevel<B, LI>::level(p, g.level_grid, s); });
     };
     if (capture) {
       for (; L < pl.max_levels - 1; L++) {
@@ -490,9 +498,9 @@ hipError_t launch_all(Workspace* ws, const Params& base, const Plan& pl, const G
       for (; L < pl.max_levels - 1; L++) {
         Params p = base;
         p.level = L;
-        e = ws->timed(8, L, [&] { return Launch<B>::pivots(p, g.pivot_grid, s); });
+        e = ws->timed(8, L, [&] { return LaunchLevel<B, LI>::pivots(p, g.pivot_grid, s); });
         if (e != hipSuccess) return e;
-        e = ws->timed(2, L, [&] { return Launch<B>::level(p, g.level_grid, s); });
+        e = ws->timed(2, L, [&] { return LaunchLevel<B, LI>::level(p, g.level_grid, s); });
         if (e != hipSuccess) return e;
       }
     } else {
@@ -502,9 +510,9 @@ hipError_t launch_all(Workspace* ws, const Params& base, const Plan& pl, const G
         for (; L < upto; L++) {
           Params p = base;
           p.level = L;
-          e = ws->timed(8, L, [&] { return Launch<B>::pivots(p, g.pivot_grid, s); });
+          e = ws->timed(8, L, [&] { return LaunchLevel<B, LI>::pivots(p, g.pivot_grid, s); });
           if (e != hipSuccess) return e;
-          e = ws->timed(2, L, [&] { return Launch<B>::level(p, g.level_grid, s); });
+          e = ws->timed(2, L, [&] { return LaunchLevel<B, LI>::level(p, g.level_grid, s); });
           if (e != hipSuccess) return e;
         }
         if (L >= pl.max_levels - 1) break;
@@ -523,12 +531,16 @@ hipError_t launch_all(Workspace* ws, const Params& base, const Plan& pl, const G
 
 hipError_t dispatch_launch(Workspace* ws, const Params& base, const Plan& pl, const Geometry& g,
                            const int64_t* offsets, uint64_t nseg, bool capture, int* levels) {
+#define VQS_LAUNCH_ALL(B)                                                                              \
+  return pl.tile ? launch_all<B, level_chunks_half(B)>(ws, base, pl, g, offsets, nseg, capture, levels) \
+                 : launch_all<B, level_chunks(B)>(ws, base, pl, g, offsets, nseg, capture, levels)
   switch (pl.bits) {
-    case 16: return launch_all<16>(ws, base, pl, g, offsets, nseg, capture, levels);
-    case 32: return launch_all<32>(ws, base, pl, g, offsets, nseg, capture, levels);
-    case 64: return launch_all<64>(ws, base, pl, g, offsets, nseg, capture, levels);
-    default: return launch_all<128>(ws, base, pl, g, offsets, nseg, capture, levels);
+    case 16: VQS_LAUNCH_ALL(16);
+    case 32: VQS_LAUNCH_ALL(32);
+    case 64: VQS_LAUNCH_ALL(64);
+    default: VQS_LAUNCH_ALL(128);
   }
+#undef VQS_LAUNCH_ALL
 }
 
 int check_offsets_host(const int64_t* offsets, uint64_t nseg, uint64_t* total, hipStream_t s) {
@@ -610,7 +622,7 @@ int sort_locked(Workspace* ws, void* keys, const int64_t* offsets, uint64_t nseg
   const bool use_graph = o && o->use_graph && offsets;
   if (use_graph) {
     GraphKey gk{base.stats, keys, offsets, nseg, n, kt, asc, pl.seed, pl.depth_limit, pl.fb_limit, pl.nb, pl.local,
-                pl.solo, pl.run_mode};
+                pl.solo, pl.run_mode, pl.tile};
     if (!(ws->graph_valid && !(gk < ws->graph_key) && !(ws->graph_key < gk))) {
       if (ws->graph) {
         (void)hipGraphExecDestroy(ws->graph);
@@ -1056,6 +1068,7 @@ int vqs_autotune_segmented(const void* keys, const int64_t* offsets, uint64_t ns
   const uint32_t locals[] = {full, full / 2};
   const uint32_t bases[] = {256, 128};
   const uint32_t modes[] = {VQS_LEVEL_LOOKBACK, VQS_LEVEL_RUNS};
+  const uint32_t tiles[] = {0, 1};
   float best = -1.0f;
   vqs_options base{};
   std::memcpy(&base, options, sizeof(vqs_options));
@@ -1066,13 +1079,15 @@ int vqs_autotune_segmented(const void* keys, const int64_t* offsets, uint64_t ns
   for (uint64_t sm : solos)
     for (uint32_t lk : locals)
       for (uint32_t nb : bases)
-        for (uint32_t lm : modes) {
+        for (uint32_t lm : modes)
+          for (uint32_t tv : tiles) {
           if (rc != VQS_OK) break;
           vqs_options c = base;
           c.solo_max = sm;
           c.local_keys = lk;
           c.base_case = nb;
           c.level_mode = lm;
+          c.tile_variant = tv;
           float t_min = -1.0f;
           for (int rep = 0; rep < 3 && rc == VQS_OK; rep++) {   // the first run warms up
             if (hipMemcpyAsync(tk, src, sub * ks, hipMemcpyDeviceToDevice, s) != hipSuccess ||
@@ -1109,6 +1124,7 @@ int vqs_autotune_segmented(const void* keys, const int64_t* offsets, uint64_t ns
   options->local_keys = chosen.local_keys;
   options->base_case = chosen.base_case;
   options->level_mode = chosen.level_mode;
+  options->tile_variant = chosen.tile_variant;
   if (best_ms) *best_ms = best;
   return VQS_OK;
 }

@@ -471,7 +471,7 @@ template <class K>
 __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(sizeof(typename K::R) >= 8 ? LEVEL_WAVES : 1))) level_kernel(Params p) {
   using R = typename K::R;
   using S = typename K::S;
-  constexpr int I = level_chunks(8 * K::SIZE);
+  constexpr int I = K::LI;
   using TL = Tile<K, LEVEL_P, I>;
   constexpr int T = TL::T;
   __shared__ S stage[T];
@@ -813,7 +813,7 @@ template <class K>
 __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(sizeof(typename K::R) >= 8 ? LEVEL_WAVES : 1))) level_runs_kernel(Params p) {
   using R = typename K::R;
   using S = typename K::S;
-  constexpr int I = level_chunks(8 * K::SIZE);
+  constexpr int I = K::LI;
   using TL = Tile<K, LEVEL_P, I>;
   constexpr int T = TL::T;
   constexpr int TC = TL::TC;
@@ -1132,7 +1132,7 @@ template <class K, int G>
 __device__ PlanState plan_first(const Params& p, int L, const Seg& sg, uint64_t g0, uint64_t nt, PlanShared<K>& sm,
                                 int gt) {
   using R = typename K::R;
-  constexpr int I = level_chunks(8 * K::SIZE);
+  constexpr int I = K::LI;
   constexpr int T = Tile<K, LEVEL_P, I>::T;
   const TileRun* tab = p.runs[(L - 1) & 1];
   const bool dst_scratch = ((L - 1) & 1) == 0;   // where level L-1 wrote
@@ -1232,7 +1232,7 @@ __device__ void plan_second(const Params& p, int L, const Seg& sg, uint64_t g0, 
                             int gt, const PlanState& st, const PlanSlots& sl_, PlanCounts& pc) {
   using R = typename K::R;
   using S = typename K::S;
-  constexpr int I = level_chunks(8 * K::SIZE);
+  constexpr int I = K::LI;
   constexpr int T = Tile<K, LEVEL_P, I>::T;
   constexpr int W = PlanShared<K>::W;
   TileRun* tab = p.runs[(L - 1) & 1];
@@ -1530,7 +1530,7 @@ template <class K>
 __global__ void __launch_bounds__(LEVEL_P) runs_plan_kernel(Params p) {
   using R = typename K::R;
   using S = typename K::S;
-  constexpr int I = level_chunks(8 * K::SIZE);
+  constexpr int I = K::LI;
   constexpr int T = Tile<K, LEVEL_P, I>::T;
   constexpr int NW = LEVEL_P / WAVE;
   constexpr uint64_t SMALL = 4 * WAVE;   // ranges of at most this many tiles: one wave each
@@ -2687,7 +2687,7 @@ __global__ void clear_kernel(Params p) {
 // Route the input ranges: offsets (nseg + 1 entries), or [0, n) when offsets is null.
 template <class K>
 __global__ void seed_kernel(Params p, const int64_t* offsets, uint64_t nseg) {
-  using TL = Tile<K, LEVEL_P, level_chunks(8 * K::SIZE)>;
+  using TL = Tile<K, LEVEL_P, K::LI>;
   const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = gid; i < nseg; i += stride) {

@@ -1,0 +1,5 @@
+// Kernel instantiations for 128-bit keys: the level kernels with half-size tiles.
+#define VQS_BITS 128
+#define VQS_LI level_chunks_half(128)
+#define VQS_WITH_SOLO 0
+#include "vqs_instantiate.inc"

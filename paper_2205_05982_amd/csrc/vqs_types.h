@@ -21,11 +21,10 @@ constexpr int LEVEL_NW = LEVEL_P / 64;  // its waves
 // 16-byte chunks per thread of a level tile, by key width (measured): 16 KB tiles for
 // u16 (its keys take one register each), 32 KB for u32, 40 KB for u64, 32 KB for u128
 // (three or four workgroups per CU)
-#ifdef VQS_LEVEL_I
-constexpr int level_chunks(int) { return VQS_LEVEL_I; }
-#else
 constexpr int level_chunks(int bits) { return bits == 16 ? 4 : bits == 32 ? 8 : bits == 64 ? 10 : 8; }
-#endif
+// the second compiled tile size (vqs_options.tile_variant = 1): half the chunks, for
+// batches of many short ranges whose last, partial tiles would otherwise dominate
+constexpr int level_chunks_half(int bits) { return level_chunks(bits) / 2; }
 #ifndef VQS_SOLO_P
 #define VQS_SOLO_P 512
 #endif

@@ -46,7 +46,7 @@ class Options(ctypes.Structure):
                 ("overflow_factor", ctypes.c_float), ("learning_rate", ctypes.c_float),
                 ("model_seed", ctypes.c_uint64), ("sample_seed", ctypes.c_uint64),
                 ("level_mode", ctypes.c_uint32), ("fallback_limit", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32), ("total_keys", ctypes.c_uint64),
+                ("tile_variant", ctypes.c_uint32), ("total_keys", ctypes.c_uint64),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64)]
 
 
@@ -208,7 +208,7 @@ def sort_segmented(t: torch.Tensor, offsets: torch.Tensor, ascending: bool = Tru
     return t
 
 
-TUNED_FIELDS = ("solo_max", "local_keys", "base_case", "level_mode")
+TUNED_FIELDS = ("solo_max", "local_keys", "base_case", "level_mode", "tile_variant")
 
 
 def autotune_segmented(t: torch.Tensor, offsets: torch.Tensor, ascending: bool = True,

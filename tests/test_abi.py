@@ -82,6 +82,7 @@ def test_options_layout_matches_binding():
     assert vqs.Options.train_steps.offset == 48
     assert vqs.Options.level_mode.offset == 88
     assert vqs.Options.total_keys.offset == 104
+    assert vqs.Options.tile_variant.offset == 96
     assert vqs.Options.workspace_bytes.offset == 120
     assert ctypes.sizeof(vqs.Stats) == 20 * 8
 

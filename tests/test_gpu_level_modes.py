@@ -257,3 +257,47 @@ def test_foreseen_degenerate_unaligned_view(vqs, mode, shift, asc):
         np.testing.assert_array_equal(got[:shift], base[:shift])
         np.testing.assert_array_equal(got[shift + n:], base[shift + n:])
         assert_stats_equal(ost, vqs.get_stats())
+
+
+# ---- the second compiled tile size ------------------------------------------------------
+
+@pytest.mark.parametrize("mode", list(MODES))
+@pytest.mark.parametrize("kt", [U16, U32, U64, U128, F32, F64])
+@pytest.mark.parametrize("asc", [True, False])
+def test_half_tiles_every_type(vqs, mode, kt, asc):
+    """Level kernels with half-size tiles (vqs_options.tile_variant = 1): the same key
+    sequences, so the same result and counters as the oracle, both placements."""
+    n = 1_300_000 if kt != U128 else 500_000
+    print(f"case: half tiles mode={mode} kt={kt} asc={asc} n={n}", flush=True)
+    gst = _check(vqs, random_keys(kt, n, seed=400 + kt), kt, mode, asc, seed=3, solo_max=20_000, tile_variant=1)
+    assert gst["levels"] >= 3
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+@pytest.mark.parametrize("dist", ["zipf", "8distinct", "m3killer"])
+def test_half_tiles_distributions(vqs, mode, dist):
+    print(f"case: half tiles dist={dist} mode={mode}", flush=True)
+    _check(vqs, W.c2(dist, 800_000), U64, mode, seed=5, solo_max=20_000, tile_variant=1)
+
+
+@pytest.mark.parametrize("use_graph", [0, 1])
+def test_half_tiles_segmented(vqs, use_graph):
+    import torch
+    print(f"case: half tiles segmented graph={use_graph}", flush=True)
+    off = W.segment_offsets(300, seed=41, lo=16, hi=1 << 18)
+    keys = W.segmented_keys(off, U32, 42)
+    want = keys.copy()
+    ost = oracle.sort_segmented(want, off, U32, stats=True)
+    t, o = to_gpu(keys), to_gpu(off)
+    for rep in range(2):
+        t.copy_(to_gpu(keys))
+        torch.cuda.synchronize()
+        vqs.sort_segmented(t, o, key_type=U32, use_graph=use_graph, tile_variant=1, solo_max=16_384,
+                           total_keys=int(off[-1]))
+        torch.cuda.synchronize()
+        assert vqs.last_error_bits() == 0
+        np.testing.assert_array_equal(to_host(t), want)
+    if not use_graph:
+        assert_stats_equal(ost, vqs.get_stats())
+    with pytest.raises(Exception):
+        vqs.sort(t, key_type=U32, tile_variant=2)

@@ -176,6 +176,7 @@ def test_autotune_segmented(vqs, tmp_path):
     assert res["base_case"] in (128, 256)
     assert res["local_keys"] in (8192, 4096)
     assert res["level_mode"] in (1, 2)
+    assert res["tile_variant"] in (0, 1)
     assert res["best_ms"] > 0
     np.testing.assert_array_equal(to_host(t), keys)          # untouched
     tuned = {k: res[k] for k in vqs.TUNED_FIELDS}
