@@ -78,6 +78,11 @@ def lib():
         L.vqo_sort_segmented.argtypes = [vp, vp, u64, i32, i32, u64, u64, i64, ctypes.POINTER(Stats)]
         L.vqo_sort.argtypes = [vp, u64, i32, i32, u64, u64, i64, ctypes.POINTER(Stats)]
         L.vqo_choose_pivot.argtypes = [vp, u64, u64, i32, i32, u64, vp]
+        L.vqo_choose_pivot_rng.argtypes = [vp, u64, u64, i32, i32, u64, i32, vp, vp]
+        L.vqo_sort_segmented_rng.argtypes = [vp, vp, u64, i32, i32, u64, i32, vp, u64, i64, ctypes.POINTER(Stats)]
+        L.vqo_chacha20_block.argtypes = [vp, ctypes.c_uint32, vp, vp]
+        L.vqo_chacha20_quarter_round.argtypes = [vp]
+        L.vqo_pivot_offsets_rng.argtypes = [u64, i32, vp, u64, u64, u64, vp]
         L.vqo_partition.argtypes = [vp, u64, u64, i32, i32, vp]
         L.vqo_partition.restype = i64
         L.vqo_minmax.argtypes = [vp, u64, u64, i32, i32, vp, vp]
@@ -127,34 +132,55 @@ def nkeys(keys: np.ndarray, kt: int) -> int:
     return keys.shape[0] if kt in PAIR_TYPES else keys.size
 
 
+def _key_words(key):
+    """A 256-bit ChaCha20 key as eight little-endian 32-bit words (or None)."""
+    if key is None:
+        return None
+    k = np.ascontiguousarray(np.asarray(key, dtype=np.uint32).reshape(-1))
+    if k.size != 8:
+        raise ValueError("the ChaCha20 key is eight 32-bit words")
+    return k
+
+
 def sort(keys: np.ndarray, kt: int, ascending: bool = True, seed: int = 0,
-         nb: int = NB_DEFAULT, depth_limit: int = -1, stats: bool = False):
-    """Sort keys in place with the paper's method; returns stats if asked."""
+         nb: int = NB_DEFAULT, depth_limit: int = -1, stats: bool = False, rng_key=None):
+    """Sort keys in place with the paper's method; returns stats if asked.  With
+    rng_key (eight 32-bit words) the pivot sampler draws from ChaCha20 under that key
+    (the secure generator option of Sec. 2.2) instead of SFC64 from the seed."""
     _check_keys(keys, kt)
     st = Stats()
-    rc = lib().vqo_sort(_ptr(keys), nkeys(keys, kt), kt, int(bool(ascending)), seed, nb,
-                        depth_limit, ctypes.byref(st))
+    k = _key_words(rng_key)
+    offs = np.array([0, nkeys(keys, kt)], dtype=np.int64)
+    rc = lib().vqo_sort_segmented_rng(_ptr(keys), _ptr(offs), 1, kt, int(bool(ascending)), seed,
+                                      1 if k is not None else 0, _ptr(k) if k is not None else None, nb,
+                                      depth_limit, ctypes.byref(st))
     if rc != 0:
         raise RuntimeError(f"vqo_sort failed: {rc}")
     return st.as_dict() if stats else None
 
 
 def sort_segmented(keys: np.ndarray, offsets: np.ndarray, kt: int, ascending: bool = True,
-                   seed: int = 0, nb: int = NB_DEFAULT, depth_limit: int = -1, stats: bool = False):
+                   seed: int = 0, nb: int = NB_DEFAULT, depth_limit: int = -1, stats: bool = False,
+                   rng_key=None):
     _check_keys(keys, kt)
     offsets = np.ascontiguousarray(offsets, dtype=np.int64)
     st = Stats()
-    rc = lib().vqo_sort_segmented(_ptr(keys), _ptr(offsets), offsets.size - 1, kt,
-                                  int(bool(ascending)), seed, nb, depth_limit, ctypes.byref(st))
+    k = _key_words(rng_key)
+    rc = lib().vqo_sort_segmented_rng(_ptr(keys), _ptr(offsets), offsets.size - 1, kt,
+                                      int(bool(ascending)), seed, 1 if k is not None else 0,
+                                      _ptr(k) if k is not None else None, nb, depth_limit, ctypes.byref(st))
     if rc != 0:
         raise RuntimeError(f"vqo_sort_segmented failed: {rc}")
     return st.as_dict() if stats else None
 
 
-def choose_pivot(keys: np.ndarray, b: int, e: int, kt: int, ascending: bool = True, seed: int = 0):
+def choose_pivot(keys: np.ndarray, b: int, e: int, kt: int, ascending: bool = True, seed: int = 0,
+                 rng_key=None):
     _check_keys(keys, kt)
     out = np.zeros(2 if kt in PAIR_TYPES else 1, dtype=_DTYPES[kt])
-    rc = lib().vqo_choose_pivot(_ptr(keys), b, e, kt, int(bool(ascending)), seed, _ptr(out))
+    k = _key_words(rng_key)
+    rc = lib().vqo_choose_pivot_rng(_ptr(keys), b, e, kt, int(bool(ascending)), seed, 1 if k is not None else 0,
+                                    _ptr(k) if k is not None else None, _ptr(out))
     if rc != 0:
         raise RuntimeError(f"vqo_choose_pivot failed: {rc}")
     return out if kt in PAIR_TYPES else out[0]
@@ -238,10 +264,27 @@ def multiply_shift(u: int, rng: int) -> int:
     return int(lib().vqo_multiply_shift(u, rng))
 
 
-def pivot_offsets(seed: int, b: int, e: int, w: int) -> np.ndarray:
+def pivot_offsets(seed: int, b: int, e: int, w: int, rng_key=None) -> np.ndarray:
     out = np.zeros(9, dtype=np.uint64)
-    lib().vqo_pivot_offsets(seed, b, e, w, _ptr(out))
+    k = _key_words(rng_key)
+    lib().vqo_pivot_offsets_rng(seed, 1 if k is not None else 0, _ptr(k) if k is not None else None, b, e, w,
+                                _ptr(out))
     return out
+
+
+def chacha20_block(key, counter: int, nonce) -> np.ndarray:
+    """The ChaCha20 block function (RFC 8439 Sec. 2.3): sixteen 32-bit output words."""
+    k = _key_words(key)
+    nn = np.ascontiguousarray(np.asarray(nonce, dtype=np.uint32).reshape(3))
+    out = np.zeros(16, dtype=np.uint32)
+    lib().vqo_chacha20_block(_ptr(k), counter, _ptr(nn), _ptr(out))
+    return out
+
+
+def chacha20_quarter_round(a: int, b: int, c: int, d: int):
+    v = np.array([a, b, c, d], dtype=np.uint32)
+    lib().vqo_chacha20_quarter_round(_ptr(v))
+    return tuple(int(x) for x in v)
 
 
 def default_depth_limit(n: int) -> int:

@@ -45,17 +45,12 @@ static KT SFX(med3)(KT x0, KT x1, KT x2, int asc) {
  * medians of three: first whole "vectors" of KW lanes three at a time, then single
  * consecutive triples, dropping the 0..2 leftovers, until fewer than three remain.
  * The first remaining median is the pivot. */
-static KT SFX(choose_pivot)(const KT* keys, uint64_t b, uint64_t e, int asc, uint64_t seed) {
+static KT SFX(choose_pivot)(const KT* keys, uint64_t b, uint64_t e, const vqo_params* p) {
+    const int asc = p->ascending;
     const uint64_t W = KW;
     const uint64_t nchunks = (e - b) / W;      /* whole chunks; the tail is never sampled */
     uint32_t u[10];
-    uint64_t st[4];
-    seg_rng_state(seed, b, e, st);
-    for (int i = 0; i < 5; i++) {             /* five 64-bit draws -> ten 32-bit halves */
-        uint64_t r = sfc64_next(st);
-        u[2 * i] = (uint32_t)r;
-        u[2 * i + 1] = (uint32_t)(r >> 32);
-    }
+    range_draws(p, b, e, u);                   /* five 64-bit draws -> ten 32-bit halves */
     const KT* chunk[9];
     for (int i = 0; i < 9; i++) {
         uint64_t off = multiply_shift_offset(u[i], nchunks);
@@ -182,14 +177,14 @@ static void SFX(recurse)(KT* keys, KT* tmp, uint64_t b, uint64_t e, KT pivot, ui
         SFX(basecase)(keys + b, bound - b, p->ascending);
         st->basecases++;
     } else {
-        KT next = SFX(choose_pivot)(keys, b, bound, p->ascending, p->seed);
+        KT next = SFX(choose_pivot)(keys, b, bound, p);
         SFX(recurse)(keys, tmp, b, bound, next, depth + 1, p, st);
     }
     if (e - bound <= p->nb) {
         SFX(basecase)(keys + bound, e - bound, p->ascending);
         st->basecases++;
     } else {
-        KT next = SFX(choose_pivot)(keys, bound, e, p->ascending, p->seed);
+        KT next = SFX(choose_pivot)(keys, bound, e, p);
         SFX(recurse)(keys, tmp, bound, e, next, depth + 1, p, st);
     }
 }
@@ -204,6 +199,6 @@ static void SFX(sort_range)(KT* keys, KT* tmp, uint64_t b, uint64_t e, const vqo
         return;
     }
     st->depth_limit_used = p->depth_limit >= 0 ? (uint64_t)p->depth_limit : default_depth_limit(n);
-    KT pivot = SFX(choose_pivot)(keys, b, e, p->ascending, p->seed);
+    KT pivot = SFX(choose_pivot)(keys, b, e, p);
     SFX(recurse)(keys, tmp, b, e, pivot, 1, p, st);
 }

@@ -66,6 +66,8 @@ typedef struct {
     uint64_t seed;
     uint64_t nb;           /* NBaseCase: ranges of at most nb keys go to BaseCase */
     int64_t depth_limit;   /* < 0: 2*floor(log2 n)+4 */
+    int rng;               /* 0: SFC64 from the seed; 1: ChaCha20 under key (the secure option) */
+    uint32_t key[8];
 } vqo_params;
 
 /* ---- random numbers (Sec. 2.2) ---------------------------------------------- */
@@ -120,17 +122,81 @@ static uint64_t multiply_shift_offset(uint32_t u, uint64_t range) {
 
 uint64_t vqo_multiply_shift(uint32_t u, uint64_t range) { return multiply_shift_offset(u, range); }
 
-/* The nine chunk offsets (in chunks) ChoosePivot uses for [b, e) with w keys per chunk. */
-void vqo_pivot_offsets(uint64_t seed, uint64_t b, uint64_t e, uint64_t w, uint64_t out[9]) {
+/* ChaCha20 (Bernstein; the block function as specified in RFC 8439, Sec. 2.3): a
+ * 4x4 state of 32-bit words -- the constants "expand 32-byte k", the 256-bit key, a
+ * 32-bit block counter, a 96-bit nonce -- run through 20 rounds (10 column rounds
+ * and 10 diagonal rounds of the quarter round), then added to the initial state. */
+static uint32_t rotl32(uint32_t x, int n) { return (x << n) | (x >> (32 - n)); }
+
+static void quarter_round(uint32_t* a, uint32_t* b, uint32_t* c, uint32_t* d) {
+    *a += *b; *d ^= *a; *d = rotl32(*d, 16);
+    *c += *d; *b ^= *c; *b = rotl32(*b, 12);
+    *a += *b; *d ^= *a; *d = rotl32(*d, 8);
+    *c += *d; *b ^= *c; *b = rotl32(*b, 7);
+}
+
+void vqo_chacha20_quarter_round(uint32_t v[4]) { quarter_round(&v[0], &v[1], &v[2], &v[3]); }
+
+void vqo_chacha20_block(const uint32_t key[8], uint32_t counter, const uint32_t nonce[3], uint32_t out[16]) {
+    uint32_t x[16];
+    x[0] = 0x61707865u; x[1] = 0x3320646eu; x[2] = 0x79622d32u; x[3] = 0x6b206574u;
+    for (int i = 0; i < 8; i++) x[4 + i] = key[i];
+    x[12] = counter;
+    x[13] = nonce[0]; x[14] = nonce[1]; x[15] = nonce[2];
+    uint32_t w[16];
+    memcpy(w, x, sizeof(w));
+    for (int r = 0; r < 10; r++) {
+        quarter_round(&w[0], &w[4], &w[8], &w[12]);
+        quarter_round(&w[1], &w[5], &w[9], &w[13]);
+        quarter_round(&w[2], &w[6], &w[10], &w[14]);
+        quarter_round(&w[3], &w[7], &w[11], &w[15]);
+        quarter_round(&w[0], &w[5], &w[10], &w[15]);
+        quarter_round(&w[1], &w[6], &w[11], &w[12]);
+        quarter_round(&w[2], &w[7], &w[8], &w[13]);
+        quarter_round(&w[3], &w[4], &w[9], &w[14]);
+    }
+    for (int i = 0; i < 16; i++) out[i] = w[i] + x[i];
+}
+
+/* The ten 32-bit random values of the range [b, e).  SFC64 (default): the five 64-bit
+ * draws of the range's generator, low half first.  ChaCha20 (Sec. 2.2's secure
+ * generator, which the paper builds from AES rounds): the first ten words of the
+ * block with the caller's key, block counter = the low 32 bits of b, nonce = (the high
+ * 32 bits of b, the low and the high 32 bits of e), so each range draws from its own
+ * block and the draws stay a pure function of (key, b, e). */
+static void range_draws(const vqo_params* p, uint64_t b, uint64_t e, uint32_t u[10]) {
+    if (p->rng == 1) {
+        uint32_t blk[16];
+        const uint32_t nonce[3] = {(uint32_t)(b >> 32), (uint32_t)e, (uint32_t)(e >> 32)};
+        vqo_chacha20_block(p->key, (uint32_t)b, nonce, blk);
+        for (int i = 0; i < 10; i++) u[i] = blk[i];
+        return;
+    }
     uint64_t st[4];
-    uint32_t u[10];
-    seg_rng_state(seed, b, e, st);
+    seg_rng_state(p->seed, b, e, st);
     for (int i = 0; i < 5; i++) {
         uint64_t r = sfc64_next(st);
         u[2 * i] = (uint32_t)r;
         u[2 * i + 1] = (uint32_t)(r >> 32);
     }
+}
+
+/* The nine chunk offsets (in chunks) ChoosePivot uses for [b, e) with w keys per
+ * chunk; rng 0 draws from SFC64 seeded by seed, rng 1 from ChaCha20 under key. */
+void vqo_pivot_offsets_rng(uint64_t seed, int rng, const uint32_t key[8], uint64_t b, uint64_t e, uint64_t w,
+                           uint64_t out[9]) {
+    vqo_params p;
+    memset(&p, 0, sizeof(p));
+    p.seed = seed;
+    p.rng = rng;
+    if (key) memcpy(p.key, key, sizeof(p.key));
+    uint32_t u[10];
+    range_draws(&p, b, e, u);
     for (int i = 0; i < 9; i++) out[i] = multiply_shift_offset(u[i], (e - b) / w);
+}
+
+void vqo_pivot_offsets(uint64_t seed, uint64_t b, uint64_t e, uint64_t w, uint64_t out[9]) {
+    vqo_pivot_offsets_rng(seed, 0, NULL, b, e, w, out);
 }
 
 static uint64_t default_depth_limit(uint64_t n) {
@@ -459,10 +525,19 @@ int vqo_key_size(int kt) { return key_size(kt); }
  * is one segment.  nb must be at least 32 (so every partitioned range holds a whole
  * sampling chunk) and depth_limit < 0 selects the paper's limit.  Stats accumulate
  * over all segments.  Returns 0, or a negative error. */
-int vqo_sort_segmented(void* keys, const int64_t* offsets, uint64_t nseg, int kt, int ascending,
-                       uint64_t seed, uint64_t nb, int64_t depth_limit, vqo_stats* st) {
+int vqo_sort_segmented_rng(void* keys, const int64_t* offsets, uint64_t nseg, int kt, int ascending,
+                           uint64_t seed, int rng, const uint32_t key[8], uint64_t nb, int64_t depth_limit,
+                           vqo_stats* st) {
     if (nb < 32) return -1;
-    vqo_params p = {ascending ? 1 : 0, seed, nb, depth_limit};
+    if (rng != 0 && rng != 1) return -1;
+    vqo_params p;
+    memset(&p, 0, sizeof(p));
+    p.ascending = ascending ? 1 : 0;
+    p.seed = seed;
+    p.nb = nb;
+    p.depth_limit = depth_limit;
+    p.rng = rng;
+    if (key) memcpy(p.key, key, sizeof(p.key));
     vqo_stats local;
     memset(&local, 0, sizeof(local));
     uint64_t maxlen = 0;
@@ -495,6 +570,11 @@ int vqo_sort_segmented(void* keys, const int64_t* offsets, uint64_t nseg, int kt
     return 0;
 }
 
+int vqo_sort_segmented(void* keys, const int64_t* offsets, uint64_t nseg, int kt, int ascending,
+                       uint64_t seed, uint64_t nb, int64_t depth_limit, vqo_stats* st) {
+    return vqo_sort_segmented_rng(keys, offsets, nseg, kt, ascending, seed, 0, NULL, nb, depth_limit, st);
+}
+
 int vqo_sort(void* keys, uint64_t n, int kt, int ascending, uint64_t seed, uint64_t nb,
              int64_t depth_limit, vqo_stats* st) {
     int64_t offs[2] = {0, (int64_t)n};
@@ -502,19 +582,30 @@ int vqo_sort(void* keys, uint64_t n, int kt, int ascending, uint64_t seed, uint6
 }
 
 /* ChoosePivot for the range [b, e) of keys; writes the pivot key to *pivot_out. */
-int vqo_choose_pivot(const void* keys, uint64_t b, uint64_t e, int kt, int ascending, uint64_t seed,
-                     void* pivot_out) {
+int vqo_choose_pivot_rng(const void* keys, uint64_t b, uint64_t e, int kt, int ascending, uint64_t seed,
+                         int rng, const uint32_t key[8], void* pivot_out) {
     const int ks = key_size(kt);
     if (ks == 0) return -2;
     if ((e - b) < (uint64_t)(64 / ks)) return -1;   /* needs one whole chunk */
+    vqo_params prm;
+    memset(&prm, 0, sizeof(prm));
+    prm.ascending = ascending ? 1 : 0;
+    prm.seed = seed;
+    prm.rng = rng;
+    if (key) memcpy(prm.key, key, sizeof(prm.key));
 #define PIV(sfx, T)                                                                 \
     {                                                                               \
-        T p = choose_pivot_##sfx((const T*)keys, b, e, ascending ? 1 : 0, seed);    \
+        T p = choose_pivot_##sfx((const T*)keys, b, e, &prm);                       \
         memcpy(pivot_out, &p, sizeof(T));                                           \
     }
     DISPATCH(kt, PIV)
 #undef PIV
     return 0;
+}
+
+int vqo_choose_pivot(const void* keys, uint64_t b, uint64_t e, int kt, int ascending, uint64_t seed,
+                     void* pivot_out) {
+    return vqo_choose_pivot_rng(keys, b, e, kt, ascending, seed, 0, NULL, pivot_out);
 }
 
 /* Partition [b, e) of keys about *pivot in place; returns the bound. */

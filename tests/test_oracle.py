@@ -652,3 +652,57 @@ def test_plain_split_degenerate_rule_and_equal_ranges():
     keys = np.array([3] * 7_000 + [9] * 5_000, dtype=np.uint64)
     np.random.default_rng(1).shuffle(keys)
     np.testing.assert_array_equal(oracle.plain_split_sizes(keys, U64, levels=1), [7_000, 5_000])
+
+
+# ---- the secure generator option (Sec. 2.2) ----------------------------------------------
+
+def _rfc8439():
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "chacha20_rfc8439.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    return {r[0]: r[1:] for r in rows}
+
+
+def test_chacha20_rfc8439_vectors():
+    """The oracle's ChaCha20 quarter round and block function against RFC 8439's
+    worked examples (Sec. 2.1.1 and Sec. 2.3.2)."""
+    g = _rfc8439()
+    q = g["quarter"]
+    assert oracle.chacha20_quarter_round(*(int(x, 16) for x in q[:4])) == tuple(int(x, 16) for x in q[5:])
+    key = np.frombuffer(bytes(range(32)), dtype="<u4")
+    nonce = np.frombuffer(bytes([0, 0, 0, 9, 0, 0, 0, 0x4A, 0, 0, 0, 0]), dtype="<u4")
+    np.testing.assert_array_equal(oracle.chacha20_block(key, 1, nonce),
+                                  np.array([int(x, 16) for x in g["block"]], dtype=np.uint32))
+
+
+KEY = np.array([0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344, 0xA4093822, 0x299F31D0, 0x082EFA98,
+                0xEC4E6C89], dtype=np.uint32)
+
+
+def test_chacha20_sampling_offsets_come_from_the_range_block():
+    """With a key, the nine chunk offsets of [b, e) are the multiply-shift reductions
+    of the first nine words of the ChaCha20 block keyed by it, with block counter =
+    low 32 bits of b and nonce = (high 32 bits of b, low and high 32 bits of e)."""
+    for b, e, w in [(0, 10_000, 8), (2**33 + 5, 2**33 + 700_000, 16), (123, 2**40, 4)]:
+        blk = oracle.chacha20_block(KEY, b & 0xFFFFFFFF, [b >> 32, e & 0xFFFFFFFF, e >> 32])
+        nch = (e - b) // w
+        want = [oracle.multiply_shift(int(blk[i]), nch) for i in range(9)]
+        assert oracle.pivot_offsets(0, b, e, w, rng_key=KEY).tolist() == want
+        assert oracle.pivot_offsets(0, b, e, w).tolist() != want    # SFC64 draws differently
+
+
+@pytest.mark.parametrize("kt", [oracle.U16, oracle.U32, oracle.U64, oracle.U128, oracle.F32, oracle.F64])
+def test_sort_with_the_secure_generator(kt):
+    """The sort is the plain definition's sorted order with either generator, and the
+    pivots (hence the recursion) depend on the key."""
+    keys = _random_keys(kt, 60_000, seed=kt + 50)
+    a, b = keys.copy(), keys.copy()
+    sa = oracle.sort(a, kt, stats=True, rng_key=KEY)
+    sb = oracle.sort(b, kt, stats=True)
+    np.testing.assert_array_equal(a, b)
+    other = KEY.copy()
+    other[0] ^= 1
+    c = keys.copy()
+    sc = oracle.sort(c, kt, stats=True, rng_key=other)
+    np.testing.assert_array_equal(c, b)
+    assert (sa["keys_partitioned"], sa["basecases"]) != (sb["keys_partitioned"], sb["basecases"]) or \
+           (sa["keys_partitioned"], sa["basecases"]) != (sc["keys_partitioned"], sc["basecases"])
