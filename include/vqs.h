@@ -174,7 +174,22 @@ typedef struct vqs_options {
                                    statistics or error bits have been read.  Not with
                                    the learned method (VQS_EINVAL). */
     uint64_t workspace_bytes;   /* its size; below vqs_workspace_bytes(...): VQS_ESIZE */
+    uint32_t rng;               /* pivot sampler's generator (Sec. 2.2): VQS_RNG_SFC64 (default,
+                                   seeded by seed) or VQS_RNG_CHACHA20, the secure option:
+                                   each range's nine chunk offsets come from one ChaCha20
+                                   block (RFC 8439) under rng_key, with block counter = the
+                                   low 32 bits of the range start b and nonce = (the high 32
+                                   bits of b, the low and the high 32 bits of the range end),
+                                   so sampling positions cannot be predicted without the
+                                   key; other values: VQS_EINVAL */
+    uint32_t rng_key[8];        /* the 256-bit ChaCha20 key as eight little-endian words */
 } vqs_options;
+
+/* Generators of vqs_options.rng. */
+enum vqs_rng {
+    VQS_RNG_SFC64 = 0,
+    VQS_RNG_CHACHA20 = 1
+};
 
 #define VQS_FALLBACK_LIMIT_ZERO 0xFFFFFFFFu
 

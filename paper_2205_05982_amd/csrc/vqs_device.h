@@ -281,19 +281,71 @@ __device__ inline uint64_t uniform64(uint64_t x) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+// ChaCha20 block function (RFC 8439 Sec. 2.3): constants, 256-bit key, block counter,
+// 96-bit nonce; 10 double rounds (columns, then diagonals) of the quarter round, then
+// the input state added.  Only the first ten output words are produced.
+__device__ inline uint32_t rotl32(uint32_t x, int n) { return (x << n) | (x >> (32 - n)); }
+
+#define VQS_QR(a, b, c, d)     \
+  a += b;                      \
+  d = rotl32(d ^ a, 16);       \
+  c += d;                      \
+  b = rotl32(b ^ c, 12);       \
+  a += b;                      \
+  d = rotl32(d ^ a, 8);        \
+  c += d;                      \
+  b = rotl32(b ^ c, 7);
+
+__device__ inline void chacha20_ten(const uint32_t (&key)[8], uint32_t counter, uint32_t n0, uint32_t n1,
+                                    uint32_t n2, uint32_t (&u)[10]) {
+  const uint32_t x[16] = {0x61707865u, 0x3320646eu, 0x79622d32u, 0x6b206574u, key[0], key[1], key[2], key[3],
+                          key[4],      key[5],      key[6],      key[7],      counter, n0,     n1,     n2};
+  uint32_t w0 = x[0], w1 = x[1], w2 = x[2], w3 = x[3], w4 = x[4], w5 = x[5], w6 = x[6], w7 = x[7];
+  uint32_t w8 = x[8], w9 = x[9], w10 = x[10], w11 = x[11], w12 = x[12], w13 = x[13], w14 = x[14], w15 = x[15];
+  for (int r = 0; r < 10; r++) {
+    VQS_QR(w0, w4, w8, w12)
+    VQS_QR(w1, w5, w9, w13)
+    VQS_QR(w2, w6, w10, w14)
+    VQS_QR(w3, w7, w11, w15)
+    VQS_QR(w0, w5, w10, w15)
+    VQS_QR(w1, w6, w11, w12)
+    VQS_QR(w2, w7, w8, w13)
+    VQS_QR(w3, w4, w9, w14)
+  }
+  u[0] = w0 + x[0];
+  u[1] = w1 + x[1];
+  u[2] = w2 + x[2];
+  u[3] = w3 + x[3];
+  u[4] = w4 + x[4];
+  u[5] = w5 + x[5];
+  u[6] = w6 + x[6];
+  u[7] = w7 + x[7];
+  u[8] = w8 + x[8];
+  u[9] = w9 + x[9];
+}
+#undef VQS_QR
+
 // The nine chunk starts (keys from the range start) ChoosePivot samples for [b, e):
 // computed by each thread for its own range, so one wave can do it for 64 ranges.
+// The ten 32-bit random values come from the range's SFC64 generator (five 64-bit
+// draws, low half first), or, with the secure option, from the first ten words of the
+// ChaCha20 block keyed by the caller's key with block counter = the low 32 bits of b
+// and nonce = (the high 32 bits of b, the low and the high 32 bits of e).
 template <class K>
-__device__ inline void pivot_chunk_starts(uint64_t b, uint64_t e, uint64_t seed, uint64_t (&o)[9]) {
+__device__ inline void pivot_chunk_starts(uint64_t b, uint64_t e, const Params& p, uint64_t (&o)[9]) {
   constexpr int W = 64 / K::SIZE;
   const uint64_t nch = (e - b) / W;
-  Sfc64 rng = range_rng(seed, b, e);
   uint32_t u[10];
+  if (p.rng_mode == 1) {
+    chacha20_ten(p.rng_key, (uint32_t)b, (uint32_t)(b >> 32), (uint32_t)e, (uint32_t)(e >> 32), u);
+  } else {
+    Sfc64 rng = range_rng(p.seed, b, e);
 #pragma unroll
-  for (int i = 0; i < 5; i++) {
-    const uint64_t r = rng.next();
-    u[2 * i] = (uint32_t)r;
-    u[2 * i + 1] = (uint32_t)(r >> 32);
+    for (int i = 0; i < 5; i++) {
+      const uint64_t r = rng.next();
+      u[2 * i] = (uint32_t)r;
+      u[2 * i + 1] = (uint32_t)(r >> 32);
+    }
   }
 #pragma unroll
   for (int i = 0; i < 9; i++) o[i] = (((uint64_t)u[i] * nch) >> 32) * W;
@@ -304,12 +356,11 @@ __device__ typename K::R choose_pivot_from(Load load, uint64_t o0, uint64_t o1, 
                                            uint64_t o4, uint64_t o5, uint64_t o6, uint64_t o7, uint64_t o8);
 
 template <class K, class Load>
-__device__ typename K::R choose_pivot_wave(Load load, uint64_t b, uint64_t e, uint64_t seed) {
+__device__ typename K::R choose_pivot_wave(Load load, uint64_t b, uint64_t e, const Params& p) {
   b = uniform64(b);
   e = uniform64(e);
-  seed = uniform64(seed);
   uint64_t o[9];
-  pivot_chunk_starts<K>(b, e, seed, o);
+  pivot_chunk_starts<K>(b, e, p, o);
   return choose_pivot_from<K>(load, o[0], o[1], o[2], o[3], o[4], o[5], o[6], o[7], o[8]);
 }
 

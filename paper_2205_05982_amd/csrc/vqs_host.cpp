@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -48,11 +49,13 @@ struct GraphKey {
   uint32_t nb, local;
   uint64_t solo;
   int run_mode, tile;
+  uint32_t rng_mode;
+  std::array<uint32_t, 8> rng_key;
   bool operator<(const GraphKey& o) const {
     return std::tie(ws_base, keys, offsets, nseg, n, kt, asc, seed, depth_limit, fb_limit, nb, local, solo,
-                    run_mode, tile) < std::tie(o.ws_base, o.keys, o.offsets, o.nseg, o.n, o.kt, o.asc, o.seed,
-                                               o.depth_limit, o.fb_limit, o.nb, o.local, o.solo, o.run_mode,
-                                               o.tile);
+                    run_mode, tile, rng_mode, rng_key) <
+           std::tie(o.ws_base, o.keys, o.offsets, o.nseg, o.n, o.kt, o.asc, o.seed, o.depth_limit, o.fb_limit, o.nb,
+                    o.local, o.solo, o.run_mode, o.tile, o.rng_mode, o.rng_key);
   }
 };
 
@@ -224,6 +227,8 @@ struct Plan {
   int64_t fb_limit;     // < 0: default per range, else the fallback mode's own limit
   int run_mode;         // level partitions write tile-local runs
   int tile;             // level tile size: 0 default, 1 half
+  uint32_t rng_mode;    // pivot sampler: 0 SFC64, 1 ChaCha20
+  uint32_t rng_key[8];
 };
 
 int make_plan(uint64_t n, uint64_t nseg, int kt, int asc, const vqs_options* o, const Geometry& g, Plan* pl) {
@@ -235,6 +240,9 @@ int make_plan(uint64_t n, uint64_t nseg, int kt, int asc, const vqs_options* o, 
   pl->n = n;
   pl->nseg = nseg;
   pl->seed = o ? o->seed : 0;
+  pl->rng_mode = VQS_HAS(o, rng_key) ? o->rng : (uint32_t)VQS_RNG_SFC64;
+  if (pl->rng_mode > VQS_RNG_CHACHA20) return VQS_EINVAL;
+  for (int i = 0; i < 8; i++) pl->rng_key[i] = pl->rng_mode ? o->rng_key[i] : 0u;
   pl->nb = (o && o->base_case) ? o->base_case : 256;
   if (pl->nb < 32 || pl->nb > 256) return VQS_EINVAL;
   const uint64_t lbk = local_buffer_keys(bits);
@@ -575,6 +583,8 @@ void init_params(Params* base, const Params& carved, void* keys, uint64_t n, con
   b.n_total = n;
   b.mode = pl.mode;
   b.seed = pl.seed;
+  b.rng_mode = pl.rng_mode;
+  for (int i = 0; i < 8; i++) b.rng_key[i] = pl.rng_key[i];
   b.nb = pl.nb;
   b.local_cap = pl.local;
   b.solo_max = pl.solo;
@@ -622,7 +632,8 @@ int sort_locked(Workspace* ws, void* keys, const int64_t* offsets, uint64_t nseg
   const bool use_graph = o && o->use_graph && offsets;
   if (use_graph) {
     GraphKey gk{base.stats, keys, offsets, nseg, n, kt, asc, pl.seed, pl.depth_limit, pl.fb_limit, pl.nb, pl.local,
-                pl.solo, pl.run_mode, pl.tile};
+                pl.solo, pl.run_mode, pl.tile, pl.rng_mode, {}};
+    for (int i = 0; i < 8; i++) gk.rng_key[i] = pl.rng_key[i];
     if (!(ws->graph_valid && !(gk < ws->graph_key) && !(ws->graph_key < gk))) {
       if (ws->graph) {
         (void)hipGraphExecDestroy(ws->graph);

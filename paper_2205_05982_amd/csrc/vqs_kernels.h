@@ -554,7 +554,7 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
             if constexpr (sizeof(S) == sizeof(R)) r = s; else r = (R)s;
             return tmode ? K::load_t(s, tmode) : r;
           },
-          sg.b, sg.e, p.seed);
+          sg.b, sg.e, p);
       if (tid == 0) sh.pivot = pv;
     }
     __syncthreads();
@@ -1248,7 +1248,7 @@ __device__ void plan_second(const Params& p, int L, const Seg& sg, uint64_t g0, 
   if (gt < 2 && (gt == 0 ? st.piv0 : st.piv1)) {
     const Seg& cc = gt == 0 ? r0.s : r1.s;
     uint64_t o[9];
-    pivot_chunk_starts<K>(cc.b, cc.e, p.seed, o);
+    pivot_chunk_starts<K>(cc.b, cc.e, p, o);
 #pragma unroll
     for (int i = 0; i < 9; i++) sm.o[gt][i] = o[i];
   }
@@ -1561,7 +1561,7 @@ __global__ void __launch_bounds__(LEVEL_P) runs_plan_kernel(Params p) {
             if constexpr (sizeof(S) == sizeof(R)) r = sv; else r = (R)sv;
             return tmode ? K::load_t(sv, tmode) : r;
           },
-          sg.b, sg.e, p.seed);
+          sg.b, sg.e, p);
       if (lane == 0) {
         uint64_t lo, hi;
         to_words<K>(pv, lo, hi);
@@ -1693,7 +1693,7 @@ __global__ void __launch_bounds__(PIVOT_P) pivot_kernel(Params p) {
           if constexpr (sizeof(S) == sizeof(R)) r = sv; else r = (R)sv;
           return tmode ? K::load_t(sv, tmode) : r;
         },
-        sg.b, sg.e, p.seed);
+        sg.b, sg.e, p);
     {
       if (L > 0 && (sg.flags & SEG_MAXK) && !(sg.flags & SEG_FALLBACK) &&
           K::eq(pv, K::from_u64x2(sg.mx_lo, sg.mx_hi))) {
@@ -1977,7 +1977,7 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
         ls.list[0][0] = it;
         ls.nlist[0] = 1;
         uint64_t o[9];
-        pivot_chunk_starts<K>(b, e, p.seed, o);
+        pivot_chunk_starts<K>(b, e, p, o);
 #pragma unroll
         for (int i = 0; i < 9; i++) ls.pvoff[0][0][i] = (uint32_t)o[i];
       }
@@ -2228,7 +2228,7 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
       if ((uint32_t)lane < nn) {
         const LocalItem<K> ni = ls.list[cur ^ 1][lane];
         uint64_t o[9];
-        pivot_chunk_starts<K>(b + ni.lb, b + ni.le, p.seed, o);
+        pivot_chunk_starts<K>(b + ni.lb, b + ni.le, p, o);
 #pragma unroll
         for (int i = 0; i < 9; i++) ls.pvoff[cur ^ 1][lane][i] = (uint32_t)o[i];
       }
@@ -2530,7 +2530,7 @@ __global__ void __launch_bounds__(SOLO_P) __attribute__((amdgpu_waves_per_eu(sol
               if constexpr (sizeof(S) == sizeof(R)) r = s; else r = (R)s;
               return tm ? K::load_t(s, tm) : r;
             },
-            cur.b, cur.e, p.seed);
+            cur.b, cur.e, p);
         if (tid == 0) aux.pivot = pv;
       }
       __syncthreads();

@@ -118,6 +118,8 @@ struct Params {
   int off;               // keys before the first 16-byte boundary: (addr % 16) / size
   int mode;              // MODE_FLOAT | MODE_DESC transform of the caller's keys
   uint64_t seed;
+  uint32_t rng_mode;     // pivot sampler: 0 SFC64 from seed, 1 ChaCha20 under rng_key
+  uint32_t rng_key[8];
   uint32_t nb;           // NBaseCase (<= 256)
   uint32_t local_cap;    // keys per LDS local sort (<= LDS buffer capacity)
   uint64_t solo_max;     // ranges up to this length go to the solo kernel

@@ -47,7 +47,8 @@ class Options(ctypes.Structure):
                 ("model_seed", ctypes.c_uint64), ("sample_seed", ctypes.c_uint64),
                 ("level_mode", ctypes.c_uint32), ("fallback_limit", ctypes.c_uint32),
                 ("tile_variant", ctypes.c_uint32), ("total_keys", ctypes.c_uint64),
-                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64)]
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64),
+                ("rng", ctypes.c_uint32), ("rng_key", ctypes.c_uint32 * 8)]
 
 
 FALLBACK_LIMIT_ZERO = 0xFFFFFFFF
@@ -104,7 +105,12 @@ def lib():
     return _lib
 
 
+RNG_SFC64, RNG_CHACHA20 = 0, 1
+
+
 def make_options(**kw) -> Options:
+    """vqs_options from keyword arguments; rng_key (eight 32-bit words) selects the
+    ChaCha20 sampler unless rng says otherwise."""
     o = Options()
     o.struct_size = ctypes.sizeof(Options)
     for k, v in kw.items():
@@ -112,6 +118,14 @@ def make_options(**kw) -> Options:
             continue
         if k == "method" and isinstance(v, str):
             v = {"plain": PLAIN, "learned": LEARNED}[v]
+        if k == "rng_key":
+            words = [int(x) & 0xFFFFFFFF for x in v]
+            if len(words) != 8:
+                raise ValueError("rng_key is eight 32-bit words")
+            o.rng_key = (ctypes.c_uint32 * 8)(*words)
+            if "rng" not in kw:
+                o.rng = RNG_CHACHA20
+            continue
         setattr(o, k, v)
     return o
 

@@ -77,7 +77,8 @@ def test_options_layout_matches_binding():
     from paper_2205_05982_amd import vqs
     # struct vqs_options: 2*u32, u64, i64, 2*u32, u64, 4*u32, 3*float, (pad) 2*u64, 3*u32 (+ pad),
     # u64, pointer, u64
-    assert ctypes.sizeof(vqs.Options) == 128
+    assert ctypes.sizeof(vqs.Options) == 168
+    assert vqs.Options.rng.offset == 128 and vqs.Options.rng_key.offset == 132
     assert vqs.Options.model_seed.offset == 72
     assert vqs.Options.train_steps.offset == 48
     assert vqs.Options.level_mode.offset == 88

@@ -251,3 +251,54 @@ def test_traffic_counters(vqs):
     assert st["fallbacks"] == 0 and st["levels"] >= 2
     assert st["hbm_read_keys"] == st["hbm_write_keys"]
     assert 2 * n <= st["hbm_read_keys"] <= st["keys_partitioned"] + n
+
+
+# ---- the secure generator (Sec. 2.2) -------------------------------------------------------
+
+RNG_KEY = [0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344, 0xA4093822, 0x299F31D0, 0x082EFA98, 0xEC4E6C89]
+
+
+@pytest.mark.parametrize("kt,asc,n,mode", [(U64, True, 1_500_000, 2), (U64, False, 1_500_000, 1),
+                                           (U32, True, 2_000_000, 0), (F32, False, 700_000, 0),
+                                           (U128, True, 400_000, 2), (U16, True, 900_000, 0),
+                                           (F64, True, 30_000, 0)])
+def test_chacha20_sampler_matches_the_oracle(vqs, kt, asc, n, mode):
+    """With the ChaCha20 sampler every pivot is drawn from the range's block under the
+    key on the GPU as in the oracle: same output and same recursion counters, in the
+    device-wide levels (both placements), the per-workgroup partitions and LDS."""
+    import torch
+    print(f"case: chacha kt={kt} asc={asc} n={n} mode={mode}", flush=True)
+    keys = random_keys(kt, n, 90 + kt)
+    for key in (RNG_KEY, [w ^ 1 for w in RNG_KEY]):
+        want = keys.copy()
+        ost = oracle.sort(want, kt, ascending=asc, stats=True, rng_key=np.array(key, dtype=np.uint32))
+        t = to_gpu(keys)
+        vqs.sort(t, ascending=asc, key_type=kt, rng_key=key, level_mode=mode, solo_max=20_000)
+        torch.cuda.synchronize()
+        assert vqs.last_error_bits() == 0
+        np.testing.assert_array_equal(to_host(t), want)
+        assert_stats_equal(ost, vqs.get_stats())
+
+
+def test_chacha20_sampler_segmented_graph(vqs):
+    """Segments with the ChaCha20 sampler, captured once and replayed; a different key
+    is a different graph."""
+    import torch
+    print("case: chacha segmented graph", flush=True)
+    off = W.segment_offsets(250, seed=51, lo=16, hi=1 << 17)
+    keys = W.segmented_keys(off, U64, 52)
+    t, o = to_gpu(keys), to_gpu(off)
+    for key in (RNG_KEY, RNG_KEY, [w + 7 for w in RNG_KEY]):
+        want = keys.copy()
+        ost = oracle.sort_segmented(want, off, U64, stats=True, rng_key=np.array(key, dtype=np.uint32))
+        t.copy_(to_gpu(keys))
+        torch.cuda.synchronize()
+        vqs.sort_segmented(t, o, key_type=U64, use_graph=1, total_keys=int(off[-1]), rng_key=key)
+        torch.cuda.synchronize()
+        assert vqs.last_error_bits() == 0
+        np.testing.assert_array_equal(to_host(t), want)
+        st = vqs.get_stats()
+        assert (st["partitions"], st["keys_partitioned"], st["basecases"]) == \
+            (ost["partitions"], ost["keys_partitioned"], ost["basecases"])
+    with pytest.raises(vqs.VqsError):
+        vqs.sort(t, key_type=U64, rng=2)
