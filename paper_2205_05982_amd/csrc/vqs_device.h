@@ -212,6 +212,12 @@ __device__ inline uint32_t xor_lanes32(uint32_t v) {
 
 template <int M>
 __device__ inline uint32_t xor_lanes(uint32_t v) { return xor_lanes32<M>(v); }
+
+// The value of lane l (a constant lane), wave-uniform.
+__device__ inline uint32_t read_lane(uint32_t v, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)v, l); }
+__device__ inline uint64_t read_lane(uint64_t v, int l) {
+  return ((uint64_t)read_lane((uint32_t)(v >> 32), l) << 32) | read_lane((uint32_t)v, l);
+}
 template <int M>
 __device__ inline uint64_t xor_lanes(uint64_t v) {
   return ((uint64_t)xor_lanes32<M>((uint32_t)(v >> 32)) << 32) | xor_lanes32<M>((uint32_t)v);
@@ -220,6 +226,7 @@ template <int M>
 __device__ inline u128k xor_lanes(u128k v) {
   return u128k{xor_lanes<M>(v.lo), xor_lanes<M>(v.hi)};
 }
+__device__ inline u128k read_lane(u128k v, int l) { return u128k{read_lane(v.lo, l), read_lane(v.hi, l)}; }
 
 // ---- random numbers for the pivot sampler (Sec. 2.2) ---------------------------------
 

@@ -44,9 +44,15 @@ __device__ inline void to_words(typename K::R r, uint64_t& lo, uint64_t& hi) {
 
 template <class K>
 __device__ inline typename K::R wave_min(typename K::R v) {
-#pragma unroll
-  for (int m = 1; m < WAVE; m <<= 1) v = K::kmin(v, K::shfl_xor(v, m));
-  return v;
+  // minimum within each row of 16 lanes by DPP exchanges (lane ^ 1, ^ 2, ^ 7, ^ 15: each
+  // pairs the halves of the group the previous steps reduced), then the four row
+  // minima read from lanes 0, 16, 32, 48: no LDS round trip
+  v = K::kmin(v, xor_lanes<1>(v));
+  v = K::kmin(v, xor_lanes<2>(v));
+  v = K::kmin(v, xor_lanes<7>(v));
+  v = K::kmin(v, xor_lanes<15>(v));
+  const typename K::R r0 = read_lane(v, 0), r1 = read_lane(v, 16), r2 = read_lane(v, 32), r3 = read_lane(v, 48);
+  return K::kmin(K::kmin(r0, r1), K::kmin(r2, r3));
 }
 
 // number of 16-byte-aligned tiles of T keys that intersect [b, e)
@@ -2171,12 +2177,8 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
       const uint32_t len = it.le - it.lb;
       const uint32_t per = ((len + G - 1) / G + U * WAVE - 1) / (U * WAVE) * (U * WAVE);
       auto part_b = [&](int q) { const uint32_t o = (uint32_t)q * per; return it.lb + (o < len ? o : len); };
-      if (go && sw == 0) {
-        const R pv = pick_pivot(it, (uint32_t)item, s_buf);
-        if (lane == 0) ls.gpiv[item] = pv;
-      }
-      __syncthreads();
-      const R pivot = ls.gpiv[item];
+      // every wave of the group draws the same pivot itself: no broadcast barrier
+      const R pivot = go ? pick_pivot(it, (uint32_t)item, s_buf) : K::maxv();
       const uint32_t pb = part_b(sw), pe = part_b(sw + 1);
       uint32_t cnt = 0;
       R mn = K::maxv();
@@ -2236,7 +2238,8 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
     // 3. base cases, four per wave (one per 16-lane group); they are collected over
     // recursion levels and sorted together once the list could overflow at the next
     // level or no range is left to partition
-    const bool flush_bc = ls.nbc > (uint32_t)(BC_CAP - 2 * LIST_CAP) || ls.nlist[cur ^ 1] == 0;
+    const bool last = ls.nlist[cur ^ 1] == 0;
+    const bool flush_bc = ls.nbc > (uint32_t)(BC_CAP - 2 * LIST_CAP) || last;
     const uint32_t nbc = flush_bc ? (ls.nbc < BC_CAP ? ls.nbc : BC_CAP) : 0u;
     for (uint32_t q0 = wave * 4; q0 < nbc; q0 += SOLO_NW * 4) {
       const uint32_t qi = q0 + (lane >> 4);
@@ -2264,8 +2267,10 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
         if (pos < len) bufA[lb + pos] = (S)x[r];
       }
     }
-    // 4. bounded-time sorts of this level (whole workgroup, one range at a time)
-    __syncthreads();
+    // 4. bounded-time sorts of this level (whole workgroup, one range at a time).  Their
+    // ranges are disjoint from the base cases', so a wave may start on them while
+    // others still sort base cases; the list was complete at the barrier after the
+    // partitions.
     const uint32_t nbd = ls.nbounded < LIST_CAP ? ls.nbounded : LIST_CAP;
     if (tid == 0 && nbd) atomicAdd(&p.stats->bounded_lds, (unsigned long long)nbd);
     for (uint32_t f = 0; f < nbd; f++) {
@@ -2277,8 +2282,13 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
       }
       __syncthreads();
     }
+    // a flush before the last level empties the list for the next levels, once every
+    // wave has read its length (after the last level nothing more is pushed, and the
+    // next local sort starts with an empty list)
+    const bool reset_bc = flush_bc && !last;
+    if (reset_bc) __syncthreads();
     if (tid == 0) {
-      if (flush_bc) ls.nbc = 0;
+      if (reset_bc) ls.nbc = 0;
       ls.nbounded = 0;
       ls.nlist[cur] = 0;
     }

@@ -1,15 +1,19 @@
 """Summaries of rocprofv3 runs of bench.py: kernel times and HBM traffic.
 
-    python -m paper_2205_05982_amd.profile_summary KT_DIR FETCH_CSV WRITE_CSV OUT_MD "COMMANDS" "TITLE"
+    python -m paper_2205_05982_amd.profile_summary KT_DIR FETCH_CSV WRITE_CSV OUT_MD "COMMANDS" "TITLE" [COPY_BYTES]
 
 KT_DIR holds the ``--kernel-trace --stats`` CSV files (kt_kernel_stats.csv,
 kt_kernel_trace.csv); FETCH_CSV and WRITE_CSV are the counter_collection.csv files
 of a ``--pmc FETCH_SIZE`` and a ``--pmc WRITE_SIZE`` run of the same command.
 Counter values are KiB per dispatch; they are scaled by what the same counter reads
 for the device-to-device copies of the input buffers that bench.py makes (a copy of
-B bytes reads and writes B bytes).  Writes OUT_MD and, beside it, a JSON file with
-the level kernel's average HBM bytes per launch and the hash of the kernel sources
-they were measured on (bench.py reports the traffic only while the hash matches).
+B bytes reads and writes B bytes; COPY_BYTES, default 8e8, is the size of the
+input).  Writes OUT_MD and, beside it, a JSON file with the level kernel's average
+HBM bytes per launch and the hash of the kernel sources they were measured on
+(bench.py reports the traffic only while the hash matches).  Runs that include the
+learned splitter also get the time and traffic of its histogram and scatter
+kernels against their algorithmic bytes (one read; one read and one write of the
+keys).
 """
 from __future__ import annotations
 
@@ -45,8 +49,11 @@ def _rows(path):
 
 
 def _short(n: str) -> str:
+    import re
     n = n.replace("void ", "")
-    for a, b in (("vqs::Key<64> ", "u64"), ("(vqs::Params)", ""), ("vqs::", "")):
+    n = re.sub(r"vqs::KeyL<(\d+), (\d+)> ?", lambda m: f"k{m.group(1)},I{m.group(2)}", n)
+    n = re.sub(r"vqs::Key<(\d+)> ?", lambda m: f"k{m.group(1)}", n)
+    for a, b in (("(vqs::Params)", ""), ("vqs::", "")):
         n = n.replace(a, b)
     return n[:60]
 
@@ -104,6 +111,21 @@ def summarize(kt_dir, fetch_csv, write_csv, commands, title, copy_bytes=800_000_
     if sf:
         out.append(f"\nsolo_kernel per launch: read {statistics.mean(sf) * ff:.0f} KiB, written "
                    f"{statistics.mean(sw) * wf:.0f} KiB (scaled).")
+    # the learned splitter's one-pass kernels, if the run has them
+    for lk, reads, writes in (("histogram_kernel", 1, 0), ("scatter_kernel", 1, 1)):
+        kf = [float(r["Counter_Value"]) for r in f if lk in r["Kernel_Name"]]
+        kw = [float(r["Counter_Value"]) for r in w if lk in r["Kernel_Name"]]
+        kd = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in tr if lk in r["Kernel_Name"]]
+        if not (kf and kw and kd):
+            continue
+        big = [d for d in kd if d > 0.5 * max(kd)]    # the launches over the whole input
+        nbytes = max(kf) * ff * 1024 / max(reads, 1)  # one read of the keys
+        out.append(f"\n{lk}: {len(kd)} launches, the large ones average {statistics.mean(big):.1f} us; on the "
+                   f"largest input it reads {max(kf) * ff:.0f} KiB and writes {max(kw) * wf:.0f} KiB "
+                   f"(algorithmic: {reads} read{'' if not writes else ' + 1 write'} of the keys, "
+                   f"{(reads + writes) * nbytes / 1e6:.0f} MB); achieved "
+                   f"{(max(kf) * ff + max(kw) * wf) * 1024 / (statistics.mean(big) * 1e-6) / 1e9:.0f} GB/s measured "
+                   f"traffic.")
     js = {"kernel": kname, "traffic_bytes_per_launch": per_launch, "launches": len(lvf),
           "avg_launch_us_trace": lv_avg_us, "fetch_factor": ff, "write_factor": wf,
           "full_level_read_frac": mf / alg_kib, "full_level_write_frac": mw / alg_kib,
@@ -113,7 +135,8 @@ def summarize(kt_dir, fetch_csv, write_csv, commands, title, copy_bytes=800_000_
 
 def main(argv):
     kt_dir, fetch_csv, write_csv, out_md, commands, title = argv[1:7]
-    md, js = summarize(kt_dir, fetch_csv, write_csv, commands, title)
+    copy_bytes = int(float(argv[7])) if len(argv) > 7 else 800_000_000
+    md, js = summarize(kt_dir, fetch_csv, write_csv, commands, title, copy_bytes)
     with open(out_md, "w") as f:
         f.write(md)
     with open(os.path.splitext(out_md)[0] + ".traffic.json", "w") as f:
