@@ -153,7 +153,7 @@ Geometry geometry_of(int dev) {
   else
     (void)hipGetLastError();
   g.level_grid = g.num_cu * 8;
-  g.solo_grid = g.num_cu * 2;
+  g.solo_grid = g.num_cu * (1024 / SOLO_P);   // the solo kernel's LDS and registers allow 1024 threads per CU
   g.plan_grid = g.num_cu * 2;
   return g;
 }

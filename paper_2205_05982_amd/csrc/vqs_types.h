@@ -29,11 +29,17 @@ constexpr int level_chunks_half(int bits) { return level_chunks(bits) / 2; }
 #define VQS_SOLO_P 512
 #endif
 constexpr int SOLO_P = VQS_SOLO_P;  // threads per solo-kernel workgroup
-// 16-byte chunks per thread of a solo-kernel tile (32 KB tiles; 16 KB for u16, whose
-// keys take one register each)
-constexpr int solo_chunks(int bits) { return (bits == 16 ? 1024 : 2048) / SOLO_P; }
-constexpr int LOCAL_BYTES = 32768;  // one LDS buffer of the local sort
-constexpr int LOCAL_LIST_CAP = 64;  // ranges per LDS recursion level
+#ifndef VQS_LOCAL_BYTES
+#define VQS_LOCAL_BYTES 32768
+#endif
+constexpr int LOCAL_BYTES = VQS_LOCAL_BYTES;  // one LDS buffer of the local sort
+// 16-byte chunks per thread of a solo-kernel tile: a tile fills one LDS buffer (half
+// of it for u16, whose keys take one register each)
+constexpr int solo_chunks(int bits) { return (bits == 16 ? LOCAL_BYTES / 32 : LOCAL_BYTES / 16) / SOLO_P; }
+#ifndef VQS_LOCAL_LIST_CAP
+#define VQS_LOCAL_LIST_CAP 64
+#endif
+constexpr int LOCAL_LIST_CAP = VQS_LOCAL_LIST_CAP;  // ranges per LDS recursion level
 
 // ---- shared structures -------------------------------------------------------------
 
