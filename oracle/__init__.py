@@ -80,6 +80,10 @@ def lib():
         L.vqo_choose_pivot.argtypes = [vp, u64, u64, i32, i32, u64, vp]
         L.vqo_choose_pivot_rng.argtypes = [vp, u64, u64, i32, i32, u64, i32, vp, vp]
         L.vqo_sort_segmented_rng.argtypes = [vp, vp, u64, i32, i32, u64, i32, vp, u64, i64, ctypes.POINTER(Stats)]
+        L.vqo_sort_segmented_opts.argtypes = [vp, vp, u64, i32, i32, u64, i32, vp, u64, i64, i32,
+                                              ctypes.POINTER(Stats)]
+        L.vqo_partition_inplace.argtypes = [vp, u64, u64, i32, i32, vp]
+        L.vqo_partition_inplace.restype = i64
         L.vqo_chacha20_block.argtypes = [vp, ctypes.c_uint32, vp, vp]
         L.vqo_chacha20_quarter_round.argtypes = [vp]
         L.vqo_pivot_offsets_rng.argtypes = [u64, i32, vp, u64, u64, u64, vp]
@@ -143,32 +147,28 @@ def _key_words(key):
 
 
 def sort(keys: np.ndarray, kt: int, ascending: bool = True, seed: int = 0,
-         nb: int = NB_DEFAULT, depth_limit: int = -1, stats: bool = False, rng_key=None):
+         nb: int = NB_DEFAULT, depth_limit: int = -1, stats: bool = False, rng_key=None,
+         inplace: bool = False):
     """Sort keys in place with the paper's method; returns stats if asked.  With
     rng_key (eight 32-bit words) the pivot sampler draws from ChaCha20 under that key
-    (the secure generator option of Sec. 2.2) instead of SFC64 from the seed."""
-    _check_keys(keys, kt)
-    st = Stats()
-    k = _key_words(rng_key)
-    offs = np.array([0, nkeys(keys, kt)], dtype=np.int64)
-    rc = lib().vqo_sort_segmented_rng(_ptr(keys), _ptr(offs), 1, kt, int(bool(ascending)), seed,
-                                      1 if k is not None else 0, _ptr(k) if k is not None else None, nb,
-                                      depth_limit, ctypes.byref(st))
-    if rc != 0:
-        raise RuntimeError(f"vqo_sort failed: {rc}")
-    return st.as_dict() if stats else None
+    (the secure generator option of Sec. 2.2) instead of SFC64 from the seed.  With
+    inplace, Partition is the in-place bidirectional scan of Sec. 2.1 (64-key vectors,
+    four per loop iteration) instead of the out-of-place split."""
+    offs = np.array([0, nkeys(keys, kt) if keys.ndim else 0], dtype=np.int64)
+    return sort_segmented(keys, offs, kt, ascending, seed, nb, depth_limit, stats, rng_key, inplace)
 
 
 def sort_segmented(keys: np.ndarray, offsets: np.ndarray, kt: int, ascending: bool = True,
                    seed: int = 0, nb: int = NB_DEFAULT, depth_limit: int = -1, stats: bool = False,
-                   rng_key=None):
+                   rng_key=None, inplace: bool = False):
     _check_keys(keys, kt)
     offsets = np.ascontiguousarray(offsets, dtype=np.int64)
     st = Stats()
     k = _key_words(rng_key)
-    rc = lib().vqo_sort_segmented_rng(_ptr(keys), _ptr(offsets), offsets.size - 1, kt,
-                                      int(bool(ascending)), seed, 1 if k is not None else 0,
-                                      _ptr(k) if k is not None else None, nb, depth_limit, ctypes.byref(st))
+    rc = lib().vqo_sort_segmented_opts(_ptr(keys), _ptr(offsets), offsets.size - 1, kt,
+                                       int(bool(ascending)), seed, 1 if k is not None else 0,
+                                       _ptr(k) if k is not None else None, nb, depth_limit,
+                                       int(bool(inplace)), ctypes.byref(st))
     if rc != 0:
         raise RuntimeError(f"vqo_sort_segmented failed: {rc}")
     return st.as_dict() if stats else None
@@ -190,6 +190,17 @@ def partition(keys: np.ndarray, b: int, e: int, pivot, kt: int, ascending: bool 
     _check_keys(keys, kt)
     p = np.array(pivot, dtype=_DTYPES[kt]).reshape(-1)
     return int(lib().vqo_partition(_ptr(keys), b, e, kt, int(bool(ascending)), _ptr(p)))
+
+
+def partition_inplace(keys: np.ndarray, b: int, e: int, pivot, kt: int, ascending: bool = True) -> int:
+    """The in-place bidirectional Partition of Sec. 2.1 on [b, e); returns the bound."""
+    _check_keys(keys, kt)
+    p = np.array(pivot, dtype=_DTYPES[kt]).reshape(-1)
+    return int(lib().vqo_partition_inplace(_ptr(keys), b, e, kt, int(bool(ascending)), _ptr(p)))
+
+
+IP_LANES, IP_UNROLL = 64, 4          # the in-place Partition's vector and loop iteration
+IP_BLOCK = IP_LANES * IP_UNROLL
 
 
 def minmax(keys: np.ndarray, b: int, e: int, kt: int, ascending: bool = True):

@@ -13,7 +13,8 @@
  *
  * Every routine follows one step of the paper's method:
  *   Sec. 2 / Alg. 1    Recurse (partition, degenerate handling, base case, tail calls)
- *   Sec. 2.1           Partition (keys not after the pivot go left)
+ *   Sec. 2.1           Partition (keys not after the pivot go left): the plain
+ *                      out-of-place split, or the paper's in-place bidirectional scan
  *   Sec. 2.2           ChoosePivot (nine random 64-byte chunks, medians of three),
  *                      depth limit 2*log2(n)+4 with Heapsort as the fallback
  *   Sec. 2.3, Sec. 3   BaseCase (16-row matrix, Green's 16-input column network,
@@ -95,6 +96,81 @@ static uint64_t SFX(partition)(KT* keys, KT* tmp, uint64_t b, uint64_t e, KT piv
     return l;
 }
 
+/* In-place Partition (Sec. 2.1): the bidirectional scan, taken with a vector of
+ * IP_LANES keys and IP_UNROLL vectors per loop iteration (one "block").  Only
+ * O(block) keys are held outside the array.
+ *
+ *  1. A range of fewer than two blocks, or else its first n mod IP_BLOCK keys, goes
+ *     through the small loop: keys not after the pivot are compress-stored in place
+ *     from the front, the others collected in order in a buffer.  The range's last
+ *     keys, as many as the buffer holds, then move in order into the gap behind the
+ *     left keys, and the buffer is stored at the end of the range.
+ *  2. The rest of the range, whole blocks (at least two), is the main loop's input.
+ *     Its first and last blocks are held back (read first, partitioned last).  Each
+ *     iteration loads the next unread block from the side whose capacity (distance
+ *     between read and write position) is smaller, the left side on a tie, and
+ *     partitions its vectors in address order: a vector's left keys are stored at
+ *     writeL in lane order, writeR moves down by the number of its right keys, which
+ *     are stored from writeR in lane order.
+ *  3. The two held-back blocks, first then last, are partitioned the same way.  The
+ *     write positions then meet at the bound.
+ *
+ * Stores write exactly the valid lanes, so the paper's last-vector adjustment for a
+ * blended store that could touch memory past the range does not apply. */
+#ifndef IP_LANES
+#define IP_LANES 64
+#define IP_UNROLL 4
+#define IP_BLOCK (IP_LANES * IP_UNROLL)
+#endif
+
+/* One vector's CompressStores (step 2 above). */
+static void SFX(ip_vector)(KT* keys, const KT* v, KT pivot, int asc, uint64_t* wl, uint64_t* wr) {
+    KT right[IP_LANES];
+    uint64_t nr = 0;
+    for (uint64_t x = 0; x < IP_LANES; x++) {
+        if (!SFX(before)(pivot, v[x], asc)) keys[(*wl)++] = v[x];
+        else right[nr++] = v[x];
+    }
+    *wr -= nr;
+    memcpy(keys + *wr, right, nr * sizeof(KT));
+}
+
+static uint64_t SFX(partition_inplace)(KT* keys, uint64_t b, uint64_t e, KT pivot, int asc) {
+    const uint64_t n = e - b;
+    const uint64_t nrem = n < 2 * IP_BLOCK ? n : n % IP_BLOCK;
+    KT buf[IP_BLOCK], first[IP_BLOCK], last[IP_BLOCK], blk[IP_BLOCK];
+    /* 1. the small loop */
+    uint64_t left = b, nbuf = 0;
+    for (uint64_t i = b; i < b + nrem; i++) {
+        const KT k = keys[i];
+        if (!SFX(before)(pivot, k, asc)) keys[left++] = k;
+        else buf[nbuf++] = k;
+    }
+    const uint64_t right = e - nbuf;
+    memmove(keys + left, keys + right, nbuf * sizeof(KT));
+    memcpy(keys + right, buf, nbuf * sizeof(KT));
+    if (nrem == n) return left;
+    /* 2. the main loop on [left, right) */
+    memcpy(first, keys + left, sizeof(first));
+    memcpy(last, keys + right - IP_BLOCK, sizeof(last));
+    uint64_t readL = left + IP_BLOCK, readR = right - IP_BLOCK;
+    uint64_t wl = left, wr = right;
+    while (readL < readR) {
+        if (readL - wl <= wr - readR) {
+            memcpy(blk, keys + readL, sizeof(blk));
+            readL += IP_BLOCK;
+        } else {
+            readR -= IP_BLOCK;
+            memcpy(blk, keys + readR, sizeof(blk));
+        }
+        for (int v = 0; v < IP_UNROLL; v++) SFX(ip_vector)(keys, blk + v * IP_LANES, pivot, asc, &wl, &wr);
+    }
+    /* 3. the held-back blocks */
+    for (int v = 0; v < IP_UNROLL; v++) SFX(ip_vector)(keys, first + v * IP_LANES, pivot, asc, &wl, &wr);
+    for (int v = 0; v < IP_UNROLL; v++) SFX(ip_vector)(keys, last + v * IP_LANES, pivot, asc, &wl, &wr);
+    return wl;
+}
+
 /* ScanMinMax (Alg. 1): first and last key of the range in sort order. */
 static void SFX(minmax)(const KT* keys, uint64_t b, uint64_t e, int asc, KT* first, KT* last) {
     KT f = keys[b], l = keys[b];
@@ -159,7 +235,8 @@ static void SFX(recurse)(KT* keys, KT* tmp, uint64_t b, uint64_t e, KT pivot, ui
         return;
     }
     if (depth > st->max_depth) st->max_depth = depth;
-    const uint64_t bound = SFX(partition)(keys, tmp, b, e, pivot, p->ascending);
+    const uint64_t bound = p->inplace ? SFX(partition_inplace)(keys, b, e, pivot, p->ascending)
+                                      : SFX(partition)(keys, tmp, b, e, pivot, p->ascending);
     st->partitions++;
     st->keys_partitioned += e - b;
     if (bound == e) {                               /* degenerate: right side empty */

@@ -68,6 +68,7 @@ typedef struct {
     int64_t depth_limit;   /* < 0: 2*floor(log2 n)+4 */
     int rng;               /* 0: SFC64 from the seed; 1: ChaCha20 under key (the secure option) */
     uint32_t key[8];
+    int inplace;           /* 1: the in-place bidirectional Partition of Sec. 2.1 */
 } vqo_params;
 
 /* ---- random numbers (Sec. 2.2) ---------------------------------------------- */
@@ -525,11 +526,12 @@ int vqo_key_size(int kt) { return key_size(kt); }
  * is one segment.  nb must be at least 32 (so every partitioned range holds a whole
  * sampling chunk) and depth_limit < 0 selects the paper's limit.  Stats accumulate
  * over all segments.  Returns 0, or a negative error. */
-int vqo_sort_segmented_rng(void* keys, const int64_t* offsets, uint64_t nseg, int kt, int ascending,
-                           uint64_t seed, int rng, const uint32_t key[8], uint64_t nb, int64_t depth_limit,
-                           vqo_stats* st) {
+int vqo_sort_segmented_opts(void* keys, const int64_t* offsets, uint64_t nseg, int kt, int ascending,
+                            uint64_t seed, int rng, const uint32_t key[8], uint64_t nb, int64_t depth_limit,
+                            int inplace, vqo_stats* st) {
     if (nb < 32) return -1;
     if (rng != 0 && rng != 1) return -1;
+    if (inplace != 0 && inplace != 1) return -1;
     vqo_params p;
     memset(&p, 0, sizeof(p));
     p.ascending = ascending ? 1 : 0;
@@ -537,6 +539,7 @@ int vqo_sort_segmented_rng(void* keys, const int64_t* offsets, uint64_t nseg, in
     p.nb = nb;
     p.depth_limit = depth_limit;
     p.rng = rng;
+    p.inplace = inplace;
     if (key) memcpy(p.key, key, sizeof(p.key));
     vqo_stats local;
     memset(&local, 0, sizeof(local));
@@ -546,7 +549,8 @@ int vqo_sort_segmented_rng(void* keys, const int64_t* offsets, uint64_t nseg, in
         uint64_t len = (uint64_t)(offsets[i + 1] - offsets[i]);
         if (len > maxlen) maxlen = len;
     }
-    void* tmp = malloc((size_t)(offsets[nseg] > 0 ? offsets[nseg] : 1) * (size_t)key_size(kt));
+    /* the out-of-place Partition's buffer; the in-place one needs none */
+    void* tmp = malloc((size_t)(offsets[nseg] > 0 && !inplace ? offsets[nseg] : 1) * (size_t)key_size(kt));
     if (!tmp) return -3;
 #define SORT_SEGS(sfx, T)                                                                     \
     for (uint64_t i = 0; i < nseg; i++)                                                       \
@@ -568,6 +572,12 @@ int vqo_sort_segmented_rng(void* keys, const int64_t* offsets, uint64_t nseg, in
     free(tmp);
     if (st) *st = local;
     return 0;
+}
+
+int vqo_sort_segmented_rng(void* keys, const int64_t* offsets, uint64_t nseg, int kt, int ascending,
+                           uint64_t seed, int rng, const uint32_t key[8], uint64_t nb, int64_t depth_limit,
+                           vqo_stats* st) {
+    return vqo_sort_segmented_opts(keys, offsets, nseg, kt, ascending, seed, rng, key, nb, depth_limit, 0, st);
 }
 
 int vqo_sort_segmented(void* keys, const int64_t* offsets, uint64_t nseg, int kt, int ascending,
@@ -634,6 +644,20 @@ int64_t vqo_partition(void* keys, uint64_t b, uint64_t e, int kt, int ascending,
     }
 #undef PART
     free(tmp);
+    return bound;
+}
+
+/* In-place Partition (Sec. 2.1) of [b, e) of keys about *pivot; returns the bound. */
+int64_t vqo_partition_inplace(void* keys, uint64_t b, uint64_t e, int kt, int ascending, const void* pivot) {
+    int64_t bound = -1;
+#define PIP(sfx, T)                                                                            \
+    {                                                                                          \
+        T p;                                                                                   \
+        memcpy(&p, pivot, sizeof(T));                                                          \
+        bound = (int64_t)partition_inplace_##sfx((T*)keys, b, e, p, ascending ? 1 : 0);        \
+    }
+    DISPATCH(kt, PIP)
+#undef PIP
     return bound;
 }
 
