@@ -25,8 +25,9 @@
  *    sorted rearrangement of the input.  vqs_sort_stable keeps equal keys in input
  *    order and returns the permutation.
  *  - Workspace: unless options.workspace supplies one, the library keeps a device
- *    workspace (a scratch array of n keys for the out-of-place partitions, plus range
- *    lists, tile tables and counters; vqs_workspace_bytes gives its size) per
+ *    workspace (a scratch array of n keys for the out-of-place partitions, none with
+ *    options.inplace, plus range lists, tile tables and counters;
+ *    vqs_workspace_bytes gives its size) per
  *    (device, stream), allocated on first use, grown when needed and reused.  If it
  *    cannot be allocated, VQS_ENOMEM is returned and keys is untouched.  Calls on
  *    distinct streams are thread safe.
@@ -183,6 +184,18 @@ typedef struct vqs_options {
                                    so sampling positions cannot be predicted without the
                                    key; other values: VQS_EINVAL */
     uint32_t rng_key[8];        /* the 256-bit ChaCha20 key as eight little-endian words */
+    uint32_t reserved0;         /* zero */
+    uint32_t inplace;           /* 1: partition in place, in the order of the paper's
+                                   in-place bidirectional scan (Sec. 2.1: 64-key vectors,
+                                   four per loop iteration; the side with less capacity
+                                   is read next, the first and last blocks are held
+                                   back), keeping no scratch array of keys: the
+                                   workspace shrinks to about n / 40 keys of block
+                                   counts and saved blocks plus the lists.  The result
+                                   is the same sorted array; the recursion counters are
+                                   those of the oracle's in-place Partition.  Plain
+                                   method only, without use_graph or level_mode; other
+                                   values: VQS_EINVAL */
 } vqs_options;
 
 /* Generators of vqs_options.rng. */

@@ -51,11 +51,12 @@ struct GraphKey {
   int run_mode, tile;
   uint32_t rng_mode;
   std::array<uint32_t, 8> rng_key;
+  int inplace;
   bool operator<(const GraphKey& o) const {
     return std::tie(ws_base, keys, offsets, nseg, n, kt, asc, seed, depth_limit, fb_limit, nb, local, solo,
-                    run_mode, tile, rng_mode, rng_key) <
+                    run_mode, tile, rng_mode, rng_key, inplace) <
            std::tie(o.ws_base, o.keys, o.offsets, o.nseg, o.n, o.kt, o.asc, o.seed, o.depth_limit, o.fb_limit, o.nb,
-                    o.local, o.solo, o.run_mode, o.tile, o.rng_mode, o.rng_key);
+                    o.local, o.solo, o.run_mode, o.tile, o.rng_mode, o.rng_key, o.inplace);
   }
 };
 
@@ -73,6 +74,7 @@ struct Workspace {
   size_t bytes = 0;
   // capacities the allocation was carved for
   uint64_t cap_n = 0, cap_lvl = 0, cap_tiles = 0, cap_solo = 0, cap_scratch_bytes = 0;
+  uint64_t cap_ip_stash = 0, cap_ip_pfx = 0;
   int cap_levels = 0;
   Params p{};  // carved pointers
   unsigned long long* host_pinned = nullptr;
@@ -229,6 +231,8 @@ struct Plan {
   int tile;             // level tile size: 0 default, 1 half
   uint32_t rng_mode;    // pivot sampler: 0 SFC64, 1 ChaCha20
   uint32_t rng_key[8];
+  int inplace;          // in-place partitions, no key scratch
+  uint32_t ip_steps;    // in-place level tiles: loop blocks per tile
 };
 
 int make_plan(uint64_t n, uint64_t nseg, int kt, int asc, const vqs_options* o, const Geometry& g, Plan* pl) {
@@ -303,6 +307,19 @@ int make_plan(uint64_t n, uint64_t nseg, int kt, int asc, const vqs_options* o, 
   // many copy entries
   pl->cap_lvl = 3 * (n / (pl->solo + 1)) + 4;
   pl->cap_tiles = n / T + 2 * pl->cap_lvl + 2;
+  pl->inplace = VQS_HAS(o, inplace) ? (int)o->inplace : 0;
+  pl->ip_steps = ip_steps_of(pl->ks);
+  if (pl->inplace < 0 || pl->inplace > 1) return VQS_EINVAL;
+  if (pl->inplace) {
+    if (o->use_graph || o->method != VQS_METHOD_PLAIN) return VQS_EINVAL;
+    // the solo kernel's in-place partitions keep their block tables in LDS
+    if (o->solo_max && (o->solo_max < IP_SOLO_MIN || o->solo_max > IP_SOLO_MAX)) return VQS_EINVAL;
+    pl->solo = std::min<uint64_t>(std::max<uint64_t>(pl->solo, IP_SOLO_MIN), IP_SOLO_MAX);
+    pl->run_mode = 0;   // (level_mode and tile_variant do not apply)
+    pl->tile = 0;
+    pl->cap_lvl = n / (pl->solo + 1) + 4;
+    pl->cap_tiles = n / ((uint64_t)IP_B * pl->ip_steps) + pl->cap_lvl + 2;
+  }
   pl->cap_solo = nseg + 2ull * (uint64_t)pl->max_levels * pl->cap_lvl + n / FILL_CHUNK + 64;
   return VQS_OK;
 }
@@ -313,10 +330,14 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 struct Caps {
   uint64_t scratch_bytes, lvl, tiles, solo;
   int levels;
+  uint64_t ip_stash_bytes, ip_pfx;   // in-place levels: saved keys, block prefix entries
 };
 
 Caps caps_of(const Plan& pl) {
-  return Caps{(pl.n + 32) * (uint64_t)pl.ks + 64, pl.cap_lvl, pl.cap_tiles, pl.cap_solo, pl.max_levels};
+  if (pl.inplace)
+    return Caps{0, pl.cap_lvl, pl.cap_tiles, pl.cap_solo, pl.max_levels,
+                pl.cap_lvl * IP_STASH * (uint64_t)pl.ks, pl.cap_tiles * pl.ip_steps};
+  return Caps{(pl.n + 32) * (uint64_t)pl.ks + 64, pl.cap_lvl, pl.cap_tiles, pl.cap_solo, pl.max_levels, 0, 0};
 }
 
 // Layout of a workspace with capacities c: returns its size in bytes and, when mem is
@@ -346,7 +367,13 @@ size_t carve(char* mem, const Caps& c, Params* p) {
   const size_t o_sord = take(c.solo * 4);
   const size_t o_stats = take(sizeof(DevStats));
   const size_t o_err = take(16);
+  const size_t o_ipst = take(c.ip_stash_bytes);
+  const size_t o_ippf = take(c.ip_pfx * 8);
+  const size_t o_iprg = take(c.ip_stash_bytes ? c.lvl * sizeof(IpRange) : 0);
   if (!mem) return off;
+  p->ip_stash = mem + o_ipst;
+  p->ip_pfx = (unsigned long long*)(mem + o_ippf);
+  p->ip_rng = (IpRange*)(mem + o_iprg);
   p->scratch = mem + o_scratch;  // re-based per call to the keys' alignment
   p->lvl_segs[0] = (Seg*)(mem + o_seg0);
   p->lvl_segs[1] = (Seg*)(mem + o_seg1);
@@ -377,15 +404,23 @@ void set_caps(Workspace* ws, const Caps& c) {
   ws->cap_tiles = c.tiles;
   ws->cap_solo = c.solo;
   ws->cap_levels = c.levels;
+  ws->cap_ip_stash = c.ip_stash_bytes;
+  ws->cap_ip_pfx = c.ip_pfx;
+}
+
+Caps caps_held(const Workspace* ws) {
+  return Caps{ws->cap_scratch_bytes, ws->cap_lvl, ws->cap_tiles, ws->cap_solo, ws->cap_levels, ws->cap_ip_stash,
+              ws->cap_ip_pfx};
 }
 
 // Allocate (or reuse) the workspace for a plan.  Caller holds g_mu.
 int ensure_workspace(Workspace* ws, const Plan& pl) {
   const Caps need = caps_of(pl);
   if (ws->mem && need.scratch_bytes <= ws->cap_scratch_bytes && need.lvl <= ws->cap_lvl &&
-      need.tiles <= ws->cap_tiles && need.solo <= ws->cap_solo && need.levels <= ws->cap_levels) {
+      need.tiles <= ws->cap_tiles && need.solo <= ws->cap_solo && need.levels <= ws->cap_levels &&
+      need.ip_stash_bytes <= ws->cap_ip_stash && need.ip_pfx <= ws->cap_ip_pfx) {
     if (ws->p_external) {   // the last call used a caller's workspace
-      const Caps c{ws->cap_scratch_bytes, ws->cap_lvl, ws->cap_tiles, ws->cap_solo, ws->cap_levels};
+      const Caps c = caps_held(ws);
       carve(ws->mem, c, &ws->p);
       ws->p_levels = c.levels;
       ws->p_external = false;
@@ -404,7 +439,8 @@ int ensure_workspace(Workspace* ws, const Plan& pl) {
   }
   const Caps c{std::max(need.scratch_bytes, ws->cap_scratch_bytes), std::max(need.lvl, ws->cap_lvl),
                std::max(need.tiles, ws->cap_tiles), std::max(need.solo, ws->cap_solo),
-               std::max(need.levels, ws->cap_levels)};
+               std::max(need.levels, ws->cap_levels), std::max(need.ip_stash_bytes, ws->cap_ip_stash),
+               std::max(need.ip_pfx, ws->cap_ip_pfx)};
   const size_t bytes = carve(nullptr, c, nullptr);
   void* mem = nullptr;
   if (hipMalloc(&mem, bytes) != hipSuccess || !mem) {
@@ -501,6 +537,27 @@ hipError_t launch_all(Workspace* ws, const Params& base, const Plan& pl, const G
         batch = LEVEL_BATCH_NEXT;
       }
     }
+  } else if (pl.n > pl.solo && base.inplace) {
+    // in place: pivots, then the counting and partition launches, per level
+    int batch = capture ? pl.max_levels : level_batch(pl);
+    for (;;) {
+      const int upto = std::min(L + batch, pl.max_levels - 1);
+      for (; L < upto; L++) {
+        Params p = base;
+        p.level = L;
+        e = ws->timed(8, L, [&] { return LaunchLevel<B, LI>::pivots(p, g.pivot_grid, s); });
+        if (e != hipSuccess) return e;
+        e = ws->timed(2, L, [&] { return Launch<B>::ip_level(p, g.level_grid, s); });
+        if (e != hipSuccess) return e;
+      }
+      if (L >= pl.max_levels - 1 || capture) break;
+      e = hipMemcpyAsync(ws->ctr_word(), &base.lvl_ctr[L].packed, 8, hipMemcpyDeviceToHost, s);
+      if (e != hipSuccess) return e;
+      e = hipStreamSynchronize(s);
+      if (e != hipSuccess) return e;
+      if (ws->ctr_word()[0] == 0) break;
+      batch = LEVEL_BATCH_NEXT;
+    }
   } else if (pl.n > pl.solo) {
     if (capture) {
       for (; L < pl.max_levels - 1; L++) {
@@ -594,6 +651,8 @@ void init_params(Params* base, const Params& carved, void* keys, uint64_t n, con
   b.fixed_limit = pl.depth_limit;
   b.fb_limit = pl.fb_limit;
   b.run_mode = pl.run_mode;
+  b.inplace = pl.inplace;
+  b.ip_steps = pl.ip_steps;
 }
 
 // Prepare base parameters for keys on ws (caller holds g_mu).
@@ -632,7 +691,7 @@ int sort_locked(Workspace* ws, void* keys, const int64_t* offsets, uint64_t nseg
   const bool use_graph = o && o->use_graph && offsets;
   if (use_graph) {
     GraphKey gk{base.stats, keys, offsets, nseg, n, kt, asc, pl.seed, pl.depth_limit, pl.fb_limit, pl.nb, pl.local,
-                pl.solo, pl.run_mode, pl.tile, pl.rng_mode, {}};
+                pl.solo, pl.run_mode, pl.tile, pl.rng_mode, {}, pl.inplace};
     for (int i = 0; i < 8; i++) gk.rng_key[i] = pl.rng_key[i];
     if (!(ws->graph_valid && !(gk < ws->graph_key) && !(ws->graph_key < gk))) {
       if (ws->graph) {
@@ -683,6 +742,7 @@ int sort_impl(void* keys, const int64_t* offsets, uint64_t nseg, uint64_t n, int
   if (o && o->method > VQS_METHOD_LEARNED) return VQS_EINVAL;
   const bool learned = o && o->method == VQS_METHOD_LEARNED;
   if (learned && (kt != VQS_U64 || offsets || !asc)) return VQS_EINVAL;
+  if (learned && VQS_HAS(o, inplace) && o->inplace) return VQS_EINVAL;   // its buckets need the scratch
   if (VQS_HAS(o, workspace_bytes) && o->workspace && (learned || (uintptr_t)o->workspace % 256)) return VQS_EINVAL;
   if (n == 0) return VQS_OK;
   if (!keys) return VQS_EINVAL;

@@ -27,6 +27,10 @@
 // written from the range start in input order, the others from the range end
 // backwards (reverse input order).  This is the layout of the oracle's scalar
 // out-of-place split, so pivots, ranges and recursion depths agree at every level.
+//
+// In-place mode (vqs_inplace.h) keeps no key scratch: every partition, device-wide,
+// per workgroup or in LDS, leaves the order of the paper's in-place bidirectional
+// scan (the oracle's in-place Partition), again so that the recursion agrees.
 #pragma once
 #include "vqs_device.h"
 #include "vqs_types.h"
@@ -323,7 +327,7 @@ __device__ inline void reserve_level(const Params& p, int next_level, const Seg&
     set_err(p, ERR_LEVEL_OVERFLOW);
     return;
   }
-  const unsigned long long nt = tiles_of(s.b, s.e, p.off, (uint64_t)T);
+  const unsigned long long nt = p.inplace ? ip_tiles_of(s.e - s.b, p.ip_steps) : tiles_of(s.b, s.e, p.off, (uint64_t)T);
   const unsigned long long old = atomicAdd(&p.lvl_ctr[next_level].packed, (1ull << 40) | nt);
   if ((old >> 40) >= p.cap_lvl || (old & TILE_MASK40) + nt > p.cap_tiles) {
     set_err(p, ERR_LEVEL_OVERFLOW);
@@ -1684,7 +1688,7 @@ __global__ void __launch_bounds__(PIVOT_P) pivot_kernel(Params p) {
   const uint32_t nseg = (uint32_t)(packed >> 40);
   if (nseg == 0) return;
   Seg* segs = p.lvl_segs[L & 1];
-  const S* src = (const S*)((L & 1) ? p.scratch : p.keys);
+  const S* src = (const S*)((L & 1) && !p.inplace ? p.scratch : p.keys);
   const int tmode = (L == 0) ? p.mode : 0;
   const uint32_t wave = (blockIdx.x * PIVOT_P + threadIdx.x) / WAVE;
   const uint32_t nwaves = gridDim.x * (PIVOT_P / WAVE);
@@ -1918,6 +1922,8 @@ __device__ void wg_bitonic_lds(S* a, uint32_t n) {
   }
 }
 
+#include "vqs_inplace.h"
+
 // Sort keys [b, e) of `src` (n <= local_cap) in LDS and write them to `out` (the
 // caller's array, output transform applied) or, if out_internal, to `out` in internal
 // form.  bufA/bufB hold local_cap keys each.  item_flags: LI_OVERRIDE / LI_FB /
@@ -1930,7 +1936,7 @@ __device__ void wg_bitonic_lds(S* a, uint32_t n) {
 // 2*log2(len)+4 is sorted by the bounded-time bitonic network.  Work in fallback mode
 // is not counted as the paper's partitions or base cases (the paper's fallback is one
 // leaf); entering it is counted as one fallback of the range's length.
-template <class K>
+template <class K, bool IP>
 __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* bufA, typename K::S* bufB,
                            const typename K::S* src, bool raw, uint64_t b, uint64_t e, uint32_t depth,
                            uint32_t limit, uint32_t item_flags, typename K::R pv, typename K::S* out,
@@ -2019,7 +2025,7 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
     // most half as many ranges as waves, G waves per range (the largest power of two
     // with nitems * G <= waves)
     int G = 1;
-    while (nitems > 0 && 2u * G * nitems <= (uint32_t)SOLO_NW) G *= 2;
+    while (!IP && nitems > 0 && 2u * G * nitems <= (uint32_t)SOLO_NW) G *= 2;
     // depth check of an item: true if it is to be partitioned (possibly now in
     // fallback mode); false if it went to the bounded-time list (by lane 0 of the
     // wave that reports it)
@@ -2160,8 +2166,14 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
         S* d_buf = (it.flags & LI_INB) ? bufA : bufB;
         const R pivot = pick_pivot(it, it_i, s_buf);
         R mn = K::maxv();
-        const uint32_t bound = scatter(s_buf, d_buf, it.lb, it.le, it.lb, it.le, pivot, strict, mn);
-        plan(it, bound, wave_min<K>(mn), pivot);
+        if constexpr (IP) {
+          // the in-place scan's order (Sec. 2.1), so that later pivots see the same ranges
+          const uint32_t bound = ip_partition_wave<K>(s_buf, d_buf, it.lb, it.le, pivot, strict, mn);
+          plan(it, bound, mn, pivot);
+        } else {
+          const uint32_t bound = scatter(s_buf, d_buf, it.lb, it.le, it.lb, it.le, pivot, strict, mn);
+          plan(it, bound, wave_min<K>(mn), pivot);
+        }
       }
     } else {
       // wave group: wave sw of item wave / G takes the sw-th part of the range; a
@@ -2442,7 +2454,9 @@ __device__ void fallback_global(const Params& p, typename K::S* bufA, const Seg&
   __syncthreads();
 }
 
-template <class K>
+// IP: in-place mode (its own instantiation, so that the default one's registers are
+// allocated as without it)
+template <class K, bool IP>
 __global__ void __launch_bounds__(SOLO_P) __attribute__((amdgpu_waves_per_eu(solo_waves<K::SIZE>()))) solo_kernel(Params p) {
   using R = typename K::R;
   using S = typename K::S;
@@ -2489,15 +2503,20 @@ __global__ void __launch_bounds__(SOLO_P) __attribute__((amdgpu_waves_per_eu(sol
       const S* src = (const S*)(in_scratch ? p.scratch : p.keys);
       S* dst = (S*)(in_scratch ? p.keys : p.scratch);
       const bool raw = (cur.flags & SEG_RAW) != 0;
-      if (cur.flags & SEG_BOUNDED) {
-        fallback_global<K>(p, bufA, cur, hrd, hwr);
+      // the bounded-time sort: through the key scratch, or in place without one
+      auto bounded = [&](const Seg& sgb) {
+        if constexpr (IP) fallback_global_inplace<K>(p, bufA, sgb, hrd, hwr);
+        else fallback_global<K>(p, bufA, sgb, hrd, hwr);
         __syncthreads();
+      };
+      if (cur.flags & SEG_BOUNDED) {
+        bounded(cur);
         continue;
       }
       if (n <= p.local_cap) {
         const uint32_t lf = ((cur.flags & SEG_OVERRIDE) ? LI_OVERRIDE : 0u) |
                             ((cur.flags & SEG_FALLBACK) ? LI_FB : 0u) | ((cur.flags & SEG_STRICT) ? LI_STRICT : 0u);
-        local_sort<K>(p, ls, bufA, bufB, src, raw, cur.b, cur.e, cur.depth, cur.limit, lf,
+        local_sort<K, IP>(p, ls, bufA, bufB, src, raw, cur.b, cur.e, cur.depth, cur.limit, lf,
                       K::from_u64x2(cur.pv_lo, cur.pv_hi), (S*)p.keys, false);
         if (tid == 0) {
           hrd += n;
@@ -2507,8 +2526,7 @@ __global__ void __launch_bounds__(SOLO_P) __attribute__((amdgpu_waves_per_eu(sol
       }
       if (cur.depth > cur.limit) {
         if (cur.flags & SEG_FALLBACK) {
-          fallback_global<K>(p, bufA, cur, hrd, hwr);
-          __syncthreads();
+          bounded(cur);
           continue;
         }
         // the paper's depth limit: continue this range in fallback mode
@@ -2520,8 +2538,7 @@ __global__ void __launch_bounds__(SOLO_P) __attribute__((amdgpu_waves_per_eu(sol
         cur.depth = 1;
         cur.limit = fb_limit_of(p, n);
         if (cur.depth > cur.limit) {   // a fallback-mode limit of 0
-          fallback_global<K>(p, bufA, cur, hrd, hwr);
-          __syncthreads();
+          bounded(cur);
           continue;
         }
       }
@@ -2545,11 +2562,24 @@ __global__ void __launch_bounds__(SOLO_P) __attribute__((amdgpu_waves_per_eu(sol
       }
       __syncthreads();
       const R pivot = aux.pivot;
+      if (IP && n > IP_SOLO_MAX) {   // (ranges are routed here only up to the threshold)
+        if (tid == 0) set_err(p, ERR_SOLO_OVERFLOW);
+        __syncthreads();
+        continue;
+      }
+      R mn = K::maxv();
+      uint64_t bound;
+      if constexpr (IP) {
+        // in place, in the paper's bidirectional order (a counting pass, then the pass
+        // that moves the keys)
+        bound = ip_partition_workgroup<K, SOLO_P>((S*)p.keys, cur.b, cur.e, pivot, strict, raw ? p.mode : 0, bufA,
+                                                  bufB, &mn);
+        if (tid == 0) hrd += n;
+      } else {
       // partition tile by tile: src -> dst
       const S* src_aligned = src - p.off;
       const uint64_t k0 = (cur.b + p.off) / T, k1 = (cur.e - 1 + p.off) / T;
       uint64_t excl_l = 0, excl_r = 0;
-      R mn = K::maxv();
       for (uint64_t k = k0; k <= k1; k++) {
         const uint64_t vs = (k * T > cur.b + p.off) ? k * T : cur.b + p.off;
         const uint64_t ve = ((k + 1) * T < cur.e + p.off) ? (k + 1) * T : cur.e + p.off;
@@ -2565,7 +2595,8 @@ __global__ void __launch_bounds__(SOLO_P) __attribute__((amdgpu_waves_per_eu(sol
         if (tid == 0) mn = K::kmin(mn, tmin);
         __syncthreads();
       }
-      const uint64_t bound = cur.b + excl_l;
+      bound = cur.b + excl_l;
+      }
       if (tid == 0) {
         sh_min = mn;
         hrd += n;
@@ -2580,13 +2611,14 @@ __global__ void __launch_bounds__(SOLO_P) __attribute__((amdgpu_waves_per_eu(sol
         }
       }
       __syncthreads();
-      const uint32_t cf = (in_scratch ? 0u : SEG_SCRATCH) | (fb ? SEG_FALLBACK : 0u);
+      const uint32_t cf = (in_scratch || IP ? 0u : SEG_SCRATCH) | (fb ? SEG_FALLBACK : 0u);
       // keys of [fb_, fe_) equal the pivot and are final.  Whole range: the caller's
       // array holds the range's keys (source or partition output), so only transformed
       // keys need writing back; part of a range: unless the partition wrote the
-      // caller's array untransformed, it holds other keys there
+      // caller's array untransformed, it holds other keys there.  In place: the
+      // partition wrote the caller's array in internal form
       auto retire_equal = [&](uint64_t fb_, uint64_t fe_, bool part) {
-        const bool need = part ? (!in_scratch || p.mode != 0) : (p.mode != 0 && !raw);
+        const bool need = IP ? p.mode != 0 : part ? (!in_scratch || p.mode != 0) : (p.mode != 0 && !raw);
         if (need && fe_ > fb_) {
           fill_range<K>(p, fb_, fe_, pivot);
           if (tid == 0) hwr += fe_ - fb_;
@@ -2680,7 +2712,7 @@ __global__ void clear_kernel(Params p) {
     p.lvl_ctr[i].packed = 0;
     p.lvl_ctr[i].keys = 0;
     p.lvl_ctr[i].ticket = 0;
-    p.lvl_ctr[i].pad = 0;
+    p.lvl_ctr[i].ticket2 = 0;
     p.lvl_ctr[i].pad2 = 0;
   }
   if (gid == 0) {

@@ -41,6 +41,26 @@ constexpr int solo_chunks(int bits) { return (bits == 16 ? LOCAL_BYTES / 32 : LO
 #endif
 constexpr int LOCAL_LIST_CAP = VQS_LOCAL_LIST_CAP;  // ranges per LDS recursion level
 
+// In-place partitions (Sec. 2.1, the bidirectional scan): a vector is one wavefront's
+// 64 keys, a loop iteration reads a block of four vectors
+constexpr int IP_V = 64;
+constexpr int IP_U = 4;
+constexpr int IP_B = IP_V * IP_U;
+constexpr uint32_t IP_STASH = 3 * IP_B;   // keys saved per range: the remainder, the two held-back blocks
+// loop blocks per in-place level tile and per chunk of an in-place solo partition
+// (at most 16, at most 32 KB of keys: a thread holds at most eight keys)
+constexpr uint32_t ip_steps_of(int key_bytes) {
+  return 32768u / (uint32_t)(IP_B * key_bytes) < 16u ? 32768u / (uint32_t)(IP_B * key_bytes) : 16u;
+}
+// loop blocks (main-loop iterations) of a range of len >= 2 * IP_B keys
+constexpr uint64_t ip_loop_blocks(uint64_t len) { return len / IP_B - 2; }
+// tiles of an in-place level for a range of len >= 2 * IP_B keys
+constexpr uint64_t ip_tiles_of(uint64_t len, uint32_t steps) {
+  return ip_loop_blocks(len) ? (ip_loop_blocks(len) + steps - 1) / steps : 1;
+}
+// in-place mode: the solo kernel's ranges (its block tables hold 256 blocks)
+constexpr uint64_t IP_SOLO_MIN = 4 * IP_B, IP_SOLO_MAX = 256 * IP_B;
+
 // ---- shared structures -------------------------------------------------------------
 
 enum : uint32_t {
@@ -84,11 +104,17 @@ struct TileRun {
   uint32_t nl, nv;
 };
 
+// In-place partitions: a range of an in-place level, as its count launch leaves it for
+// the partition launch (left counts of the remainder and of the two held-back blocks)
+struct IpRange {
+  uint32_t lrem, cfirst, clast, pad;
+};
+
 struct LevelCtr {
   unsigned long long packed;  // (segments << 40) | tiles
   unsigned long long keys;    // keys in the level's ranges
   unsigned int ticket;
-  unsigned int pad;
+  unsigned int ticket2;       // in-place levels: tickets of the partition launch
   unsigned long long pad2;
 };
 
@@ -150,6 +176,11 @@ struct Params {
   TileRun* runs[2];      // run mode: per-tile table of the current and the previous level
   TileRef* tref;         // run mode: range and first run of each tile of the level being planned
   uint32_t* tnl;         // run mode: left count of each tile of the level just partitioned
+  int inplace;           // partitions in place (no key scratch): the paper's bidirectional order
+  uint32_t ip_steps;     // in-place level tiles: loop blocks per tile
+  void* ip_stash;        // in-place levels: per range, its remainder and held-back blocks
+  unsigned long long* ip_pfx;   // in-place levels: left-count prefix of every loop block
+  IpRange* ip_rng;       // in-place levels: per range, the counts its count launch found
 };
 
 constexpr uint64_t FILL_CHUNK = 1ull << 16;

@@ -48,7 +48,8 @@ class Options(ctypes.Structure):
                 ("level_mode", ctypes.c_uint32), ("fallback_limit", ctypes.c_uint32),
                 ("tile_variant", ctypes.c_uint32), ("total_keys", ctypes.c_uint64),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64),
-                ("rng", ctypes.c_uint32), ("rng_key", ctypes.c_uint32 * 8)]
+                ("rng", ctypes.c_uint32), ("rng_key", ctypes.c_uint32 * 8),
+                ("reserved0", ctypes.c_uint32), ("inplace", ctypes.c_uint32)]
 
 
 FALLBACK_LIMIT_ZERO = 0xFFFFFFFF

@@ -76,9 +76,10 @@ def test_argument_errors_return_before_any_device_call(lib):
 def test_options_layout_matches_binding():
     from paper_2205_05982_amd import vqs
     # struct vqs_options: 2*u32, u64, i64, 2*u32, u64, 4*u32, 3*float, (pad) 2*u64, 3*u32 (+ pad),
-    # u64, pointer, u64
-    assert ctypes.sizeof(vqs.Options) == 168
+    # u64, pointer, u64, 10*u32 (+ pad)
+    assert ctypes.sizeof(vqs.Options) == 176
     assert vqs.Options.rng.offset == 128 and vqs.Options.rng_key.offset == 132
+    assert vqs.Options.inplace.offset == 168
     assert vqs.Options.model_seed.offset == 72
     assert vqs.Options.train_steps.offset == 48
     assert vqs.Options.level_mode.offset == 88
@@ -95,12 +96,12 @@ def test_options_and_stats_layout_match_the_header(tmp_path):
     src = tmp_path / "layout.c"
     src.write_text(
         '#include <stddef.h>\n#include <stdio.h>\n#include "vqs.h"\n'
-        'int main(void) { printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(vqs_options),'
+        'int main(void) { printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(vqs_options),'
         ' offsetof(vqs_options, train_steps), offsetof(vqs_options, model_seed),'
         ' offsetof(vqs_options, level_mode), sizeof(vqs_stats), offsetof(vqs_stats, train_loss),'
         ' offsetof(vqs_options, fallback_limit), offsetof(vqs_options, total_keys),'
         ' offsetof(vqs_options, workspace), offsetof(vqs_options, workspace_bytes),'
-        ' offsetof(vqs_stats, bounded_global)); return 0; }\n')
+        ' offsetof(vqs_stats, bounded_global), offsetof(vqs_options, inplace)); return 0; }\n')
     exe = tmp_path / "layout"
     inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
     subprocess.run(["gcc", "-I", inc, str(src), "-o", str(exe)], check=True)
@@ -109,7 +110,7 @@ def test_options_and_stats_layout_match_the_header(tmp_path):
                    vqs.Options.level_mode.offset, ctypes.sizeof(vqs.Stats), vqs.Stats.train_loss.offset,
                    vqs.Options.fallback_limit.offset, vqs.Options.total_keys.offset,
                    vqs.Options.workspace.offset, vqs.Options.workspace_bytes.offset,
-                   vqs.Stats.bounded_global.offset]
+                   vqs.Stats.bounded_global.offset, vqs.Options.inplace.offset]
 
 
 def test_noalloc_argument_errors_return_before_any_device_call(lib):
