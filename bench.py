@@ -11,7 +11,9 @@ The line also carries "learned_vs_plain": the 5e8-key lognormal-mixture workload
 sorted by both methods (median of a few sorts each), the speedup of the learned
 256-bucket splitter and whether both outputs are identical; and "batched": the
 65,536-segment u32 batch sorted by one hipGraph replay (library defaults and the
-autotuner's choice) against one vqs_sort call per segment.
+autotuner's choice) against one vqs_sort call per segment; and "inplace": the same
+input sorted in place (the paper's in-place partition order, no key scratch), its
+time, key traffic and workspace against the default path's.
 
 Roofline: the dominant kernel is the device-wide partition (level kernel).  Its
 algorithmic traffic per launch is 2 * keys * key_size bytes (each key of the level
@@ -34,6 +36,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -283,6 +286,40 @@ def learned_vs_plain(n: int, reps: int) -> dict:
     }
 
 
+def inplace_record(vqs, bufs, src, kt: int, n: int, ms_default: float, reps: int = 3) -> dict:
+    """The same workload sorted in place (vqs_options.inplace: every partition in the
+    order of the paper's in-place scan, no key scratch): median of reps sorts after a
+    warm-up, its key traffic, its workspace against the default one, and whether its
+    output equals the default path's."""
+    import torch
+    stream = torch.cuda.current_stream()
+    times = []
+    for r in range(reps + 1):
+        bufs[0].copy_(src)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        vqs.sort(bufs[0], key_type=kt, inplace=1)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if r:
+            times.append(e0.elapsed_time(e1))
+    st = vqs.get_stats()
+    if vqs.last_error_bits():
+        raise RuntimeError("device error bits in the in-place sort")
+    bufs[1].copy_(src)
+    vqs.sort(bufs[1], key_type=kt)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(bufs[0], bufs[1]))
+    ms = statistics.median(times)
+    return {"ms": round(ms, 3), "gkeys_s": round(n / (ms * 1e-3) / 1e9, 4),
+            "vs_default": round(ms_default / ms, 3),
+            "passes": round((st["hbm_read_keys"] + st["hbm_write_keys"]) / (2.0 * n), 3),
+            "levels": st["levels"], "workspace_bytes": vqs.workspace_bytes(n, kt, inplace=1),
+            "workspace_bytes_default": vqs.workspace_bytes(n, kt), "identical_to_default": same}
+
+
 def check_output(out, src, kt):
     """(sorted, same multiset) for the sorted tensor out of input src: non-decreasing
     in the key order; equal sums and sums of squares (mod 2^64) of the keys' words."""
@@ -507,6 +544,8 @@ def main():
             cp_ms.append(e0.elapsed_time(e1))
     copy_gbs = 2 * n * ks / (min(cp_ms) * 1e-3) / 1e9
 
+    inplace = inplace_record(vqs, bufs, src, kt, n, ms_step) if len(bufs) >= 2 else None
+
     # free the timed buffers before the larger comparison
     del bufs, out
     torch.cuda.empty_cache()
@@ -557,6 +596,7 @@ def main():
         "cpu_baseline": cpu,
         "learned_vs_plain": lvp,
         "batched": batched,
+        "inplace": inplace,
     }
     print(json.dumps(line), flush=True)
 
