@@ -78,6 +78,9 @@ __device__ inline uint32_t ip_find_seg(const unsigned long long* tbase, uint32_t
 }
 
 constexpr unsigned long long IP_ST_AGG = 1ull << 46, IP_ST_INC = 2ull << 46, IP_VAL = (1ull << 46) - 1;
+// predecessors an in-place look-back step polls: the nearest inclusive tile is usually
+// a few tiles back, and polling 64 device-coherent words per step cost 3 % (1e8 u64)
+constexpr int IP_LB_WIN = 16;
 
 // Decoupled look-back over the tiles [g0, g) of a range, one wave: waits until every
 // predecessor back to the nearest inclusive one has published in this epoch and returns
@@ -92,7 +95,7 @@ __device__ inline unsigned long long ip_lookback(const Params& p, unsigned long 
   unsigned long long top = g - 1;
   uint32_t spins = 0;
   for (;;) {
-    const bool inr = top >= g0 + (unsigned long long)lane;
+    const bool inr = lane < IP_LB_WIN && top >= g0 + (unsigned long long)lane;
     unsigned long long f = 0;
     if (inr) f = __hip_atomic_load(&p.flags[top - lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const bool ready = inr && (f & ~((1ull << 48) - 1)) == epoch && (f & (3ull << 46)) != 0;
@@ -115,8 +118,8 @@ __device__ inline unsigned long long ip_lookback(const Params& p, unsigned long 
     for (int m = 1; m < WAVE; m <<= 1) v += (unsigned long long)__shfl_xor((long long)v, m);
     excl += v;
     if (incm) break;
-    if (top < g0 + WAVE) break;   // cannot happen: tile g0 always publishes inclusive
-    top -= WAVE;
+    if (top < g0 + IP_LB_WIN) break;   // cannot happen: tile g0 always publishes inclusive
+    top -= IP_LB_WIN;
   }
   return excl;
 }
@@ -247,11 +250,30 @@ __global__ void __launch_bounds__(LEVEL_P) ip_count_kernel(Params p) {
     const uint64_t k0 = 1 + t * ST;   // the tile's first loop block
     const uint32_t nblk = t * ST < nl ? (uint32_t)(nl - t * ST < ST ? nl - t * ST : ST) : 0u;
     R mn = K::maxv();
-    for (uint32_t q = (uint32_t)w; q < nblk * IP_U; q += NW) {
-      const R x = ip_load<K>(keys, ms + (k0 + q / IP_U) * IP_B + (q % IP_U) * IP_V + lane, tmode);
-      mn = K::kmin(mn, x);
-      const uint32_t c = (uint32_t)__popcll(ballot(ip_left<K>(x, pv, strict)));
-      if (lane == 0) atomicAdd(&sh_cnt[q / IP_U], c);
+    {
+      // wave w counts blocks w, w + NW, ...: all of its loads issued before any is used
+      constexpr int BPW = (int)((ST + NW - 1) / NW);
+      R x[BPW][IP_U];
+#pragma unroll
+      for (int r = 0; r < BPW; r++) {
+        const uint32_t kk = (uint32_t)w + (uint32_t)r * NW;
+#pragma unroll
+        for (int v = 0; v < IP_U; v++)
+          x[r][v] = ip_load<K>(keys, kk < nblk ? ms + (k0 + kk) * IP_B + v * IP_V + lane : sg.b, tmode);
+      }
+#pragma unroll
+      for (int r = 0; r < BPW; r++) {
+        const uint32_t kk = (uint32_t)w + (uint32_t)r * NW;
+        if (kk < nblk) {
+          uint32_t c = 0;
+#pragma unroll
+          for (int v = 0; v < IP_U; v++) {
+            mn = K::kmin(mn, x[r][v]);
+            c += (uint32_t)__popcll(ballot(ip_left<K>(x[r][v], pv, strict)));
+          }
+          if (lane == 0) sh_cnt[kk] = c;
+        }
+      }
     }
     if (t == 0) {
       // the remainder and the held-back blocks, saved in internal form: the partition
@@ -365,9 +387,9 @@ __global__ void __launch_bounds__(LEVEL_P) ip_scatter_kernel(Params p) {
     const unsigned long long* pf = p.ip_pfx + g0 * ST;   // pf[k - 1]: left keys of loop blocks 1..k
     const uint64_t s0 = t * ST;
     const uint32_t ns = s0 < nl ? (uint32_t)(nl - s0 < ST ? nl - s0 : ST) : 0u;
-    const uint64_t Q = nl ? pf[nl - 1] : 0;
-    // 1. the tile's iterations: blocks read, and the counts stored before the first one
+    // 1. the tile's iterations: blocks read, and the left keys stored before the first
     if (w == 0) {
+      const uint64_t Q = nl ? pf[nl - 1] : 0;
       auto Pv = [&](uint64_t k) -> uint64_t { return k ? pf[k - 1] : 0ull; };
       auto A = [&](uint64_t i) -> uint64_t { return (uint64_t)IP_B * i - Pv(i); };
       auto B = [&](uint64_t j) -> uint64_t { return Q - Pv(nl - j); };
@@ -395,6 +417,8 @@ __global__ void __launch_bounds__(LEVEL_P) ip_scatter_kernel(Params p) {
         aw = i0 + lane < nl ? A(i0 + lane) : ~0ull;
         bw = j0 + lane < nl ? B(j0 + lane) : ~0ull;
       }
+      const uint64_t a0 = read_lane(aw, 0), b0 = read_lane(bw, 0);
+      // the walk over the windows: iteration x reads on the left iff A(i) <= B(j)
       uint32_t di = 0, dj = 0;
       for (uint32_t x = 0; x < ns; x++) {
         const uint64_t a = read_lane(aw, (int)di), bb = read_lane(bw, (int)dj);
@@ -404,7 +428,7 @@ __global__ void __launch_bounds__(LEVEL_P) ip_scatter_kernel(Params p) {
         else dj++;
       }
       // left keys stored before iteration s0: those of the first i0 and the last j0 blocks
-      if (lane == 0) sh_lc0 = ns ? (uint64_t)IP_B * i0 - read_lane(aw, 0) + read_lane(bw, 0) : Q;
+      if (lane == 0) sh_lc0 = ns ? (uint64_t)IP_B * i0 - a0 + b0 : Q;
     }
     __syncthreads();
     const uint64_t lc0 = sh_lc0, rc0 = (uint64_t)IP_B * s0 - lc0;
@@ -479,6 +503,8 @@ __global__ void __launch_bounds__(LEVEL_P) ip_scatter_kernel(Params p) {
     auto held = [&](uint32_t i) -> R { return ip_load<K>(sv, IP_B + i, 0); };
     if (t == 0 && w == 2) ip_store_remainder<K>(saved, store_key, sg.b, me, nrem, pv, strict);
     const bool last = t == nt - 1;
+    // the last tile ends the loop: the loop's left keys are those before it and its own
+    const uint64_t Q = lc0 + nlt;
     if (last) ip_store_held<K>(held, store_key, ms, me, Q, (uint64_t)IP_B * nl - Q, ir.cfirst, pv, strict, w);
     if (tid == 0) {
       nread += nvalid;

@@ -471,6 +471,13 @@ __device__ inline typename K::R range_min(const Params& p, const Seg& sg, int gt
 
 // ---- level kernel ------------------------------------------------------------------------
 
+#ifndef VQS_LB_WIN
+#define VQS_LB_WIN 64
+#endif
+// predecessors a look-back step polls (the wave's first LB_WIN lanes)
+constexpr int LB_WIN = VQS_LB_WIN;
+static_assert(LB_WIN >= 1 && LB_WIN <= WAVE, "look-back window");
+
 #ifndef VQS_LEVEL_WAVES
 #define VQS_LEVEL_WAVES 4
 #endif
@@ -600,7 +607,7 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
         unsigned long long top = g - 1;   // highest predecessor not yet summed
         uint32_t spins = 0;
         for (;;) {
-          const bool inr = top >= g0 + (unsigned long long)lane;   // lane reads tile top - lane
+          const bool inr = lane < LB_WIN && top >= g0 + (unsigned long long)lane;   // lane reads tile top - lane
           unsigned long long f = 0;
           if (inr) f = __hip_atomic_load(&p.flags[top - lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           const bool ready = inr && (f & ~((1ull << 48) - 1)) == epoch && (f & (3ull << 46)) != 0;
@@ -624,8 +631,8 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(si
           for (int m = 1; m < WAVE; m <<= 1) v += (unsigned long long)__shfl_xor((long long)v, m);
           excl += v;
           if (incm) break;
-          if (top < g0 + WAVE) break;   // cannot happen: tile g0 is always inclusive
-          top -= WAVE;
+          if (top < g0 + LB_WIN) break;   // cannot happen: tile g0 is always inclusive
+          top -= LB_WIN;
         }
       }
       if (lane == 0) {
