@@ -612,7 +612,7 @@ __device__ uint64_t ip_partition_workgroup(typename K::S* keys, uint64_t b, uint
                                            int tmode, typename K::S* bufA, typename K::S* bufB, typename K::R* mn) {
   using R = typename K::R;
   using S = typename K::S;
-  constexpr uint32_t CS = ip_steps_of(K::SIZE);     // iterations per chunk
+  constexpr uint32_t CS = ip_chunk_steps(K::SIZE);  // iterations per chunk
   constexpr uint32_t NV = CS * IP_U;
   constexpr int NW = P / WAVE;
   constexpr int VPW = (int)((NV + NW - 1) / NW);

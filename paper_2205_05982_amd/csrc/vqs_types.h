@@ -47,9 +47,14 @@ constexpr int IP_V = 64;
 constexpr int IP_U = 4;
 constexpr int IP_B = IP_V * IP_U;
 constexpr uint32_t IP_STASH = 3 * IP_B;   // keys saved per range: the remainder, the two held-back blocks
-// loop blocks per in-place level tile and per chunk of an in-place solo partition
-// (at most 16, at most 32 KB of keys: a thread holds at most eight keys)
+// loop blocks per in-place level tile: 32 KB of keys, at most 32 blocks (a thread then
+// holds at most 16 keys)
 constexpr uint32_t ip_steps_of(int key_bytes) {
+  return 32768u / (uint32_t)(IP_B * key_bytes) < 32u ? 32768u / (uint32_t)(IP_B * key_bytes) : 32u;
+}
+// loop blocks per chunk of one workgroup's in-place partition: at most 16, so that a
+// thread holds at most eight keys in the solo kernel
+constexpr uint32_t ip_chunk_steps(int key_bytes) {
   return 32768u / (uint32_t)(IP_B * key_bytes) < 16u ? 32768u / (uint32_t)(IP_B * key_bytes) : 16u;
 }
 // loop blocks (main-loop iterations) of a range of len >= 2 * IP_B keys

@@ -106,16 +106,50 @@ def summarize(kt_dir, fetch_csv, write_csv, commands, title, copy_bytes=800_000_
     per_launch = (statistics.mean(lvf) * ff + statistics.mean(lvw) * wf) * 1024
     out.append(f"Average over all {len(lvf)} {kname} dispatches: {per_launch / 1e6:.1f} MB per launch "
                f"(read + written, scaled).")
-    sf = [float(r["Counter_Value"]) for r in f if "solo_kernel" in r["Kernel_Name"]]
-    sw = [float(r["Counter_Value"]) for r in w if "solo_kernel" in r["Kernel_Name"]]
+    def solo(name, inplace):
+        return "solo_kernel" in name and (", true>" in name) == inplace
+
+    sf = [float(r["Counter_Value"]) for r in f if solo(r["Kernel_Name"], False)]
+    sw = [float(r["Counter_Value"]) for r in w if solo(r["Kernel_Name"], False)]
     if sf:
         out.append(f"\nsolo_kernel per launch: read {statistics.mean(sf) * ff:.0f} KiB, written "
                    f"{statistics.mean(sw) * wf:.0f} KiB (scaled).")
+    # in-place mode (bench.py's in-place record), if the run has it
+    ipk = [("ip_count_kernel", 1, 0), ("ip_scatter_kernel", 1, 1)]
+    if any("ip_count_kernel" in r["Kernel_Name"] for r in tr):
+        out.append("\n## In-place mode (the bench's in-place sorts)\n")
+        for lk, reads, writes in ipk:
+            kf = [float(r["Counter_Value"]) for r in f if lk in r["Kernel_Name"]]
+            kw = [float(r["Counter_Value"]) for r in w if lk in r["Kernel_Name"]]
+            kd = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in tr if lk in r["Kernel_Name"]]
+            if not (kf and kw and kd):
+                continue
+            full_d = [d for d in kd if d > 0.8 * max(kd)]
+            full_f = [v for v in kf if v > 0.9 * max(kf)]
+            full_w = [v for v in kw if v > 0.9 * max(kw)] if max(kw) > 0 else [0.0]
+            rd, wr = statistics.mean(full_f) * ff, statistics.mean(full_w) * wf
+            wtxt = (f"writes {wr:.0f} KiB ({wr / alg_kib:.3f} of one pass)" if writes else
+                    f"writes {wr:.0f} KiB (block counts, saved blocks, tile minima)")
+            out.append(f"{lk}: {len(kd)} launches, {sum(kd) / 1e3:.3f} ms in all; on a full level "
+                       f"(about {statistics.mean(full_d):.0f} us) it reads {rd:.0f} KiB ({rd / alg_kib:.3f} of "
+                       f"one pass over the keys) and {wtxt}; "
+                       f"{(rd + wr) * 1024 / (statistics.mean(full_d) * 1e-6) / 1e9:.0f} GB/s measured traffic.")
+        isf = [float(r["Counter_Value"]) for r in f if solo(r["Kernel_Name"], True)]
+        isw = [float(r["Counter_Value"]) for r in w if solo(r["Kernel_Name"], True)]
+        isd = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in tr
+               if solo(r["Kernel_Name"], True)]
+        if isf and isd:
+            out.append(f"solo_kernel (in place): {statistics.mean(isd):.0f} us per launch, read "
+                       f"{statistics.mean(isf) * ff:.0f} KiB, written {statistics.mean(isw) * wf:.0f} KiB (scaled).")
     # the learned splitter's one-pass kernels, if the run has them
+    def learned(name, lk):
+        return lk in name and "ip_" + lk not in name
+
     for lk, reads, writes in (("histogram_kernel", 1, 0), ("scatter_kernel", 1, 1)):
-        kf = [float(r["Counter_Value"]) for r in f if lk in r["Kernel_Name"]]
-        kw = [float(r["Counter_Value"]) for r in w if lk in r["Kernel_Name"]]
-        kd = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in tr if lk in r["Kernel_Name"]]
+        kf = [float(r["Counter_Value"]) for r in f if learned(r["Kernel_Name"], lk)]
+        kw = [float(r["Counter_Value"]) for r in w if learned(r["Kernel_Name"], lk)]
+        kd = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in tr
+              if learned(r["Kernel_Name"], lk)]
         if not (kf and kw and kd):
             continue
         big = [d for d in kd if d > 0.5 * max(kd)]    # the launches over the whole input
