@@ -946,6 +946,114 @@ __device__ uint32_t ip_partition_wave(const typename K::S* s, typename K::S* d, 
   return ms + Q + read_lane(ck, 0) + read_lane(ck, (int)(mb - 1));
 }
 
+// Partition s[lb, le) into d[lb, le) in the in-place order by a group of G waves (this
+// wave is number sw of its group; go: the group has a range).  Every wave of the
+// workgroup calls it: it holds two barriers.  The group's waves count the blocks
+// k = sw, sw + G, ... (a vector's left count in tab[4k + v]); wave 0 of the group gives
+// every block its merge rank and offsets (lane k, into the table's second half) and
+// the bound; then the waves store their blocks, wave 0 also the remainder.  A range
+// under two blocks is split by wave 0 alone.  tab: 512 bytes of LDS for the group.
+// Returns the bound (wave 0 of the group); mn gets the wave's minimum of what it read.
+template <class K>
+__device__ uint32_t ip_partition_group(const typename K::S* s, typename K::S* d, uint32_t lb, uint32_t le,
+                                       typename K::R pv, bool strict, int G, int sw, bool go, uint8_t* tab,
+                                       typename K::R& mn) {
+  using R = typename K::R;
+  const int lane = lane_id();
+  const uint32_t n = go ? le - lb : 0u;
+  R m = K::maxv();
+  auto ld = [&](uint32_t i) -> R { return (R)s[i]; };
+  auto st = [&](uint32_t i, R x) { d[i] = ip_s<K>(x); };
+  uint16_t* off = reinterpret_cast<uint16_t*>(tab + 256);   // block k: [2k] left, [2k + 1] right keys before it
+  uint32_t bound = lb;
+  const bool small = n < 2 * IP_B;
+  const uint32_t nrem = n % IP_B, mb = n / IP_B, nl = mb >= 2 ? mb - 2 : 0u;
+  uint32_t lrem = 0;
+  if (go && !small) {
+    for (uint32_t x0 = 0; x0 < nrem; x0 += WAVE) {
+      const bool valid = x0 + (uint32_t)lane < nrem;
+      const R x = ld(lb + (valid ? x0 + (uint32_t)lane : 0u));
+      if (valid && sw == 0) m = K::kmin(m, x);
+      lrem += (uint32_t)__popcll(ballot(valid && ip_left<K>(x, pv, strict)));
+    }
+  }
+  const uint32_t rrem = nrem - lrem, ms = lb + lrem, me = le - rrem;
+  auto at = [&](uint32_t t) -> uint32_t { return t < rrem ? me + t : ms + t; };
+  // 1. counts
+  if (go && !small) {
+    for (uint32_t k = (uint32_t)sw; k < mb; k += (uint32_t)G) {
+#pragma unroll
+      for (int v = 0; v < IP_U; v++) {
+        const R x = ld(at(k * IP_B + v * IP_V + (uint32_t)lane));
+        m = K::kmin(m, x);
+        const uint32_t c = (uint32_t)__popcll(ballot(ip_left<K>(x, pv, strict)));
+        if (lane == 0) tab[4 * k + v] = (uint8_t)c;
+      }
+    }
+  }
+  __syncthreads();
+  // 2. ranks and offsets (wave 0 of the group; lane k = block k); the small split
+  if (go && sw == 0) {
+    if (small) {
+      bound = ip_partition_wave<K>(s, d, lb, le, pv, strict, m);
+    } else {
+      const uint32_t k = (uint32_t)lane;
+      uint32_t c4[IP_U];
+#pragma unroll
+      for (int v = 0; v < IP_U; v++) c4[v] = k < mb ? tab[4 * k + v] : 0u;
+      const uint32_t ck = c4[0] + c4[1] + c4[2] + c4[3];
+      const uint32_t P = (uint32_t)wave_incl_scan64((lane >= 1 && k <= nl) ? ck : 0u);
+      const uint32_t Q = read_lane(P, (int)nl);
+      const uint32_t pkm1 = (uint32_t)__shfl((int)P, lane >= 1 ? lane - 1 : 0);
+      const uint32_t ai = (uint32_t)IP_B * (k - 1) - pkm1;
+      const uint32_t bj = Q - P;
+      uint32_t cb = 0, ca = 0;
+      for (uint32_t x = 0; x < nl; x++) {
+        const uint32_t Ax = (uint32_t)IP_B * x - read_lane(P, (int)x);
+        const uint32_t Bx = Q - read_lane(P, (int)(nl - x));
+        cb += Bx < ai ? 1u : 0u;
+        ca += Ax <= bj ? 1u : 0u;
+      }
+      const bool loop_blk = k >= 1 && k <= nl;
+      const uint32_t pa = (k - 1) + cb;
+      const bool from_left = pa < nl;
+      const uint32_t step = loop_blk ? (from_left ? pa : (nl - k) + ca) : (k == 0 ? nl : nl + 1);
+      const uint32_t i = loop_blk ? (from_left ? k - 1 : step - (nl - k)) : 0u;
+      const uint32_t j = loop_blk ? step - i : 0u;
+      const uint32_t pi = (uint32_t)__shfl((int)P, (int)(i & (WAVE - 1)));
+      const uint32_t pj = (uint32_t)__shfl((int)P, (int)((nl - j) & (WAVE - 1)));
+      const uint32_t ck0 = read_lane(ck, 0);
+      const uint32_t lcb = loop_blk ? pi + (Q - pj) : Q + (k == 0 ? 0u : ck0);
+      if (k < mb) {
+        off[2 * k] = (uint16_t)lcb;
+        off[2 * k + 1] = (uint16_t)((uint32_t)IP_B * step - lcb);
+      }
+      bound = ms + Q + ck0 + read_lane(ck, (int)(mb - 1));
+    }
+  }
+  __syncthreads();
+  // 3. stores
+  if (go && !small) {
+    for (uint32_t k = (uint32_t)sw; k < mb; k += (uint32_t)G) {
+      const uint32_t l0 = off[2 * k], r0 = off[2 * k + 1];
+      uint32_t l = 0, r = 0;
+#pragma unroll
+      for (int v = 0; v < IP_U; v++) {
+        const R x = ld(at(k * IP_B + v * IP_V + (uint32_t)lane));
+        const uint32_t nlv = ip_store_vector<K>(x, ip_left<K>(x, pv, strict), st, ms + l0 + l, me - r0 - r);
+        l += nlv;
+        r += IP_V - nlv;
+      }
+    }
+    if (sw == 0) {
+      auto rem = [&](uint32_t i2) -> R { return ld(lb + i2); };
+      ip_store_remainder<K>(rem, st, lb, me, nrem, pv, strict);
+    }
+  }
+  mn = wave_min<K>(m);
+  return bound;
+}
+
 // ---- bounded-time sort in place ---------------------------------------------------------
 
 // Half-cleaner stages d = top .. 2 (pairs i, i + d/2 inside aligned blocks of d) of

@@ -2032,7 +2032,7 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
     // most half as many ranges as waves, G waves per range (the largest power of two
     // with nitems * G <= waves)
     int G = 1;
-    while (!IP && nitems > 0 && 2u * G * nitems <= (uint32_t)SOLO_NW) G *= 2;
+    while (nitems > 0 && 2u * G * nitems <= (uint32_t)SOLO_NW) G *= 2;
     // depth check of an item: true if it is to be partitioned (possibly now in
     // fallback mode); false if it went to the bounded-time list (by lane 0 of the
     // wave that reports it)
@@ -2198,6 +2198,21 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
       auto part_b = [&](int q) { const uint32_t o = (uint32_t)q * per; return it.lb + (o < len ? o : len); };
       // every wave of the group draws the same pivot itself: no broadcast barrier
       const R pivot = go ? pick_pivot(it, (uint32_t)item, s_buf) : K::maxv();
+      if constexpr (IP) {
+        // the in-place order; the group's block tables live in the next level's
+        // pivot-offset rows, which are written only after this level's partitions
+        static_assert(sizeof(ls.pvoff[0]) >= (SOLO_NW / 2) * 512, "in-place group tables");
+        uint8_t* tab = reinterpret_cast<uint8_t*>(&ls.pvoff[cur ^ 1][0][0]) + item * 512;
+        R mn;
+        const uint32_t bound = ip_partition_group<K>(s_buf, d_buf, it.lb, it.le, pivot, strict, G, sw, go, tab, mn);
+        if (go && lane == 0) ls.gmin[wave] = mn;
+        __syncthreads();
+        if (go && sw == 0) {
+          R gm = K::maxv();
+          for (int q = 0; q < G; q++) gm = K::kmin(gm, ls.gmin[item * G + q]);
+          plan(it, bound, gm, pivot);
+        }
+      } else {
       const uint32_t pb = part_b(sw), pe = part_b(sw + 1);
       uint32_t cnt = 0;
       R mn = K::maxv();
@@ -2239,6 +2254,7 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
       }
       __syncthreads();   // the whole partition is in d_buf before runs of it are copied
       if (go && sw == 0) plan(it, it.lb + ltot, gm, pivot);
+      }
     }
     __syncthreads();
     // the next level's ranges are known: one wave computes their ChoosePivot chunk
