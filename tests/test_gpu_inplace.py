@@ -74,6 +74,36 @@ def test_inplace_matches_the_oracle(vqs, kt, asc, config):
             assert st["levels"] >= 1
 
 
+@pytest.mark.parametrize("kt,asc", [(7, True), (7, False), (10, True), (10, False)])
+def test_inplace_i16_and_key_with_data(vqs, kt, asc):
+    """i16 keys, and 64-bit keys with 64-bit data (sorted as the 128-bit pair)."""
+    rng = np.random.default_rng(20 + kt)
+    for n in (900, 60_000, 300_000):
+        if kt == 7:
+            keys = rng.integers(-2**15, 2**15, n, dtype=np.int16)
+        else:
+            keys = np.empty((n, 2), np.uint64)
+            keys[:, 1] = rng.integers(0, 50, n, dtype=np.uint64)        # the key: many equal
+            keys[:, 0] = rng.integers(0, 2**64, n, dtype=np.uint64)     # the data
+        print(f"case: inplace kt={kt} asc={asc} n={n}", flush=True)
+        opts = {"solo_max": 4096, "local_keys": 2048} if n > 100_000 else {}
+        _check(vqs, keys, kt, asc, **opts)
+
+
+def test_inplace_stable_sort(vqs):
+    """The stable sort on the in-place path: same keys and permutation as without it."""
+    import torch
+    keys = np.random.default_rng(4).integers(0, 1000, 500_000).astype(np.uint32)
+    t1, t2 = to_gpu(keys), to_gpu(keys)
+    _, r1 = vqs.sort_stable(t1, key_type=U32)
+    _, r2 = vqs.sort_stable(t2, key_type=U32, inplace=1)
+    torch.cuda.synchronize()
+    assert vqs.last_error_bits() == 0
+    np.testing.assert_array_equal(to_host(t1), to_host(t2))
+    np.testing.assert_array_equal(to_host(r1), to_host(r2))
+    np.testing.assert_array_equal(to_host(r2), np.argsort(keys, kind="stable"))
+
+
 @pytest.mark.parametrize("dist", ["all_equal", "two_values", "eight_distinct", "zipf", "sorted", "reverse"])
 @pytest.mark.parametrize("config", ["default", "levels"])
 def test_inplace_degenerate_and_structured(vqs, dist, config):
