@@ -189,8 +189,9 @@ __device__ inline void ip_store_remainder(Load&& sv, Store&& store, uint64_t b, 
 // earlier tile of the range has loaded, then writes its two contiguous runs.  Tile 0
 // writes the remainder, the last tile the held-back blocks, and plans the children.
 
+// (four waves per SIMD: in place 2.5e8 f32 -7 %, 2e8 u16 -13 %)
 template <class K>
-__global__ void __launch_bounds__(LEVEL_P) ip_count_kernel(Params p) {
+__global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(4))) ip_count_kernel(Params p) {
   using R = typename K::R;
   using S = typename K::S;
   constexpr uint32_t ST = ip_steps_of(K::SIZE);
@@ -330,7 +331,7 @@ __global__ void __launch_bounds__(LEVEL_P) ip_count_kernel(Params p) {
 }
 
 template <class K>
-__global__ void __launch_bounds__(LEVEL_P) ip_scatter_kernel(Params p) {
+__global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(4))) ip_scatter_kernel(Params p) {
   using R = typename K::R;
   using S = typename K::S;
   constexpr uint32_t ST = ip_steps_of(K::SIZE);
