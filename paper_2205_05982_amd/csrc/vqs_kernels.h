@@ -484,12 +484,12 @@ static_assert(LB_WIN >= 1 && LB_WIN <= WAVE, "look-back window");
 constexpr int LEVEL_WAVES = VQS_LEVEL_WAVES;   // waves per SIMD the 8- and 16-byte level kernels target
 
 
-// Four waves per SIMD (four workgroups per CU) for every key width: the 2- and 4-byte
-// instantiations then spill 20 / 112 bytes per lane and still gain (2e8 u16 -7 %, 2e8
-// u32 -0.7 %, 2.5e8 f32 -1.1 %; five or six waves lose to spills); the 8-byte one keeps
-// its registers (152) and three waves.
+// Four waves per SIMD (four workgroups per CU) for 2-byte keys: 20 bytes per lane of
+// spills, 2e8 u16 -7 %.  The 4-byte instantiation would spill 112 bytes per lane at
+// four waves (+40 % HBM traffic for -1 % time) and keeps three; the 8- and 16-byte ones
+// fit three and four workgroups by their LDS.
 template <class K>
-__global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(4))) level_kernel(Params p) {
+__global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(K::SIZE == 2 ? 4 : 1))) level_kernel(Params p) {
   using R = typename K::R;
   using S = typename K::S;
   constexpr int I = K::LI;
