@@ -288,8 +288,10 @@ int vqs_sort_stable(void* keys, uint64_t n, int key_type, int ascending, uint64_
  *
  *  - Limit: n is accepted iff vqs_workspace_bytes(n, 1, key_type, options) <=
  *    VQS_NOALLOC_SCRATCH_BYTES (with default options on a 256-CU device up to about
- *    7.2e7 u16, 3.9e7 u32 or f32, 2.0e7 u64 or f64, 1.0e7 u128 keys); a larger n
- *    returns VQS_ESIZE and launches nothing.
+ *    7.2e7 u16, 3.9e7 u32 or f32, 2.0e7 u64 or f64, 1.0e7 u128 keys; with
+ *    options.inplace, which keeps no scratch array of keys, up to about 7.1e8 u16,
+ *    6.6e8 u32, 5.8e8 u64, 2.5e8 u128 keys); a larger n returns VQS_ESIZE and
+ *    launches nothing.
  *  - options: as for vqs_sort_ex, but method must be VQS_METHOD_PLAIN, use_graph 0
  *    and workspace NULL (VQS_EINVAL otherwise).
  *  - Sharing: every call on a device uses that device's one array, which keeps the
