@@ -374,6 +374,8 @@ size_t carve(char* mem, const Caps& c, Params* p) {
   p->ip_stash = mem + o_ipst;
   p->ip_pfx = (unsigned long long*)(mem + o_ippf);
   p->ip_rng = (IpRange*)(mem + o_iprg);
+  // the tile ranges share run mode's per-tile left counts (run mode is off in place)
+  p->ip_tseg = (uint32_t*)(mem + o_tnl);
   p->scratch = mem + o_scratch;  // re-based per call to the keys' alignment
   p->lvl_segs[0] = (Seg*)(mem + o_seg0);
   p->lvl_segs[1] = (Seg*)(mem + o_seg1);

@@ -58,25 +58,6 @@ __device__ inline bool ip_left(typename K::R x, typename K::R pv, bool strict) {
   return strict ? K::lt(x, pv) : !K::lt(pv, x);
 }
 
-// Range of level tile g: the last s with tbase[s] <= g (one wave, 64-fold narrowing
-// per step; wave-uniform result).
-__device__ inline uint32_t ip_find_seg(const unsigned long long* tbase, uint32_t nseg, unsigned long long g) {
-  const int lane = lane_id();
-  uint32_t lo = 0, hi = nseg;
-  while (hi - lo > 1) {
-    const uint32_t span = hi - lo;
-    const uint32_t step = (span + WAVE - 1) / WAVE;
-    const uint32_t pos = lo + (uint32_t)lane * step;
-    const bool le = pos < hi && tbase[pos] <= g;
-    const uint64_t m = ballot(le);
-    const int last = 63 - __builtin_clzll(m);
-    const uint32_t nlo = lo + (uint32_t)last * step;
-    hi = (nlo + step < hi) ? nlo + step : hi;
-    lo = nlo;
-  }
-  return lo;
-}
-
 constexpr unsigned long long IP_ST_AGG = 1ull << 46, IP_ST_INC = 2ull << 46, IP_VAL = (1ull << 46) - 1;
 // predecessors an in-place look-back step polls: the nearest inclusive tile is usually
 // a few tiles back, and polling 64 device-coherent words per step cost 3 % (1e8 u64)
@@ -189,6 +170,86 @@ __device__ inline void ip_store_remainder(Load&& sv, Store&& store, uint64_t b, 
 // earlier tile of the range has loaded, then writes its two contiguous runs.  Tile 0
 // writes the remainder, the last tile the held-back blocks, and plans the children.
 
+// A level's ranges, one wave each, after their pivots are known: the remainder's left
+// count, the remainder and the held-back blocks saved in internal form (the partition
+// launch overwrites their places before it stores them), the held-back blocks' left
+// counts, the smallest of these keys, and every tile's range.
+constexpr int IP_PRO_P = 256;
+
+template <class K>
+__global__ void __launch_bounds__(IP_PRO_P) ip_prologue_kernel(Params p) {
+  using R = typename K::R;
+  using S = typename K::S;
+  constexpr uint32_t ST = ip_steps_of(K::SIZE);
+  const int L = p.level;
+  const uint32_t nseg = (uint32_t)(p.lvl_ctr[L].packed >> 40);
+  const Seg* segs = p.lvl_segs[L & 1];
+  const unsigned long long* tbase = p.lvl_tbase[L & 1];
+  const S* keys = (const S*)p.keys;
+  const int tmode = (L == 0) ? p.mode : 0;
+  const int lane = lane_id();
+  const uint32_t wave0 = (blockIdx.x * IP_PRO_P + threadIdx.x) / WAVE;
+  const uint32_t nwaves = gridDim.x * (IP_PRO_P / WAVE);
+  unsigned long long keys_read = 0;
+  for (uint32_t si = wave0; si < nseg; si += nwaves) {
+    const Seg sg = segs[si];
+    if (lane == 0 && !(sg.flags & (SEG_PIVOT | SEG_OVERRIDE))) set_err(p, ERR_NO_PIVOT);
+    const uint64_t len = sg.e - sg.b;
+    const uint32_t nrem = (uint32_t)(len % IP_B);
+    const uint64_t nt = ip_tiles_of(len, ST);
+    const R pv = K::from_u64x2(sg.pv_lo, sg.pv_hi);
+    const bool strict = (sg.flags & SEG_STRICT) != 0;
+    S* sv = (S*)p.ip_stash + (uint64_t)si * IP_STASH;
+    R mn = K::maxv();
+    // the remainder (at most four vectors, all loads first)
+    R rk[IP_U];
+#pragma unroll
+    for (int u = 0; u < IP_U; u++) {
+      const uint32_t i = (uint32_t)(u * IP_V + lane);
+      rk[u] = ip_load<K>(keys, sg.b + (i < nrem ? i : 0u), tmode);
+    }
+    uint32_t lrem = 0;
+#pragma unroll
+    for (int u = 0; u < IP_U; u++) {
+      const uint32_t i = (uint32_t)(u * IP_V + lane);
+      if (i < nrem) {
+        sv[i] = ip_s<K>(rk[u]);
+        mn = K::kmin(mn, rk[u]);
+      }
+      lrem += (uint32_t)__popcll(ballot(i < nrem && ip_left<K>(rk[u], pv, strict)));
+    }
+    const uint32_t rrem = nrem - lrem;
+    const uint64_t ms = sg.b + lrem, me = sg.e - rrem;
+    // the held-back blocks: main index y of the first block is the range's last rrem
+    // keys, then the keys after the remainder's left ones
+    R hk[2 * IP_U];
+#pragma unroll
+    for (int u = 0; u < 2 * IP_U; u++) {
+      const uint32_t y = (uint32_t)((u % IP_U) * IP_V + lane);
+      hk[u] = ip_load<K>(keys, u < IP_U ? (y < rrem ? me + y : ms + y) : me - IP_B + y, tmode);
+    }
+    uint32_t cf = 0, cl = 0;
+#pragma unroll
+    for (int u = 0; u < 2 * IP_U; u++) {
+      sv[IP_B + u * IP_V + lane] = ip_s<K>(hk[u]);
+      mn = K::kmin(mn, hk[u]);
+      const uint32_t c = (uint32_t)__popcll(ballot(ip_left<K>(hk[u], pv, strict)));
+      if (u < IP_U) cf += c;
+      else cl += c;
+    }
+    mn = wave_min<K>(mn);
+    if (lane == 0) {
+      IpRange r{lrem, cf, cl, 0u, 0, 0};
+      to_words<K>(mn, r.mn_lo, r.mn_hi);
+      p.ip_rng[si] = r;
+    }
+    const unsigned long long g0 = tbase[si];
+    for (uint64_t t = (uint64_t)lane; t < nt; t += WAVE) p.ip_tseg[g0 + t] = si;
+    keys_read += nrem + 2 * IP_B;
+  }
+  if (lane == 0 && keys_read) atomicAdd(&p.stats->hbm_read_keys, keys_read);
+}
+
 // (four waves per SIMD: in place 2.5e8 f32 -7 %, 2e8 u16 -13 %)
 template <class K>
 __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(4))) ip_count_kernel(Params p) {
@@ -198,13 +259,11 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(4)
   constexpr int NW = LEVEL_P / WAVE;
   static_assert(ST <= WAVE, "one lane per block of a tile");
   __shared__ unsigned long long sh_ticket, sh_excl;
-  __shared__ uint32_t sh_seg, sh_lrem;
-  __shared__ uint32_t sh_cnt[ST + 2];   // loop blocks of the tile; [ST], [ST + 1]: held-back blocks
+  __shared__ uint32_t sh_cnt[ST];   // loop blocks of the tile
   __shared__ R sh_wmin[NW];
 
   const int L = p.level;
   const unsigned long long packed = p.lvl_ctr[L].packed;
-  const uint32_t nseg = (uint32_t)(packed >> 40);
   const unsigned long long ntiles = packed & TILE_MASK40;
   if (ntiles == 0) return;
   const Seg* segs = p.lvl_segs[L & 1];
@@ -216,38 +275,19 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(4)
   unsigned long long keys_read = 0;
   for (;;) {
     if (tid == 0) sh_ticket = atomicAdd(&p.lvl_ctr[L].ticket, 1u);
-    if (tid < (int)ST + 2) sh_cnt[tid] = 0;
     __syncthreads();
     const unsigned long long g = sh_ticket;
     if (g >= ntiles) break;
-    if (w == 0) {
-      const uint32_t si = ip_find_seg(tbase, nseg, g);
-      if (lane == 0) sh_seg = si;
-    }
-    __syncthreads();
-    const uint32_t si = sh_seg;
+    const uint32_t si = p.ip_tseg[g];
     const Seg sg = segs[si];
     const unsigned long long g0 = tbase[si];
     const uint64_t t = g - g0;
     const uint64_t len = sg.e - sg.b;
-    const uint32_t nrem = (uint32_t)(len % IP_B);
     const uint64_t nl = ip_loop_blocks(len);
     const R pv = K::from_u64x2(sg.pv_lo, sg.pv_hi);
     const bool strict = (sg.flags & SEG_STRICT) != 0;
-    if (tid == 0 && !(sg.flags & (SEG_PIVOT | SEG_OVERRIDE))) set_err(p, ERR_NO_PIVOT);
-    // the remainder's left count places the loop blocks: every tile takes it
-    if (w == 0) {
-      uint32_t c = 0;
-      for (uint32_t x0 = 0; x0 < nrem; x0 += WAVE) {
-        const bool valid = x0 + (uint32_t)lane < nrem;
-        const R x = ip_load<K>(keys, sg.b + (valid ? x0 + (uint32_t)lane : 0u), tmode);
-        c += (uint32_t)__popcll(ballot(valid && ip_left<K>(x, pv, strict)));
-      }
-      if (lane == 0) sh_lrem = c;
-    }
-    __syncthreads();
-    const uint32_t lrem = sh_lrem, rrem = nrem - lrem;
-    const uint64_t ms = sg.b + lrem, me = sg.e - rrem;
+    // the remainder's left count (from the prologue) places the loop blocks
+    const uint64_t ms = sg.b + p.ip_rng[si].lrem;
     const uint64_t k0 = 1 + t * ST;   // the tile's first loop block
     const uint32_t nblk = t * ST < nl ? (uint32_t)(nl - t * ST < ST ? nl - t * ST : ST) : 0u;
     R mn = K::maxv();
@@ -274,25 +314,6 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(4)
           }
           if (lane == 0) sh_cnt[kk] = c;
         }
-      }
-    }
-    if (t == 0) {
-      // the remainder and the held-back blocks, saved in internal form: the partition
-      // launch overwrites their places before it stores them
-      S* sv = (S*)p.ip_stash + (uint64_t)si * IP_STASH;
-      for (uint32_t x = (uint32_t)tid; x < IP_STASH; x += LEVEL_P) {   // whole waves per part
-        const uint32_t part = x / IP_B, y = x % IP_B;
-        const bool valid = part != 0 || y < nrem;
-        // main index y of the first block: the range's last rrem keys, then the keys after
-        // the remainder's left ones
-        const uint64_t pos = part == 0 ? sg.b + y : part == 1 ? (y < rrem ? me + y : ms + y) : me - IP_B + y;
-        const R v = ip_load<K>(keys, valid ? pos : sg.b, tmode);
-        if (valid) {
-          sv[x] = ip_s<K>(v);
-          mn = K::kmin(mn, v);
-        }
-        const uint32_t c = (uint32_t)__popcll(ballot(part != 0 && ip_left<K>(v, pv, strict)));
-        if (lane == 0 && part != 0) atomicAdd(&sh_cnt[ST + part - 1], c);
       }
     }
     mn = wave_min<K>(mn);
@@ -323,8 +344,7 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(4)
       v = wave_incl_scan64(v);
       if ((uint32_t)lane < nblk) p.ip_pfx[g0 * ST + (k0 - 1) + lane] = sh_excl + v;
     }
-    if (t == 0 && tid == 0) p.ip_rng[si] = IpRange{lrem, sh_cnt[ST], sh_cnt[ST + 1], 0u};
-    if (tid == 0) keys_read += (uint64_t)nblk * IP_B + (t == 0 ? nrem + 2 * IP_B : 0u);
+    if (tid == 0) keys_read += (uint64_t)nblk * IP_B;
     __syncthreads();
   }
   if (tid == 0 && keys_read) atomicAdd(&p.stats->hbm_read_keys, keys_read);
@@ -342,7 +362,7 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(4)
   using TW = Tile<K, LEVEL_P, 1>;
   __shared__ __attribute__((aligned(16))) S stage[ST * IP_B];
   __shared__ unsigned long long sh_ticket, sh_lc0, sh_fill0;
-  __shared__ uint32_t sh_seg, sh_nlt;
+  __shared__ uint32_t sh_nlt;
   __shared__ uint32_t sh_blk[ST];
   __shared__ uint32_t sh_vc[NV], sh_vlo[NV], sh_vro[NV];
   __shared__ R sh_wmin[NW];
@@ -350,7 +370,6 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(4)
 
   const int L = p.level;
   const unsigned long long packed = p.lvl_ctr[L].packed;
-  const uint32_t nseg = (uint32_t)(packed >> 40);
   const unsigned long long ntiles = packed & TILE_MASK40;
   if (ntiles == 0) return;
   const Seg* segs = p.lvl_segs[L & 1];
@@ -367,12 +386,7 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(4)
     __syncthreads();
     const unsigned long long g = sh_ticket;
     if (g >= ntiles) break;
-    if (w == 0) {
-      const uint32_t si = ip_find_seg(tbase, nseg, g);
-      if (lane == 0) sh_seg = si;
-    }
-    __syncthreads();
-    const uint32_t si = sh_seg;
+    const uint32_t si = p.ip_tseg[g];
     const Seg sg = segs[si];
     const unsigned long long g0 = tbase[si];
     const uint64_t t = g - g0;
@@ -559,8 +573,8 @@ __global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(4)
         if (tid == 0) route<K, 1>(p, make_seg<K>(sg.b, bound, sg.depth + 1, sg.limit, cf, pv), L + 1);
       } else if (bound == sg.e && !fb) {
         // degenerate: the range minimum decides (Alg. 1, ScanMinMax), from the count
-        // launch's tile minima
-        R m = K::maxv();
+        // launch's tile minima and the prologue's minimum of the other keys
+        R m = K::from_u64x2(ir.mn_lo, ir.mn_hi);
         for (unsigned long long tt = g0 + tid; tt < g0 + nt; tt += LEVEL_P)
           m = K::kmin(m, K::from_u64x2(p.tilemin[tt].lo, p.tilemin[tt].hi));
         m = wave_min<K>(m);

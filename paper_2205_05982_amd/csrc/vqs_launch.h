@@ -13,7 +13,7 @@ template <int BITS>
 struct Launch {
   static hipError_t clear(const Params& p, hipStream_t s);
   static hipError_t solo(const Params& p, int grid, hipStream_t s);
-  // in-place level: the counting launch, then the partition launch
+  // in-place level: the prologue, counting and partition launches
   static hipError_t ip_level(const Params& p, int grid, hipStream_t s);
   static constexpr uint64_t local_buffer_keys() { return (uint64_t)LOCAL_BYTES / (BITS / 8); }
 };

@@ -109,10 +109,12 @@ struct TileRun {
   uint32_t nl, nv;
 };
 
-// In-place partitions: a range of an in-place level, as its count launch leaves it for
-// the partition launch (left counts of the remainder and of the two held-back blocks)
+// In-place partitions: a range of an in-place level, as its prologue leaves it for the
+// counting and partition launches (left counts of the remainder and of the two
+// held-back blocks, and the smallest of their keys)
 struct IpRange {
   uint32_t lrem, cfirst, clast, pad;
+  uint64_t mn_lo, mn_hi;   // smallest of the remainder and held-back keys (internal form)
 };
 
 struct LevelCtr {
@@ -185,7 +187,8 @@ struct Params {
   uint32_t ip_steps;     // in-place level tiles: loop blocks per tile
   void* ip_stash;        // in-place levels: per range, its remainder and held-back blocks
   unsigned long long* ip_pfx;   // in-place levels: left-count prefix of every loop block
-  IpRange* ip_rng;       // in-place levels: per range, the counts its count launch found
+  IpRange* ip_rng;       // in-place levels: per range, what its prologue found
+  uint32_t* ip_tseg;     // in-place levels: the range of every tile
 };
 
 constexpr uint64_t FILL_CHUNK = 1ull << 16;
