@@ -129,7 +129,7 @@ def summarize(kt_dir, fetch_csv, write_csv, commands, title, copy_bytes=800_000_
             full_w = [v for v in kw if v > 0.9 * max(kw)] if max(kw) > 0 else [0.0]
             rd, wr = statistics.mean(full_f) * ff, statistics.mean(full_w) * wf
             wtxt = (f"writes {wr:.0f} KiB ({wr / alg_kib:.3f} of one pass)" if writes else
-                    f"writes {wr:.0f} KiB (block counts, saved blocks, tile minima)")
+                    f"writes {wr:.0f} KiB (block counts and their look-back words)")
             out.append(f"{lk}: {len(kd)} launches, {sum(kd) / 1e3:.3f} ms in all; on a full level "
                        f"(about {statistics.mean(full_d):.0f} us) it reads {rd:.0f} KiB ({rd / alg_kib:.3f} of "
                        f"one pass over the keys) and {wtxt}; "
