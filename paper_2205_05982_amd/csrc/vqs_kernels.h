@@ -135,19 +135,28 @@ struct Tile {
   __device__ static uint32_t rank_and_stage(S* stage, Aux& sh, const R (&key)[I][V], uint64_t k,
                                             uint64_t vs, uint64_t ve, R pivot, bool strict, R* tmin,
                                             Pub&& publish) {
+    return strict ? rank_and_stage_t<true>(stage, sh, key, k, vs, ve, pivot, tmin, publish)
+                  : rank_and_stage_t<false>(stage, sh, key, k, vs, ve, pivot, tmin, publish);
+  }
+  template <bool ST, class Pub>
+  __device__ static uint32_t rank_and_stage_t(S* stage, Aux& sh, const R (&key)[I][V], uint64_t k,
+                                              uint64_t vs, uint64_t ve, R pivot, R* tmin, Pub& publish) {
     const int tid = threadIdx.x;
     const int w = tid / WAVE;
     uint32_t pre[I];
     uint32_t flag[I];  // bit q: key (j, q) goes left
     R mn = K::maxv();
+    // positions relative to the tile's first v-index, so that bounds take 32-bit compares
+    const uint64_t tb = k * (uint64_t)T;
+    const uint32_t rlo = (uint32_t)(vs - tb), rhi = (uint32_t)(ve - tb);
 #pragma unroll
     for (int j = 0; j < I; j++) {
-      const uint64_t v0 = (k * TC + (uint64_t)j * P + tid) * V;
+      const uint32_t r0 = (uint32_t)(j * P + tid) * V;
       uint32_t f = 0, lanepre = 0, tot = 0;
 #pragma unroll
       for (int q = 0; q < V; q++) {
-        const bool valid = (v0 + q >= vs) && (v0 + q < ve);
-        const bool left = valid && (strict ? K::lt(key[j][q], pivot) : !K::lt(pivot, key[j][q]));
+        const bool valid = (r0 + q >= rlo) && (r0 + q < rhi);
+        const bool left = valid && (ST ? K::lt(key[j][q], pivot) : !K::lt(pivot, key[j][q]));
         if (valid) mn = K::kmin(mn, key[j][q]);
         const uint64_t m = ballot(left);
         lanepre += mbcnt(m);
@@ -182,13 +191,13 @@ struct Tile {
     const uint32_t nvalid = (uint32_t)(ve - vs);
 #pragma unroll
     for (int j = 0; j < I; j++) {
-      const uint64_t v0 = (k * TC + (uint64_t)j * P + tid) * V;
+      const uint32_t r0 = (uint32_t)(j * P + tid) * V;
       uint32_t lb = mybase[j] + pre[j];
 #pragma unroll
       for (int q = 0; q < V; q++) {
-        const uint64_t v = v0 + q;
-        if (v >= vs && v < ve) {
-          const uint32_t pos_in_tile = (uint32_t)(v - vs);
+        const uint32_t rv = r0 + q;
+        if (rv >= rlo && rv < rhi) {
+          const uint32_t pos_in_tile = rv - rlo;
           uint32_t dst;
           if ((flag[j] >> q) & 1u) {
             dst = lb;
@@ -2130,43 +2139,75 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
       }
     };
     constexpr int U = 4;   // four 64-key groups per step: independent loads, ballots, stores
-    // keys of [pb, pe) (a multiple of U*WAVE from the range start) to d_buf: left keys
-    // in order from l, right keys in order downward from r - 1
-    // keys of [pb, pe) (a multiple of U*WAVE from the range start) to d_buf: left keys
-    // in order from l, right keys in order downward from r - 1.  Branch-free: loads are
-    // clamped into the range, both predicates are evaluated, one masked store per key.
-    auto scatter = [&](const S* s_buf, S* d_buf, uint32_t pb, uint32_t pe, uint32_t l, uint32_t r, R pivot,
-                       bool strict, R& mn) -> uint32_t {
-      const uint32_t last = pe - 1;
-      for (uint32_t base = pb; base < pe; base += U * WAVE) {
+    // Keys of [pb, pe) to d_buf: left keys in order from l, right keys in order downward
+    // from r - 1; returns the final l.  The predicate (left: not after the pivot, or
+    // before it for a strict split) is fixed per instantiation, and whole steps of U
+    // vectors need no bounds: only the tail's last vector is partial.
+    auto scatter = [&](auto strict_tag, const S* s_buf, S* d_buf, uint32_t pb, uint32_t pe, uint32_t l, uint32_t r,
+                       R pivot) -> uint32_t {
+      constexpr bool ST = decltype(strict_tag)::value;
+      uint32_t base = pb;
+      for (; base + U * WAVE <= pe; base += U * WAVE) {
         R kx[U];
-        bool valid[U], isl[U];
-        uint64_t ml[U], vm[U];
+        bool isl[U];
+        uint64_t ml[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) kx[u] = (R)s_buf[base + u * WAVE + lane];
 #pragma unroll
         for (int u = 0; u < U; u++) {
-          const uint32_t i = base + u * WAVE + lane;
-          valid[u] = i < pe;
-          kx[u] = (R)s_buf[i < pe ? i : last];
-        }
-#pragma unroll
-        for (int u = 0; u < U; u++) {
-          const bool before = K::lt(kx[u], pivot), not_after = !K::lt(pivot, kx[u]);
-          isl[u] = valid[u] && (strict ? before : not_after);
-          mn = K::sel(valid[u], K::kmin(mn, kx[u]), mn);
+          isl[u] = ST ? K::lt(kx[u], pivot) : !K::lt(pivot, kx[u]);
           ml[u] = ballot(isl[u]);
-          vm[u] = ballot(valid[u]);
         }
 #pragma unroll
         for (int u = 0; u < U; u++) {
-          const uint32_t lrank = mbcnt(ml[u]), vrank = mbcnt(vm[u]);
-          const uint32_t d = isl[u] ? l + lrank : r - 1 - (vrank - lrank);
-          if (valid[u]) d_buf[d] = (S)kx[u];
+          const uint32_t lrank = mbcnt(ml[u]);
+          const uint32_t d = isl[u] ? l + lrank : r - 1 - ((uint32_t)lane - lrank);
+          d_buf[d] = (S)kx[u];
           const uint32_t nlft = (uint32_t)__popcll(ml[u]);
           l += nlft;
-          r -= (uint32_t)__popcll(vm[u]) - nlft;
+          r -= (uint32_t)WAVE - nlft;
         }
       }
+      for (; base < pe; base += WAVE) {
+        const uint32_t i = base + lane;
+        const bool valid = i < pe;
+        const R kx = (R)s_buf[valid ? i : pe - 1];
+        const bool isl = valid && (ST ? K::lt(kx, pivot) : !K::lt(pivot, kx));
+        const uint64_t ml = ballot(isl), vm = ballot(valid);
+        const uint32_t lrank = mbcnt(ml), vrank = mbcnt(vm);
+        const uint32_t d = isl ? l + lrank : r - 1 - (vrank - lrank);
+        if (valid) d_buf[d] = (S)kx;
+        const uint32_t nlft = (uint32_t)__popcll(ml);
+        l += nlft;
+        r -= (uint32_t)__popcll(vm) - nlft;
+      }
       return l;
+    };
+    // left count of [pb, pe) (the wave groups' counting pass)
+    auto count_left = [&](auto strict_tag, const S* s_buf, uint32_t pb, uint32_t pe, R pivot) -> uint32_t {
+      constexpr bool ST = decltype(strict_tag)::value;
+      uint32_t cnt = 0, base = pb;
+      for (; base + U * WAVE <= pe; base += U * WAVE) {
+        R kx[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) kx[u] = (R)s_buf[base + u * WAVE + lane];
+#pragma unroll
+        for (int u = 0; u < U; u++) cnt += (uint32_t)__popcll(ballot(ST ? K::lt(kx[u], pivot) : !K::lt(pivot, kx[u])));
+      }
+      for (; base < pe; base += WAVE) {
+        const uint32_t i = base + lane;
+        const bool valid = i < pe;
+        const R kx = (R)s_buf[valid ? i : pe - 1];
+        cnt += (uint32_t)__popcll(ballot(valid && (ST ? K::lt(kx, pivot) : !K::lt(pivot, kx))));
+      }
+      return cnt;
+    };
+    // The range minimum is needed only when nothing went right (Alg. 1's degenerate
+    // case, whose next pivot it is): taken then, from the partition's output, by one wave.
+    auto range_min = [&](const S* buf, uint32_t lb, uint32_t le) -> R {
+      R m = K::maxv();
+      for (uint32_t i = lb + lane; i < le; i += WAVE) m = K::kmin(m, (R)buf[i]);
+      return wave_min<K>(m);
     };
     if (G == 1) {
       for (uint32_t it_i = wave; it_i < nitems; it_i += SOLO_NW) {
@@ -2182,8 +2223,10 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
           const uint32_t bound = ip_partition_wave<K>(s_buf, d_buf, it.lb, it.le, pivot, strict, mn);
           plan(it, bound, mn, pivot);
         } else {
-          const uint32_t bound = scatter(s_buf, d_buf, it.lb, it.le, it.lb, it.le, pivot, strict, mn);
-          plan(it, bound, wave_min<K>(mn), pivot);
+          const uint32_t bound = strict ? scatter(std::true_type{}, s_buf, d_buf, it.lb, it.le, it.lb, it.le, pivot)
+                                        : scatter(std::false_type{}, s_buf, d_buf, it.lb, it.le, it.lb, it.le, pivot);
+          if (bound == it.le && !strict) mn = range_min(d_buf, it.lb, it.le);
+          plan(it, bound, mn, pivot);
         }
       }
     } else {
@@ -2218,30 +2261,13 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
         }
       } else {
       const uint32_t pb = part_b(sw), pe = part_b(sw + 1);
-      uint32_t cnt = 0;
-      R mn = K::maxv();
       if (go) {
-        for (uint32_t base = pb; base < pe; base += U * WAVE) {
-#pragma unroll
-          for (int u = 0; u < U; u++) {
-            const uint32_t i = base + u * WAVE + lane;
-            const bool valid = i < pe;
-            const R kx = (R)s_buf[i < pe ? i : pe - 1];
-            const bool before = K::lt(kx, pivot), not_after = !K::lt(pivot, kx);
-            const bool isl = valid && (strict ? before : not_after);
-            mn = K::sel(valid, K::kmin(mn, kx), mn);
-            cnt += (uint32_t)__popcll(ballot(isl));
-          }
-        }
-        mn = wave_min<K>(mn);
-        if (lane == 0) {
-          ls.gcnt[wave] = cnt;
-          ls.gmin[wave] = mn;
-        }
+        const uint32_t cnt = strict ? count_left(std::true_type{}, s_buf, pb, pe, pivot)
+                                    : count_left(std::false_type{}, s_buf, pb, pe, pivot);
+        if (lane == 0) ls.gcnt[wave] = cnt;
       }
       __syncthreads();
       uint32_t ltot = 0;
-      R gm = K::maxv();
       if (go) {
         uint32_t lbef = 0, rbef = 0;
         for (int q = 0; q < G; q++) {
@@ -2251,13 +2277,16 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
             rbef += (part_b(q + 1) - part_b(q)) - c;
           }
           ltot += c;
-          gm = K::kmin(gm, ls.gmin[item * G + q]);
         }
-        R unused = K::maxv();
-        scatter(s_buf, d_buf, pb, pe, it.lb + lbef, it.le - rbef, pivot, strict, unused);
+        if (strict) scatter(std::true_type{}, s_buf, d_buf, pb, pe, it.lb + lbef, it.le - rbef, pivot);
+        else scatter(std::false_type{}, s_buf, d_buf, pb, pe, it.lb + lbef, it.le - rbef, pivot);
       }
       __syncthreads();   // the whole partition is in d_buf before runs of it are copied
-      if (go && sw == 0) plan(it, it.lb + ltot, gm, pivot);
+      if (go && sw == 0) {
+        const uint32_t bound = it.lb + ltot;
+        const R gm = (bound == it.le && !strict) ? range_min(d_buf, it.lb, it.le) : K::maxv();
+        plan(it, bound, gm, pivot);
+      }
       }
     }
     __syncthreads();
