@@ -94,8 +94,17 @@ struct Tile {
   // Load the tile's chunks; key (j, q) of this thread sits at v-index
   // (k*TC + j*P + tid)*V + q.  Only chunks holding a key of [vs, ve) are read: a
   // 16-byte aligned load touching a valid key never leaves its page.
+  // SPLIT: a separate path for tiles wholly inside the range (most of them), which need
+  // no clamping (the solo kernel keeps one path: its registers are at their bound)
+  template <bool SPLIT = true>
   __device__ static void load(const S* base_aligned, uint64_t k, uint64_t vs, uint64_t ve, int tmode,
                               R (&key)[I][V]) {
+    if (SPLIT && vs == k * (uint64_t)T && ve == vs + T) load_t<true>(base_aligned, k, vs, ve, tmode, key);
+    else load_t<false>(base_aligned, k, vs, ve, tmode, key);
+  }
+  template <bool FULL>
+  __device__ static void load_t(const S* base_aligned, uint64_t k, uint64_t vs, uint64_t ve, int tmode,
+                                R (&key)[I][V]) {
     const int tid = threadIdx.x;
     // All chunk loads are issued, unconditionally, before any value is used, so they
     // are in flight together (a use or a branch between them makes each wait for its
@@ -106,7 +115,7 @@ struct Tile {
 #pragma unroll
     for (int j = 0; j < I; j++) {
       uint64_t c = k * TC + (uint64_t)j * P + tid;
-      c = c < cmin ? cmin : (c > cmax ? cmax : c);
+      if (!FULL) c = c < cmin ? cmin : (c > cmax ? cmax : c);
       raw[j] = *reinterpret_cast<const uint4*>(reinterpret_cast<const char*>(base_aligned) + c * 16);
     }
 #pragma unroll
@@ -135,10 +144,19 @@ struct Tile {
   __device__ static uint32_t rank_and_stage(S* stage, Aux& sh, const R (&key)[I][V], uint64_t k,
                                             uint64_t vs, uint64_t ve, R pivot, bool strict, R* tmin,
                                             Pub&& publish) {
-    return strict ? rank_and_stage_t<true>(stage, sh, key, k, vs, ve, pivot, tmin, publish)
-                  : rank_and_stage_t<false>(stage, sh, key, k, vs, ve, pivot, tmin, publish);
+    // A path for tiles wholly inside the range (no bounds per key) only for 2-byte keys:
+    // wider keys' kernels would need more than 168 registers with both paths inlined,
+    // which leaves two waves per SIMD instead of three (measured slower).
+    if constexpr (sizeof(S) == 2) {
+      if (vs == k * (uint64_t)T && ve == vs + T)
+        return strict ? rank_and_stage_t<true, true>(stage, sh, key, k, vs, ve, pivot, tmin, publish)
+                      : rank_and_stage_t<false, true>(stage, sh, key, k, vs, ve, pivot, tmin, publish);
+    }
+    return strict ? rank_and_stage_t<true, false>(stage, sh, key, k, vs, ve, pivot, tmin, publish)
+                  : rank_and_stage_t<false, false>(stage, sh, key, k, vs, ve, pivot, tmin, publish);
   }
-  template <bool ST, class Pub>
+  // ST: strict split; FULL: every key of the tile is in the range
+  template <bool ST, bool FULL, class Pub>
   __device__ static uint32_t rank_and_stage_t(S* stage, Aux& sh, const R (&key)[I][V], uint64_t k,
                                               uint64_t vs, uint64_t ve, R pivot, R* tmin, Pub& publish) {
     const int tid = threadIdx.x;
@@ -155,7 +173,7 @@ struct Tile {
       uint32_t f = 0, lanepre = 0, tot = 0;
 #pragma unroll
       for (int q = 0; q < V; q++) {
-        const bool valid = (r0 + q >= rlo) && (r0 + q < rhi);
+        const bool valid = FULL || ((r0 + q >= rlo) && (r0 + q < rhi));
         const bool left = valid && (ST ? K::lt(key[j][q], pivot) : !K::lt(pivot, key[j][q]));
         if (valid) mn = K::kmin(mn, key[j][q]);
         const uint64_t m = ballot(left);
@@ -196,7 +214,7 @@ struct Tile {
 #pragma unroll
       for (int q = 0; q < V; q++) {
         const uint32_t rv = r0 + q;
-        if (rv >= rlo && rv < rhi) {
+        if (FULL || (rv >= rlo && rv < rhi)) {
           const uint32_t pos_in_tile = rv - rlo;
           uint32_t dst;
           if ((flag[j] >> q) & 1u) {
@@ -2640,7 +2658,7 @@ __global__ void __launch_bounds__(SOLO_P) __attribute__((amdgpu_waves_per_eu(sol
         const uint64_t vs = (k * T > cur.b + p.off) ? k * T : cur.b + p.off;
         const uint64_t ve = ((k + 1) * T < cur.e + p.off) ? (k + 1) * T : cur.e + p.off;
         R key[SI][K::V];
-        TL::load(src_aligned, k, vs, ve, raw ? p.mode : 0, key);
+        TL::template load<false>(src_aligned, k, vs, ve, raw ? p.mode : 0, key);
         R tmin;
         const uint32_t nl = TL::rank_and_stage(bufA, aux, key, k, vs, ve, pivot, strict, &tmin, [](uint32_t, R) {});
         const uint32_t nvalid = (uint32_t)(ve - vs);
