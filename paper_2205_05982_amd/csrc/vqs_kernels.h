@@ -252,9 +252,14 @@ struct Tile {
   // the workgroup-sequential partitions of the solo kernel measured faster this way.
   __device__ static void write_out_keys(const S* stage, S* dst, uint32_t nleft, uint32_t nvalid,
                                         uint64_t left_base, uint64_t right_base, int tmode, uint64_t n_total) {
-    for (uint32_t s = threadIdx.x; s < nvalid; s += P) {
-      const uint64_t idx = s < nleft ? left_base + s : right_base + (s - nleft);
-      if (idx < n_total) dst[idx] = out_t(stage[s], tmode);
+    // the two runs in turn; the bounds check is per run (both always hold)
+    if (left_base + nleft <= n_total) {
+      S* d = dst + left_base;
+      for (uint32_t s = threadIdx.x; s < nleft; s += P) d[s] = out_t(stage[s], tmode);
+    }
+    if (right_base + (nvalid - nleft) <= n_total) {
+      S* d = dst + right_base;
+      for (uint32_t s = nleft + threadIdx.x; s < nvalid; s += P) d[s - nleft] = out_t(stage[s], tmode);
     }
   }
 
@@ -505,10 +510,11 @@ __device__ inline typename K::R range_min(const Params& p, const Seg& sg, int gt
 constexpr int LB_WIN = VQS_LB_WIN;
 static_assert(LB_WIN >= 1 && LB_WIN <= WAVE, "look-back window");
 
-#ifndef VQS_LEVEL_WAVES
-#define VQS_LEVEL_WAVES 4
-#endif
-constexpr int LEVEL_WAVES = VQS_LEVEL_WAVES;   // waves per SIMD the 8- and 16-byte level kernels target
+// Waves per SIMD the run-mode level kernel is compiled for: as many as its LDS lets in
+// (three workgroups of 40 KB tiles per CU for 8-byte keys, four of 32 KB for 16-byte
+// keys).  Asking for more than that is not a bound the compiler keeps.
+template <int SIZE>
+constexpr int runs_waves() { return SIZE == 8 ? 3 : SIZE == 16 ? 4 : 1; }
 
 
 // Four waves per SIMD (four workgroups per CU) for 2-byte keys: 20 bytes per lane of
@@ -858,7 +864,7 @@ struct RunEnt {
 // minimum; runs_plan_kernel plans the ranges afterwards.  Copy entries only gather
 // their runs into [b, e) for the solo kernel.
 template <class K>
-__global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(sizeof(typename K::R) >= 8 ? LEVEL_WAVES : 1))) level_runs_kernel(Params p) {
+__global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(runs_waves<sizeof(typename K::R)>()))) level_runs_kernel(Params p) {
   using R = typename K::R;
   using S = typename K::S;
   constexpr int I = K::LI;
@@ -2034,19 +2040,22 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
     }
   }
   if (c1 > c0) {
+    // range position of chunk c's first key: (c - c0) * V - head (32-bit)
+    const uint32_t head = (uint32_t)(vb - c0 * V), nch = (uint32_t)(c1 - c0);
 #pragma unroll
     for (int j = 0; j < LC; j++) {
-      const uint64_t c = c0 + tid + (uint64_t)j * SOLO_P;
-      if (c < c1) {
+      const uint32_t ci = (uint32_t)tid + (uint32_t)j * SOLO_P;
+      if (ci < nch) {
         R tmp[V];
         K::unpack(rawc[j], tmp);
+        const int32_t r0 = (int32_t)(ci * V) - (int32_t)head;
 #pragma unroll
         for (int q = 0; q < V; q++) {
-          const uint64_t v = c * V + q;
-          if (v >= vb && v < ve) {
+          const int32_t ri = r0 + q;
+          if (ri >= 0 && (uint32_t)ri < n) {
             R r = tmp[q];
             if (tmode) r = K::load_t((S)r, tmode);
-            bufA[v - vb] = (S)r;
+            bufA[ri] = (S)r;
           }
         }
       }
