@@ -517,12 +517,13 @@ template <int SIZE>
 constexpr int runs_waves() { return SIZE == 8 ? 3 : SIZE == 16 ? 4 : 1; }
 
 
-// Four waves per SIMD (four workgroups per CU) for 2-byte keys: 20 bytes per lane of
-// spills, 2e8 u16 -7 %.  The 4-byte instantiation would spill 112 bytes per lane at
-// four waves (+40 % HBM traffic for -1 % time) and keeps three; the 8- and 16-byte ones
-// fit three and four workgroups by their LDS.
+// Four waves per SIMD (four workgroups per CU) for 2- and 4-byte keys, with 40 and 36
+// bytes per lane of spills: 2e8 u16 -7 %, 2.5e8 f32 -3 % and 2e8 u32 -2.4 % (the 4-byte
+// kernel spilled 112 bytes at four waves and gained nothing before its ranking lost its
+// per-key branch work); the 8- and 16-byte ones fit three and four workgroups by their
+// LDS.
 template <class K>
-__global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(K::SIZE == 2 ? 4 : 1))) level_kernel(Params p) {
+__global__ void __launch_bounds__(LEVEL_P) __attribute__((amdgpu_waves_per_eu(K::SIZE <= 4 ? 4 : 1))) level_kernel(Params p) {
   using R = typename K::R;
   using S = typename K::S;
   constexpr int I = K::LI;
