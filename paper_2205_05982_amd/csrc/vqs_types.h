@@ -19,9 +19,10 @@ constexpr int MODE_SIGNED = 4;   // two's-complement integers: the sign bit flip
 constexpr int LEVEL_P = VQS_LEVEL_P;  // threads per level-kernel workgroup
 constexpr int LEVEL_NW = LEVEL_P / 64;  // its waves
 // 16-byte chunks per thread of a level tile, by key width (measured): 16 KB tiles for
-// u16 (its keys take one register each), 32 KB for u32, 40 KB for u64, 32 KB for u128
-// (three or four workgroups per CU)
-constexpr int level_chunks(int bits) { return bits == 16 ? 4 : bits == 32 ? 8 : bits == 64 ? 10 : 8; }
+// u16 (its keys take one register each), 36 KB for u32 (four workgroups per CU; 2.5e8
+// f32 -4.3 % against 32 KB), 40 KB for u64 (three per CU; 44 and 48 KB slower), 32 KB
+// for u128
+constexpr int level_chunks(int bits) { return bits == 16 ? 4 : bits == 32 ? 9 : bits == 64 ? 10 : 8; }
 // the second compiled tile size (vqs_options.tile_variant = 1): half the chunks, for
 // batches of many short ranges whose last, partial tiles would otherwise dominate
 constexpr int level_chunks_half(int bits) { return level_chunks(bits) / 2; }
