@@ -261,14 +261,15 @@ int make_plan(uint64_t n, uint64_t nseg, int kt, int asc, const vqs_options* o, 
     pl->solo = o->solo_max;
     if (pl->solo < pl->local) return VQS_EINVAL;
   } else {
-    // ranges above 48K keys are partitioned by the device-wide level kernel, which
+    // ranges above 32K keys are partitioned by the device-wide level kernel, which
     // moves data faster than one workgroup's partitions (below that, a level's fixed
-    // costs outweigh it: 1e8 u64 and 2.5e8 f32 -0.7 % and -0.9 % against 32K, 16K and
-    // 64K slower); a few times more ranges than solo workgroups keep the solo kernel
-    // busy on very large inputs, and on inputs too small to give it four such ranges
-    // per workgroup the threshold drops towards the LDS capacity (2e7 u64: -3.4 %)
+    // costs outweigh it: measured on 1e8 u64 and 2e8 u32; 48K: 1e8 u64 even, 1e8 Zipf
+    // +2.5 %, 2.5e8 f32 -0.9 %); a few times more ranges than solo workgroups keep the
+    // solo kernel busy on very large inputs, and on inputs too small to give it four
+    // 32K-key ranges per workgroup the threshold drops towards the LDS capacity (2e7
+    // u64: -3.4 %)
     uint64_t s = n / ((uint64_t)g.solo_grid * 16);
-    const uint64_t floor_ = std::min<uint64_t>(3u << 14, n / ((uint64_t)g.solo_grid * 4));
+    const uint64_t floor_ = std::min<uint64_t>(1u << 15, n / ((uint64_t)g.solo_grid * 4));
     s = std::max<uint64_t>(s, std::max<uint64_t>(pl->local, floor_));
     s = std::min<uint64_t>(s, 1ull << 20);
     pl->solo = std::max<uint64_t>(s, pl->local);
