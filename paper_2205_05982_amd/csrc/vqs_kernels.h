@@ -1928,6 +1928,12 @@ struct LocalItem {
   typename K::R pv;
 };
 
+// The recursion counts of a workgroup's local sorts, summed in LDS by its thread 0 and
+// added to the device-wide counters once, when the solo kernel ends.
+struct LocalCounts {
+  unsigned long long part, pkeys, bc, deg, eq, fb, fbkeys, maxd;
+};
+
 template <class K>
 struct LocalShared {
   LocalItem<K> list[2][LIST_CAP];
@@ -1987,7 +1993,7 @@ template <class K, bool IP>
 __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* bufA, typename K::S* bufB,
                            const typename K::S* src, bool raw, uint64_t b, uint64_t e, uint32_t depth,
                            uint32_t limit, uint32_t item_flags, typename K::R pv, typename K::S* out,
-                           bool out_internal) {
+                           bool out_internal, LocalCounts& acc) {
   using R = typename K::R;
   using S = typename K::S;
   constexpr int V = K::V;
@@ -2411,19 +2417,14 @@ __device__ void local_sort(const Params& p, LocalShared<K>& ls, typename K::S* b
     out[b + i] = val;
   }
   if (tid == 0) {
-    if (ls.stat_part) {
-      atomicAdd(&p.stats->partitions, (unsigned long long)ls.stat_part);
-      atomicAdd(&p.stats->lds_partitions, (unsigned long long)ls.stat_part);
-      atomicAdd(&p.stats->keys_partitioned, (unsigned long long)ls.stat_pkeys);
-      atomicMax(&p.stats->max_depth, (unsigned long long)ls.stat_maxd);
-    }
-    if (ls.stat_bc) atomicAdd(&p.stats->basecases, (unsigned long long)ls.stat_bc);
-    if (ls.stat_deg) atomicAdd(&p.stats->degenerate, (unsigned long long)ls.stat_deg);
-    if (ls.stat_eq) atomicAdd(&p.stats->all_equal, (unsigned long long)ls.stat_eq);
-    if (ls.stat_fb) {
-      atomicAdd(&p.stats->fallbacks, (unsigned long long)ls.stat_fb);
-      atomicAdd(&p.stats->fallback_keys, (unsigned long long)ls.stat_fbkeys);
-    }
+    acc.part += ls.stat_part;
+    acc.pkeys += ls.stat_pkeys;
+    acc.maxd = ls.stat_maxd > acc.maxd ? ls.stat_maxd : acc.maxd;
+    acc.bc += ls.stat_bc;
+    acc.deg += ls.stat_deg;
+    acc.eq += ls.stat_eq;
+    acc.fb += ls.stat_fb;
+    acc.fbkeys += ls.stat_fbkeys;
   }
   __syncthreads();
 }
@@ -2563,6 +2564,8 @@ __global__ void __launch_bounds__(SOLO_P) __attribute__((amdgpu_waves_per_eu(sol
   const unsigned long long count = p.solo_ctr->count;
   const unsigned long long nitems = count < p.cap_solo ? count : p.cap_solo;
   unsigned long long hrd = 0, hwr = 0;   // thread 0: keys read / written by whole-key sweeps
+  __shared__ LocalCounts acc;            // the local sorts' recursion counts (thread 0 writes)
+  if (tid == 0) acc = LocalCounts{};
   for (;;) {
     if (tid == 0) sh_item = atomicAdd(&p.solo_ctr->ticket, 1ull);
     __syncthreads();
@@ -2603,7 +2606,7 @@ __global__ void __launch_bounds__(SOLO_P) __attribute__((amdgpu_waves_per_eu(sol
         const uint32_t lf = ((cur.flags & SEG_OVERRIDE) ? LI_OVERRIDE : 0u) |
                             ((cur.flags & SEG_FALLBACK) ? LI_FB : 0u) | ((cur.flags & SEG_STRICT) ? LI_STRICT : 0u);
         local_sort<K, IP>(p, ls, bufA, bufB, src, raw, cur.b, cur.e, cur.depth, cur.limit, lf,
-                      K::from_u64x2(cur.pv_lo, cur.pv_hi), (S*)p.keys, false);
+                      K::from_u64x2(cur.pv_lo, cur.pv_hi), (S*)p.keys, false, acc);
         if (tid == 0) {
           hrd += n;
           hwr += n;
@@ -2748,6 +2751,21 @@ __global__ void __launch_bounds__(SOLO_P) __attribute__((amdgpu_waves_per_eu(sol
   if (tid == 0 && (hrd | hwr)) {
     atomicAdd(&p.stats->hbm_read_keys, hrd);
     atomicAdd(&p.stats->hbm_write_keys, hwr);
+  }
+  if (tid == 0) {
+    if (acc.part) {
+      atomicAdd(&p.stats->partitions, acc.part);
+      atomicAdd(&p.stats->lds_partitions, acc.part);
+      atomicAdd(&p.stats->keys_partitioned, acc.pkeys);
+      atomicMax(&p.stats->max_depth, acc.maxd);
+    }
+    if (acc.bc) atomicAdd(&p.stats->basecases, acc.bc);
+    if (acc.deg) atomicAdd(&p.stats->degenerate, acc.deg);
+    if (acc.eq) atomicAdd(&p.stats->all_equal, acc.eq);
+    if (acc.fb) {
+      atomicAdd(&p.stats->fallbacks, acc.fb);
+      atomicAdd(&p.stats->fallback_keys, acc.fbkeys);
+    }
   }
 }
 
