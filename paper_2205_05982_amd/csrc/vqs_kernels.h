@@ -1928,10 +1928,12 @@ struct LocalItem {
   typename K::R pv;
 };
 
-// The recursion counts of a workgroup's local sorts, summed in LDS by its thread 0 and
-// added to the device-wide counters once, when the solo kernel ends.
+// The recursion counts of a solo workgroup (its local sorts and its partitions through
+// device memory), summed in LDS by its thread 0 and added to the device-wide counters
+// once, when the solo kernel ends.
 struct LocalCounts {
   unsigned long long part, pkeys, bc, deg, eq, fb, fbkeys, maxd;
+  unsigned long long gpart, gkeys, fbpart;   // the solo kernel's partitions through device memory
 };
 
 template <class K>
@@ -2691,12 +2693,11 @@ __global__ void __launch_bounds__(SOLO_P) __attribute__((amdgpu_waves_per_eu(sol
         hrd += n;
         hwr += n;
         if (!fb) {
-          atomicAdd(&p.stats->partitions, 1ull);
-          atomicAdd(&p.stats->global_solo_partitions, 1ull);
-          atomicAdd(&p.stats->keys_partitioned, (unsigned long long)n);
-          atomicMax(&p.stats->max_depth, (unsigned long long)cur.depth);
+          acc.gpart++;
+          acc.gkeys += n;
+          acc.maxd = cur.depth > acc.maxd ? cur.depth : acc.maxd;
         } else {
-          atomicAdd(&p.stats->fallback_partitions, 1ull);
+          acc.fbpart++;
         }
       }
       __syncthreads();
@@ -2753,12 +2754,14 @@ __global__ void __launch_bounds__(SOLO_P) __attribute__((amdgpu_waves_per_eu(sol
     atomicAdd(&p.stats->hbm_write_keys, hwr);
   }
   if (tid == 0) {
-    if (acc.part) {
-      atomicAdd(&p.stats->partitions, acc.part);
-      atomicAdd(&p.stats->lds_partitions, acc.part);
-      atomicAdd(&p.stats->keys_partitioned, acc.pkeys);
+    if (acc.part | acc.gpart) {
+      atomicAdd(&p.stats->partitions, acc.part + acc.gpart);
+      atomicAdd(&p.stats->keys_partitioned, acc.pkeys + acc.gkeys);
       atomicMax(&p.stats->max_depth, acc.maxd);
     }
+    if (acc.part) atomicAdd(&p.stats->lds_partitions, acc.part);
+    if (acc.gpart) atomicAdd(&p.stats->global_solo_partitions, acc.gpart);
+    if (acc.fbpart) atomicAdd(&p.stats->fallback_partitions, acc.fbpart);
     if (acc.bc) atomicAdd(&p.stats->basecases, acc.bc);
     if (acc.deg) atomicAdd(&p.stats->degenerate, acc.deg);
     if (acc.eq) atomicAdd(&p.stats->all_equal, acc.eq);
