@@ -9,7 +9,8 @@ timed region starts and nothing but sorting is timed.  Prints one JSON line.
 
 The line also carries "learned_vs_plain": the 5e8-key lognormal-mixture workload
 sorted by both methods (median of a few sorts each), the speedup of the learned
-256-bucket splitter and whether both outputs are identical; and "batched": the
+256-bucket splitter, whether both outputs are identical and the bucket balance of
+the trained model against the same model untrained; and "batched": the
 65,536-segment u32 batch sorted by one hipGraph replay (library defaults and the
 autotuner's choice) against one vqs_sort call per segment; and "inplace": the same
 input sorted in place (the paper's in-place partition order, no key scratch), its
@@ -145,9 +146,11 @@ def bench_batched(args, kt: int, desc: str) -> None:
     print(json.dumps(line), flush=True)
 
 
-def batched_record(reps: int = 3, tune_keys: int = 200_000_000) -> dict:
+def batched_record(reps: int = 3, tune_keys: int = 0) -> dict:
     """The 65,536-segment u32 batch (lengths log-uniform in [16, 2^20], 6.1e9 keys):
-    the autotuner's choice on a prefix of about tune_keys keys, then the whole batch
+    the autotuner's choice on a prefix of about tune_keys keys (0: the whole batch; the
+    library's default solo threshold grows with the key count, so a threshold chosen on
+    a prefix need not suit the whole batch), then the whole batch
     sorted by one hipGraph replay (total key count given, so a replay never waits on
     the host) with the library defaults and with the tuned settings, median of reps
     each, against one vqs_sort call per segment (once)."""
@@ -210,11 +213,33 @@ def batched_record(reps: int = 3, tune_keys: int = 200_000_000) -> dict:
         "workload": "65,536 u32 segments, lengths log-uniform [16, 2^20] (seed 12), keys seed 13",
         "n": n, "segments": 65536,
         "graph_ms_default": round(ms_default, 2), "graph_ms_tuned": round(ms_tuned, 2),
-        "tuned": settings, "tune_prefix_keys": tune_keys, "tune_s": round(tune_s, 1),
+        "tuned": settings, "tune_prefix_keys": tune_keys or n, "tune_s": round(tune_s, 1),
         "gkeys": round(n / best / 1e6, 2), "gbs": gbs(best),
         "per_array_ms": round(ms_per_array, 1), "per_array_gbs": gbs(ms_per_array),
         "speedup_vs_per_array": round(ms_per_array / best, 1), "sorted": ok,
     }
+
+
+def bucket_balance(vqs, keys) -> dict:
+    """Bucket sizes of the model the learned sort trains on `keys` (library defaults)
+    and of the same model before training (same input scaling), over every key:
+    largest bucket / expected size n/256, rms relative deviation, empty buckets."""
+    import torch
+    trained = vqs.learned_fit(keys)
+    untrained = torch.empty_like(trained)
+    vqs.mlp_init(untrained, 16, torch.tensor([0.0, 1.0], dtype=torch.float32, device=keys.device))
+    untrained[vqs.MLP_NPARAM:] = trained[vqs.MLP_NPARAM:]
+    expected = keys.numel() / 256
+    out = {}
+    for name, params in (("trained", trained), ("untrained", untrained)):
+        h = torch.bincount(vqs.mlp_buckets(params, keys).long(), minlength=256).double()
+        dev = (h - expected) / expected
+        out[name] = {"max_over_expected": round(float(h.max()) / expected, 3),
+                     "rms_rel_dev": round(float(dev.pow(2).mean().sqrt()), 3),
+                     "empty": int((h == 0).sum())}
+        del h
+    torch.cuda.empty_cache()
+    return out
 
 
 def learned_vs_plain(n: int, reps: int) -> dict:
@@ -268,6 +293,7 @@ def learned_vs_plain(n: int, reps: int) -> dict:
                               "overflow_buckets": st["overflow_buckets"],
                               "train_loss": st["train_loss"]})
         outs[name] = work.clone() if method == 0 else work
+    balance = bucket_balance(vqs, src)
     identical = bool(torch.equal(outs["plain"].view(torch.int64), outs["learned"].view(torch.int64)))
     o = outs["learned"].view(torch.int64) ^ torch.tensor(-(2**63), dtype=torch.int64, device=dev)
     sorted_ok = bool((o[1:] >= o[:-1]).all().item())
@@ -280,6 +306,7 @@ def learned_vs_plain(n: int, reps: int) -> dict:
         "learned_gkeys": round(n / res["learned"]["ms"] / 1e6, 3),
         "identical_output": identical,
         "sorted": sorted_ok,
+        "bucket_balance": balance,
         "learned": {k: v for k, v in res["learned"].items() if k != "ms"},
         "plain": {k: v for k, v in res["plain"].items() if k != "ms"},
         "reps": reps,
