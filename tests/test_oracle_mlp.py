@@ -146,3 +146,17 @@ def test_untrained_model_is_near_identity_on_xn():
     xn = (x - 0.5) * 4.0
     assert np.max(np.abs(y - xn)) < 0.06
     assert (p[mlp.SL["W2"]] > 0).all()
+
+
+def test_learning_rate_schedule_endpoints_and_linearity():
+    """The schedule's defining properties: lr at the first step, lr/10 at the last,
+    equal decrements in between (a linear decay), and a lone step at lr."""
+    lr, steps = 0.003, 100
+    sched = np.array([mlp.lr_at(s, steps, lr) for s in range(1, steps + 1)])
+    assert sched[0] == pytest.approx(lr, rel=1e-15)
+    assert sched[-1] == pytest.approx(lr / 10, rel=1e-12)
+    d = np.diff(sched)
+    assert np.all(d < 0)
+    np.testing.assert_allclose(d, d[0], rtol=1e-9)
+    assert d.sum() == pytest.approx(-0.9 * lr, rel=1e-12)
+    assert mlp.lr_at(1, 1, lr) == lr
