@@ -83,6 +83,8 @@ def parse():
     ap.add_argument("--learned-reps", type=int, default=3)
     ap.add_argument("--per-array", action="store_true",
                     help="batched workloads: also time one vqs_sort call per segment")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="batched workloads: library defaults instead of the autotuner's choice")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 65,536-segment batch record of the default line")
     return ap.parse_args()
@@ -90,9 +92,10 @@ def parse():
 
 def bench_batched(args, kt: int, desc: str) -> None:
     """The 65,536-segment batch: keys generated on the GPU (SplitMix64 by index), the
-    autotuner's settings chosen on a prefix of about 2e8 keys, then the whole batch
-    sorted by one vqs_sort_segmented call replaying a hipGraph (total key count
-    given, so a replay never waits on the host)."""
+    autotuner's settings chosen on the whole batch (with --no-tune the library
+    defaults, e.g. for a profiled run that should trace only the timed sorts), then
+    the whole batch sorted by one vqs_sort_segmented call replaying a hipGraph (total
+    key count given, so a replay never waits on the host)."""
     import torch
     from paper_2205_05982_amd import vqs
     from paper_2205_05982_amd import workloads as W
@@ -105,9 +108,11 @@ def bench_batched(args, kt: int, desc: str) -> None:
     o = torch.from_numpy(off).to(dev)
     stream = torch.cuda.current_stream()
     work.copy_(src)
-    tuned = vqs.autotune_segmented(work, o, key_type=kt, max_keys=200_000_000)
-    settings = {k: tuned[k] for k in vqs.TUNED_FIELDS}
-    print(f"# tuned on a prefix: {settings}", file=sys.stderr, flush=True)
+    settings = {}
+    if not args.no_tune:
+        tuned = vqs.autotune_segmented(work, o, key_type=kt)
+        settings = {k: tuned[k] for k in vqs.TUNED_FIELDS}
+        print(f"# tuned on the whole batch: {settings}", file=sys.stderr, flush=True)
     times = []
     for r in range(args.warmup + args.steps):
         work.copy_(src)
