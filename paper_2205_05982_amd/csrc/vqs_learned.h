@@ -21,8 +21,11 @@ constexpr int MLP_NBLOCK = MLP_NPARAM + 2;                                      
 constexpr int MLP_W1 = 0, MLP_B1 = 32, MLP_W2 = 64, MLP_B2 = 64 + 1024, MLP_W3 = MLP_B2 + 32,
               MLP_B3 = MLP_W3 + 32, MLP_X0 = MLP_B3 + 1, MLP_XS = MLP_X0 + 1;
 constexpr int MLP_MAX_BATCH = 256;     // samples per optimiser step (one workgroup)
-constexpr int LEARN_TILE = 4096;       // keys per histogram / scatter tile
-constexpr int CHUNK_TILES = 16;        // consecutive tiles counted together and scattered by one workgroup
+#ifndef VQS_LEARN_TILE
+#define VQS_LEARN_TILE 8192
+#endif
+constexpr int LEARN_TILE = VQS_LEARN_TILE;      // keys per histogram / scatter tile
+constexpr int CHUNK_TILES = 65536 / LEARN_TILE; // consecutive tiles counted together and scattered by one workgroup
 constexpr int NBUCKET = 256;
 
 struct TrainArgs {

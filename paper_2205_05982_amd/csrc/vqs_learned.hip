@@ -581,7 +581,7 @@ __global__ void classify_kernel(const uint64_t* keys, uint64_t n, const uint64_t
 // XCD (partial cache lines only where a stretch begins or ends).
 
 constexpr int LT_P = 256;
-constexpr int LT_PER = LEARN_TILE / LT_P;   // 16 keys per thread
+constexpr int LT_PER = LEARN_TILE / LT_P;   // keys per thread
 constexpr int LT_NW = LT_P / WAVE;
 static_assert(LT_P == NBUCKET, "thread b of a workgroup owns bucket b");
 
@@ -701,8 +701,16 @@ __global__ void __launch_bounds__(LT_P) offsets_kernel(const uint64_t* totals, u
 // the tile per bucket (LDS atomics), stage bucket-major in LDS, write each bucket's run of
 // the tile to the bucket's running destination (offsets[b] + its keys in earlier chunks +
 // its keys in earlier tiles of this chunk).  The next tile's loads are issued before the
-// current tile is written out.
-__global__ void __launch_bounds__(LT_P) scatter_kernel(const uint64_t* keys, uint64_t n, const uint64_t* thr,
+// current tile is written out.  SC_P threads per workgroup; threads b < NBUCKET also own
+// bucket b (its count, staged start and running destination).
+#ifndef VQS_SCATTER_THREADS
+#define VQS_SCATTER_THREADS 256
+#endif
+constexpr int SC_P = VQS_SCATTER_THREADS;
+constexpr int SC_PER = LEARN_TILE / SC_P;   // keys per thread
+static_assert(SC_P >= NBUCKET && SC_P % WAVE == 0 && LEARN_TILE % SC_P == 0, "scatter workgroup shape");
+
+__global__ void __launch_bounds__(SC_P) scatter_kernel(const uint64_t* keys, uint64_t n, const uint64_t* thr,
                                                        const uint32_t* nvalid, const uint32_t* hist,
                                                        uint64_t nchunks, const int64_t* offsets, uint64_t* out) {
   __shared__ uint64_t E[NBUCKET];
@@ -711,68 +719,71 @@ __global__ void __launch_bounds__(LT_P) scatter_kernel(const uint64_t* keys, uin
   __shared__ uint64_t DL[NBUCKET];           // destination of staged slot s of bucket b: DL[b] + s
   __shared__ uint64_t stage[LEARN_TILE];
   __shared__ uint8_t bid[LEARN_TILE];
-  __shared__ uint32_t W[LT_NW];
+  __shared__ uint32_t W[NBUCKET / WAVE];
+  const bool own = threadIdx.x < NBUCKET;
   tree_load(E, thr);
-  C[threadIdx.x] = 0;
+  if (own) C[threadIdx.x] = 0;
   const int J = (int)*nvalid;
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
   const uint64_t ntiles = (n + LEARN_TILE - 1) / LEARN_TILE;
-  uint64_t k[LT_PER];
+  uint64_t k[SC_PER];
   auto load = [&](uint64_t tile) {
     const uint64_t base = tile * LEARN_TILE;
     if (base + LEARN_TILE <= n) {
 #pragma unroll
-      for (int q = 0; q < LT_PER; q++) k[q] = keys[base + (uint64_t)q * LT_P + threadIdx.x];
+      for (int q = 0; q < SC_PER; q++) k[q] = keys[base + (uint64_t)q * SC_P + threadIdx.x];
     } else {
 #pragma unroll
-      for (int q = 0; q < LT_PER; q++) {
-        const uint64_t i = base + (uint64_t)q * LT_P + threadIdx.x;
+      for (int q = 0; q < SC_PER; q++) {
+        const uint64_t i = base + (uint64_t)q * SC_P + threadIdx.x;
         k[q] = i < n ? keys[i] : 0;
       }
     }
   };
   for (uint64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
-    // thread b alone reads and writes dst (its bucket's running destination)
-    uint64_t dst = (uint64_t)offsets[threadIdx.x] + hist[ch * NBUCKET + threadIdx.x];
+    // thread b < NBUCKET alone reads and writes dst (its bucket's running destination)
+    uint64_t dst = own ? (uint64_t)offsets[threadIdx.x] + hist[ch * NBUCKET + threadIdx.x] : 0;
     const uint64_t t0 = ch * CHUNK_TILES, t1 = min(t0 + CHUNK_TILES, ntiles);
     load(t0);
     __syncthreads();
     for (uint64_t tile = t0; tile < t1; tile++) {
       const uint32_t cnt = (uint32_t)min((uint64_t)LEARN_TILE, n - tile * LEARN_TILE);
-      int bb[LT_PER];
-      uint32_t r[LT_PER];
+      int bb[SC_PER];
+      uint32_t r[SC_PER];
 #pragma unroll
-      for (int q = 0; q < LT_PER; q++) bb[q] = classify(E, J, k[q]);
+      for (int q = 0; q < SC_PER; q++) bb[q] = classify(E, J, k[q]);
       if (cnt == LEARN_TILE) {
 #pragma unroll
-        for (int q = 0; q < LT_PER; q++) r[q] = atomicAdd(&C[bb[q]], 1u);
+        for (int q = 0; q < SC_PER; q++) r[q] = atomicAdd(&C[bb[q]], 1u);
       } else {
 #pragma unroll
-        for (int q = 0; q < LT_PER; q++)
-          r[q] = (uint32_t)(q * LT_P + threadIdx.x) < cnt ? atomicAdd(&C[bb[q]], 1u) : 0u;
+        for (int q = 0; q < SC_PER; q++)
+          r[q] = (uint32_t)(q * SC_P + threadIdx.x) < cnt ? atomicAdd(&C[bb[q]], 1u) : 0u;
       }
       __syncthreads();
       {  // exclusive scan of the tile's bucket counts; thread b owns C[b] from here on
-        const uint32_t v = C[threadIdx.x];
+        const uint32_t v = own ? C[threadIdx.x] : 0u;
         uint32_t inc = v;
 #pragma unroll
         for (int d = 1; d < WAVE; d <<= 1) {
           const uint32_t o = (uint32_t)__shfl_up((int)inc, d);
           if (lane >= d) inc += o;
         }
-        if (lane == WAVE - 1) W[w] = inc;
+        if (own && lane == WAVE - 1) W[w] = inc;
         __syncthreads();
-        uint32_t lo = inc - v;
-        for (int kk = 0; kk < w; kk++) lo += W[kk];
-        LO[threadIdx.x] = lo;
-        DL[threadIdx.x] = dst - lo;
-        dst += v;
-        C[threadIdx.x] = 0;
+        if (own) {
+          uint32_t lo = inc - v;
+          for (int kk = 0; kk < w; kk++) lo += W[kk];
+          LO[threadIdx.x] = lo;
+          DL[threadIdx.x] = dst - lo;
+          dst += v;
+          C[threadIdx.x] = 0;
+        }
       }
       __syncthreads();
 #pragma unroll
-      for (int q = 0; q < LT_PER; q++) {
-        if ((uint32_t)(q * LT_P + threadIdx.x) < cnt) {
+      for (int q = 0; q < SC_PER; q++) {
+        if ((uint32_t)(q * SC_P + threadIdx.x) < cnt) {
           const uint32_t pos = LO[bb[q]] + r[q];
           stage[pos] = k[q];
           bid[pos] = (uint8_t)bb[q];
@@ -784,12 +795,12 @@ __global__ void __launch_bounds__(LT_P) scatter_kernel(const uint64_t* keys, uin
       // the clamp keeps every store inside the output even for an input changed in between
       if (cnt == LEARN_TILE) {
 #pragma unroll
-        for (int q = 0; q < LT_PER; q++) {
-          const uint32_t s = q * LT_P + threadIdx.x;
+        for (int q = 0; q < SC_PER; q++) {
+          const uint32_t s = q * SC_P + threadIdx.x;
           out[min(DL[bid[s]] + s, n - 1)] = stage[s];
         }
       } else {
-        for (uint32_t s = threadIdx.x; s < cnt; s += LT_P) out[min(DL[bid[s]] + s, n - 1)] = stage[s];
+        for (uint32_t s = threadIdx.x; s < cnt; s += SC_P) out[min(DL[bid[s]] + s, n - 1)] = stage[s];
       }
       __syncthreads();
     }
@@ -874,7 +885,7 @@ hipError_t launch_offsets(const uint64_t* totals, uint64_t n, float overflow_fac
 hipError_t launch_scatter(const uint64_t* keys, uint64_t n, const uint64_t* thr, const uint32_t* nvalid,
                           const uint32_t* hist, uint64_t nchunks, const int64_t* offsets, uint64_t* out,
                           hipStream_t s) {
-  hipLaunchKernelGGL(scatter_kernel, dim3(grid_for(nchunks, 1, 1 << 20)), dim3(LT_P), 0, s, keys, n, thr, nvalid,
+  hipLaunchKernelGGL(scatter_kernel, dim3(grid_for(nchunks, 1, 1 << 20)), dim3(SC_P), 0, s, keys, n, thr, nvalid,
                      hist, nchunks, offsets, out);
   return hipGetLastError();
 }
