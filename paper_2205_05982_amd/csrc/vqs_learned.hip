@@ -581,8 +581,10 @@ __global__ void classify_kernel(const uint64_t* keys, uint64_t n, const uint64_t
 // XCD (partial cache lines only where a stretch begins or ends).
 
 constexpr int LT_P = 256;
-constexpr int LT_PER = LEARN_TILE / LT_P;   // keys per thread
+constexpr int HIST_TILE = 4096;             // keys a histogram workgroup counts per step
+constexpr int LT_PER = HIST_TILE / LT_P;    // 16 keys per thread and step
 constexpr int LT_NW = LT_P / WAVE;
+static_assert((LEARN_TILE * CHUNK_TILES) % HIST_TILE == 0, "a chunk is whole histogram steps");
 static_assert(LT_P == NBUCKET, "thread b of a workgroup owns bucket b");
 
 // per-chunk bucket counts, chunk-major: hist[chunk * NBUCKET + b]
@@ -596,10 +598,12 @@ __global__ void __launch_bounds__(LT_P) histogram_kernel(const uint64_t* keys, u
   for (uint64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
     for (int i = threadIdx.x; i < LT_NW * NBUCKET; i += LT_P) (&C[0][0])[i] = 0;
     __syncthreads();
-    for (uint64_t tile = ch * CHUNK_TILES; tile < (ch + 1) * CHUNK_TILES; tile++) {
-      const uint64_t base = tile * LEARN_TILE;
+    // the chunk's keys in steps of HIST_TILE (the counts are per chunk, so the step
+    // need not be the scatter's tile: 16 keys per thread keep seven waves per SIMD)
+    constexpr uint64_t CHUNK = (uint64_t)LEARN_TILE * CHUNK_TILES;
+    for (uint64_t base = ch * CHUNK; base < (ch + 1) * CHUNK; base += HIST_TILE) {
       if (base >= n) break;
-      if (base + LEARN_TILE <= n) {
+      if (base + HIST_TILE <= n) {
         uint64_t k[LT_PER];
 #pragma unroll
         for (int q = 0; q < LT_PER; q++) k[q] = keys[base + (uint64_t)q * LT_P + threadIdx.x];
