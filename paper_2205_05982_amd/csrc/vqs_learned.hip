@@ -3,9 +3,9 @@
 // Pipeline (host side in vqs_host.cpp): sample 1% of the keys in random aligned
 // 64-byte chunks (the pivot sampler's unit); sort the sample with the plain method;
 // mid-rank CDF targets; train the model with Adam in one workgroup; compile the
-// monotone bucket map into 255 exact thresholds; per-tile 256-bin histograms; a
-// per-bucket scan over tiles; one scatter pass into 256 contiguous buckets; then
-// the buckets are sorted as segments by the plain method.
+// monotone bucket map into 255 exact thresholds; 256-bin histograms per 65,536-key
+// chunk; a per-bucket scan over the chunks; one scatter pass into 256 contiguous
+// buckets; then the buckets are sorted as segments by the plain method.
 //
 // Every FP32 operation of the model's forward pass is a single correctly rounded
 // operation in a fixed order (explicit fused multiply-adds, no contraction), so
